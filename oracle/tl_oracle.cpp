@@ -1,0 +1,338 @@
+// Serial FP64 CPU oracle for the per-grid-point tensor expressions of
+// Lewis & Pfeiffer, "Automatic generation of CUDA code performing tensor
+// manipulations using C++ expression templates" (arXiv:1804.10120).
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+// reference that the GPU library is checked against.  It shares no code with
+// the GPU path and is only ever called from the tests, from the smoke check and
+// from the benchmark's CPU-baseline leg; the product path never calls it.
+//
+// Every function follows the definition it cites, in the paper's notation and
+// operand order, with full index loops over i,j,k,l = 0..2 (the paper's
+// 1..3), serially over grid points, in IEEE double (built without fast-math
+// and without FP contraction).  Nothing is fused, reassociated or reduced.
+//
+// Storage conventions (shared with the GPU library's header by value only):
+//   a field with C independent components over n points is a contiguous
+//   [C][n] array; component c of point p is at ptr[c*n + p].
+//   symmetric pair (i,j) -> s(i,j): 00->0 01->1 02->2 11->3 12->4 22->5, the
+//     order in which the paper's symmetric loop nests visit the pairs
+//     (Sec. 2.4 tensor-index loop; Sec. 3 expression-tree example).
+//   dg     [18]: k*6 + s(i,j)  = partial_k g_ij
+//   gamma  [18]: i*6 + s(j,k)  = Gamma^i_jk   (symmetric in jk)
+//   gamma27[27]: (i*3+j)*3+k   = Gamma^i_jk   (all 27, for symmetry checks)
+//   dbeta  [9] : j*3 + i       = partial_j beta_i
+//   nabla  [9] : j*3 + i       = nabla_j beta_i
+//
+// The scalar type is a template parameter so that the same definitions also
+// yield exact forward-mode derivatives (dual numbers) and reverse-mode
+// gradients (a per-point operation tape); those are the adjoint oracle.
+
+#include <cstdint>
+#include <cstddef>
+#include <vector>
+
+namespace {
+
+inline int sym(int i, int j) {
+  static const int table[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+  return table[i][j];
+}
+
+// ---------------------------------------------------------------------------
+// Scalar types.
+
+// Forward-mode dual number: value and directional derivative.
+struct Dual {
+  double v, d;
+  Dual() : v(0.0), d(0.0) {}
+  Dual(double x) : v(x), d(0.0) {}
+  Dual(double x, double dx) : v(x), d(dx) {}
+};
+inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(Dual a, Dual b) {
+  const double q = a.v / b.v;
+  return Dual(q, (a.d - q * b.d) / b.v);
+}
+
+// Reverse mode: every operation appends a node holding the indices of its
+// (at most two) operands and the partial derivatives with respect to them.
+struct Tape {
+  std::vector<int> lhs, rhs;
+  std::vector<double> dl, dr;
+  int push(int a, double da, int b, double db) {
+    lhs.push_back(a);
+    dl.push_back(da);
+    rhs.push_back(b);
+    dr.push_back(db);
+    return static_cast<int>(lhs.size()) - 1;
+  }
+  void clear() { lhs.clear(); rhs.clear(); dl.clear(); dr.clear(); }
+};
+thread_local Tape* g_tape = nullptr;
+
+struct Var {
+  double v;
+  int id;  // -1: constant, carries no gradient
+  Var() : v(0.0), id(-1) {}
+  Var(double x) : v(x), id(-1) {}
+  static Var leaf(double x) {
+    Var r(x);
+    r.id = g_tape->push(-1, 0.0, -1, 0.0);
+    return r;
+  }
+};
+inline Var make(double v, int a, double da, int b, double db) {
+  Var r(v);
+  if (a >= 0 || b >= 0) r.id = g_tape->push(a, da, b, db);
+  return r;
+}
+inline Var operator+(Var a, Var b) { return make(a.v + b.v, a.id, 1.0, b.id, 1.0); }
+inline Var operator-(Var a, Var b) { return make(a.v - b.v, a.id, 1.0, b.id, -1.0); }
+inline Var operator-(Var a) { return make(-a.v, a.id, -1.0, -1, 0.0); }
+inline Var operator*(Var a, Var b) { return make(a.v * b.v, a.id, b.v, b.id, a.v); }
+inline Var operator/(Var a, Var b) {
+  const double q = a.v / b.v;
+  return make(q, a.id, 1.0 / b.v, b.id, -q / b.v);
+}
+
+// Adjoints of every tape node, given seeds on some nodes.
+void sweep(const Tape& t, std::vector<double>& adj) {
+  for (int i = static_cast<int>(t.lhs.size()) - 1; i >= 0; --i) {
+    const double a = adj[i];
+    if (a == 0.0) continue;
+    if (t.lhs[i] >= 0) adj[t.lhs[i]] += t.dl[i] * a;
+    if (t.rhs[i] >= 0) adj[t.rhs[i]] += t.dr[i] * a;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-point definitions.
+
+// Inverse metric g^ij of the symmetric 3x3 g_ij (Sec. 1, the inverse that
+// enters the Christoffel definition; the paper takes it as a given input and
+// names no method).  Definition used: Cramer's rule, inverse = adjugate /
+// determinant, with the cofactor C_ij = (-1)^(i+j) M_ij written for 3x3 by
+// cyclic indices and the determinant expanded along the first row.
+template <class T>
+void inverse_point(const T g[6], T ginv[6]) {
+  T a[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) a[i][j] = g[sym(i, j)];
+  T cof[3][3];
+  for (int i = 0; i < 3; ++i) {
+    const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+    for (int j = 0; j < 3; ++j) {
+      const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+      cof[i][j] = a[i1][j1] * a[i2][j2] - a[i1][j2] * a[i2][j1];
+    }
+  }
+  T det = a[0][0] * cof[0][0] + a[0][1] * cof[0][1] + a[0][2] * cof[0][2];
+  // (g^-1)_ij = adj(g)_ij / det = C_ji / det
+  for (int i = 0; i < 3; ++i)
+    for (int j = i; j < 3; ++j) ginv[sym(i, j)] = cof[j][i] / det;
+}
+
+// Christoffel symbols of the second kind, all 27 (Sec. 1, Christoffel
+// definition eq:SpatialChristoffel, and its TLoops form):
+//   Gamma^i_jk = 1/2 sum_l g^il (d_k g_jl + d_j g_lk - d_l g_jk).
+template <class T>
+void christoffel_point(const T ginv[6], const T dg[18], T gam27[27]) {
+  auto G = [&](int i, int j) { return ginv[sym(i, j)]; };
+  auto D = [&](int k, int i, int j) { return dg[k * 6 + sym(i, j)]; };  // d_k g_ij
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) {
+        T sum(0.0);
+        for (int l = 0; l < 3; ++l)
+          sum = sum + G(i, l) * ((D(k, j, l) + D(j, l, k)) - D(l, j, k));
+        gam27[(i * 3 + j) * 3 + k] = T(0.5) * sum;
+      }
+}
+
+// Covariant derivative of the shift covector (Sec. 1, footnote to the
+// schematic dtg listing):  nabla_j beta_i = d_j beta_i - Gamma^k_ij beta_k.
+template <class T>
+void cov_deriv_point(const T gam27[27], const T beta[3], const T dbeta[9], T nb[9]) {
+  for (int j = 0; j < 3; ++j)
+    for (int i = 0; i < 3; ++i) {
+      T sum(0.0);
+      for (int k = 0; k < 3; ++k) sum = sum + gam27[(k * 3 + i) * 3 + j] * beta[k];
+      nb[j * 3 + i] = dbeta[j * 3 + i] - sum;
+    }
+}
+
+// Metric evolution (Sec. 1, eq:dtg_ij and the schematic/TLoops listings):
+//   d_t g_ij = -2 alpha K_ij + nabla_i beta_j + nabla_j beta_i,  i <= j.
+template <class T>
+void dtg_point(const T& alpha, const T K[6], const T nb[9], T dtg[6]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = i; j < 3; ++j)
+      dtg[sym(i, j)] = T(-2.0) * alpha * K[sym(i, j)] + nb[i * 3 + j] + nb[j * 3 + i];
+}
+
+// The chain, step by step: inverse, Christoffel, covariant derivative, dtg.
+template <class T>
+void chain_point(const T g[6], const T dg[18], const T beta[3], const T dbeta[9], const T K[6],
+                 const T& alpha, T dtg[6]) {
+  T ginv[6], gam27[27], nb[9];
+  inverse_point(g, ginv);
+  christoffel_point(ginv, dg, gam27);
+  cov_deriv_point(gam27, beta, dbeta, nb);
+  dtg_point(alpha, K, nb, dtg);
+}
+
+// Field access helpers for contiguous [C][n] arrays.
+template <class T>
+inline void gather(const double* f, int64_t n, int64_t p, int ncomp, T* out) {
+  for (int c = 0; c < ncomp; ++c) out[c] = T(f[c * n + p]);
+}
+inline void scatter(double* f, int64_t n, int64_t p, int ncomp, const double* in) {
+  for (int c = 0; c < ncomp; ++c) f[c * n + p] = in[c];
+}
+
+}  // namespace
+
+extern "C" {
+
+int tlo_abi_version(void) { return 1; }
+
+void tlo_sym_inverse(int64_t n, const double* g, double* ginv) {
+  for (int64_t p = 0; p < n; ++p) {
+    double a[6], r[6];
+    gather(g, n, p, 6, a);
+    inverse_point(a, r);
+    scatter(ginv, n, p, 6, r);
+  }
+}
+
+void tlo_christoffel_full(int64_t n, const double* ginv, const double* dg, double* gamma27) {
+  for (int64_t p = 0; p < n; ++p) {
+    double G[6], D[18], r[27];
+    gather(ginv, n, p, 6, G);
+    gather(dg, n, p, 18, D);
+    christoffel_point(G, D, r);
+    scatter(gamma27, n, p, 27, r);
+  }
+}
+
+void tlo_christoffel(int64_t n, const double* ginv, const double* dg, double* gamma) {
+  for (int64_t p = 0; p < n; ++p) {
+    double G[6], D[18], r[27], out[18];
+    gather(ginv, n, p, 6, G);
+    gather(dg, n, p, 18, D);
+    christoffel_point(G, D, r);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        for (int k = j; k < 3; ++k) out[i * 6 + sym(j, k)] = r[(i * 3 + j) * 3 + k];
+    scatter(gamma, n, p, 18, out);
+  }
+}
+
+void tlo_cov_deriv(int64_t n, const double* gamma, const double* beta, const double* dbeta,
+                   double* nabla) {
+  for (int64_t p = 0; p < n; ++p) {
+    double Gs[18], g27[27], b[3], db[9], r[9];
+    gather(gamma, n, p, 18, Gs);
+    gather(beta, n, p, 3, b);
+    gather(dbeta, n, p, 9, db);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k) g27[(i * 3 + j) * 3 + k] = Gs[i * 6 + sym(j, k)];
+    cov_deriv_point(g27, b, db, r);
+    scatter(nabla, n, p, 9, r);
+  }
+}
+
+void tlo_dtg(int64_t n, const double* alpha, const double* K, const double* nabla, double* dtg) {
+  for (int64_t p = 0; p < n; ++p) {
+    double k6[6], nb[9], r[6];
+    gather(K, n, p, 6, k6);
+    gather(nabla, n, p, 9, nb);
+    dtg_point(alpha[p], k6, nb, r);
+    scatter(dtg, n, p, 6, r);
+  }
+}
+
+void tlo_dtg_chain(int64_t n, const double* g, const double* dg, const double* beta,
+                   const double* dbeta, const double* K, const double* alpha, double* dtg) {
+  for (int64_t p = 0; p < n; ++p) {
+    double a[6], D[18], b[3], db[9], k6[6], r[6];
+    gather(g, n, p, 6, a);
+    gather(dg, n, p, 18, D);
+    gather(beta, n, p, 3, b);
+    gather(dbeta, n, p, 9, db);
+    gather(K, n, p, 6, k6);
+    chain_point(a, D, b, db, k6, alpha[p], r);
+    scatter(dtg, n, p, 6, r);
+  }
+}
+
+// Forward-mode derivative of the chain: dtg and its directional derivative
+// along the tangent fields (t_g, ..., t_alpha), exact up to rounding.
+void tlo_dtg_chain_jvp(int64_t n, const double* g, const double* dg, const double* beta,
+                       const double* dbeta, const double* K, const double* alpha,
+                       const double* tg, const double* tdg, const double* tbeta,
+                       const double* tdbeta, const double* tK, const double* talpha, double* dtg,
+                       double* dtg_dot) {
+  for (int64_t p = 0; p < n; ++p) {
+    Dual a[6], D[18], b[3], db[9], k6[6], r[6];
+    for (int c = 0; c < 6; ++c) a[c] = Dual(g[c * n + p], tg[c * n + p]);
+    for (int c = 0; c < 18; ++c) D[c] = Dual(dg[c * n + p], tdg[c * n + p]);
+    for (int c = 0; c < 3; ++c) b[c] = Dual(beta[c * n + p], tbeta[c * n + p]);
+    for (int c = 0; c < 9; ++c) db[c] = Dual(dbeta[c * n + p], tdbeta[c * n + p]);
+    for (int c = 0; c < 6; ++c) k6[c] = Dual(K[c * n + p], tK[c * n + p]);
+    const Dual al(alpha[p], talpha[p]);
+    chain_point(a, D, b, db, k6, al, r);
+    for (int c = 0; c < 6; ++c) {
+      dtg[c * n + p] = r[c].v;
+      dtg_dot[c * n + p] = r[c].d;
+    }
+  }
+}
+
+// Reverse-mode gradient of L = sum_p sum_s W_s(p) dtg_s(p) with respect to
+// every stored input component (an off-diagonal stored slot of g, dg or K
+// receives the sum of its (i,j) and (j,i) partials, because both read the same
+// stored value).  Any output pointer may be NULL to skip that gradient.
+void tlo_dtg_chain_vjp(int64_t n, const double* g, const double* dg, const double* beta,
+                       const double* dbeta, const double* K, const double* alpha, const double* W,
+                       double* g_bar, double* dg_bar, double* beta_bar, double* dbeta_bar,
+                       double* K_bar, double* alpha_bar) {
+  Tape tape;
+  g_tape = &tape;
+  std::vector<double> adj;
+  for (int64_t p = 0; p < n; ++p) {
+    tape.clear();
+    Var a[6], D[18], b[3], db[9], k6[6], r[6];
+    for (int c = 0; c < 6; ++c) a[c] = Var::leaf(g[c * n + p]);
+    for (int c = 0; c < 18; ++c) D[c] = Var::leaf(dg[c * n + p]);
+    for (int c = 0; c < 3; ++c) b[c] = Var::leaf(beta[c * n + p]);
+    for (int c = 0; c < 9; ++c) db[c] = Var::leaf(dbeta[c * n + p]);
+    for (int c = 0; c < 6; ++c) k6[c] = Var::leaf(K[c * n + p]);
+    const Var al = Var::leaf(alpha[p]);
+    chain_point(a, D, b, db, k6, al, r);
+    adj.assign(tape.lhs.size(), 0.0);
+    for (int c = 0; c < 6; ++c)
+      if (r[c].id >= 0) adj[r[c].id] += W[c * n + p];
+    sweep(tape, adj);
+    auto grad = [&](const Var& v) { return v.id >= 0 ? adj[v.id] : 0.0; };
+    if (g_bar)
+      for (int c = 0; c < 6; ++c) g_bar[c * n + p] = grad(a[c]);
+    if (dg_bar)
+      for (int c = 0; c < 18; ++c) dg_bar[c * n + p] = grad(D[c]);
+    if (beta_bar)
+      for (int c = 0; c < 3; ++c) beta_bar[c * n + p] = grad(b[c]);
+    if (dbeta_bar)
+      for (int c = 0; c < 9; ++c) dbeta_bar[c * n + p] = grad(db[c]);
+    if (K_bar)
+      for (int c = 0; c < 6; ++c) K_bar[c * n + p] = grad(k6[c]);
+    if (alpha_bar) alpha_bar[p] = grad(al);
+  }
+  g_tape = nullptr;
+}
+
+}  // extern "C"

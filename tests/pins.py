@@ -1,0 +1,358 @@
+"""Checks that pin the CPU oracle to mathematics other than its own formulas.
+
+Each ``pin_*`` function takes an ``oracle.Oracle`` and raises AssertionError if
+the oracle disagrees with a closed form, an invariant, an independent method
+(LAPACK inverse, the linear system that metric compatibility imposes on Gamma,
+the Lie-derivative form of d_t g) or finite differences.  The same functions
+run against deliberately broken builds of the oracle source (see
+``test_oracle_mutants.py``) to show that each plausible mistake fails a pin.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import closed_forms as cf
+from metrics import rel_err
+from paper_1804_10120_amd.synth import make_fields
+
+EPS = np.finfo(np.float64).eps
+TOL = 1e-12          # per-component relative error gate
+
+
+def _assert(cond, msg):
+    if not cond:
+        raise AssertionError(msg)
+
+
+def _close(x, r, tol, what, scale="component"):
+    e = rel_err(x, r, scale)
+    _assert(e <= tol, f"{what}: relative error {e:.3e} > {tol:.1e}")
+
+
+def _random(n, seed=11):
+    return make_fields(n, seed=seed)
+
+
+def _spd(n, seed=5):
+    """General SPD metrics, condition numbers up to ~1e2."""
+    rng = np.random.default_rng(seed)
+    A = rng.uniform(-1, 1, size=(n, 3, 3))
+    M = A @ A.transpose(0, 2, 1) + 0.05 * np.eye(3)
+    return cf.sym6(M.transpose(1, 2, 0)), M
+
+
+# --------------------------------------------------------------------------- inverse
+
+def pin_inverse_residual(orc):
+    """g^il g_lj = delta_ij, within 64 eps kappa."""
+    for g6, M in ((_random(512)["g"], None), _spd(512)):
+        Gi = cf.full33(orc.sym_inverse(g6)).transpose(2, 0, 1)
+        Mg = cf.full33(g6).transpose(2, 0, 1)
+        kappa = np.linalg.cond(Mg)
+        res = np.abs(Gi @ Mg - np.eye(3)).max(axis=(1, 2))
+        _assert(np.all(res <= 64 * EPS * kappa), f"inverse residual {res.max():.3e}")
+
+
+def pin_inverse_lapack(orc):
+    """Agrees with LAPACK's LU-based inverse (a different method)."""
+    g6, M = _spd(256, seed=9)
+    ref = cf.sym6(np.linalg.inv(M).transpose(1, 2, 0))
+    kappa = np.linalg.cond(M).max()
+    _close(orc.sym_inverse(g6), ref, 64 * EPS * kappa, "inverse vs LAPACK")
+
+
+def pin_inverse_diagonal(orc):
+    """Diagonal metrics of powers of two invert exactly."""
+    g = np.zeros((6, 4))
+    g[[0, 3, 5]] = np.array([[2.0, 0.5, 4.0, 1.0], [4.0, 8.0, 0.25, 1.0],
+                             [0.5, 2.0, 1.0, 16.0]])
+    G = orc.sym_inverse(g)
+    exp = np.zeros_like(g)
+    exp[[0, 3, 5]] = 1.0 / g[[0, 3, 5]]
+    _assert(np.array_equal(G, exp), "diagonal inverse not exact")
+
+
+# --------------------------------------------------------------------------- Christoffel
+
+def _gamma27(orc, g, dg):
+    return orc.christoffel(orc.sym_inverse(g), dg, full=True)
+
+
+def compat_solve(g, dg):
+    """Gamma as the unique connection that is symmetric in its lower indices
+    and leaves the metric covariantly constant: solves, at every point, the 18
+    linear equations d_k g_ij = g_il Gamma^l_jk + g_jl Gamma^l_ik for the 18
+    unknowns Gamma^l_(jk) with LAPACK.  Returns [27, n]."""
+    n = g.shape[1]
+    G = cf.full33(g)
+    D = cf.dg_full(dg)
+    unk = [(l, j, k) for l in range(3) for j, k in cf.PAIRS]
+    col = {u: c for c, u in enumerate(unk)}
+
+    def cidx(l, a, b):
+        return col[(l, min(a, b), max(a, b))]
+
+    A = np.zeros((n, 18, 18))
+    rhs = np.zeros((n, 18))
+    row = 0
+    for k in range(3):
+        for i, j in cf.PAIRS:
+            for l in range(3):
+                A[:, row, cidx(l, j, k)] += G[i, l]
+                A[:, row, cidx(l, i, k)] += G[j, l]
+            rhs[:, row] = D[k, i, j]
+            row += 1
+    x = np.linalg.solve(A, rhs[..., None])[..., 0]
+    out = np.zeros((3, 3, 3, n))
+    for (l, j, k), c in col.items():
+        out[l, j, k] = out[l, k, j] = x[:, c]
+    return out.reshape(27, n)
+
+
+def pin_christoffel_compatibility(orc):
+    f = _random(300, seed=21)
+    _close(_gamma27(orc, f["g"], f["dg"]), compat_solve(f["g"], f["dg"]), 1e-12,
+           "Gamma vs metric-compatibility solve")
+    g6, _ = _spd(200, seed=3)
+    dg = np.random.default_rng(4).uniform(-1, 1, size=(18, 200))
+    _close(_gamma27(orc, g6, dg), compat_solve(g6, dg), 1e-10,
+           "Gamma vs metric-compatibility solve (general SPD)")
+
+
+def pin_christoffel_symmetry(orc):
+    """Gamma^i_jk == Gamma^i_kj, bitwise (all 27 computed independently)."""
+    f = _random(256, seed=22)
+    G = _gamma27(orc, f["g"], f["dg"]).reshape(3, 3, 3, -1)
+    _assert(np.array_equal(G, G.transpose(0, 2, 1, 3)), "Gamma not symmetric in jk")
+
+
+def pin_christoffel_flat(orc):
+    """d_k g_ij = 0 gives Gamma = 0 bitwise."""
+    f = _random(64, seed=23)
+    G = _gamma27(orc, f["g"], np.zeros((18, 64)))
+    _assert(np.all(G == 0.0), "Gamma nonzero for constant metric")
+
+
+def pin_christoffel_closed_forms(orc):
+    rng = np.random.default_rng(24)
+    r = rng.uniform(0.5, 2.0, 200)
+    th = rng.uniform(0.3, np.pi - 0.3, 200)
+    g, dg, exp = cf.flat_spherical(r, th)
+    _close(_gamma27(orc, g, dg), exp, 1e-13, "Gamma flat spherical", "tensor")
+    r = rng.uniform(3.0, 10.0, 200)
+    g, dg, exp = cf.schwarzschild_areal(r, th, 1.0)
+    _close(_gamma27(orc, g, dg), exp, 1e-13, "Gamma Schwarzschild areal", "tensor")
+    x = rng.uniform(-3, 3, size=(3, 200))
+    x[0] += np.sign(x[0]) * 1.0
+    g, dg, exp = cf.schwarzschild_isotropic(x, 1.0)
+    _close(_gamma27(orc, g, dg), exp, 1e-13, "Gamma Schwarzschild isotropic", "tensor")
+    cv = cf.Curvilinear(300)
+    _close(_gamma27(orc, cv.g, cv.dg), cv.gamma27, 1e-13, "Gamma flat curvilinear", "tensor")
+
+
+def pin_christoffel_stored(orc):
+    """The 18 stored components are the jk <= pairs of the 27."""
+    f = _random(64, seed=25)
+    Gi = orc.sym_inverse(f["g"])
+    G27 = orc.christoffel(Gi, f["dg"], full=True).reshape(3, 3, 3, -1)
+    G18 = orc.christoffel(Gi, f["dg"])
+    exp = np.concatenate([cf.sym6(G27[i]) for i in range(3)])
+    _assert(np.array_equal(G18, exp), "stored Gamma layout")
+
+
+# --------------------------------------------------------------------------- nabla beta
+
+def _nabla(orc, g, dg, beta, dbeta):
+    return orc.cov_deriv(orc.christoffel(orc.sym_inverse(g), dg), beta, dbeta)
+
+
+def pin_covderiv_closed_forms(orc):
+    cv = cf.Curvilinear(300, seed=31)
+    b, db = cv.gradient_shift()
+    nb = _nabla(orc, cv.g, cv.dg, b, db)
+    _assert(np.abs(nb).max() <= 1e-13, f"gradient shift: |nabla beta| {np.abs(nb).max():.2e}")
+    b, db = cv.homothety_shift()
+    _close(_nabla(orc, cv.g, cv.dg, b, db), cf.full33(cv.g).reshape(9, -1), 1e-13,
+           "homothety nabla beta = g", "tensor")
+    b, db, exp = cv.killing_shift()
+    _close(_nabla(orc, cv.g, cv.dg, b, db), exp, 1e-13, "Killing nabla beta", "tensor")
+    rng = np.random.default_rng(32)
+    r = rng.uniform(0.5, 2.0, 100)
+    th = rng.uniform(0.3, np.pi - 0.3, 100)
+    g, dg, _ = cf.flat_spherical(r, th)
+    b, db = cf.spherical_shift_dz(r, th)
+    nb = _nabla(orc, g, dg, b, db)
+    _assert(np.abs(nb).max() <= 1e-14, "spherical dz: nabla beta != 0")
+
+
+def pin_covderiv_no_connection(orc):
+    """Gamma = 0 gives nabla_j beta_i = d_j beta_i bitwise."""
+    f = _random(64, seed=33)
+    nb = orc.cov_deriv(np.zeros((18, 64)), f["beta"], f["dbeta"])
+    _assert(np.array_equal(nb, f["dbeta"]), "nabla beta != d beta for Gamma = 0")
+
+
+def pin_covderiv_raised_index(orc):
+    """nabla_j beta_i = g_ik (d_j beta^k + Gamma^k_jl beta^l) with beta^k =
+    g^kl beta_l and d_j beta^k = g^kl d_j beta_l - g^ka (d_j g_ab) g^bl beta_l,
+    using LAPACK's inverse and the compatibility-solve Gamma."""
+    f = _random(256, seed=34)
+    n = 256
+    G = cf.full33(f["g"]).transpose(2, 0, 1)
+    Gi = np.linalg.inv(G)
+    D = cf.dg_full(f["dg"]).transpose(3, 0, 1, 2)            # [n,k,i,j]
+    Gam = compat_solve(f["g"], f["dg"]).reshape(3, 3, 3, n).transpose(3, 0, 1, 2)
+    b = f["beta"].T                                          # [n,i]
+    db = f["dbeta"].reshape(3, 3, n).transpose(2, 0, 1)      # [n,j,i]
+    bu = np.einsum("nkl,nl->nk", Gi, b)
+    dbu = (np.einsum("nkl,njl->njk", Gi, db)
+           - np.einsum("nka,njab,nb->njk", Gi, D, bu))
+    cov_up = dbu + np.einsum("nkjl,nl->njk", Gam, bu)        # nabla_j beta^k
+    exp = np.einsum("nik,njk->nji", G, cov_up)               # nabla_j beta_i
+    _close(_nabla(orc, f["g"], f["dg"], f["beta"], f["dbeta"]),
+           exp.transpose(1, 2, 0).reshape(9, n), 1e-12, "nabla beta vs raised-index form")
+
+
+# --------------------------------------------------------------------------- d_t g
+
+def lie_dtg(f):
+    """-2 alpha K_ij + (Lie derivative of g along beta^k)_ij, with beta^k =
+    g^kl beta_l: beta^k d_k g_ij + g_kj d_i beta^k + g_ik d_j beta^k."""
+    n = f["g"].shape[1]
+    G = cf.full33(f["g"]).transpose(2, 0, 1)
+    Gi = np.linalg.inv(G)
+    D = cf.dg_full(f["dg"]).transpose(3, 0, 1, 2)
+    b = f["beta"].T
+    db = f["dbeta"].reshape(3, 3, n).transpose(2, 0, 1)
+    bu = np.einsum("nkl,nl->nk", Gi, b)
+    dbu = (np.einsum("nkl,njl->njk", Gi, db)
+           - np.einsum("nka,njab,nb->njk", Gi, D, bu))       # d_j beta^k
+    lie = (np.einsum("nk,nkij->nij", bu, D) + np.einsum("nkj,nik->nij", G, dbu)
+           + np.einsum("nik,njk->nij", G, dbu))
+    out = -2 * f["alpha"][0][:, None, None] * cf.full33(f["K"]).transpose(2, 0, 1) + lie
+    return cf.sym6(out.transpose(1, 2, 0))
+
+
+def _chain(orc, f):
+    return orc.dtg_chain(f["g"], f["dg"], f["beta"], f["dbeta"], f["K"], f["alpha"])
+
+
+def pin_dtg_lie_derivative(orc):
+    f = _random(400, seed=41)
+    _close(_chain(orc, f), lie_dtg(f), 1e-12, "dtg vs Lie derivative form")
+    g6, _ = _spd(200, seed=42)
+    f = _random(200, seed=43)
+    f["g"] = g6
+    _close(_chain(orc, f), lie_dtg(f), 1e-10, "dtg vs Lie derivative form (general SPD)")
+
+
+def pin_dtg_zero_shift(orc):
+    """beta = 0 and d beta = 0 give d_t g = -2 alpha K bitwise."""
+    f = _random(64, seed=44)
+    f["beta"][:] = 0.0
+    f["dbeta"][:] = 0.0
+    _assert(np.array_equal(_chain(orc, f), -2.0 * f["alpha"] * f["K"]), "dtg zero shift")
+
+
+def pin_dtg_closed_forms(orc):
+    cv = cf.Curvilinear(200, seed=45)
+    rng = np.random.default_rng(46)
+    base = {"g": cv.g, "dg": cv.dg, "K": rng.uniform(-1, 1, (6, 200)),
+            "alpha": rng.uniform(0.5, 1.5, (1, 200))}
+    f = dict(base)
+    f["beta"], f["dbeta"], _ = cv.killing_shift()
+    _close(_chain(orc, f), -2 * f["alpha"] * f["K"], 1e-13, "dtg Killing shift", "tensor")
+    f["beta"], f["dbeta"] = cv.homothety_shift()
+    _close(_chain(orc, f), -2 * f["alpha"] * f["K"] + 2 * cv.g, 1e-13, "dtg homothety", "tensor")
+    r = rng.uniform(0.5, 2.0, 200)
+    th = rng.uniform(0.3, np.pi - 0.3, 200)
+    g, dg, _ = cf.flat_spherical(r, th)
+    f = dict(base, g=g, dg=dg)
+    f["beta"], f["dbeta"] = cf.spherical_shift_rdr(r, th)
+    _close(_chain(orc, f), -2 * f["alpha"] * f["K"] + 2 * g, 1e-13, "dtg spherical r dr", "tensor")
+
+
+def pin_dtg_steps_compose(orc):
+    """The separate steps compose to the chain, bitwise."""
+    f = _random(128, seed=47)
+    Gi = orc.sym_inverse(f["g"])
+    Gam = orc.christoffel(Gi, f["dg"])
+    nb = orc.cov_deriv(Gam, f["beta"], f["dbeta"])
+    _assert(np.array_equal(orc.dtg(f["alpha"], f["K"], nb), _chain(orc, f)),
+            "steps do not compose to the chain")
+
+
+# --------------------------------------------------------------------------- adjoint
+
+INPUTS = ("g", "dg", "beta", "dbeta", "K", "alpha")
+
+
+def _ins(f):
+    return tuple(f[k] for k in INPUTS)
+
+
+def pin_adjoint_closed_forms(orc):
+    """K_bar = -2 alpha W; alpha_bar = -2 sum_s W_s K_s; d beta_bar[j][i] =
+    W_s(i,j) off the diagonal and 2 W_s(i,i) on it (d_t g is linear in K, alpha
+    and d beta)."""
+    f = _random(256, seed=51)
+    gr = orc.dtg_chain_vjp(_ins(f), f["W"])
+    W, K, al = f["W"], f["K"], f["alpha"]
+    _assert(np.array_equal(gr["K"], -2.0 * al * W), "K_bar")
+    _close(gr["alpha"], -2.0 * (W * K).sum(0, keepdims=True), 1e-14, "alpha_bar")
+    exp = np.zeros((3, 3, W.shape[1]))
+    for i in range(3):
+        for j in range(3):
+            exp[j, i] = W[cf.S[i, j]] * (2.0 if i == j else 1.0)
+    _assert(np.array_equal(gr["dbeta"], exp.reshape(9, -1)), "dbeta_bar")
+
+
+def _loss_per_point(orc, f, W):
+    return (W * _chain(orc, f)).sum(0)
+
+
+def pin_adjoint_finite_difference(orc, n=64, h=1e-6, tol=1e-6):
+    """Central differences of L_p = sum_s W_s d_t g_s(p); points are independent,
+    so one component is perturbed at every point at once."""
+    f = _random(n, seed=52)
+    W = f["W"]
+    gr = orc.dtg_chain_vjp(_ins(f), W)
+    for k in INPUTS:
+        fd = np.empty_like(f[k])
+        for c in range(f[k].shape[0]):
+            fp = {kk: v.copy() for kk, v in f.items()}
+            fm = {kk: v.copy() for kk, v in f.items()}
+            fp[k][c] += h
+            fm[k][c] -= h
+            fd[c] = (_loss_per_point(orc, fp, W) - _loss_per_point(orc, fm, W)) / (2 * h)
+        _close(gr[k], fd, tol, f"VJP vs central differences ({k})")
+
+
+def pin_adjoint_dot_product(orc, n=256):
+    """<J v, W> = <v, J^T W> per point: forward mode (dual numbers) against
+    reverse mode (tape)."""
+    f = _random(n, seed=53)
+    rng = np.random.default_rng(54)
+    v = tuple(rng.standard_normal(f[k].shape) for k in INPUTS)
+    _, jv = orc.dtg_chain_jvp(_ins(f), v)
+    gr = orc.dtg_chain_vjp(_ins(f), f["W"])
+    lhs = (jv * f["W"]).sum(0)
+    rhs = sum((vk * gr[k]).sum(0) for vk, k in zip(v, INPUTS))
+    scale = np.abs(jv * f["W"]).sum(0) + 1e-300
+    err = np.abs(lhs - rhs) / scale
+    _assert(err.max() <= 1e-13, f"dot-product test {err.max():.3e}")
+
+
+def pin_jvp_finite_difference(orc, n=128, h=1e-6):
+    f = _random(n, seed=55)
+    rng = np.random.default_rng(56)
+    v = tuple(rng.standard_normal(f[k].shape) for k in INPUTS)
+    val, jv = orc.dtg_chain_jvp(_ins(f), v)
+    _assert(np.array_equal(val, _chain(orc, f)), "JVP primal differs from the chain")
+    fp = {k: f[k] + h * vk for k, vk in zip(INPUTS, v)}
+    fm = {k: f[k] - h * vk for k, vk in zip(INPUTS, v)}
+    fd = (_chain(orc, fp) - _chain(orc, fm)) / (2 * h)
+    _close(jv, fd, 1e-6, "JVP vs central differences")
+
+
+ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_") and callable(v)]

@@ -1,0 +1,71 @@
+"""Plants plausible mistakes in copies of the oracle source (on the CPU only)
+and checks that each one fails at least one pin.  This shows that the pins in
+``pins.py`` constrain every step of the oracle: a dropped term, a wrong sign, a
+wrong or transposed index, a wrong factor or a wrong derivative rule is caught.
+"""
+import os
+
+import pytest
+
+import oracle
+import pins
+from oracle import build as obuild
+
+SRC = open(obuild.SRC).read()
+
+# (id, text in the oracle source, replacement)
+MUTANTS = [
+    ("cofactor_sign", "a[i1][j1] * a[i2][j2] - a[i1][j2] * a[i2][j1]",
+     "a[i1][j1] * a[i2][j2] + a[i1][j2] * a[i2][j1]"),
+    ("cofactor_index", "a[i1][j1] * a[i2][j2] - a[i1][j2] * a[i2][j1]",
+     "a[i1][j1] * a[i2][j2] - a[i1][j1] * a[i2][j1]"),
+    ("det_term", "a[0][1] * cof[0][1] + a[0][2] * cof[0][2]",
+     "a[0][1] * cof[1][1] + a[0][2] * cof[0][2]"),
+    ("det_dropped", "a[0][1] * cof[0][1] + a[0][2] * cof[0][2]", "a[0][1] * cof[0][1]"),
+    ("sym_table", "{1, 3, 4}, {2, 4, 5}", "{1, 3, 5}, {2, 4, 5}"),
+    ("gamma_sign", "- D(l, j, k))", "+ D(l, j, k))"),
+    ("gamma_dropped_term", "((D(k, j, l) + D(j, l, k)) - D(l, j, k))", "(D(k, j, l) - D(l, j, k))"),
+    ("gamma_deriv_index", "((D(k, j, l) + D(j, l, k))", "((D(j, k, l) + D(j, l, k))"),
+    ("gamma_inverse_index", "G(i, l) * ((D", "G(j, l) * ((D"),
+    ("gamma_half", "T(0.5) * sum", "sum"),
+    ("gamma_dg_layout", "dg[k * 6 + sym(i, j)]", "dg[i * 6 + sym(k, j)]"),
+    ("nabla_sign", "dbeta[j * 3 + i] - sum", "dbeta[j * 3 + i] + sum"),
+    ("nabla_transposed_dbeta", "dbeta[j * 3 + i] - sum", "dbeta[i * 3 + j] - sum"),
+    ("nabla_gamma_index", "gam27[(k * 3 + i) * 3 + j] * beta[k]", "gam27[(i * 3 + k) * 3 + j] * beta[k]"),
+    ("nabla_stored_gamma", "g27[(i * 3 + j) * 3 + k] = Gs[i * 6 + sym(j, k)]",
+     "g27[(i * 3 + j) * 3 + k] = Gs[j * 6 + sym(i, k)]"),
+    ("dtg_sign", "T(-2.0) * alpha", "T(2.0) * alpha"),
+    ("dtg_dropped_term", "+ nb[i * 3 + j] + nb[j * 3 + i]", "+ nb[i * 3 + j] + nb[i * 3 + j]"),
+    ("dtg_factor", "T(-2.0) * alpha * K", "alpha * K"),
+    ("tape_mul_partials", "make(a.v * b.v, a.id, b.v, b.id, a.v)", "make(a.v * b.v, a.id, a.v, b.id, b.v)"),
+    ("tape_div_sign", "-q / b.v);", "q / b.v);"),
+    ("tape_sub_sign", "make(a.v - b.v, a.id, 1.0, b.id, -1.0)", "make(a.v - b.v, a.id, 1.0, b.id, 1.0)"),
+    ("dual_div", "(a.d - q * b.d) / b.v", "(a.d + q * b.d) / b.v"),
+    ("dual_mul", "a.d * b.v + a.v * b.d", "a.d * b.v + a.v * b.v"),
+]
+
+
+def _run_all_pins(orc):
+    failed = []
+    for pin in pins.ALL_PINS:
+        try:
+            pin(orc)
+        except AssertionError as e:
+            failed.append(f"{pin.__name__}: {e}")
+    return failed
+
+
+@pytest.mark.parametrize("mid,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(tmp_path, mid, old, new):
+    assert SRC.count(old) >= 1, f"mutation site for {mid} not found in oracle source"
+    src = tmp_path / f"mut_{mid}.cpp"
+    src.write_text(SRC.replace(old, new))
+    lib = obuild.build(str(src), str(tmp_path / f"libmut_{mid}.so"))
+    failed = _run_all_pins(oracle.Oracle(lib))
+    assert failed, f"mutant {mid} passes every pin"
+
+
+def test_unmutated_source_passes(tmp_path):
+    lib = obuild.build(obuild.SRC, str(tmp_path / "libclean.so"))
+    assert _run_all_pins(oracle.Oracle(lib)) == []
+    assert os.path.exists(lib)
