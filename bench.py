@@ -1,0 +1,287 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused FP64 metric-evolution chain on one MI355X.
+
+One step = the fused forward d_t g_ij (tl_dtg_chain) and its adjoint
+(tl_dtg_chain_bwd) over N = 128^3 grid points, through the C ABI, with the
+library's default launch shapes.  Inputs are seeded synthetic fields already
+resident in HBM (about 1.75 GB touched per step, far beyond the 256 MB
+Infinity Cache, so every step streams from HBM).
+
+Prints ONE JSON line: whole-job grid points/s for fwd+bwd, the roofline of the
+dominant kernel (algorithmic bytes / HIP-event-timed duration against the
+8 TB/s HBM peak, plus the counter-measured traffic when a profile of the
+current kernels is committed), the other hot-path rows timed in the same run
+(forward alone, the unfused steps, the 64^3 configurations, many subgrids in
+one launch), the measured copy ceiling, and the serial CPU oracle timed on a
+bounded sample.
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--edge 128]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KEYS = ("g", "dg", "beta", "dbeta", "K", "alpha")
+# Algorithmic bytes per grid point: 8 B per stored tensor element read or
+# written (the paper's effective-bandwidth count, with no scalars outside
+# the fields).
+BYTES = {"sym_inverse": 8 * 12, "christoffel": 8 * 42, "cov_deriv": 8 * 39, "dtg": 8 * 22,
+         "dtg_chain": 8 * 49, "dtg_chain_bwd": 8 * 83, "dtg_chain_batched": 8 * 49,
+         "unfused_chain": 8 * 115}
+METRIC = "grid points/s + achieved HBM GB/s, fused FP64 chain fwd and fwd+bwd"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def traffic_record(kernel, n):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    ``kernel``, if it was taken at this size from the current kernel sources."""
+    from paper_1804_10120_amd.profsum import sources_sha256
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", "|", " ")):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    if rec.get("sources_sha256") != sources_sha256() or rec.get("points") != str(n):
+        return None
+    try:
+        return float(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def device_sets(n, nsets, device, seed0):
+    import torch
+    from paper_1804_10120_amd.synth import make_fields
+    sets = []
+    for s in range(nsets):
+        f = make_fields(n, seed=seed0 + 1000 * s)
+        sets.append((f, {k: torch.from_numpy(v).to(device) for k, v in f.items()}))
+    return sets
+
+
+def time_calls(lists, reps, warmup):
+    """Runs the call lists round-robin.  Returns (wall ms per list, HIP-event
+    ms per call position averaged over reps)."""
+    import torch
+    nl, nc = len(lists), len(lists[0])
+    for i in range(warmup):
+        for c in lists[i % nl]:
+            c()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(nc + 1)] for _ in range(reps)]
+    t0 = time.perf_counter()
+    for i in range(reps):
+        e = evs[i]
+        e[0].record()
+        for j, c in enumerate(lists[i % nl]):
+            c()
+            e[j + 1].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / reps
+    per = [sum(evs[i][j].elapsed_time(evs[i][j + 1]) for i in range(reps)) / reps
+           for j in range(nc)]
+    return wall, per
+
+
+def rate(nbytes, ms):
+    return nbytes / (ms * 1e-3) / 1e9
+
+
+def copy_ceiling(device, reps=20):
+    """GB/s of the library's streaming copy over 2 x 512 MiB."""
+    import torch
+    from paper_1804_10120_amd import tl_bw_copy
+    from paper_1804_10120_amd.ops import record
+    n = 64 * 1024 * 1024
+    src = torch.rand(n, dtype=torch.float64, device=device)
+    dst = torch.empty_like(src)
+    with record() as calls:
+        tl_bw_copy(src, dst)
+    _, (ms,) = time_calls([calls], reps, 3)
+    assert torch.equal(src[:4096], dst[:4096]) and torch.equal(src[-4096:], dst[-4096:])
+    return rate(16 * n, ms)
+
+
+def cpu_baseline(f, budget_s):
+    """The serial oracle (forward chain + reverse-mode gradients) on one host
+    core, over consecutive 16^3-point slices of the benchmark's fields until
+    ``budget_s`` seconds have passed."""
+    import numpy as np
+    import oracle
+    n = f["g"].shape[1]
+    chunk = min(n, 4096)
+    done, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        lo = done % n
+        hi = min(n, lo + chunk)
+        ins = tuple(np.ascontiguousarray(f[k][:, lo:hi]) for k in KEYS)
+        oracle.dtg_chain(*ins)
+        oracle.dtg_chain_vjp(ins, np.ascontiguousarray(f["W"][:, lo:hi]))
+        done += hi - lo
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "grid points/s", "cores": 1, "kind": "oracle",
+            "sample": f"serial oracle (forward chain + tape VJP) on {done} points of the "
+                      f"benchmark fields, in 4096-point slices, {dt:.1f} s on one host core"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--edge", type=int, default=128, help="grid edge; N = edge^3 points")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-rows", action="store_true", help="time only the fwd+bwd step")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}): the hot path "
+              "is point-wise with no data exchanged between GPUs, so each GPU would run the same "
+              "kernels on its own share of the points; no multi-GPU figure is produced.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1804_10120_amd import (BatchPlan, tl_christoffel, tl_cov_deriv, tl_dtg,
+                                      tl_dtg_chain, tl_dtg_chain_bwd, tl_sym_inverse)
+    from paper_1804_10120_amd.ops import record
+    from paper_1804_10120_amd.synth import config_seed, domain_edges, make_fields
+
+    if not torch.cuda.is_available():
+        print("bench.py needs an AMD GPU", file=sys.stderr)
+        sys.exit(1)
+    device = torch.device("cuda:0")
+    torch.cuda.set_device(device)
+    n = args.edge ** 3
+    log(f"[bench] fields for {n} points")
+    (f, d), = device_sets(n, 1, device, config_seed(3))
+
+    # ---- the step: fused forward + adjoint
+    with record() as step:
+        d["dtg"] = tl_dtg_chain(*[d[k] for k in KEYS])
+        d["grads"] = tl_dtg_chain_bwd(d["g"], d["dg"], d["beta"], d["K"], d["alpha"], d["W"])
+    log(f"[bench] {args.steps} steps after {args.warmup} warm-up steps")
+    ms_step, (ms_fwd, ms_bwd) = time_calls([step], args.steps, args.warmup)
+    assert torch.isfinite(d["dtg"]).all() and torch.isfinite(d["grads"][0]).all()
+
+    res = {
+        "metric": METRIC,
+        "value": n / (ms_step * 1e-3),
+        "unit": "grid points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"fused d_t g_ij chain, forward + adjoint, N = {args.edge}^3 = "
+                               f"{n} grid points, FP64, seeded synthetic fields",
+                   "points": n, "step": ["tl_dtg_chain", "tl_dtg_chain_bwd"]},
+        "fwd": {"us": ms_fwd * 1e3, "points_per_s": n / (ms_fwd * 1e-3),
+                "GB_s": rate(BYTES["dtg_chain"] * n, ms_fwd)},
+        "bwd": {"us": ms_bwd * 1e3, "points_per_s": n / (ms_bwd * 1e-3),
+                "GB_s": rate(BYTES["dtg_chain_bwd"] * n, ms_bwd)},
+        "fwd_bwd_GB_s": rate((BYTES["dtg_chain"] + BYTES["dtg_chain_bwd"]) * n, ms_step),
+    }
+    dom, ms_dom = ("dtg_chain_bwd", ms_bwd) if ms_bwd >= ms_fwd else ("dtg_chain", ms_fwd)
+    achieved = rate(BYTES[dom] * n, ms_dom)
+    res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved,
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": traffic_record(dom, n),
+                       "algorithmic_bytes_per_launch": BYTES[dom] * n,
+                       "duration_us": ms_dom * 1e3}
+
+    log("[bench] copy ceiling")
+    cgbs = copy_ceiling(device)
+    res["copy_GB_s"] = cgbs
+    res["roofline"]["frac_of_copy"] = achieved / cgbs
+
+    if not args.no_rows:
+        rows = {}
+        log("[bench] unfused steps")
+        with record() as unf:
+            ginv = tl_sym_inverse(d["g"])
+            gam = tl_christoffel(ginv, d["dg"])
+            nb = tl_cov_deriv(gam, d["beta"], d["dbeta"])
+            tl_dtg(d["alpha"], d["K"], nb)
+        _, per = time_calls([unf], 20, 3)
+        for name, ms in zip(("sym_inverse", "christoffel", "cov_deriv", "dtg"), per):
+            rows[name] = {"us": ms * 1e3, "GB_s": rate(BYTES[name] * n, ms)}
+        rows["unfused_chain"] = {"us": sum(per) * 1e3, "points_per_s": n / (sum(per) * 1e-3),
+                                 "GB_s": rate(BYTES["unfused_chain"] * n, sum(per)),
+                                 "fused_fwd_speedup": sum(per) / ms_fwd}
+        del unf, ginv, gam, nb
+
+        log("[bench] 64^3 with 4 rotating buffer sets")
+        n64 = 64 ** 3
+        s64 = device_sets(n64, 4, device, config_seed(2))
+        lists = []
+        for _, e in s64:
+            with record() as c:
+                tl_dtg_chain(*[e[k] for k in KEYS])
+                tl_dtg_chain_bwd(e["g"], e["dg"], e["beta"], e["K"], e["alpha"], e["W"])
+            lists.append(c)
+        ms64, (f64, b64) = time_calls(lists, 100, 10)
+        rows["fwd_bwd_64cubed"] = {"points": n64, "us": ms64 * 1e3,
+                                   "points_per_s": n64 / (ms64 * 1e-3),
+                                   "fwd_us": f64 * 1e3,
+                                   "fwd_GB_s": rate(BYTES["dtg_chain"] * n64, f64),
+                                   "bwd_us": b64 * 1e3,
+                                   "bwd_GB_s": rate(BYTES["dtg_chain_bwd"] * n64, b64)}
+        del s64, lists
+
+        log("[bench] 256 subgrids")
+        edges = domain_edges(256, seed=config_seed(4))
+        doms = []
+        for i, e in enumerate(edges):
+            fe = make_fields(int(e) ** 3, seed=config_seed(4) * 1000 + i, fields=KEYS)
+            doms.append({k: torch.from_numpy(v).to(device) for k, v in fe.items()})
+        npts = sum(int(e) ** 3 for e in edges)
+        plan = BatchPlan(doms)
+        _, (ms_graph,) = time_calls([[plan.run]], 20, 3)
+        with record() as many:
+            for e in doms:
+                tl_dtg_chain(*[e[k] for k in KEYS])
+        ms_many, _ = time_calls([many], 10, 2)
+        rows["dtg_chain_batched"] = {
+            "subgrids": 256, "points": npts, "us": ms_graph * 1e3,
+            "points_per_s": npts / (ms_graph * 1e-3),
+            "GB_s": rate(BYTES["dtg_chain_batched"] * npts, ms_graph),
+            "separate_launches_us": ms_many * 1e3,
+            "separate_launches_points_per_s": npts / (ms_many * 1e-3)}
+        plan.close()
+        del doms, many
+        res["rows"] = rows
+        torch.cuda.empty_cache()
+
+    if not args.no_cpu:
+        log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
+        res["cpu_baseline"] = cpu_baseline(f, args.cpu_seconds)
+    else:
+        res["cpu_baseline"] = None
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

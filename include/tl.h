@@ -1,0 +1,193 @@
+/*
+ * tl.h -- C ABI of libtl.so: FP64 per-grid-point tensor expressions on AMD
+ * MI355X (gfx950), after Lewis & Pfeiffer, "Automatic generation of CUDA code
+ * performing tensor manipulations using C++ expression templates"
+ * (arXiv:1804.10120).
+ *
+ * Fields.  A tensor field with C independent components over n grid points is
+ * one FP64 device buffer laid out component-major: component c of point p is
+ * at ptr[c*ld + p], with ld >= n (the paper's one array per tensor component,
+ * Sec. 2.1-2.2, made contiguous: one base pointer plus a leading dimension
+ * instead of a table of per-component pointers).  Component orders:
+ *
+ *   symmetric pair (i,j), i <= j  ->  s(i,j): 00->0 01->1 02->2 11->3 12->4 22->5
+ *     (the order of the paper's symmetric tensor-index loops, Sec. 2.4)
+ *   g, ginv, K, dtg, w    6   s(i,j)
+ *   dg                   18   k*6 + s(i,j)   = d_k g_ij
+ *   gamma                18   i*6 + s(j,k)   = Gamma^i_jk  (symmetric in jk)
+ *   beta                  3   i              = beta_i
+ *   dbeta                 9   j*3 + i        = d_j beta_i
+ *   nabla_beta            9   j*3 + i        = nabla_j beta_i
+ *   alpha                 1   (ld is ignored)
+ *
+ * Ownership.  The caller owns every buffer; the plain entry points allocate
+ * nothing.  All pointers are device pointers (or host pointers of memory the
+ * device can access) of 8-byte aligned FP64 data.
+ *
+ * Execution.  Every compute call is asynchronous on `stream` (a hipStream_t;
+ * NULL = the null stream) and performs no host synchronisation; data stays on
+ * the device between calls.
+ *
+ * Errors.  Argument errors are detected before anything is launched and are
+ * returned synchronously: a NULL pointer while n > 0 (TL_ERR_NULL); n < 0 or
+ * ld < n (TL_ERR_SIZE); a pointer that is not 8-byte aligned (TL_ERR_ALIGN);
+ * an output whose address range overlaps an input's or another output's
+ * (TL_ERR_ALIAS); an invalid tuning or plan argument (TL_ERR_INVALID).  A
+ * launch failure reported by the HIP runtime returns TL_ERR_HIP.  For every
+ * error a message is available from tl_last_error() (per calling thread).
+ * n == 0 returns TL_OK without launching.  Numerical conditions are not
+ * reported: a singular metric propagates IEEE inf/NaN.  No C++ exception
+ * crosses this interface.  Stateless calls are thread-safe; a batch plan must
+ * not be used from two threads at once.
+ */
+#ifndef TL_H
+#define TL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TL_ABI_VERSION 1
+
+typedef enum {
+  TL_OK = 0,
+  TL_ERR_NULL = 1,
+  TL_ERR_SIZE = 2,
+  TL_ERR_ALIAS = 3,
+  TL_ERR_ALIGN = 4,
+  TL_ERR_HIP = 5,
+  TL_ERR_INVALID = 6
+} tl_status;
+
+/* Input field [ncomp][ld] and output field [ncomp][ld]. */
+typedef struct { const double* ptr; int64_t ld; } tl_cfield;
+typedef struct { double* ptr; int64_t ld; } tl_field;
+
+/* Launch tuning.  A NULL tl_tune* selects the measured default shape, which
+ * depends on the kernel and on n.  In a supplied tl_tune a zero block, ppt or
+ * grid_mult selects the default value of that member; flags are taken as
+ * given.
+ *   block      threads per block: 64, 128, 256, 512 or 1024
+ *   ppt        consecutive grid points per thread: 1 or 2 (2 uses 16-byte
+ *              loads and needs every field 16-byte aligned with an even ld;
+ *              otherwise the call silently uses 1)
+ *   flags      TL_TUNE_NT: non-temporal (streaming) loads and stores;
+ *              TL_TUNE_XCD: the blocks resident on one XCD (workgroups go to
+ *              the 8 XCDs round-robin) take consecutive tiles, so each XCD
+ *              streams through contiguous address ranges
+ *   grid_mult  0: one tile of block*ppt points per block; k > 0: a persistent
+ *              grid of k blocks per compute unit striding over the tiles   */
+typedef struct { int32_t block, ppt, flags, grid_mult; } tl_tune;
+#define TL_TUNE_NT 1
+#define TL_TUNE_XCD 2
+
+/* ---- Unfused steps ------------------------------------------------------ */
+
+/* Inverse metric g^ij of the symmetric 3x3 g_ij (the inverse entering the
+ * Christoffel definition, Sec. 1; the paper takes it as an input).
+ * g: 6 comps in; ginv: 6 comps out. */
+tl_status tl_sym_inverse(int64_t n, tl_cfield g, tl_field ginv, void* stream,
+                         const tl_tune* tune);
+
+/* Christoffel symbols Gamma^i_jk = 1/2 g^il (d_k g_jl + d_j g_lk - d_l g_jk)
+ * (Sec. 1, eq:SpatialChristoffel).  ginv: 6, dg: 18 in; gamma: 18 out. */
+tl_status tl_christoffel(int64_t n, tl_cfield ginv, tl_cfield dg, tl_field gamma, void* stream,
+                         const tl_tune* tune);
+
+/* Covariant derivative nabla_j beta_i = d_j beta_i - Gamma^k_ij beta_k (Sec. 1,
+ * footnote).  gamma: 18, beta: 3, dbeta: 9 in; nabla_beta: 9 out. */
+tl_status tl_cov_deriv(int64_t n, tl_cfield gamma, tl_cfield beta, tl_cfield dbeta,
+                       tl_field nabla_beta, void* stream, const tl_tune* tune);
+
+/* Metric evolution d_t g_ij = -2 alpha K_ij + nabla_i beta_j + nabla_j beta_i
+ * (Sec. 1, eq:dtg_ij).  alpha: 1, K: 6, nabla_beta: 9 in; dtg: 6 out. */
+tl_status tl_dtg(int64_t n, tl_cfield alpha, tl_cfield K, tl_cfield nabla_beta, tl_field dtg,
+                 void* stream, const tl_tune* tune);
+
+/* ---- Fused chain ---------------------------------------------------------- */
+
+/* d_t g_ij from g, d g, beta, d beta, K and alpha in one pass: the four steps
+ * above with g^ij and Gamma kept in registers (never written to memory),
+ * evaluated in the equivalent reduced form
+ *   b^l = g^lk beta_k,  F_lij = d_j g_il + d_i g_lj - d_l g_ij,
+ *   d_t g_ij = -2 alpha K_ij + d_i beta_j + d_j beta_i - b^l F_lij,
+ * which equals the definition because Gamma^k_ij beta_k = 1/2 b^l F_lij.
+ * Reads 43 and writes 6 doubles per point. */
+tl_status tl_dtg_chain(int64_t n, tl_cfield g, tl_cfield dg, tl_cfield beta, tl_cfield dbeta,
+                       tl_cfield K, tl_cfield alpha, tl_field dtg, void* stream,
+                       const tl_tune* tune);
+
+/* Adjoint of tl_dtg_chain: given w = dL/d(dtg) (6 comps), writes the gradient
+ * of L with respect to every stored input component (an off-diagonal stored
+ * slot of g, dg or K receives the sum of its (i,j) and (j,i) partials).
+ * g^ij and b^l are recomputed, not stored.  d beta is not an input: d_t g is
+ * linear in it, so its gradient depends on w only.  An output whose ptr is
+ * NULL is skipped (ld ignored); at least one output must be non-NULL.
+ * Reads 40 and writes up to 43 doubles per point. */
+tl_status tl_dtg_chain_bwd(int64_t n, tl_cfield g, tl_cfield dg, tl_cfield beta, tl_cfield K,
+                           tl_cfield alpha, tl_cfield w, tl_field g_bar, tl_field dg_bar,
+                           tl_field beta_bar, tl_field dbeta_bar, tl_field K_bar,
+                           tl_field alpha_bar, void* stream, const tl_tune* tune);
+
+/* ---- Many subgrids in one launch (multi-domain grids, Sec. 1) ------------- */
+
+/* One subgrid: n points and its seven fields (as for tl_dtg_chain). */
+typedef struct {
+  int64_t n;
+  tl_cfield g, dg, beta, dbeta, K, alpha;
+  tl_field dtg;
+} tl_domain;
+
+typedef struct tl_batch_plan tl_batch_plan;
+
+/* Builds a plan that evaluates tl_dtg_chain on every domain with one
+ * persistent kernel launch, captured once into a HIP graph.  The plan copies
+ * the domain table to device memory (the only allocation it makes) and
+ * borrows the domains' buffers, which must outlive it; if any pointer
+ * changes, destroy the plan and create a new one.  ndom >= 1; domains with
+ * n == 0 are allowed.  Validation is as for tl_dtg_chain, per domain, plus:
+ * no domain's output may overlap any domain's input or output. */
+tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tune* tune,
+                               tl_batch_plan** out);
+/* Replays the captured launch on `stream` (asynchronous). */
+tl_status tl_batch_plan_launch(tl_batch_plan* plan, void* stream);
+/* Launches the same kernel directly, without the graph (asynchronous). */
+tl_status tl_batch_plan_launch_direct(tl_batch_plan* plan, void* stream);
+/* Total points, tiles and grid size of a plan (any pointer may be NULL). */
+tl_status tl_batch_plan_info(const tl_batch_plan* plan, int64_t* points, int64_t* tiles,
+                             int64_t* blocks);
+/* Waits for the plan's work, then frees it; NULL is a no-op. */
+tl_status tl_batch_plan_destroy(tl_batch_plan* plan);
+
+/* ---- Bandwidth reference ---------------------------------------------------- */
+
+/* dst[i] = src[i] for i < n: a plain streaming copy, the library's analogue of
+ * a device bandwidth test (Sec. 4, measured bandwidth).  Non-overlapping. */
+tl_status tl_bw_copy(int64_t n, const double* src, double* dst, void* stream);
+
+/* ---- Introspection -------------------------------------------------------------- */
+
+typedef struct {
+  int32_t block, ppt, flags;   /* the instantiation the tuning resolves to */
+  int32_t num_regs;            /* registers per thread reported by the runtime */
+  int32_t local_bytes;         /* private (scratch) bytes per thread */
+  int32_t max_threads;         /* max threads per block for the kernel */
+} tl_kernel_attr;
+
+/* Attributes of the kernel that `kernel` ("sym_inverse", "christoffel",
+ * "cov_deriv", "dtg", "dtg_chain", "dtg_chain_bwd", "dtg_chain_batched") would
+ * run with `tune` (ppt assumes aligned fields). */
+tl_status tl_kernel_info(const char* kernel, const tl_tune* tune, tl_kernel_attr* out);
+
+const char* tl_status_string(tl_status s);
+/* Message of the last error on the calling thread ("" if none). */
+const char* tl_last_error(void);
+int tl_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TL_H */

@@ -1,0 +1,542 @@
+// C ABI of libtl.so: argument validation, tuning resolution, launches, batch
+// plans (device descriptor table + HIP graph) and error reporting.  The
+// argument checks are the library's counterpart of the paper's extent and
+// index checks on assignment (Sec. 2.4): every field must cover the n points
+// of the call, and an output may not overlap anything else.
+#include "../../include/tl.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tl_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tl_status fail(tl_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+tl_status hip_fail(hipError_t e, const char* what) {
+  return fail(TL_ERR_HIP, "%s: %s (%d)", what, hipGetErrorString(e), static_cast<int>(e));
+}
+
+// A field as validated: byte range [lo, hi) for overlap checks.
+struct Span {
+  const char* name;
+  uintptr_t lo, hi;
+  bool output;
+};
+
+struct Checker {
+  int64_t n;
+  std::vector<Span> spans;
+  bool vec_ok = true;  // every field 16-byte aligned with even ld (for ppt = 2)
+  tl_status st = TL_OK;
+
+  explicit Checker(int64_t n_) : n(n_) {}
+
+  void field(const char* name, const void* ptr, int64_t ld, int ncomp, bool output,
+             bool optional = false) {
+    if (st != TL_OK) return;
+    if (ptr == nullptr) {
+      if (optional) return;
+      st = fail(TL_ERR_NULL, "%s is NULL", name);
+      return;
+    }
+    if (ncomp == 1) ld = n;
+    if (ld < n) {
+      st = fail(TL_ERR_SIZE, "%s: ld=%lld < n=%lld", name, (long long)ld, (long long)n);
+      return;
+    }
+    if (ld > (INT64_MAX / 8 - n) / ncomp) {
+      st = fail(TL_ERR_SIZE, "%s: ld=%lld too large", name, (long long)ld);
+      return;
+    }
+    const uintptr_t a = reinterpret_cast<uintptr_t>(ptr);
+    if (a % 8 != 0) {
+      st = fail(TL_ERR_ALIGN, "%s is not 8-byte aligned", name);
+      return;
+    }
+    if (a % 16 != 0 || (ncomp > 1 && ld % 2 != 0)) vec_ok = false;
+    const uintptr_t bytes = static_cast<uintptr_t>((ncomp - 1) * ld + n) * 8u;
+    spans.push_back({name, a, a + bytes, output});
+  }
+
+  tl_status overlaps() {
+    if (st != TL_OK) return st;
+    for (size_t i = 0; i < spans.size(); ++i)
+      for (size_t j = i + 1; j < spans.size(); ++j) {
+        const Span &x = spans[i], &y = spans[j];
+        if (!x.output && !y.output) continue;
+        if (x.lo < y.hi && y.lo < x.hi)
+          return st = fail(TL_ERR_ALIAS, "%s overlaps %s", x.name, y.name);
+      }
+    return st;
+  }
+};
+
+int num_cus() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  static int cache[64] = {0};
+  if (dev >= 0 && dev < 64 && cache[dev] > 0) return cache[dev];
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
+    cu = 256;
+  if (dev >= 0 && dev < 64) cache[dev] = cu;
+  return cu;
+}
+
+// Default launch shapes, measured on MI355X with the library's autotuner.
+// Every kernel streams, so one rule serves all of them: non-temporal loads
+// and stores always; for large grids one point per lane in blocks of 256 with
+// XCD-contiguous tiles; below 2^20 points (where the whole grid is in flight
+// at once and the XCD order buys nothing) two points per lane in blocks of
+// 512.  The batched kernel uses the large-grid shape on a persistent grid.
+tl::Resolved defaults(tl::KernelId k, int64_t n) {
+  tl::Resolved r;
+  r.nt = true;
+  r.grid_mult = 0;
+  if (k == tl::KernelId::ChainBatched || n >= (int64_t(1) << 20)) {
+    r.block = 256;
+    r.ppt = 1;
+    r.xcd = true;
+  } else {
+    r.block = 512;
+    r.ppt = 2;
+    r.xcd = false;
+  }
+  return r;
+}
+
+tl_status resolve(tl::KernelId k, const tl_tune* t, bool vec_ok, int64_t n, tl::Resolved* out) {
+  tl::Resolved r = defaults(k, n);
+  if (t != nullptr) {
+    if (t->block != 0) {
+      if (t->block != 64 && t->block != 128 && t->block != 256 && t->block != 512 &&
+          t->block != 1024)
+        return fail(TL_ERR_INVALID, "tune.block=%d not in {64,128,256,512,1024}", t->block);
+      r.block = t->block;
+    }
+    if (t->ppt != 0) {
+      if (t->ppt != 1 && t->ppt != 2) return fail(TL_ERR_INVALID, "tune.ppt=%d not in {1,2}", t->ppt);
+      r.ppt = t->ppt;
+    }
+    if (t->flags & ~(TL_TUNE_NT | TL_TUNE_XCD))
+      return fail(TL_ERR_INVALID, "tune.flags=%d has unknown bits", t->flags);
+    r.nt = (t->flags & TL_TUNE_NT) != 0;
+    r.xcd = (t->flags & TL_TUNE_XCD) != 0;
+    if (t->grid_mult < 0 || t->grid_mult > 1024)
+      return fail(TL_ERR_INVALID, "tune.grid_mult=%d not in [0,1024]", t->grid_mult);
+    r.grid_mult = t->grid_mult;
+  }
+  if (!vec_ok) r.ppt = 1;
+  r.num_cu = num_cus();
+  *out = r;
+  return TL_OK;
+}
+
+tl_status run(tl::KernelId k, const Checker& c, const tl_tune* tune, const tl::KArgs& a,
+              void* stream) {
+  tl::Resolved r;
+  tl_status s = resolve(k, tune, c.vec_ok, c.n, &r);
+  if (s != TL_OK) return s;
+  hipError_t e = tl::launch_kernel(k, r, a, c.n, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return TL_OK;
+}
+
+tl::KArgs zero_args() {
+  tl::KArgs a;
+  std::memset(&a, 0, sizeof(a));
+  return a;
+}
+
+void set_in(tl::KArgs& a, int f, tl_cfield x) {
+  a.in[f] = x.ptr;
+  a.ldin[f] = x.ld;
+}
+void set_out(tl::KArgs& a, int f, tl_field x) {
+  a.out[f] = x.ptr;
+  a.ldout[f] = x.ld;
+}
+
+}  // namespace
+
+struct tl_batch_plan {
+  int device = 0;
+  tl::Resolved r;
+  int32_t ndom = 0;
+  int64_t points = 0, ntiles = 0, grid = 0;
+  tl::BatchDomain* d_doms = nullptr;
+  int64_t* d_start = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int tl_abi_version(void) { return TL_ABI_VERSION; }
+
+const char* tl_last_error(void) { return g_last_error.c_str(); }
+
+const char* tl_status_string(tl_status s) {
+  switch (s) {
+    case TL_OK: return "TL_OK";
+    case TL_ERR_NULL: return "TL_ERR_NULL";
+    case TL_ERR_SIZE: return "TL_ERR_SIZE";
+    case TL_ERR_ALIAS: return "TL_ERR_ALIAS";
+    case TL_ERR_ALIGN: return "TL_ERR_ALIGN";
+    case TL_ERR_HIP: return "TL_ERR_HIP";
+    case TL_ERR_INVALID: return "TL_ERR_INVALID";
+    default: return "TL_ERR_UNKNOWN";
+  }
+}
+
+tl_status tl_sym_inverse(int64_t n, tl_cfield g, tl_field ginv, void* stream, const tl_tune* tune) {
+  if (n < 0) return fail(TL_ERR_SIZE, "n=%lld < 0", (long long)n);
+  if (n == 0) return TL_OK;
+  Checker c(n);
+  c.field("g", g.ptr, g.ld, 6, false);
+  c.field("ginv", ginv.ptr, ginv.ld, 6, true);
+  if (c.overlaps() != TL_OK) return c.st;
+  tl::KArgs a = zero_args();
+  set_in(a, 0, g);
+  set_out(a, 0, ginv);
+  return run(tl::KernelId::SymInverse, c, tune, a, stream);
+}
+
+tl_status tl_christoffel(int64_t n, tl_cfield ginv, tl_cfield dg, tl_field gamma, void* stream,
+                         const tl_tune* tune) {
+  if (n < 0) return fail(TL_ERR_SIZE, "n=%lld < 0", (long long)n);
+  if (n == 0) return TL_OK;
+  Checker c(n);
+  c.field("ginv", ginv.ptr, ginv.ld, 6, false);
+  c.field("dg", dg.ptr, dg.ld, 18, false);
+  c.field("gamma", gamma.ptr, gamma.ld, 18, true);
+  if (c.overlaps() != TL_OK) return c.st;
+  tl::KArgs a = zero_args();
+  set_in(a, 0, ginv);
+  set_in(a, 1, dg);
+  set_out(a, 0, gamma);
+  return run(tl::KernelId::Christoffel, c, tune, a, stream);
+}
+
+tl_status tl_cov_deriv(int64_t n, tl_cfield gamma, tl_cfield beta, tl_cfield dbeta,
+                       tl_field nabla_beta, void* stream, const tl_tune* tune) {
+  if (n < 0) return fail(TL_ERR_SIZE, "n=%lld < 0", (long long)n);
+  if (n == 0) return TL_OK;
+  Checker c(n);
+  c.field("gamma", gamma.ptr, gamma.ld, 18, false);
+  c.field("beta", beta.ptr, beta.ld, 3, false);
+  c.field("dbeta", dbeta.ptr, dbeta.ld, 9, false);
+  c.field("nabla_beta", nabla_beta.ptr, nabla_beta.ld, 9, true);
+  if (c.overlaps() != TL_OK) return c.st;
+  tl::KArgs a = zero_args();
+  set_in(a, 0, gamma);
+  set_in(a, 1, beta);
+  set_in(a, 2, dbeta);
+  set_out(a, 0, nabla_beta);
+  return run(tl::KernelId::CovDeriv, c, tune, a, stream);
+}
+
+tl_status tl_dtg(int64_t n, tl_cfield alpha, tl_cfield K, tl_cfield nabla_beta, tl_field dtg,
+                 void* stream, const tl_tune* tune) {
+  if (n < 0) return fail(TL_ERR_SIZE, "n=%lld < 0", (long long)n);
+  if (n == 0) return TL_OK;
+  Checker c(n);
+  c.field("alpha", alpha.ptr, alpha.ld, 1, false);
+  c.field("K", K.ptr, K.ld, 6, false);
+  c.field("nabla_beta", nabla_beta.ptr, nabla_beta.ld, 9, false);
+  c.field("dtg", dtg.ptr, dtg.ld, 6, true);
+  if (c.overlaps() != TL_OK) return c.st;
+  tl::KArgs a = zero_args();
+  set_in(a, 0, alpha);
+  set_in(a, 1, K);
+  set_in(a, 2, nabla_beta);
+  set_out(a, 0, dtg);
+  return run(tl::KernelId::Dtg, c, tune, a, stream);
+}
+
+static void chain_fields(Checker& c, const char* prefix, tl_cfield g, tl_cfield dg, tl_cfield beta,
+                         tl_cfield dbeta, tl_cfield K, tl_cfield alpha, tl_field dtg) {
+  (void)prefix;
+  c.field("g", g.ptr, g.ld, 6, false);
+  c.field("dg", dg.ptr, dg.ld, 18, false);
+  c.field("beta", beta.ptr, beta.ld, 3, false);
+  c.field("dbeta", dbeta.ptr, dbeta.ld, 9, false);
+  c.field("K", K.ptr, K.ld, 6, false);
+  c.field("alpha", alpha.ptr, alpha.ld, 1, false);
+  c.field("dtg", dtg.ptr, dtg.ld, 6, true);
+}
+
+static tl::KArgs chain_args(tl_cfield g, tl_cfield dg, tl_cfield beta, tl_cfield dbeta, tl_cfield K,
+                            tl_cfield alpha, tl_field dtg) {
+  tl::KArgs a = zero_args();
+  set_in(a, 0, g);
+  set_in(a, 1, dg);
+  set_in(a, 2, beta);
+  set_in(a, 3, dbeta);
+  set_in(a, 4, K);
+  set_in(a, 5, alpha);
+  a.ldin[5] = 0;
+  set_out(a, 0, dtg);
+  return a;
+}
+
+tl_status tl_dtg_chain(int64_t n, tl_cfield g, tl_cfield dg, tl_cfield beta, tl_cfield dbeta,
+                       tl_cfield K, tl_cfield alpha, tl_field dtg, void* stream,
+                       const tl_tune* tune) {
+  if (n < 0) return fail(TL_ERR_SIZE, "n=%lld < 0", (long long)n);
+  if (n == 0) return TL_OK;
+  Checker c(n);
+  chain_fields(c, "", g, dg, beta, dbeta, K, alpha, dtg);
+  if (c.overlaps() != TL_OK) return c.st;
+  return run(tl::KernelId::Chain, c, tune, chain_args(g, dg, beta, dbeta, K, alpha, dtg), stream);
+}
+
+tl_status tl_dtg_chain_bwd(int64_t n, tl_cfield g, tl_cfield dg, tl_cfield beta, tl_cfield K,
+                           tl_cfield alpha, tl_cfield w, tl_field g_bar, tl_field dg_bar,
+                           tl_field beta_bar, tl_field dbeta_bar, tl_field K_bar,
+                           tl_field alpha_bar, void* stream, const tl_tune* tune) {
+  if (n < 0) return fail(TL_ERR_SIZE, "n=%lld < 0", (long long)n);
+  if (n == 0) return TL_OK;
+  if (!g_bar.ptr && !dg_bar.ptr && !beta_bar.ptr && !dbeta_bar.ptr && !K_bar.ptr && !alpha_bar.ptr)
+    return fail(TL_ERR_NULL, "every gradient output is NULL");
+  Checker c(n);
+  c.field("g", g.ptr, g.ld, 6, false);
+  c.field("dg", dg.ptr, dg.ld, 18, false);
+  c.field("beta", beta.ptr, beta.ld, 3, false);
+  c.field("K", K.ptr, K.ld, 6, false);
+  c.field("alpha", alpha.ptr, alpha.ld, 1, false);
+  c.field("w", w.ptr, w.ld, 6, false);
+  c.field("g_bar", g_bar.ptr, g_bar.ld, 6, true, true);
+  c.field("dg_bar", dg_bar.ptr, dg_bar.ld, 18, true, true);
+  c.field("beta_bar", beta_bar.ptr, beta_bar.ld, 3, true, true);
+  c.field("dbeta_bar", dbeta_bar.ptr, dbeta_bar.ld, 9, true, true);
+  c.field("K_bar", K_bar.ptr, K_bar.ld, 6, true, true);
+  c.field("alpha_bar", alpha_bar.ptr, alpha_bar.ld, 1, true, true);
+  if (c.overlaps() != TL_OK) return c.st;
+  tl::KArgs a = zero_args();
+  set_in(a, 0, g);
+  set_in(a, 1, dg);
+  set_in(a, 2, beta);
+  set_in(a, 3, K);
+  set_in(a, 4, alpha);
+  a.ldin[4] = 0;
+  set_in(a, 5, w);
+  set_out(a, 0, g_bar);
+  set_out(a, 1, dg_bar);
+  set_out(a, 2, beta_bar);
+  set_out(a, 3, dbeta_bar);
+  set_out(a, 4, K_bar);
+  set_out(a, 5, alpha_bar);
+  a.ldout[5] = 0;
+  return run(tl::KernelId::ChainBwd, c, tune, a, stream);
+}
+
+tl_status tl_bw_copy(int64_t n, const double* src, double* dst, void* stream) {
+  if (n < 0) return fail(TL_ERR_SIZE, "n=%lld < 0", (long long)n);
+  if (n == 0) return TL_OK;
+  Checker c(n);
+  c.field("src", src, n, 1, false);
+  c.field("dst", dst, n, 1, true);
+  if (c.overlaps() != TL_OK) return c.st;
+  int64_t grid = (n + 511) / 512;
+  if (grid > (1 << 20)) grid = 1 << 20;
+  hipError_t e = tl::launch_copy(src, dst, n, grid, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "copy launch");
+  return TL_OK;
+}
+
+// ---------------------------------------------------------------- batch plans
+
+tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tune* tune,
+                               tl_batch_plan** out) {
+  if (out == nullptr) return fail(TL_ERR_NULL, "out is NULL");
+  *out = nullptr;
+  if (doms == nullptr) return fail(TL_ERR_NULL, "doms is NULL");
+  if (ndom < 1) return fail(TL_ERR_SIZE, "ndom=%d < 1", ndom);
+
+  // Per-domain validation, then overlap of every output with every field of
+  // every domain.
+  std::vector<Span> all;
+  bool vec_ok = true;
+  int64_t points = 0;
+  for (int32_t d = 0; d < ndom; ++d) {
+    const tl_domain& x = doms[d];
+    if (x.n < 0) return fail(TL_ERR_SIZE, "domain %d: n=%lld < 0", d, (long long)x.n);
+    if (x.n == 0) continue;
+    Checker c(x.n);
+    chain_fields(c, "", x.g, x.dg, x.beta, x.dbeta, x.K, x.alpha, x.dtg);
+    if (c.overlaps() != TL_OK) return fail(c.st, "domain %d: %s", d, g_last_error.c_str());
+    vec_ok = vec_ok && c.vec_ok;
+    all.insert(all.end(), c.spans.begin(), c.spans.end());
+    points += x.n;
+  }
+  {
+    std::vector<size_t> outs;
+    for (size_t i = 0; i < all.size(); ++i)
+      if (all[i].output) outs.push_back(i);
+    for (size_t oi : outs)
+      for (size_t j = 0; j < all.size(); ++j) {
+        if (j == oi) continue;
+        if (all[oi].lo < all[j].hi && all[j].lo < all[oi].hi)
+          return fail(TL_ERR_ALIAS, "a domain's dtg overlaps another field of the batch");
+      }
+  }
+
+  tl::Resolved r;
+  tl_status s = resolve(tl::KernelId::ChainBatched, tune, vec_ok, points, &r);
+  if (s != TL_OK) return s;
+  if (tune == nullptr || tune->grid_mult == 0) r.grid_mult = 8;  // persistent by default
+
+  std::vector<tl::BatchDomain> h(ndom);
+  std::vector<int64_t> start(ndom + 1);
+  const int64_t per = static_cast<int64_t>(r.block) * r.ppt;
+  start[0] = 0;
+  for (int32_t d = 0; d < ndom; ++d) {
+    const tl_domain& x = doms[d];
+    std::memset(&h[d], 0, sizeof(tl::BatchDomain));
+    h[d].n = x.n;
+    if (x.n > 0) h[d].args = chain_args(x.g, x.dg, x.beta, x.dbeta, x.K, x.alpha, x.dtg);
+    start[d + 1] = start[d] + (x.n + per - 1) / per;
+  }
+
+  tl_batch_plan* p = new (std::nothrow) tl_batch_plan;
+  if (p == nullptr) return fail(TL_ERR_INVALID, "out of host memory");
+  p->r = r;
+  p->ndom = ndom;
+  p->points = points;
+  p->ntiles = start[ndom];
+  p->grid = tl::grid_size(r, p->ntiles);
+  hipError_t e = hipGetDevice(&p->device);
+  auto cleanup = [&](hipError_t err, const char* what) {
+    tl_status st = hip_fail(err, what);
+    tl_batch_plan_destroy(p);
+    return st;
+  };
+  if (e != hipSuccess) return cleanup(e, "hipGetDevice");
+  e = hipMalloc(reinterpret_cast<void**>(&p->d_doms), sizeof(tl::BatchDomain) * ndom);
+  if (e != hipSuccess) return cleanup(e, "hipMalloc(domains)");
+  e = hipMalloc(reinterpret_cast<void**>(&p->d_start), sizeof(int64_t) * (ndom + 1));
+  if (e != hipSuccess) return cleanup(e, "hipMalloc(tile starts)");
+  e = hipMemcpy(p->d_doms, h.data(), sizeof(tl::BatchDomain) * ndom, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return cleanup(e, "hipMemcpy(domains)");
+  e = hipMemcpy(p->d_start, start.data(), sizeof(int64_t) * (ndom + 1), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return cleanup(e, "hipMemcpy(tile starts)");
+  if (p->ntiles > 0) {
+    e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return cleanup(e, "hipStreamCreate");
+    e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return cleanup(e, "hipStreamBeginCapture");
+    hipError_t le = tl::launch_batched(p->r, p->d_doms, p->d_start, ndom, p->ntiles, p->grid, p->cap);
+    e = hipStreamEndCapture(p->cap, &p->graph);
+    if (le != hipSuccess) return cleanup(le, "captured launch");
+    if (e != hipSuccess) return cleanup(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return cleanup(e, "hipGraphInstantiate");
+  }
+  *out = p;
+  return TL_OK;
+}
+
+static tl_status plan_device_check(const tl_batch_plan* p) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail(TL_ERR_INVALID, "plan belongs to device %d, current device is %d", p->device, dev);
+  return TL_OK;
+}
+
+tl_status tl_batch_plan_launch(tl_batch_plan* p, void* stream) {
+  if (p == nullptr) return fail(TL_ERR_NULL, "plan is NULL");
+  if (plan_device_check(p) != TL_OK) return TL_ERR_INVALID;
+  if (p->ntiles == 0) return TL_OK;
+  hipError_t e = hipGraphLaunch(p->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return TL_OK;
+}
+
+tl_status tl_batch_plan_launch_direct(tl_batch_plan* p, void* stream) {
+  if (p == nullptr) return fail(TL_ERR_NULL, "plan is NULL");
+  if (plan_device_check(p) != TL_OK) return TL_ERR_INVALID;
+  if (p->ntiles == 0) return TL_OK;
+  hipError_t e = tl::launch_batched(p->r, p->d_doms, p->d_start, p->ndom, p->ntiles, p->grid,
+                                    static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "batched launch");
+  return TL_OK;
+}
+
+tl_status tl_batch_plan_info(const tl_batch_plan* p, int64_t* points, int64_t* tiles,
+                             int64_t* blocks) {
+  if (p == nullptr) return fail(TL_ERR_NULL, "plan is NULL");
+  if (points) *points = p->points;
+  if (tiles) *tiles = p->ntiles;
+  if (blocks) *blocks = p->grid;
+  return TL_OK;
+}
+
+tl_status tl_batch_plan_destroy(tl_batch_plan* p) {
+  if (p == nullptr) return TL_OK;
+  hipError_t first = hipSuccess;
+  auto keep = [&](hipError_t e) {
+    if (first == hipSuccess && e != hipSuccess) first = e;
+  };
+  if (p->d_doms || p->d_start || p->exec) keep(hipDeviceSynchronize());
+  if (p->exec) keep(hipGraphExecDestroy(p->exec));
+  if (p->graph) keep(hipGraphDestroy(p->graph));
+  if (p->cap) keep(hipStreamDestroy(p->cap));
+  if (p->d_doms) keep(hipFree(p->d_doms));
+  if (p->d_start) keep(hipFree(p->d_start));
+  delete p;
+  if (first != hipSuccess) return hip_fail(first, "plan destroy");
+  return TL_OK;
+}
+
+// ---------------------------------------------------------------- introspection
+
+tl_status tl_kernel_info(const char* kernel, const tl_tune* tune, tl_kernel_attr* out) {
+  if (kernel == nullptr || out == nullptr) return fail(TL_ERR_NULL, "kernel or out is NULL");
+  static const struct {
+    const char* name;
+    tl::KernelId id;
+  } names[] = {{"sym_inverse", tl::KernelId::SymInverse}, {"christoffel", tl::KernelId::Christoffel},
+               {"cov_deriv", tl::KernelId::CovDeriv},     {"dtg", tl::KernelId::Dtg},
+               {"dtg_chain", tl::KernelId::Chain},        {"dtg_chain_bwd", tl::KernelId::ChainBwd},
+               {"dtg_chain_batched", tl::KernelId::ChainBatched}};
+  const tl::KernelId* id = nullptr;
+  for (const auto& x : names)
+    if (std::strcmp(x.name, kernel) == 0) id = &x.id;
+  if (id == nullptr) return fail(TL_ERR_INVALID, "unknown kernel '%s'", kernel);
+  tl::Resolved r;
+  tl_status s = resolve(*id, tune, true, int64_t(1) << 24, &r);
+  if (s != TL_OK) return s;
+  const void* fn = tl::kernel_address(*id, r);
+  if (fn == nullptr) return fail(TL_ERR_INVALID, "no instantiation for this tuning");
+  hipFuncAttributes attr;
+  hipError_t e = hipFuncGetAttributes(&attr, fn);
+  if (e != hipSuccess) return hip_fail(e, "hipFuncGetAttributes");
+  out->block = r.block;
+  out->ppt = r.ppt;
+  out->flags = (r.nt ? TL_TUNE_NT : 0) | (r.xcd ? TL_TUNE_XCD : 0);
+  out->num_regs = attr.numRegs;
+  out->local_bytes = static_cast<int32_t>(attr.localSizeBytes);
+  out->max_threads = attr.maxThreadsPerBlock;
+  return TL_OK;
+}
+
+}  // extern "C"

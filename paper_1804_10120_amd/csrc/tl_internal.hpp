@@ -1,0 +1,58 @@
+// Internal interface between the C ABI (tl_abi.cpp) and the kernels
+// (tl_kernels.hip).  Not installed, not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tl {
+
+constexpr int kMaxFields = 8;
+
+// Base pointer and leading dimension of each input and output field, in the
+// field order of the kernel's per-point body.  A NULL output is skipped.
+struct KArgs {
+  const double* in[kMaxFields];
+  int64_t ldin[kMaxFields];
+  double* out[kMaxFields];
+  int64_t ldout[kMaxFields];
+};
+
+// One subgrid of a batch plan, as stored in device memory.
+struct alignas(64) BatchDomain {
+  KArgs args;
+  int64_t n;
+};
+
+enum class KernelId { SymInverse, Christoffel, CovDeriv, Dtg, Chain, ChainBwd, ChainBatched };
+
+// A tuning request resolved to one compiled instantiation.
+struct Resolved {
+  int block = 256;
+  int ppt = 1;
+  bool nt = false;
+  bool xcd = false;  // XCD-contiguous tile order (grid is then a multiple of 8)
+  int grid_mult = 0;
+  int num_cu = 256;
+};
+
+inline int64_t grid_size(const Resolved& r, int64_t ntiles) {
+  int64_t g = ntiles;
+  if (r.grid_mult > 0) {
+    const int64_t cap = static_cast<int64_t>(r.grid_mult) * r.num_cu;
+    if (g > cap) g = cap;
+  }
+  if (g > 0x7ffffff0) g = 0x7ffffff0;
+  if (g < 1) g = 1;
+  if (r.xcd) g = (g + 7) & ~static_cast<int64_t>(7);
+  return g;
+}
+
+hipError_t launch_kernel(KernelId k, const Resolved& r, const KArgs& a, int64_t n, hipStream_t s);
+const void* kernel_address(KernelId k, const Resolved& r);
+hipError_t launch_batched(const Resolved& r, const BatchDomain* doms, const int64_t* start,
+                          int32_t ndom, int64_t ntiles, int64_t grid, hipStream_t s);
+hipError_t launch_copy(const double* src, double* dst, int64_t n, int64_t grid, hipStream_t s);
+
+}  // namespace tl

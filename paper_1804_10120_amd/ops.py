@@ -1,0 +1,336 @@
+"""Python binding of the C ABI over torch device tensors.
+
+Each ``tl_*`` function has the name and argument order of the C entry point
+in ``include/tl.h``.  It only checks and marshals arguments -- dtype float64,
+one HIP device, shape [C, n] with unit stride along points (``alpha`` may be
+[n]) -- allocates missing outputs with ``torch.empty`` and calls the library on
+the current torch stream of the tensors' device.  Every step of the
+computation runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _abi
+from ._abi import CField, Domain, Field, KernelAttr, TLError, Tune, check, lib
+
+NCOMP = {"g": 6, "ginv": 6, "K": 6, "dtg": 6, "w": 6, "dg": 18, "gamma": 18, "beta": 3,
+         "dbeta": 9, "nabla_beta": 9, "alpha": 1}
+
+
+def _points(t, ncomp, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name}: expected torch.float64, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name}: expected a HIP device tensor, got device {t.device}")
+    if ncomp == 1 and t.dim() == 1:
+        n = t.shape[0]
+    elif t.dim() == 2 and t.shape[0] == ncomp:
+        n = t.shape[1]
+    else:
+        raise ValueError(f"{name}: expected shape [{ncomp}, n]" + (" or [n]" if ncomp == 1 else "")
+                         + f", got {tuple(t.shape)}")
+    if n > 1 and t.stride(-1) != 1:
+        raise ValueError(f"{name}: points must be contiguous (stride(-1) == 1)")
+    return n
+
+
+def _ld(t, ncomp):
+    if ncomp == 1 or t.dim() == 1:
+        return max(1, t.shape[-1])
+    return t.stride(0)
+
+
+def _cf(t, ncomp):
+    return CField(t.data_ptr(), _ld(t, ncomp))
+
+
+def _f(t, ncomp):
+    if t is None:
+        return Field(None, 0)
+    return Field(t.data_ptr(), _ld(t, ncomp))
+
+
+class _Call:
+    """Collects the tensors of one call: common n, common device."""
+
+    def __init__(self):
+        self.n = None
+        self.device = None
+        self.keep = []
+
+    def add(self, t, name, ncomp=None):
+        ncomp = NCOMP[name] if ncomp is None else ncomp
+        n = _points(t, ncomp, name)
+        self.keep.append(t)
+        if self.n is None:
+            self.n, self.device = n, t.device
+        else:
+            if n != self.n:
+                raise ValueError(f"{name}: {n} points, expected {self.n}")
+            if t.device != self.device:
+                raise ValueError(f"{name}: on {t.device}, expected {self.device}")
+        return t
+
+    def out(self, t, name, like, ncomp=None):
+        ncomp = NCOMP[name] if ncomp is None else ncomp
+        if t is None:
+            shape = (self.n,) if ncomp == 1 and like.dim() == 1 else (ncomp, self.n)
+            return torch.empty(shape, dtype=torch.float64, device=self.device)
+        return self.add(t, name, ncomp)
+
+
+def _stream(device, stream):
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def make_tune(tune):
+    """None (library default), a Tune, a dict with keys block, ppt, nt, xcd,
+    grid_mult (missing numbers mean the default; nt/xcd default to off), or a
+    tuple (block, ppt, flags, grid_mult) -> Tune pointer or None."""
+    if tune is None:
+        return None
+    if isinstance(tune, Tune):
+        t = tune
+    elif isinstance(tune, dict):
+        t = Tune(int(tune.get("block", 0)), int(tune.get("ppt", 0)),
+                 int(tune.get("flags", 0)) | (_abi.TL_TUNE_NT if tune.get("nt") else 0)
+                 | (_abi.TL_TUNE_XCD if tune.get("xcd") else 0),
+                 int(tune.get("grid_mult", 0)))
+    else:
+        t = Tune(*[int(v) for v in tune])
+    return ctypes.pointer(t)
+
+
+class Prepared:
+    """One fully marshalled C-ABI call: calling it re-enters the library with
+    the same arguments (validation included) and no Python-side checks.  It
+    holds references to the tensors it names."""
+
+    def __init__(self, fn, args, keep, device):
+        self.fn, self.args, self.keep, self.device = fn, args, keep, device
+
+    def __call__(self):
+        st = self.fn(*self.args)
+        if st:
+            check(st)
+
+
+_recorder = None
+
+
+class record:
+    """Context manager: tl_* calls made inside are marshalled into Prepared
+    objects (outputs are still allocated) instead of being launched.
+
+        with record() as calls:
+            tl_dtg_chain(...)
+        for c in calls: c()
+    """
+
+    def __enter__(self):
+        global _recorder
+        if _recorder is not None:
+            raise RuntimeError("record() does not nest")
+        _recorder = []
+        return _recorder
+
+    def __exit__(self, *exc):
+        global _recorder
+        _recorder = None
+        return False
+
+
+def _run(fn, c, *args, stream=None, tune=None):
+    with torch.cuda.device(c.device):
+        full = (c.n, *args, _stream(c.device, stream), make_tune(tune))
+        if _recorder is not None:
+            _recorder.append(Prepared(fn, full, c.keep, c.device))
+            return
+        check(fn(*full))
+
+
+def tl_sym_inverse(g, ginv=None, *, stream=None, tune=None):
+    """g^ij = inverse of the symmetric g_ij: [6,n] -> [6,n]."""
+    c = _Call()
+    c.add(g, "g")
+    ginv = c.out(ginv, "ginv", g)
+    _run(lib().tl_sym_inverse, c, _cf(g, 6), _f(ginv, 6), stream=stream, tune=tune)
+    return ginv
+
+
+def tl_christoffel(ginv, dg, gamma=None, *, stream=None, tune=None):
+    """Gamma^i_jk from g^ij [6,n] and d_k g_ij [18,n] -> [18,n]."""
+    c = _Call()
+    c.add(ginv, "ginv")
+    c.add(dg, "dg")
+    gamma = c.out(gamma, "gamma", dg)
+    _run(lib().tl_christoffel, c, _cf(ginv, 6), _cf(dg, 18), _f(gamma, 18), stream=stream,
+         tune=tune)
+    return gamma
+
+
+def tl_cov_deriv(gamma, beta, dbeta, nabla_beta=None, *, stream=None, tune=None):
+    """nabla_j beta_i from Gamma [18,n], beta_i [3,n], d_j beta_i [9,n] -> [9,n]."""
+    c = _Call()
+    c.add(gamma, "gamma")
+    c.add(beta, "beta")
+    c.add(dbeta, "dbeta")
+    nabla_beta = c.out(nabla_beta, "nabla_beta", dbeta)
+    _run(lib().tl_cov_deriv, c, _cf(gamma, 18), _cf(beta, 3), _cf(dbeta, 9), _f(nabla_beta, 9),
+         stream=stream, tune=tune)
+    return nabla_beta
+
+
+def tl_dtg(alpha, K, nabla_beta, dtg=None, *, stream=None, tune=None):
+    """d_t g_ij from alpha [n], K_ij [6,n], nabla_j beta_i [9,n] -> [6,n]."""
+    c = _Call()
+    c.add(alpha, "alpha")
+    c.add(K, "K")
+    c.add(nabla_beta, "nabla_beta")
+    dtg = c.out(dtg, "dtg", K)
+    _run(lib().tl_dtg, c, _cf(alpha, 1), _cf(K, 6), _cf(nabla_beta, 9), _f(dtg, 6),
+         stream=stream, tune=tune)
+    return dtg
+
+
+def tl_dtg_chain(g, dg, beta, dbeta, K, alpha, dtg=None, *, stream=None, tune=None):
+    """Fused d_t g_ij from g, d g, beta, d beta, K, alpha -> [6,n]."""
+    c = _Call()
+    for t, name in ((g, "g"), (dg, "dg"), (beta, "beta"), (dbeta, "dbeta"), (K, "K"),
+                    (alpha, "alpha")):
+        c.add(t, name)
+    dtg = c.out(dtg, "dtg", K)
+    _run(lib().tl_dtg_chain, c, _cf(g, 6), _cf(dg, 18), _cf(beta, 3), _cf(dbeta, 9), _cf(K, 6),
+         _cf(alpha, 1), _f(dtg, 6), stream=stream, tune=tune)
+    return dtg
+
+
+GRAD_NAMES = ("g", "dg", "beta", "dbeta", "K", "alpha")
+
+
+def tl_dtg_chain_bwd(g, dg, beta, K, alpha, w, g_bar=None, dg_bar=None, beta_bar=None,
+                     dbeta_bar=None, K_bar=None, alpha_bar=None, *, want=None, stream=None,
+                     tune=None):
+    """Adjoint of the fused chain for w = dL/d(d_t g) [6,n].
+
+    Returns the tuple (g_bar, dg_bar, beta_bar, dbeta_bar, K_bar, alpha_bar).
+    ``want`` is a 6-tuple of booleans in that order; an unwanted gradient is
+    neither computed into memory nor allocated and comes back as None.
+    """
+    c = _Call()
+    for t, name in ((g, "g"), (dg, "dg"), (beta, "beta"), (K, "K"), (alpha, "alpha"), (w, "w")):
+        c.add(t, name)
+    want = (True,) * 6 if want is None else tuple(bool(x) for x in want)
+    outs = [g_bar, dg_bar, beta_bar, dbeta_bar, K_bar, alpha_bar]
+    ncomp = (6, 18, 3, 9, 6, 1)
+    likes = (g, dg, beta, dg, K, alpha)
+    for i in range(6):
+        if outs[i] is not None or want[i]:
+            outs[i] = c.out(outs[i], GRAD_NAMES[i] + "_bar", likes[i], ncomp[i])
+    if all(o is None for o in outs):
+        raise ValueError("tl_dtg_chain_bwd: no gradient requested")
+    fields = [_f(o, nc) for o, nc in zip(outs, ncomp)]
+    _run(lib().tl_dtg_chain_bwd, c, _cf(g, 6), _cf(dg, 18), _cf(beta, 3), _cf(K, 6),
+         _cf(alpha, 1), _cf(w, 6), *fields, stream=stream, tune=tune)
+    return tuple(outs)
+
+
+def tl_bw_copy(src, dst=None, *, stream=None):
+    """dst = src for a contiguous float64 device tensor (bandwidth reference)."""
+    if src.dtype != torch.float64 or not src.is_contiguous() or src.device.type != "cuda":
+        raise ValueError("tl_bw_copy: src must be a contiguous float64 device tensor")
+    if dst is None:
+        dst = torch.empty_like(src)
+    if dst.shape != src.shape or not dst.is_contiguous() or dst.dtype != torch.float64:
+        raise ValueError("tl_bw_copy: dst must match src")
+    with torch.cuda.device(src.device):
+        args = (src.numel(), ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                _stream(src.device, stream))
+        if _recorder is not None:
+            _recorder.append(Prepared(lib().tl_bw_copy, args, [src, dst], src.device))
+        else:
+            check(lib().tl_bw_copy(*args))
+    return dst
+
+
+def tl_kernel_info(kernel, tune=None):
+    """Attributes (registers, scratch, ...) of the kernel a call would run."""
+    a = KernelAttr()
+    check(lib().tl_kernel_info(kernel.encode(), make_tune(tune), ctypes.byref(a)))
+    return {k: getattr(a, k) for k, _ in KernelAttr._fields_}
+
+
+class BatchPlan:
+    """tl_batch_plan_*: d_t g over many subgrids in one graph-captured launch.
+
+    ``domains`` is a sequence of dicts with the tensors g, dg, beta, dbeta, K,
+    alpha and (optionally) dtg of one subgrid each; missing outputs are
+    allocated.  The plan keeps references to every tensor, so the buffers it
+    borrows outlive it.
+    """
+
+    def __init__(self, domains, tune=None):
+        self._plan = None
+        self.domains = []
+        arr = (Domain * len(domains))()
+        device = None
+        for i, d in enumerate(domains):
+            c = _Call()
+            for name in ("g", "dg", "beta", "dbeta", "K", "alpha"):
+                c.add(d[name], name)
+            if device is None:
+                device = c.device
+            elif c.device != device:
+                raise ValueError("all subgrids must be on one device")
+            out = c.out(d.get("dtg"), "dtg", d["K"])
+            dom = dict(d, dtg=out)
+            self.domains.append(dom)
+            arr[i] = Domain(c.n, _cf(d["g"], 6), _cf(d["dg"], 18), _cf(d["beta"], 3),
+                            _cf(d["dbeta"], 9), _cf(d["K"], 6), _cf(d["alpha"], 1), _f(out, 6))
+        if device is None:
+            raise ValueError("BatchPlan needs at least one subgrid")
+        self.device = device
+        plan = ctypes.c_void_p()
+        with torch.cuda.device(device):
+            check(lib().tl_batch_plan_create(arr, len(domains), make_tune(tune), ctypes.byref(plan)))
+        self._plan = plan
+        p, t, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(lib().tl_batch_plan_info(plan, ctypes.byref(p), ctypes.byref(t), ctypes.byref(b)))
+        self.points, self.tiles, self.blocks = p.value, t.value, b.value
+
+    @property
+    def outputs(self):
+        return [d["dtg"] for d in self.domains]
+
+    def run(self, stream=None):
+        """Replay the captured graph on ``stream`` (default: current stream)."""
+        with torch.cuda.device(self.device):
+            check(lib().tl_batch_plan_launch(self._plan, _stream(self.device, stream)))
+
+    def run_direct(self, stream=None):
+        """Launch the persistent kernel directly (no graph)."""
+        with torch.cuda.device(self.device):
+            check(lib().tl_batch_plan_launch_direct(self._plan, _stream(self.device, stream)))
+
+    def close(self):
+        if self._plan is not None:
+            with torch.cuda.device(self.device):
+                check(lib().tl_batch_plan_destroy(self._plan))
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = ["record", "Prepared", "tl_sym_inverse", "tl_christoffel", "tl_cov_deriv", "tl_dtg", "tl_dtg_chain",
+           "tl_dtg_chain_bwd", "tl_bw_copy", "tl_kernel_info", "BatchPlan", "TLError"]

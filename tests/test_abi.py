@@ -1,0 +1,194 @@
+"""The C-ABI library without a GPU: it loads, exports every function that
+include/tl.h declares, and rejects bad arguments before touching the device.
+
+Fake (never dereferenced) host addresses are used: every call here returns an
+argument error before any HIP runtime call or launch.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1804_10120_amd import _abi
+from paper_1804_10120_amd._abi import CField, Domain, Field, Tune
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tl.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tl_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_1804_10120_amd import build
+        build.build()
+    return _abi.lib()
+
+
+def test_header_declares_the_hot_path():
+    names = declared()
+    for n in ("tl_sym_inverse", "tl_christoffel", "tl_cov_deriv", "tl_dtg", "tl_dtg_chain",
+              "tl_dtg_chain_bwd", "tl_batch_plan_create", "tl_batch_plan_launch",
+              "tl_batch_plan_destroy"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    missing = [n for n in declared() if not hasattr(L, n)]
+    assert missing == []
+    assert set(declared()) <= set(_abi.SIGNATURES)
+
+
+def test_version_and_strings(L):
+    assert L.tl_abi_version() == _abi.ABI_VERSION
+    for s, name in enumerate(["TL_OK", "TL_ERR_NULL", "TL_ERR_SIZE", "TL_ERR_ALIAS",
+                              "TL_ERR_ALIGN", "TL_ERR_HIP", "TL_ERR_INVALID"]):
+        assert L.tl_status_string(s).decode() == name
+
+
+BASE = 1 << 40          # fake, 256-byte aligned, never dereferenced
+MB = 1 << 20
+
+
+def cf(addr, ld):
+    return CField(addr, ld)
+
+
+def f(addr, ld):
+    return Field(addr, ld)
+
+
+def chain_args(n, ld=None, out_addr=None, alpha_addr=None):
+    ld = n if ld is None else ld
+    a = [cf(BASE + i * 64 * MB, ld) for i in range(6)]
+    if alpha_addr is not None:
+        a[5] = cf(alpha_addr, ld)
+    out = f(BASE + 6 * 64 * MB if out_addr is None else out_addr, ld)
+    return a, out
+
+
+def call_chain(L, n, a, out, tune=None):
+    return L.tl_dtg_chain(n, *a, out, None, tune)
+
+
+def test_zero_points_is_a_noop(L):
+    a, out = chain_args(0)
+    assert call_chain(L, 0, [cf(None, 0)] * 6, f(None, 0)) == _abi.TL_OK
+
+
+def test_negative_n(L):
+    a, out = chain_args(16)
+    assert call_chain(L, -1, a, out) == _abi.TL_ERR_SIZE
+    assert b"n=-1" in L.tl_last_error()
+
+
+def test_null_pointer(L):
+    a, out = chain_args(16)
+    a[2] = cf(None, 16)
+    assert call_chain(L, 16, a, out) == _abi.TL_ERR_NULL
+    assert b"beta" in L.tl_last_error()
+    a, out = chain_args(16)
+    assert call_chain(L, 16, a, f(None, 16)) == _abi.TL_ERR_NULL
+
+
+def test_ld_smaller_than_n(L):
+    a, out = chain_args(100)
+    a[1] = cf(a[1].ptr, 99)
+    assert call_chain(L, 100, a, out) == _abi.TL_ERR_SIZE
+    assert b"dg" in L.tl_last_error()
+
+
+def test_misaligned(L):
+    a, out = chain_args(16)
+    a[0] = cf(BASE + 4, 16)
+    assert call_chain(L, 16, a, out) == _abi.TL_ERR_ALIGN
+
+
+def test_output_overlapping_input(L):
+    n = 1000
+    a, _ = chain_args(n)
+    # dtg starts inside the last component of dg
+    out = f(a[1].ptr + (17 * n + 10) * 8, n)
+    assert call_chain(L, n, a, out) == _abi.TL_ERR_ALIAS
+    # touching but not overlapping is fine up to validation (would launch): check the
+    # boundary on the unfused inverse, whose only other check is the tuning
+    g = cf(BASE, n)
+    ginv = f(BASE + (5 * n + n - 1) * 8, n)        # starts on g's last element
+    assert L.tl_sym_inverse(n, g, ginv, None, None) == _abi.TL_ERR_ALIAS
+
+
+def test_inputs_may_alias_each_other(L):
+    # identical input pointers are allowed; with an invalid tuning the call stops
+    # after validation, before any device work
+    n = 64
+    a = [cf(BASE, n)] * 6
+    out = f(BASE + 64 * MB, n)
+    bad = ctypes.pointer(Tune(96, 0, 0, 0))
+    assert call_chain(L, n, a, out, bad) == _abi.TL_ERR_INVALID
+
+
+@pytest.mark.parametrize("tune", [(96, 0, 0, 0), (256, 3, 0, 0), (256, 1, 4, 0), (256, 1, 0, -1)])
+def test_invalid_tuning(L, tune):
+    a, out = chain_args(64)
+    assert call_chain(L, 64, a, out, ctypes.pointer(Tune(*tune))) == _abi.TL_ERR_INVALID
+
+
+def test_bwd_needs_an_output(L):
+    n = 32
+    ins = [cf(BASE + i * MB, n) for i in range(6)]
+    outs = [f(None, 0)] * 6
+    assert L.tl_dtg_chain_bwd(n, *ins, *outs, None, None) == _abi.TL_ERR_NULL
+
+
+def test_bwd_outputs_may_not_overlap(L):
+    n = 32
+    ins = [cf(BASE + i * MB, n) for i in range(6)]
+    outs = [f(BASE + 10 * MB, n), f(BASE + 10 * MB + 8 * 40, n)] + [f(None, 0)] * 4
+    assert L.tl_dtg_chain_bwd(n, *ins, *outs, None, None) == _abi.TL_ERR_ALIAS
+
+
+def test_unfused_validation(L):
+    n = 10
+    assert L.tl_christoffel(n, cf(BASE, n), cf(None, n), f(BASE + MB, n), None, None) == _abi.TL_ERR_NULL
+    assert L.tl_cov_deriv(n, cf(BASE, n), cf(BASE + MB, n), cf(BASE + 2 * MB, 9),
+                          f(BASE + 3 * MB, n), None, None) == _abi.TL_ERR_SIZE
+    assert L.tl_dtg(n, cf(BASE, 0), cf(BASE + MB, n), cf(BASE + 2 * MB, n),
+                    f(BASE + 8 * 3, n), None, None) == _abi.TL_ERR_ALIAS
+
+
+def test_batch_plan_validation(L):
+    plan = ctypes.c_void_p()
+    assert L.tl_batch_plan_create(None, 1, None, ctypes.byref(plan)) == _abi.TL_ERR_NULL
+    doms = (Domain * 2)()
+    assert L.tl_batch_plan_create(doms, 0, None, ctypes.byref(plan)) == _abi.TL_ERR_SIZE
+    n = 100
+    for d in range(2):
+        a, out = chain_args(n)
+        base = d * 512 * MB
+        doms[d] = Domain(n, *[cf(x.ptr + base, n) for x in a], f(out.ptr + base, n))
+    doms[1].dtg = Field(doms[0].g.ptr, n)         # second domain writes the first one's g
+    assert L.tl_batch_plan_create(doms, 2, None, ctypes.byref(plan)) == _abi.TL_ERR_ALIAS
+    assert not plan.value
+    doms[1].n = -5
+    assert L.tl_batch_plan_create(doms, 2, None, ctypes.byref(plan)) == _abi.TL_ERR_SIZE
+    assert L.tl_batch_plan_destroy(None) == _abi.TL_OK
+
+
+def test_kernel_info_unknown(L):
+    a = _abi.KernelAttr()
+    assert L.tl_kernel_info(b"nope", None, ctypes.byref(a)) == _abi.TL_ERR_INVALID
+
+
+def test_python_binding_rejects_host_tensors():
+    import torch
+    from paper_1804_10120_amd import tl_sym_inverse
+    with pytest.raises(ValueError, match="HIP device"):
+        tl_sym_inverse(torch.zeros(6, 4, dtype=torch.float64))
+    with pytest.raises(TypeError, match="float64"):
+        tl_sym_inverse(torch.zeros(6, 4, dtype=torch.float32))

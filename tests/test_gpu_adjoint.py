@@ -1,0 +1,145 @@
+"""The adjoint kernel and the autograd wrapper against the oracle's
+reverse-mode gradients, closed forms and central finite differences."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import DevField, assert_close, dev, need_gpu
+from paper_1804_10120_amd import dtg_chain, tl_dtg_chain, tl_dtg_chain_bwd
+from paper_1804_10120_amd.synth import config_seed, make_fields
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("g", "dg", "beta", "dbeta", "K", "alpha")
+TUNES = [None, dict(block=64, ppt=1), dict(block=128, ppt=2), dict(block=256, ppt=2, nt=True),
+         dict(block=512, ppt=1, grid_mult=1), dict(block=256, ppt=1, nt=True, xcd=True),
+         dict(block=64, ppt=2, nt=True, xcd=True, grid_mult=1)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _vjp_ref(f):
+    return oracle.dtg_chain_vjp(tuple(f[k] for k in KEYS), f["W"])
+
+
+def _bwd(f, tune=None, want=None, **kw):
+    return tl_dtg_chain_bwd(dev(f["g"]), dev(f["dg"]), dev(f["beta"]), dev(f["K"]),
+                            dev(f["alpha"]), dev(f["W"]), want=want, tune=tune, **kw)
+
+
+def _tid(t):
+    return "default" if t is None else "-".join(f"{k}{v}" for k, v in t.items())
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 65, 512, 4097, 10007, 40000])
+@pytest.mark.parametrize("tune", TUNES, ids=_tid)
+def test_bwd_vs_oracle_vjp(n, tune):
+    f = make_fields(n, seed=100 + n)
+    ref = _vjp_ref(f)
+    got = _bwd(f, tune)
+    for k, x in zip(KEYS, got):
+        assert_close(x, ref[k], what=f"{k}_bar")
+
+
+def test_bwd_closed_forms_exact():
+    n = 1000
+    f = make_fields(n, seed=7)
+    gb, dgb, bb, dbb, Kb, ab = _bwd(f)
+    assert np.array_equal(Kb.cpu().numpy(), -2.0 * f["alpha"] * f["W"])
+    S = np.array([[0, 1, 2], [1, 3, 4], [2, 4, 5]])
+    exp = np.stack([f["W"][S[i, j]] * (2.0 if i == j else 1.0) for j in range(3) for i in range(3)])
+    assert np.array_equal(dbb.cpu().numpy(), exp)
+
+
+def test_bwd_full_size():
+    """Adjoint at 64^3 points in the benchmark's launch shape."""
+    n = 64 ** 3
+    f = make_fields(n, seed=config_seed(5))
+    ref = _vjp_ref(f)
+    got = _bwd(f)
+    for k, x in zip(KEYS, got):
+        assert_close(x, ref[k], what=f"{k}_bar 64^3")
+
+
+@pytest.mark.parametrize("want", [(1, 0, 0, 0, 0, 0), (0, 1, 0, 0, 0, 0), (0, 0, 1, 0, 1, 0),
+                                  (0, 0, 0, 1, 0, 1), (1, 1, 1, 1, 1, 1)])
+def test_bwd_output_subsets(want):
+    n = 999
+    f = make_fields(n, seed=13)
+    ref = _vjp_ref(f)
+    got = _bwd(f, want=want)
+    for k, w, x in zip(KEYS, want, got):
+        if w:
+            assert_close(x, ref[k], what=f"{k}_bar subset")
+        else:
+            assert x is None
+
+
+def test_bwd_guard_bands_and_padding():
+    n = 1553
+    f = make_fields(n, seed=17)
+    ref = _vjp_ref(f)
+    outs = [DevField.empty(c, n, pad=3, offset=1) for c in (6, 18, 3, 9, 6, 1)]
+    tl_dtg_chain_bwd(dev(f["g"]), dev(f["dg"]), dev(f["beta"]), dev(f["K"]), dev(f["alpha"]),
+                     dev(f["W"]), *[o.view for o in outs])
+    torch.cuda.synchronize()
+    for k, o in zip(KEYS, outs):
+        assert_close(o.view, ref[k], what=f"{k}_bar padded")
+        assert o.canaries_intact()
+
+
+def _leafs(f, requires=KEYS):
+    return {k: dev(f[k]).requires_grad_(k in requires) for k in KEYS}
+
+
+def test_autograd_matches_oracle():
+    n = 4097
+    f = make_fields(n, seed=19)
+    t = _leafs(f)
+    out = dtg_chain(*[t[k] for k in KEYS])
+    out.backward(dev(f["W"]))
+    ref = _vjp_ref(f)
+    for k in KEYS:
+        assert_close(t[k].grad, ref[k], what=f"autograd {k}")
+
+
+def test_autograd_subset_and_alpha_1d():
+    n = 300
+    f = make_fields(n, seed=23)
+    t = _leafs(f, requires=("K", "alpha"))
+    t["alpha"] = torch.from_numpy(f["alpha"][0].copy()).cuda().requires_grad_(True)
+    out = dtg_chain(*[t[k] for k in KEYS])
+    (out * dev(f["W"])).sum().backward()
+    ref = _vjp_ref(f)
+    assert_close(t["K"].grad, ref["K"], what="K grad")
+    assert t["alpha"].grad.shape == (n,)
+    assert_close(t["alpha"].grad[None], ref["alpha"], what="alpha grad")
+    assert t["g"].grad is None
+
+
+def test_finite_differences_8cubed():
+    """Central differences (h = 1e-6) of L_p = sum_s W_s d_t g_s(p) computed with
+    the GPU forward, one component perturbed at all points at once."""
+    n = 8 ** 3
+    h = 1e-6
+    f = make_fields(n, seed=config_seed(5))
+    W = f["W"]
+    got = dict(zip(KEYS, _bwd(f)))
+
+    def loss(ff):
+        out = tl_dtg_chain(*[dev(ff[k]) for k in KEYS]).cpu().numpy()
+        return (W * out).sum(0)
+
+    for k in KEYS:
+        fd = np.empty_like(f[k])
+        for c in range(f[k].shape[0]):
+            fp = {kk: v.copy() for kk, v in f.items()}
+            fm = {kk: v.copy() for kk, v in f.items()}
+            fp[k][c] += h
+            fm[k][c] -= h
+            fd[c] = (loss(fp) - loss(fm)) / (2 * h)
+        assert_close(got[k], fd, tol=1e-6, what=f"FD {k}")

@@ -1,0 +1,106 @@
+"""Many subgrids in one graph-captured persistent launch: every subgrid equals
+the plain fused kernel on that subgrid and the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_close, dev, need_gpu
+from paper_1804_10120_amd import BatchPlan, tl_dtg_chain
+from paper_1804_10120_amd.synth import config_seed, domain_edges, make_fields
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("g", "dg", "beta", "dbeta", "K", "alpha")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _domains(sizes, seed=0):
+    hosts, devs = [], []
+    for d, n in enumerate(sizes):
+        f = make_fields(int(n), seed=seed * 1000 + d)
+        hosts.append(f)
+        devs.append({k: dev(f[k]) for k in KEYS})
+    return hosts, devs
+
+
+def _check(plan, hosts, devs, tune=None):
+    for f, d, out in zip(hosts, devs, plan.outputs):
+        ref = oracle.dtg_chain(*[f[k] for k in KEYS])
+        assert_close(out, ref, what=f"domain n={out.shape[1]}")
+        plain = tl_dtg_chain(*[d[k] for k in KEYS], tune=tune)
+        if not torch.equal(plain, out):     # same per-point body: expected bitwise
+            assert_close(out, plain.cpu().numpy(), what="batched vs plain kernel")
+
+
+@pytest.mark.parametrize("tune", [None, dict(block=64, ppt=1, grid_mult=1),
+                                  dict(block=256, ppt=2, nt=True, grid_mult=2),
+                                  dict(block=128, ppt=1, grid_mult=0),
+                                  dict(block=64, ppt=1, nt=True, xcd=True, grid_mult=1)],
+                         ids=["default", "b64", "b256ppt2nt", "b128grid", "b64xcd"])
+def test_small_batch(tune):
+    sizes = [1, 0, 63, 64, 65, 512, 1000, 4097, 0, 27, 8 ** 3, 12 ** 3, 3]
+    hosts, devs = _domains(sizes, seed=1)
+    plan = BatchPlan(devs, tune=tune)
+    assert plan.points == sum(sizes)
+    plan.run()
+    torch.cuda.synchronize()
+    _check(plan, hosts, devs, tune)
+    plan.close()
+
+
+def test_replay_and_direct_are_idempotent():
+    sizes = [100, 2000, 30000, 7]
+    hosts, devs = _domains(sizes, seed=2)
+    plan = BatchPlan(devs)
+    plan.run()
+    torch.cuda.synchronize()
+    first = [o.clone() for o in plan.outputs]
+    for o in plan.outputs:
+        o.fill_(0.0)
+    for _ in range(3):
+        plan.run()
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(first, plan.outputs))
+    for o in plan.outputs:
+        o.fill_(0.0)
+    plan.run_direct()
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(first, plan.outputs))
+    _check(plan, hosts, devs)
+
+
+def test_new_plan_after_pointer_change():
+    sizes = [500, 700]
+    hosts, devs = _domains(sizes, seed=3)
+    plan = BatchPlan(devs)
+    plan.run()
+    hosts2, devs2 = _domains(sizes, seed=4)
+    plan.close()
+    plan2 = BatchPlan(devs2)
+    plan2.run()
+    torch.cuda.synchronize()
+    _check(plan2, hosts2, devs2)
+
+
+def test_full_multidomain_workload():
+    """256 subgrids with edges uniform on 8..48 (the benchmark's batch)."""
+    edges = domain_edges(256, seed=config_seed(4))
+    sizes = [int(e) ** 3 for e in edges]
+    hosts, devs = _domains(sizes, seed=config_seed(4))
+    plan = BatchPlan(devs)
+    plan.run()
+    torch.cuda.synchronize()
+    idx = np.random.default_rng(0).choice(256, 24, replace=False)
+    for d in idx:                      # oracle on a sample of whole subgrids
+        ref = oracle.dtg_chain(*[hosts[d][k] for k in KEYS])
+        assert_close(plan.outputs[d], ref, what=f"subgrid {d}")
+    for d in range(256):               # every subgrid against the plain kernel
+        plain = tl_dtg_chain(*[devs[d][k] for k in KEYS])
+        if not torch.equal(plain, plan.outputs[d]):
+            assert_close(plan.outputs[d], plain.cpu().numpy(), what=f"subgrid {d} vs plain")
+    plan.close()

@@ -1,0 +1,181 @@
+"""GPU kernels against the CPU oracle, element by element (FP64, per-component
+relative error <= 1e-12), across launch shapes, ragged sizes, padded and
+misaligned layouts, and at the full workload sizes."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import TOL, DevField, assert_close, dev, need_gpu
+from paper_1804_10120_amd import (tl_christoffel, tl_cov_deriv, tl_dtg, tl_dtg_chain,
+                                  tl_kernel_info, tl_sym_inverse)
+from paper_1804_10120_amd.synth import config_seed, make_fields
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 63, 64, 65, 127, 129, 512, 1553, 4096, 4097, 10007]
+TUNES = [None, dict(block=64, ppt=1), dict(block=128, ppt=2), dict(block=256, ppt=2, nt=True),
+         dict(block=512, ppt=1, nt=True), dict(block=1024, ppt=1), dict(block=256, ppt=1, grid_mult=1),
+         dict(block=256, ppt=1, nt=True, xcd=True), dict(block=64, ppt=2, xcd=True, grid_mult=1)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _fields(n, seed=1):
+    return make_fields(n, seed=seed + n)
+
+
+def _tid(t):
+    return "default" if t is None else "-".join(f"{k}{v}" for k, v in t.items())
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("tune", TUNES, ids=_tid)
+def test_sym_inverse(n, tune):
+    f = _fields(n)
+    out = tl_sym_inverse(dev(f["g"]), tune=tune)
+    assert_close(out, oracle.sym_inverse(f["g"]), what="ginv")
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("tune", TUNES, ids=_tid)
+def test_christoffel(n, tune):
+    f = _fields(n)
+    ginv = oracle.sym_inverse(f["g"])
+    out = tl_christoffel(dev(ginv), dev(f["dg"]), tune=tune)
+    assert_close(out, oracle.christoffel(ginv, f["dg"]), what="gamma")
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("tune", TUNES, ids=_tid)
+def test_cov_deriv(n, tune):
+    f = _fields(n)
+    gam = oracle.christoffel(oracle.sym_inverse(f["g"]), f["dg"])
+    out = tl_cov_deriv(dev(gam), dev(f["beta"]), dev(f["dbeta"]), tune=tune)
+    assert_close(out, oracle.cov_deriv(gam, f["beta"], f["dbeta"]), what="nabla beta")
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("tune", TUNES, ids=_tid)
+def test_dtg(n, tune):
+    f = _fields(n)
+    nb = oracle.cov_deriv(oracle.christoffel(oracle.sym_inverse(f["g"]), f["dg"]),
+                          f["beta"], f["dbeta"])
+    out = tl_dtg(dev(f["alpha"][0]), dev(f["K"]), dev(nb), tune=tune)
+    assert_close(out, oracle.dtg(f["alpha"], f["K"], nb), what="dtg")
+
+
+def _chain_dev(f, **kw):
+    return [DevField(f[k], **kw) for k in ("g", "dg", "beta", "dbeta", "K", "alpha")]
+
+
+def _oracle_chain(f):
+    return oracle.dtg_chain(f["g"], f["dg"], f["beta"], f["dbeta"], f["K"], f["alpha"])
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("tune", TUNES, ids=_tid)
+def test_chain(n, tune):
+    f = _fields(n)
+    ins = _chain_dev(f)
+    out = tl_dtg_chain(*[x.view for x in ins], tune=tune)
+    assert_close(out, _oracle_chain(f), what="fused chain")
+
+
+@pytest.mark.parametrize("n", [1, 65, 4097, 10007])
+def test_unfused_chain_matches_oracle_and_fused(n):
+    f = _fields(n, seed=3)
+    d = {k: dev(v) for k, v in f.items()}
+    ginv = tl_sym_inverse(d["g"])
+    gam = tl_christoffel(ginv, d["dg"])
+    nb = tl_cov_deriv(gam, d["beta"], d["dbeta"])
+    unfused = tl_dtg(d["alpha"], d["K"], nb)
+    fused = tl_dtg_chain(d["g"], d["dg"], d["beta"], d["dbeta"], d["K"], d["alpha"])
+    ref = _oracle_chain(f)
+    assert_close(unfused, ref, what="unfused chain")
+    assert_close(fused, unfused.cpu().numpy(), what="fused vs unfused")
+
+
+@pytest.mark.parametrize("pad,offset", [(0, 0), (1, 0), (3, 1), (64, 2), (5, 3)])
+@pytest.mark.parametrize("tune", [None, dict(block=128, ppt=2, nt=True)], ids=_tid)
+def test_layouts_and_guard_bands(pad, offset, tune):
+    n = 1553
+    f = _fields(n, seed=5)
+    ins = _chain_dev(f, pad=pad, offset=offset)
+    out = DevField.empty(6, n, pad=pad, offset=offset + 1)
+    tl_dtg_chain(*[x.view for x in ins], out.view, tune=tune)
+    torch.cuda.synchronize()
+    assert_close(out.view, _oracle_chain(f), what=f"chain pad={pad} offset={offset}")
+    assert out.canaries_intact()
+    assert all(x.canaries_intact() for x in ins)
+    g = DevField(f["g"], pad=pad, offset=offset)
+    gi = DevField.empty(6, n, pad=pad + 2, offset=offset)
+    tl_sym_inverse(g.view, gi.view, tune=tune)
+    torch.cuda.synchronize()
+    assert_close(gi.view, oracle.sym_inverse(f["g"]), what="ginv layout")
+    assert gi.canaries_intact()
+
+
+def test_zero_points_touches_nothing():
+    f = _fields(0)
+    out = DevField.empty(6, 0)
+    tl_dtg_chain(*[dev(f[k]) for k in ("g", "dg", "beta", "dbeta", "K", "alpha")], out.view)
+    torch.cuda.synchronize()
+    assert out.canaries_intact()
+
+
+def test_points_are_independent():
+    n = 777
+    f = _fields(n, seed=9)
+    base = tl_dtg_chain(*[dev(f[k]) for k in ("g", "dg", "beta", "dbeta", "K", "alpha")])
+    p = 400
+    f2 = {k: v.copy() for k, v in f.items()}
+    for k in ("g", "dg", "beta", "dbeta", "K", "alpha"):
+        f2[k][:, p] *= 1.01
+    pert = tl_dtg_chain(*[dev(f2[k]) for k in ("g", "dg", "beta", "dbeta", "K", "alpha")])
+    diff = (pert != base).any(dim=0).cpu().numpy()
+    assert diff[p] and diff.sum() == 1
+
+
+@pytest.mark.parametrize("edge", [64, 128])
+def test_full_size_chain(edge):
+    """The fused chain at 64^3 and 128^3 points in the benchmark's launch shape."""
+    n = edge ** 3
+    f = make_fields(n, seed=config_seed(2 if edge == 64 else 3))
+    ins = _chain_dev(f)
+    out = tl_dtg_chain(*[x.view for x in ins])
+    assert_close(out, _oracle_chain(f), what=f"chain {edge}^3")
+
+
+def test_full_size_christoffel_config():
+    """Inverse and Christoffel symbols at 16^3 points (unfused)."""
+    n = 16 ** 3
+    f = make_fields(n, seed=config_seed(1))
+    ginv = tl_sym_inverse(dev(f["g"]))
+    gam = tl_christoffel(ginv, dev(f["dg"]))
+    gi_ref = oracle.sym_inverse(f["g"])
+    assert_close(ginv, gi_ref, what="ginv 16^3")
+    assert_close(gam, oracle.christoffel(gi_ref, f["dg"]), what="gamma 16^3")
+
+
+def test_singular_metric_propagates_nonfinite():
+    n = 64
+    f = _fields(n, seed=11)
+    f["g"][:, 5] = 0.0                    # g = 0 at point 5: det = 0
+    out = tl_dtg_chain(*[dev(f[k]) for k in ("g", "dg", "beta", "dbeta", "K", "alpha")]).cpu().numpy()
+    ref = _oracle_chain(f)
+    assert not np.isfinite(out[:, 5]).all()
+    assert not np.isfinite(ref[:, 5]).all()
+    keep = np.ones(n, bool)
+    keep[5] = False
+    assert_close(out[:, keep], ref[:, keep], what="finite points")
+
+
+@pytest.mark.parametrize("kernel", ["sym_inverse", "christoffel", "cov_deriv", "dtg", "dtg_chain",
+                                    "dtg_chain_bwd", "dtg_chain_batched"])
+def test_kernel_info(kernel):
+    a = tl_kernel_info(kernel)
+    assert a["num_regs"] > 0 and a["max_threads"] >= a["block"]
