@@ -233,6 +233,24 @@ def main():
                                  "fused_fwd_speedup": sum(per) / ms_fwd}
         del unf, ginv, gam, nb
 
+        log("[bench] bandwidth twins")
+        twins = {}
+        from paper_1804_10120_amd import tl_bw_twin
+        from paper_1804_10120_amd._abi import TWIN_SHAPES
+        for nin, nout in TWIN_SHAPES:
+            if nin == 1:
+                continue
+            src = torch.rand(nin, n, dtype=torch.float64, device=device)
+            dst = torch.empty(nout, n, dtype=torch.float64, device=device)
+            with record() as tw:
+                tl_bw_twin(src, nout, dst)
+            _, (ms,) = time_calls([tw], 20, 3)
+            twins[f"{nin}r{nout}w"] = rate(8 * (nin + nout) * n, ms)
+            del src, dst, tw
+        rows["twin_GB_s"] = twins
+        shape = "40r43w" if dom == "dtg_chain_bwd" else "43r6w"
+        res["roofline"]["frac_of_twin"] = achieved / twins[shape]
+
         log("[bench] 64^3 with 4 rotating buffer sets")
         n64 = 64 ** 3
         s64 = device_sets(n64, 4, device, config_seed(2))

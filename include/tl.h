@@ -142,8 +142,10 @@ typedef struct {
 
 typedef struct tl_batch_plan tl_batch_plan;
 
-/* Builds a plan that evaluates tl_dtg_chain on every domain with one
- * persistent kernel launch, captured once into a HIP graph.  The plan copies
+/* Builds a plan that evaluates tl_dtg_chain on every domain with one kernel
+ * launch over the tiles of all domains, captured once into a HIP graph (by
+ * default one block per tile; tune->grid_mult > 0 makes it persistent, each
+ * block walking a contiguous chunk of tiles).  The plan copies
  * the domain table to device memory (the only allocation it makes) and
  * borrows the domains' buffers, which must outlive it; if any pointer
  * changes, destroy the plan and create a new one.  ndom >= 1; domains with
@@ -166,6 +168,14 @@ tl_status tl_batch_plan_destroy(tl_batch_plan* plan);
 /* dst[i] = src[i] for i < n: a plain streaming copy, the library's analogue of
  * a device bandwidth test (Sec. 4, measured bandwidth).  Non-overlapping. */
 tl_status tl_bw_copy(int64_t n, const double* src, double* dst, void* stream);
+
+/* Bandwidth twin of a row's access shape: reads the first nin components of
+ * `in` and writes the first nout components of `out` (out_c = sum of the
+ * inputs + c) with the library's launch machinery and tuning, and no other
+ * arithmetic.  Supported (nin, nout): (1,1), (6,6), (24,18), (30,9), (16,6),
+ * (43,6), (40,43) -- the shapes of the rows above; others: TL_ERR_INVALID. */
+tl_status tl_bw_twin(int64_t n, int32_t nin, tl_cfield in, int32_t nout, tl_field out,
+                     void* stream, const tl_tune* tune);
 
 /* ---- Introspection -------------------------------------------------------------- */
 

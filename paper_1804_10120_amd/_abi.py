@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(PKG, "libtl.so")
 TL_OK, TL_ERR_NULL, TL_ERR_SIZE, TL_ERR_ALIAS, TL_ERR_ALIGN, TL_ERR_HIP, TL_ERR_INVALID = range(7)
 TL_TUNE_NT = 1
 TL_TUNE_XCD = 2
+TWIN_SHAPES = ((1, 1), (6, 6), (24, 18), (30, 9), (16, 6), (43, 6), (40, 43))
 ABI_VERSION = 1
 
 
@@ -65,6 +66,7 @@ SIGNATURES = {
                            ctypes.POINTER(_I64)],
     "tl_batch_plan_destroy": [ctypes.c_void_p],
     "tl_bw_copy": [_I64, ctypes.c_void_p, ctypes.c_void_p, _S],
+    "tl_bw_twin": [_I64, ctypes.c_int32, _C, ctypes.c_int32, _F, _S, _T],
     "tl_kernel_info": [ctypes.c_char_p, _T, ctypes.POINTER(KernelAttr)],
     "tl_status_string": [ctypes.c_int],
     "tl_last_error": [],

@@ -185,24 +185,17 @@ struct OpChainBwd {
   static constexpr int fin[NF_IN] = {6, 18, 3, 6, 1, 6};
   static constexpr int fout[NF_OUT] = {6, 18, 3, 9, 6, 1};
   static constexpr int NIN = 40, NOUT = 43;
-  __device__ static inline void apply(const double* x, double* y) {
-    const double* g = x;
-    const double* D = x + 6;
-    const double* beta = x + 24;
-    const double* K = x + 27;
-    const double alpha = x[33];
-    const double* w = x + 34;
-    double* g_bar = y;
-    double* dg_bar = y + 6;
-    double* beta_bar = y + 24;
-    double* dbeta_bar = y + 27;
-    double* K_bar = y + 36;
-    double* alpha_bar = y + 42;
 
-    double cof[6], det;
+  // Everything that does not need d g: b = g^-1 beta (kept as cofactors, 1/det
+  // and b for phase2) and the gradients with respect to K, alpha, d beta and
+  // d g, which depend on w, alpha, K and b only.
+  __device__ static inline void phase1(const double* g, const double* beta, const double* K,
+                                       double alpha, const double* w, double* cof, double& r,
+                                       double* b, double* dg_bar, double* dbeta_bar,
+                                       double* K_bar, double* alpha_bar) {
+    double det;
     cofactors(g, cof, det);
-    const double r = 1.0 / det;
-    double b[3];
+    r = 1.0 / det;
 #pragma unroll
     for (int l = 0; l < 3; ++l)
       b[l] = (cof[sym(l, 0)] * beta[0] + cof[sym(l, 1)] * beta[1] + cof[sym(l, 2)] * beta[2]) * r;
@@ -237,8 +230,13 @@ struct OpChainBwd {
           dg_bar[l * 6 + s] -= c;
         }
       }
+  }
 
-    // b_bar^l = -sum_s w_s F_l,s
+  // The gradients that need d g: b_bar^l = -sum_s w_s F_l,s, beta_bar =
+  // g^-1 b_bar and g_bar = -beta_bar b^T on the stored slots.
+  __device__ static inline void phase2(const double* D, const double* w, const double* cof,
+                                       double r, const double* b, double* g_bar,
+                                       double* beta_bar) {
     double bb[3];
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
@@ -261,6 +259,31 @@ struct OpChainBwd {
       for (int j = i; j < 3; ++j)
         g_bar[sym(i, j)] =
             i == j ? -(beta_bar[i] * b[i]) : -(beta_bar[i] * b[j] + beta_bar[j] * b[i]);
+  }
+
+  __device__ static inline void apply(const double* x, double* y) {
+    double cof[6], r, b[3];
+    phase1(x, x + 24, x + 27, x[33], x + 34, cof, r, b, y + 6, y + 27, y + 36, y + 42);
+    phase2(x + 6, x + 34, cof, r, b, y, y + 24);
+  }
+};
+
+// ---------------------------------------------------------------- twin
+// Bandwidth twin of a row: reads NI component streams and writes NO, with no
+// arithmetic beyond a sum (each output is the sum of the inputs plus its own
+// index), so it measures the memory ceiling of that access shape.
+template <int NI, int NO>
+struct OpTwin {
+  static constexpr int NF_IN = 1, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {NI};
+  static constexpr int fout[NF_OUT] = {NO};
+  static constexpr int NIN = NI, NOUT = NO;
+  __device__ static inline void apply(const double* x, double* y) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) s += x[i];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) y[o] = s + static_cast<double>(o);
   }
 };
 

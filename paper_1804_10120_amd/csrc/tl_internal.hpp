@@ -49,10 +49,16 @@ inline int64_t grid_size(const Resolved& r, int64_t ntiles) {
   return g;
 }
 
+// (reads, writes) shapes of the bandwidth twin: those of the rows, and a copy.
+#define TL_TWIN_SHAPES(X) X(1, 1) X(6, 6) X(24, 18) X(30, 9) X(16, 6) X(43, 6) X(40, 43)
+
 hipError_t launch_kernel(KernelId k, const Resolved& r, const KArgs& a, int64_t n, hipStream_t s);
+hipError_t launch_twin(int nin, int nout, const Resolved& r, const KArgs& a, int64_t n,
+                       hipStream_t s);
 const void* kernel_address(KernelId k, const Resolved& r);
 hipError_t launch_batched(const Resolved& r, const BatchDomain* doms, const int64_t* start,
-                          int32_t ndom, int64_t ntiles, int64_t grid, hipStream_t s);
+                          const int32_t* tile_dom, int64_t ntiles, int64_t grid, int64_t chunk,
+                          hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, int64_t n, int64_t grid, hipStream_t s);
 
 }  // namespace tl

@@ -157,20 +157,32 @@ __global__ __launch_bounds__(BLOCK) void k_points(KArgs a, int64_t n, int64_t nt
   for (int64_t t = logical_block(xcd); t < ntiles; t += gridDim.x) tile<Op, BLOCK, PPT, NT>(a, n, t);
 }
 
-// Many subgrids: tile t belongs to the domain d with start[d] <= t < start[d+1].
+// Many subgrids: global tile t belongs to subgrid d = tile_dom[t] and is that
+// subgrid's tile t - start[d] (block-uniform loads, so scalar).  Block lb
+// walks the contiguous chunk of tiles [lb*chunk, (lb+1)*chunk), so
+// consecutive tiles of a block are mostly in the same subgrid and its
+// descriptor is fetched again only when the subgrid changes.  With chunk = 1
+// and one block per tile this is a plain (non-persistent) launch.
 template <int BLOCK, int PPT, bool NT>
 __global__ __launch_bounds__(BLOCK) void k_chain_batched(const BatchDomain* __restrict__ doms,
                                                           const int64_t* __restrict__ start,
-                                                          int32_t ndom, int64_t ntiles, int32_t xcd) {
-  for (int64_t t = logical_block(xcd); t < ntiles; t += gridDim.x) {
-    int lo = 0, hi = ndom;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (start[mid] <= t) lo = mid;
-      else hi = mid;
+                                                          const int32_t* __restrict__ tile_dom,
+                                                          int64_t ntiles, int64_t chunk,
+                                                          int32_t xcd) {
+  const int64_t t0 = logical_block(xcd) * chunk;
+  const int64_t t1 = t0 + chunk < ntiles ? t0 + chunk : ntiles;
+  int32_t cur = -1;
+  KArgs a;
+  int64_t n = 0, s0 = 0;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int32_t d = tile_dom[t];
+    if (d != cur) {
+      cur = d;
+      a = doms[d].args;
+      n = doms[d].n;
+      s0 = start[d];
     }
-    const BatchDomain& d = doms[lo];
-    tile<OpChain, BLOCK, PPT, NT>(d.args, d.n, t - start[lo]);
+    tile<OpChain, BLOCK, PPT, NT>(a, n, t - s0);
   }
 }
 
@@ -266,6 +278,15 @@ static const void* ptr_batched(const Resolved& r) {
 #undef TL_PTR
 }
 
+hipError_t launch_twin(int nin, int nout, const Resolved& r, const KArgs& a, int64_t n,
+                       hipStream_t s) {
+#define TL_TWIN(I, O) \
+  if (nin == I && nout == O) return launch_op<OpTwin<I, O>>(r, a, n, s);
+  TL_TWIN_SHAPES(TL_TWIN)
+#undef TL_TWIN
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_kernel(KernelId k, const Resolved& r, const KArgs& a, int64_t n,
                          hipStream_t s) {
   switch (k) {
@@ -293,12 +314,13 @@ const void* kernel_address(KernelId k, const Resolved& r) {
 }
 
 hipError_t launch_batched(const Resolved& r, const BatchDomain* doms, const int64_t* start,
-                          int32_t ndom, int64_t ntiles, int64_t grid, hipStream_t s) {
+                          const int32_t* tile_dom, int64_t ntiles, int64_t grid, int64_t chunk,
+                          hipStream_t s) {
   const void* fn = ptr_batched(r);
   if (fn == nullptr) return hipErrorInvalidValue;
   int32_t xcd = r.xcd ? 1 : 0;
-  void* args[] = {const_cast<BatchDomain**>(&doms), const_cast<int64_t**>(&start), &ndom, &ntiles,
-                  &xcd};
+  void* args[] = {const_cast<BatchDomain**>(&doms), const_cast<int64_t**>(&start),
+                  const_cast<int32_t**>(&tile_dom), &ntiles, &chunk, &xcd};
   hipError_t e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(grid)), dim3(r.block), args, 0, s);
   if (e != hipSuccess) return e;
   return hipGetLastError();

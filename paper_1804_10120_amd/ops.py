@@ -92,7 +92,7 @@ def _stream(device, stream):
 
 def make_tune(tune):
     """None (library default), a Tune, a dict with keys block, ppt, nt, xcd,
-    grid_mult (missing numbers mean the default; nt/xcd default to off), or a
+    grid_mult (missing numbers mean the default; flags default to off), or a
     tuple (block, ppt, flags, grid_mult) -> Tune pointer or None."""
     if tune is None:
         return None
@@ -260,6 +260,23 @@ def tl_bw_copy(src, dst=None, *, stream=None):
     return dst
 
 
+def tl_bw_twin(src, nout, dst=None, *, stream=None, tune=None):
+    """Bandwidth twin: reads every component of ``src`` [nin, n], writes
+    ``nout`` components (out_c = sum of the inputs + c)."""
+    c = _Call()
+    nin = src.shape[0] if src.dim() == 2 else 0
+    c.add(src, "in", nin)
+    dst = c.out(dst, "out", src, nout)
+    with torch.cuda.device(c.device):
+        full = (c.n, nin, _cf(src, nin), nout, _f(dst, nout), _stream(c.device, stream),
+                make_tune(tune))
+        if _recorder is not None:
+            _recorder.append(Prepared(lib().tl_bw_twin, full, c.keep, c.device))
+        else:
+            check(lib().tl_bw_twin(*full))
+    return dst
+
+
 def tl_kernel_info(kernel, tune=None):
     """Attributes (registers, scratch, ...) of the kernel a call would run."""
     a = KernelAttr()
@@ -333,4 +350,4 @@ class BatchPlan:
 
 
 __all__ = ["record", "Prepared", "tl_sym_inverse", "tl_christoffel", "tl_cov_deriv", "tl_dtg", "tl_dtg_chain",
-           "tl_dtg_chain_bwd", "tl_bw_copy", "tl_kernel_info", "BatchPlan", "TLError"]
+           "tl_dtg_chain_bwd", "tl_bw_copy", "tl_bw_twin", "tl_kernel_info", "BatchPlan", "TLError"]

@@ -192,3 +192,8 @@ def test_python_binding_rejects_host_tensors():
         tl_sym_inverse(torch.zeros(6, 4, dtype=torch.float64))
     with pytest.raises(TypeError, match="float64"):
         tl_sym_inverse(torch.zeros(6, 4, dtype=torch.float32))
+
+
+def test_twin_rejects_unknown_shapes(L):
+    assert L.tl_bw_twin(16, 5, cf(BASE, 16), 5, f(BASE + MB, 16), None, None) == _abi.TL_ERR_INVALID
+    assert L.tl_bw_twin(16, 43, cf(BASE, 16), 6, f(BASE + 8 * 16, 16), None, None) == _abi.TL_ERR_ALIAS

@@ -67,11 +67,12 @@ def test_bwd_full_size():
 
 @pytest.mark.parametrize("want", [(1, 0, 0, 0, 0, 0), (0, 1, 0, 0, 0, 0), (0, 0, 1, 0, 1, 0),
                                   (0, 0, 0, 1, 0, 1), (1, 1, 1, 1, 1, 1)])
-def test_bwd_output_subsets(want):
+@pytest.mark.parametrize("tune", [None, dict(block=128, ppt=2, nt=True, xcd=True)], ids=_tid)
+def test_bwd_output_subsets(want, tune):
     n = 999
     f = make_fields(n, seed=13)
     ref = _vjp_ref(f)
-    got = _bwd(f, want=want)
+    got = _bwd(f, want=want, tune=tune)
     for k, w, x in zip(KEYS, want, got):
         if w:
             assert_close(x, ref[k], what=f"{k}_bar subset")

@@ -53,6 +53,23 @@ def test_small_batch(tune):
     plan.close()
 
 
+@pytest.mark.parametrize("tune", [dict(block=64, ppt=1, grid_mult=1),
+                                  dict(block=64, ppt=2, nt=True, xcd=True, grid_mult=1)],
+                         ids=["b64", "b64xcd"])
+def test_persistent_chunks_cross_subgrids(tune):
+    """More tiles than blocks: each block walks a chunk of tiles that spans
+    several subgrids (including empty and one-point ones)."""
+    rng = np.random.default_rng(5)
+    sizes = [int(x) for x in rng.integers(0, 2500, size=40)] + [0, 1, 1]
+    hosts, devs = _domains(sizes, seed=6)
+    plan = BatchPlan(devs, tune=tune)
+    assert plan.tiles > plan.blocks
+    plan.run()
+    torch.cuda.synchronize()
+    _check(plan, hosts, devs, tune)
+    plan.close()
+
+
 def test_replay_and_direct_are_idempotent():
     sizes = [100, 2000, 30000, 7]
     hosts, devs = _domains(sizes, seed=2)

@@ -1,0 +1,39 @@
+"""The bandwidth-twin and copy kernels (the measured memory ceilings)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import DevField, need_gpu
+from paper_1804_10120_amd import tl_bw_copy, tl_bw_twin
+from paper_1804_10120_amd._abi import TWIN_SHAPES
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.mark.parametrize("nin,nout", TWIN_SHAPES)
+@pytest.mark.parametrize("n", [1, 129, 4097])
+@pytest.mark.parametrize("tune", [None, dict(block=64, ppt=2, nt=True, xcd=True)],
+                         ids=["default", "b64ppt2"])
+def test_twin(nin, nout, n, tune):
+    x = np.random.default_rng(nin * 1000 + n).standard_normal((nin, n))
+    src = DevField(x, pad=2)
+    dst = DevField.empty(nout, n, pad=4, offset=2)
+    tl_bw_twin(src.view, nout, dst.view, tune=tune)
+    torch.cuda.synchronize()
+    s = np.zeros(n)
+    for i in range(nin):          # the kernel's summation order
+        s = s + x[i]
+    exp = np.stack([s + c for c in range(nout)])
+    assert np.array_equal(dst.numpy(), exp)
+    assert dst.canaries_intact()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 1001, 1 << 20])
+def test_copy(n):
+    src = torch.randn(n, dtype=torch.float64, device="cuda")
+    assert torch.equal(tl_bw_copy(src), src)
