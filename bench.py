@@ -251,6 +251,31 @@ def main():
         shape = "40r43w" if dom == "dtg_chain_bwd" else "43r6w"
         res["roofline"]["frac_of_twin"] = achieved / twins[shape]
 
+        log("[bench] Christoffel symbols at 16^3 points")
+        n16 = 16 ** 3
+        (_, e16), = device_sets(n16, 1, device, config_seed(1))
+        with record() as cs:
+            gi16 = tl_sym_inverse(e16["g"])
+            tl_christoffel(gi16, e16["dg"])
+        _, (ms_i, ms_c) = time_calls([cs], 200, 20)
+        graph = torch.cuda.CUDAGraph()
+        gi_g = torch.empty_like(gi16)
+        ga_g = torch.empty(18, n16, dtype=torch.float64, device=device)
+        with torch.cuda.graph(graph):       # launches go to the capture stream
+            for _ in range(10):
+                tl_sym_inverse(e16["g"], gi_g)
+                tl_christoffel(gi_g, e16["dg"], ga_g)
+        _, (ms_g,) = time_calls([[graph.replay]], 20, 3)
+        rows["christoffel_16cubed"] = {
+            "points": n16, "sym_inverse_us": ms_i * 1e3, "christoffel_us": ms_c * 1e3,
+            "graph_us_per_pair": ms_g * 1e3 / 10,
+            "points_per_s": n16 / (ms_g * 1e-3 / 10),
+            "note": "latency-bound: 1.6 MB per pair; graph = 10 pairs per replay"}
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(gi_g, gi16)
+        del graph, cs, gi16, e16, gi_g, ga_g
+
         log("[bench] 64^3 with 4 rotating buffer sets")
         n64 = 64 ** 3
         s64 = device_sets(n64, 4, device, config_seed(2))

@@ -105,7 +105,8 @@ int num_cus() {
 // and stores always; for large grids one point per lane in blocks of 256 with
 // XCD-contiguous tiles; below 2^20 points (where the whole grid is in flight
 // at once and the XCD order buys nothing) two points per lane in blocks of
-// 512.  The batched kernel: one block of 128 per tile in plain order (its
+// 512; below 2^16 points (a few memory round trips in all) one point per lane
+// in blocks of 64, to spread the grid over as many compute units as possible.  The batched kernel: one block of 128 per tile in plain order (its
 // subgrids are already contiguous runs of tiles; a persistent grid measured
 // 20% slower than letting the dispatcher balance the uneven subgrids).
 tl::Resolved defaults(tl::KernelId k, int64_t n) {
@@ -120,6 +121,10 @@ tl::Resolved defaults(tl::KernelId k, int64_t n) {
     r.block = 256;
     r.ppt = 1;
     r.xcd = true;
+  } else if (n < (int64_t(1) << 16)) {
+    r.block = 64;
+    r.ppt = 1;
+    r.xcd = false;
   } else {
     r.block = 512;
     r.ppt = 2;

@@ -111,7 +111,9 @@ def make_tune(tune):
 class Prepared:
     """One fully marshalled C-ABI call: calling it re-enters the library with
     the same arguments (validation included) and no Python-side checks.  It
-    holds references to the tensors it names."""
+    holds references to the tensors it names.  The stream is bound when the
+    call is recorded: to capture into a graph, call the tl_* function inside
+    the capture instead."""
 
     def __init__(self, fn, args, keep, device):
         self.fn, self.args, self.keep, self.device = fn, args, keep, device
