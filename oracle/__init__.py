@@ -4,8 +4,9 @@ This package is the plain, slow, obviously correct reference implementation of
 the per-grid-point tensor expressions of Lewis & Pfeiffer (arXiv:1804.10120):
 the inverse metric, the Christoffel symbols (Sec. 1, eq:SpatialChristoffel),
 the covariant derivative of the shift (Sec. 1, footnote) and the metric
-evolution d_t g_ij (Sec. 1, eq:dtg_ij), plus forward- and reverse-mode
-derivatives of their chain.  The arithmetic lives in ``tl_oracle.cpp`` (plain
+evolution d_t g_ij (Sec. 1, eq:dtg_ij), forward- and reverse-mode derivatives
+of their chain, and the benchmark expressions of Sec. 5.1 (assignments,
+additions, outer products, chained contractions, K_ij).  The arithmetic lives in ``tl_oracle.cpp`` (plain
 serial loops, IEEE double, no FP contraction); this module only marshals numpy
 arrays into it.
 
@@ -41,6 +42,8 @@ _SIGS = {
     "tlo_dtg_chain_jvp": [_I] + [_P] * 14,
     "tlo_dtg_chain_vjp": [_I] + [_P] * 13,
 }
+EXPRS = ("assign1", "assign2", "assign3", "add1", "add2", "add3", "mult1", "mult2", "mult3",
+         "contract1", "contract2", "contract3", "kij")
 GRAD_KEYS = (("g", 6), ("dg", 18), ("beta", 3), ("dbeta", 9), ("K", 6), ("alpha", 1))
 
 
@@ -73,6 +76,35 @@ class Oracle:
             fn = getattr(self.lib, name)
             fn.argtypes = args
             fn.restype = None
+        self.lib.tlo_expr_shape.argtypes = [ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 3
+        self.lib.tlo_expr_shape.restype = ctypes.c_int
+        self.lib.tlo_expr.argtypes = [ctypes.c_int, _I, ctypes.POINTER(ctypes.c_void_p), _P]
+        self.lib.tlo_expr.restype = ctypes.c_int
+
+    def expr_shape(self, name):
+        """(input component counts, output component count) of a benchmark
+        expression of Sec. 5.1."""
+        nin, oc = ctypes.c_int(), ctypes.c_int()
+        ic = (ctypes.c_int * 4)()
+        if self.lib.tlo_expr_shape(EXPRS.index(name), ctypes.byref(nin), ic, ctypes.byref(oc)):
+            raise ValueError(name)
+        return tuple(ic[:nin.value]), oc.value
+
+    def expr(self, name, *inputs):
+        """Benchmark expression ``name`` (Sec. 5.1) over [C, n] inputs given in
+        the order of its right-hand side -> [C_out, n]."""
+        ic, oc = self.expr_shape(name)
+        if len(inputs) != len(ic):
+            raise ValueError(f"{name}: expected {len(ic)} inputs")
+        ins = [_field(x, c, name=f"{name} input {k}") for k, (x, c) in enumerate(zip(inputs, ic))]
+        n = ins[0].shape[1]
+        if any(a.shape[1] != n for a in ins):
+            raise ValueError(f"{name}: inputs differ in n")
+        out = np.empty((oc, n))
+        ptrs = (ctypes.c_void_p * len(ins))(*[a.ctypes.data for a in ins])
+        if self.lib.tlo_expr(EXPRS.index(name), n, ptrs, _ptr(out)):
+            raise ValueError(name)
+        return out
 
     def sym_inverse(self, g):
         """g [6,n] -> g^ij [6,n] (Cramer's rule: adjugate / determinant)."""
@@ -190,3 +222,11 @@ def dtg_chain_jvp(inputs, tangents):
 
 def dtg_chain_vjp(inputs, W):
     return default().dtg_chain_vjp(inputs, W)
+
+
+def expr(name, *inputs):
+    return default().expr(name, *inputs)
+
+
+def expr_shape(name):
+    return default().expr_shape(name)

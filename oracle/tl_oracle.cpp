@@ -335,4 +335,159 @@ void tlo_dtg_chain_vjp(int64_t n, const double* g, const double* dg, const doubl
   g_tape = nullptr;
 }
 
+// ---------------------------------------------------------------------------
+// The benchmark expressions of Sec. 5.1 (eq:Assign1-3, eq:Add1-3,
+// eq:Mult1-3, eq:Contract1-3, eq:Kij), with three-dimensional indices.  A
+// non-symmetric tensor of rank r has 3^r components stored row-major over its
+// indices (A_ij at i*3+j, A_ijk at (i*3+j)*3+k, ...); a mixed B_i^m is stored
+// as B[i*3+m]; K_ij and g_ij are symmetric (6 components, s(i,j)); alpha is a
+// scalar field.  Inputs are the right-hand-side tensors in the order they are
+// written in the equation; the output is the left-hand side.
+//
+//   id  expression                              inputs (components)     out
+//    0  A_i = B_i                               3                        3
+//    1  A_ij = B_ij                             9                        9
+//    2  A_ijk = B_ijk                           27                       27
+//    3  A_i = B_i + C_i                         3 3                      3
+//    4  A_i = B_i + C_i + D_i                   3 3 3                    3
+//    5  A_i = B_i + C_i + D_i + E_i             3 3 3 3                  3
+//    6  A_ij = B_i C_j                          3 3                      9
+//    7  A_ijk = B_i C_j D_k                     3 3 3                    27
+//    8  A_ijkl = B_i C_j D_k E_l                3 3 3 3                  81
+//    9  A_ijkl = B_i^m E_mjkl                   9 81                     81
+//   10  A_ijkl = C_j^n B_i^m E_mnkl             9 9 81                   81
+//   11  A_ijkl = D_k^o C_j^n B_i^m E_mnol       9 9 9 81                 81
+//   12  K_ij = 2 alpha g_ij + beta_i beta_j     1 6 3                    6
+namespace {
+
+int ipow3(int r) { return r == 0 ? 1 : 3 * ipow3(r - 1); }
+
+void expr_point(int id, const std::vector<const double*>& in, double* out) {
+  switch (id) {
+    case 0:
+    case 1:
+    case 2: {
+      const int m = ipow3(id + 1);
+      for (int c = 0; c < m; ++c) out[c] = in[0][c];
+      break;
+    }
+    case 3:
+      for (int i = 0; i < 3; ++i) out[i] = in[0][i] + in[1][i];
+      break;
+    case 4:
+      for (int i = 0; i < 3; ++i) out[i] = in[0][i] + in[1][i] + in[2][i];
+      break;
+    case 5:
+      for (int i = 0; i < 3; ++i) out[i] = in[0][i] + in[1][i] + in[2][i] + in[3][i];
+      break;
+    case 6:
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) out[i * 3 + j] = in[0][i] * in[1][j];
+      break;
+    case 7:
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          for (int k = 0; k < 3; ++k) out[(i * 3 + j) * 3 + k] = in[0][i] * in[1][j] * in[2][k];
+      break;
+    case 8:
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l)
+              out[((i * 3 + j) * 3 + k) * 3 + l] = in[0][i] * in[1][j] * in[2][k] * in[3][l];
+      break;
+    case 9: {  // B = in[0], E = in[1]
+      const double *B = in[0], *E = in[1];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l) {
+              double sum = 0.0;
+              for (int m = 0; m < 3; ++m) sum += B[i * 3 + m] * E[((m * 3 + j) * 3 + k) * 3 + l];
+              out[((i * 3 + j) * 3 + k) * 3 + l] = sum;
+            }
+      break;
+    }
+    case 10: {  // C = in[0], B = in[1], E = in[2]
+      const double *C = in[0], *B = in[1], *E = in[2];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l) {
+              double sum = 0.0;
+              for (int n = 0; n < 3; ++n)
+                for (int m = 0; m < 3; ++m)
+                  sum += C[j * 3 + n] * B[i * 3 + m] * E[((m * 3 + n) * 3 + k) * 3 + l];
+              out[((i * 3 + j) * 3 + k) * 3 + l] = sum;
+            }
+      break;
+    }
+    case 11: {  // D = in[0], C = in[1], B = in[2], E = in[3]
+      const double *D = in[0], *C = in[1], *B = in[2], *E = in[3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l) {
+              double sum = 0.0;
+              for (int o = 0; o < 3; ++o)
+                for (int n = 0; n < 3; ++n)
+                  for (int m = 0; m < 3; ++m)
+                    sum += D[k * 3 + o] * C[j * 3 + n] * B[i * 3 + m] *
+                           E[((m * 3 + n) * 3 + o) * 3 + l];
+              out[((i * 3 + j) * 3 + k) * 3 + l] = sum;
+            }
+      break;
+    }
+    case 12: {  // alpha = in[0], g = in[1], beta = in[2]
+      const double alpha = in[0][0];
+      for (int i = 0; i < 3; ++i)
+        for (int j = i; j < 3; ++j)
+          out[sym(i, j)] = 2.0 * alpha * in[1][sym(i, j)] + in[2][i] * in[2][j];
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+const int kExprIn[13][4] = {{3}, {9}, {27}, {3, 3}, {3, 3, 3}, {3, 3, 3, 3}, {3, 3}, {3, 3, 3},
+                            {3, 3, 3, 3}, {9, 81}, {9, 9, 81}, {9, 9, 9, 81}, {1, 6, 3}};
+const int kExprOut[13] = {3, 9, 27, 3, 3, 3, 9, 27, 81, 81, 81, 81, 6};
+
+}  // namespace
+
+// Shape of expression `id`: number of inputs, their component counts and the
+// output's; returns 0, or -1 for an unknown id.
+int tlo_expr_shape(int id, int* nin, int* in_ncomp, int* out_ncomp) {
+  if (id < 0 || id > 12) return -1;
+  int k = 0;
+  while (k < 4 && kExprIn[id][k] > 0) {
+    in_ncomp[k] = kExprIn[id][k];
+    ++k;
+  }
+  *nin = k;
+  *out_ncomp = kExprOut[id];
+  return 0;
+}
+
+// Expression `id` over n points; in[] are contiguous [C][n] inputs in the
+// order of the table above, out a contiguous [C][n] output.
+int tlo_expr(int id, int64_t n, const double* const* in, double* out) {
+  int nin, ic[4], oc;
+  if (tlo_expr_shape(id, &nin, ic, &oc) != 0) return -1;
+  std::vector<std::vector<double>> x(nin);
+  for (int f = 0; f < nin; ++f) x[f].resize(ic[f]);
+  std::vector<const double*> xp(nin);
+  std::vector<double> y(oc);
+  for (int64_t p = 0; p < n; ++p) {
+    for (int f = 0; f < nin; ++f) {
+      for (int c = 0; c < ic[f]; ++c) x[f][c] = in[f][c * n + p];
+      xp[f] = x[f].data();
+    }
+    expr_point(id, xp, y.data());
+    for (int c = 0; c < oc; ++c) out[c * n + p] = y[c];
+  }
+  return 0;
+}
+
 }  // extern "C"

@@ -355,4 +355,65 @@ def pin_jvp_finite_difference(orc, n=128, h=1e-6):
     _close(jv, fd, 1e-6, "JVP vs central differences")
 
 
+# --------------------------------------------------------------------------- Sec. 5.1 family
+
+def _ints(shape, seed, lo=-8, hi=8):
+    """Small integers as doubles: every sum and product below is exact."""
+    return np.random.default_rng(seed).integers(lo, hi + 1, size=shape).astype(np.float64)
+
+
+def pin_expr_assign_add(orc):
+    n = 97
+    for r, name in ((1, "assign1"), (2, "assign2"), (3, "assign3")):
+        B = np.random.default_rng(r).standard_normal((3 ** r, n))
+        _assert(np.array_equal(orc.expr(name, B), B), f"{name} is not a copy")
+    X = [_ints((3, n), 60 + k) for k in range(4)]
+    for m, name in ((2, "add1"), (3, "add2"), (4, "add3")):
+        _assert(np.array_equal(orc.expr(name, *X[:m]), np.sum(X[:m], axis=0)), name)
+
+
+def pin_expr_outer_products(orc):
+    n = 64
+    B, C, D, E = (_ints((3, n), 70 + k) for k in range(4))
+    exp = [np.einsum("in,jn->ijn", B, C),
+           np.einsum("in,jn,kn->ijkn", B, C, D),
+           np.einsum("in,jn,kn,ln->ijkln", B, C, D, E)]
+    for name, args, e in (("mult1", (B, C), exp[0]), ("mult2", (B, C, D), exp[1]),
+                          ("mult3", (B, C, D, E), exp[2])):
+        _assert(np.array_equal(orc.expr(name, *args), e.reshape(-1, n)), name)
+
+
+def pin_expr_contractions(orc):
+    """Against numpy's einsum on small integers (exact), and the reductions:
+    an identity B gives E back; an identity C (D) reduces two (three) chained
+    contractions to one (two)."""
+    n = 50
+    B, C, D = (_ints((3, 3, n), 80 + k, -3, 3) for k in range(3))
+    E = _ints((3, 3, 3, 3, n), 84, -3, 3)
+    fl = lambda a: a.reshape(-1, n)
+    _assert(np.array_equal(orc.expr("contract1", fl(B), fl(E)),
+                           fl(np.einsum("imp,mjklp->ijklp", B, E))), "contract1")
+    _assert(np.array_equal(orc.expr("contract2", fl(C), fl(B), fl(E)),
+                           fl(np.einsum("jnp,imp,mnklp->ijklp", C, B, E))), "contract2")
+    _assert(np.array_equal(orc.expr("contract3", fl(D), fl(C), fl(B), fl(E)),
+                           fl(np.einsum("kop,jnp,imp,mnolp->ijklp", D, C, B, E))), "contract3")
+    I = np.repeat(np.eye(3)[:, :, None], n, axis=2)
+    _assert(np.array_equal(orc.expr("contract1", fl(I), fl(E)), fl(E)), "contract1 identity")
+    _assert(np.array_equal(orc.expr("contract2", fl(I), fl(B), fl(E)),
+                           orc.expr("contract1", fl(B), fl(E))), "contract2 reduction")
+    _assert(np.array_equal(orc.expr("contract3", fl(I), fl(C), fl(B), fl(E)),
+                           orc.expr("contract2", fl(C), fl(B), fl(E))), "contract3 reduction")
+
+
+def pin_expr_kij(orc):
+    """K_ij = 2 alpha g_ij + beta_i beta_j on small integers; beta = 0 gives
+    2 alpha g, alpha = 0 gives the symmetric outer product."""
+    n = 40
+    al, g, b = _ints((1, n), 90), _ints((6, n), 91), _ints((3, n), 92)
+    bb = cf.sym6(np.einsum("in,jn->ijn", b, b))
+    _assert(np.array_equal(orc.expr("kij", al, g, b), 2 * al * g + bb), "kij")
+    _assert(np.array_equal(orc.expr("kij", al, g, 0 * b), 2 * al * g), "kij beta = 0")
+    _assert(np.array_equal(orc.expr("kij", 0 * al, g, b), bb), "kij alpha = 0")
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_") and callable(v)]

@@ -42,6 +42,23 @@ MUTANTS = [
     ("tape_sub_sign", "make(a.v - b.v, a.id, 1.0, b.id, -1.0)", "make(a.v - b.v, a.id, 1.0, b.id, 1.0)"),
     ("dual_div", "(a.d - q * b.d) / b.v", "(a.d + q * b.d) / b.v"),
     ("dual_mul", "a.d * b.v + a.v * b.d", "a.d * b.v + a.v * b.v"),
+    ("add3_dropped_term", "in[0][i] + in[1][i] + in[2][i] + in[3][i]",
+     "in[0][i] + in[1][i] + in[3][i] + in[3][i]"),
+    ("mult2_index", "in[0][i] * in[1][j] * in[2][k]", "in[0][i] * in[1][k] * in[2][j]"),
+    ("mult3_index", "in[0][i] * in[1][j] * in[2][k] * in[3][l]",
+     "in[0][i] * in[1][j] * in[2][l] * in[3][k]"),
+    ("contract1_transposed_b", "sum += B[i * 3 + m] * E[((m * 3 + j) * 3 + k) * 3 + l]",
+     "sum += B[m * 3 + i] * E[((m * 3 + j) * 3 + k) * 3 + l]"),
+    ("contract1_e_index", "sum += B[i * 3 + m] * E[((m * 3 + j) * 3 + k) * 3 + l]",
+     "sum += B[i * 3 + m] * E[((m * 3 + k) * 3 + j) * 3 + l]"),
+    ("contract2_c_index", "sum += C[j * 3 + n] * B[i * 3 + m] * E[((m * 3 + n) * 3 + k) * 3 + l]",
+     "sum += C[n * 3 + j] * B[i * 3 + m] * E[((m * 3 + n) * 3 + k) * 3 + l]"),
+    ("contract3_e_index", "E[((m * 3 + n) * 3 + o) * 3 + l]", "E[((n * 3 + m) * 3 + o) * 3 + l]"),
+    ("contract3_d_index", "sum += D[k * 3 + o] * C[j * 3 + n]", "sum += D[o * 3 + k] * C[j * 3 + n]"),
+    ("kij_factor", "out[sym(i, j)] = 2.0 * alpha * in[1][sym(i, j)]",
+     "out[sym(i, j)] = alpha * in[1][sym(i, j)]"),
+    ("kij_outer", "+ in[2][i] * in[2][j]", "+ in[2][i] * in[2][i]"),
+    ("expr_table", "{9, 81}, {9, 9, 81}", "{9, 81}, {9, 81, 9}"),
 ]
 
 
@@ -50,8 +67,8 @@ def _run_all_pins(orc):
     for pin in pins.ALL_PINS:
         try:
             pin(orc)
-        except AssertionError as e:
-            failed.append(f"{pin.__name__}: {e}")
+        except Exception as e:           # a wrong result or a rejected shape
+            failed.append(f"{pin.__name__}: {type(e).__name__}: {e}")
     return failed
 
 
