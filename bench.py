@@ -139,6 +139,76 @@ def cpu_baseline(f, budget_s):
                       f"benchmark fields, in 4096-point slices, {dt:.1f} s on one host core"}
 
 
+SWEEP_SIZES = tuple(32 * 4 ** k for k in range(9)) + (2 ** 21,)
+
+
+def paper_family(device, sizes, reps=21):
+    """BW_eff (the paper's effective bandwidth: 8 B x elements x N / t) of the
+    Sec. 5.1 benchmark expressions, the Christoffel symbols (g^ij given, as in
+    the paper) and the fused chain, at each grid size.  Each size: ``reps``
+    launches timed with HIP events, the first discarded, the median kept (the
+    paper's method).  Smaller grids are views of the largest fields."""
+    import torch
+    from paper_1804_10120_amd import tl_christoffel, tl_dtg_chain, tl_expr, tl_expr_shape
+    from paper_1804_10120_amd.ops import record
+    from paper_1804_10120_amd.synth import EXPR_INPUTS, make_expr_inputs, make_fields
+    nmax = max(sizes)
+    table = {}
+
+    def run(name, ne, launch):
+        row = {}
+        for n in sizes:
+            with record() as calls:
+                launch(n)
+            c = calls[0]
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(reps)]
+            for a, b in ev:
+                a.record()
+                c()
+                b.record()
+            torch.cuda.synchronize()
+            ts = sorted(a.elapsed_time(b) for a, b in ev[1:])
+            row[n] = rate(8 * ne * n, ts[len(ts) // 2])
+        table[name] = row
+
+    for name in EXPR_INPUTS:
+        ic, oc = tl_expr_shape(name)
+        xs = [torch.from_numpy(x).to(device) for x in make_expr_inputs(name, nmax, seed=5)]
+        out = torch.empty(oc, nmax, dtype=torch.float64, device=device)
+        run(name, sum(ic) + oc,
+            lambda n: tl_expr(name, *[x[:, :n] for x in xs], out=out[:, :n]))
+        del xs, out
+    f = {k: torch.from_numpy(v).to(device) for k, v in
+         make_fields(nmax, seed=7, fields=KEYS).items()}
+    gam = torch.empty(18, nmax, dtype=torch.float64, device=device)
+    run("christoffel", 42, lambda n: tl_christoffel(f["g"][:, :n], f["dg"][:, :n], gam[:, :n]))
+    dtg = torch.empty(6, nmax, dtype=torch.float64, device=device)
+    run("dtg_chain", 49, lambda n: tl_dtg_chain(*[f[k][:, :n] for k in KEYS], dtg[:, :n]))
+    del f, gam, dtg
+    torch.cuda.empty_cache()
+    return table
+
+
+def family_summary(table):
+    """Rate at the largest size and the smallest swept size reaching half of it."""
+    out = {}
+    for name, row in table.items():
+        top = row[max(row)]
+        half = min((n for n, g in row.items() if g >= 0.5 * top), default=None)
+        out[name] = {"GB_s": top, "half_rate_at_points": half}
+    return out
+
+
+def write_sweep(table, path):
+    sizes = sorted(next(iter(table.values())))
+    with open(path, "w") as f:
+        f.write("| expression | " + " | ".join(str(n) for n in sizes) + " |\n")
+        f.write("|---" * (len(sizes) + 1) + "|\n")
+        for name, row in table.items():
+            f.write(f"| {name} | " + " | ".join(f"{row[n]:.0f}" for n in sizes) + " |\n")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -149,6 +219,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-rows", action="store_true", help="time only the fwd+bwd step")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--sweep", metavar="FILE",
+                    help="also write the full grid-size sweep (GB/s) as a Markdown table")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -315,6 +387,11 @@ def main():
             "separate_launches_points_per_s": npts / (ms_many * 1e-3)}
         plan.close()
         del doms, many
+        log("[bench] the paper's benchmark expressions, grid-size sweep")
+        table = paper_family(device, SWEEP_SIZES)
+        rows["paper_family"] = family_summary(table)
+        if args.sweep:
+            write_sweep(table, args.sweep)
         res["rows"] = rows
         torch.cuda.empty_cache()
 

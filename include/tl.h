@@ -163,6 +163,41 @@ tl_status tl_batch_plan_info(const tl_batch_plan* plan, int64_t* points, int64_t
 /* Waits for the plan's work, then frees it; NULL is a no-op. */
 tl_status tl_batch_plan_destroy(tl_batch_plan* plan);
 
+/* ---- The paper's benchmark expressions (Sec. 5.1) ------------------------- */
+
+/* Three-dimensional indices.  A non-symmetric rank-r tensor has 3^r
+ * components stored row-major over its indices (A_ij at i*3+j, A_ijk at
+ * (i*3+j)*3+k, ...); a mixed B_i^m is stored as B[i*3+m]; K_ij and g_ij are
+ * symmetric (s(i,j)); alpha is a scalar field.  in[] holds the right-hand-side
+ * tensors in the order they are written; out is the left-hand side.
+ *
+ *   id                  expression                            in (comps)   out
+ *   TL_ASSIGN1          A_i = B_i               eq:Assign1    3            3
+ *   TL_ASSIGN2          A_ij = B_ij             eq:Assign2    9            9
+ *   TL_ASSIGN3          A_ijk = B_ijk           eq:Assign3    27           27
+ *   TL_ADD1             A_i = B_i + C_i         eq:Add1       3 3          3
+ *   TL_ADD2             ... + D_i               eq:Add2       3 3 3        3
+ *   TL_ADD3             ... + E_i               eq:Add3       3 3 3 3      3
+ *   TL_MULT1            A_ij = B_i C_j          eq:Mult1      3 3          9
+ *   TL_MULT2            A_ijk = B_i C_j D_k     eq:Mult2      3 3 3        27
+ *   TL_MULT3            A_ijkl = B_i C_j D_k E_l eq:Mult3     3 3 3 3      81
+ *   TL_CONTRACT1        A_ijkl = B_i^m E_mjkl   eq:Contract1  9 81         81
+ *   TL_CONTRACT2        C_j^n B_i^m E_mnkl      eq:Contract2  9 9 81       81
+ *   TL_CONTRACT3        D_k^o C_j^n B_i^m E_mnol eq:Contract3 9 9 9 81     81
+ *   TL_KIJ              K_ij = 2 alpha g_ij + beta_i beta_j  eq:Kij  1 6 3  6
+ *
+ * Validation and execution as for the other entry points; a wrong nin or an
+ * unknown id returns TL_ERR_INVALID. */
+typedef enum {
+  TL_ASSIGN1 = 0, TL_ASSIGN2, TL_ASSIGN3, TL_ADD1, TL_ADD2, TL_ADD3, TL_MULT1, TL_MULT2,
+  TL_MULT3, TL_CONTRACT1, TL_CONTRACT2, TL_CONTRACT3, TL_KIJ, TL_EXPR_COUNT
+} tl_expr_id;
+
+tl_status tl_expr(int32_t expr, int64_t n, const tl_cfield* in, int32_t nin, tl_field out,
+                  void* stream, const tl_tune* tune);
+/* Number of inputs, their component counts (up to 4) and the output's. */
+tl_status tl_expr_shape(int32_t expr, int32_t* nin, int32_t* in_ncomp, int32_t* out_ncomp);
+
 /* ---- Bandwidth reference ---------------------------------------------------- */
 
 /* dst[i] = src[i] for i < n: a plain streaming copy, the library's analogue of
@@ -187,8 +222,9 @@ typedef struct {
 } tl_kernel_attr;
 
 /* Attributes of the kernel that `kernel` ("sym_inverse", "christoffel",
- * "cov_deriv", "dtg", "dtg_chain", "dtg_chain_bwd", "dtg_chain_batched") would
- * run with `tune` (ppt assumes aligned fields). */
+ * "cov_deriv", "dtg", "dtg_chain", "dtg_chain_bwd", "dtg_chain_batched", or an
+ * expression name "assign1" ... "contract3", "kij") would run with `tune`
+ * on a large grid (ppt assumes aligned fields). */
 tl_status tl_kernel_info(const char* kernel, const tl_tune* tune, tl_kernel_attr* out);
 
 const char* tl_status_string(tl_status s);

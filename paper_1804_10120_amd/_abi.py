@@ -14,6 +14,8 @@ LIB_PATH = os.path.join(PKG, "libtl.so")
 TL_OK, TL_ERR_NULL, TL_ERR_SIZE, TL_ERR_ALIAS, TL_ERR_ALIGN, TL_ERR_HIP, TL_ERR_INVALID = range(7)
 TL_TUNE_NT = 1
 TL_TUNE_XCD = 2
+EXPRS = ("assign1", "assign2", "assign3", "add1", "add2", "add3", "mult1", "mult2", "mult3",
+         "contract1", "contract2", "contract3", "kij")
 TWIN_SHAPES = ((1, 1), (6, 6), (24, 18), (30, 9), (16, 6), (43, 6), (40, 43))
 ABI_VERSION = 1
 
@@ -67,6 +69,9 @@ SIGNATURES = {
     "tl_batch_plan_destroy": [ctypes.c_void_p],
     "tl_bw_copy": [_I64, ctypes.c_void_p, ctypes.c_void_p, _S],
     "tl_bw_twin": [_I64, ctypes.c_int32, _C, ctypes.c_int32, _F, _S, _T],
+    "tl_expr": [ctypes.c_int32, _I64, ctypes.POINTER(CField), ctypes.c_int32, _F, _S, _T],
+    "tl_expr_shape": [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
     "tl_kernel_info": [ctypes.c_char_p, _T, ctypes.POINTER(KernelAttr)],
     "tl_status_string": [ctypes.c_int],
     "tl_last_error": [],

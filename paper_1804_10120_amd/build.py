@@ -12,6 +12,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -20,24 +21,30 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libtl.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["tl_kernels.hip", "tl_abi.cpp"]
+SOURCES = ["tl_kernels.hip", "tl_expr.hip", "tl_abi.cpp"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
+def _compile(src, verbose):
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    if src.endswith(".hip"):
+        cmd.insert(1, "-Rpass-analysis=kernel-resource-usage")
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    return src, obj, r
+
+
 def build(verbose: bool = False) -> str:
+    """Compiles every translation unit (in parallel) and links libtl.so."""
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    report = []
-    for src in SOURCES:
-        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
-        if src.endswith(".hip"):
-            cmd.insert(1, "-Rpass-analysis=kernel-resource-usage")
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
+        results = list(pool.map(lambda s: _compile(s, verbose), SOURCES))
+    objs, report = [], []
+    for src, obj, r in results:
         report.append(r.stderr)
         if r.returncode != 0:
             sys.stderr.write(r.stderr)

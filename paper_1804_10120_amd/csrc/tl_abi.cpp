@@ -361,6 +361,56 @@ tl_status tl_dtg_chain_bwd(int64_t n, tl_cfield g, tl_cfield dg, tl_cfield beta,
   return run(tl::KernelId::ChainBwd, c, tune, a, stream);
 }
 
+namespace {
+// Input component counts (0-terminated) and output count of each expression.
+const int kExprIn[TL_EXPR_COUNT][5] = {{3}, {9}, {27}, {3, 3}, {3, 3, 3}, {3, 3, 3, 3}, {3, 3},
+                                       {3, 3, 3}, {3, 3, 3, 3}, {9, 81}, {9, 9, 81},
+                                       {9, 9, 9, 81}, {1, 6, 3}};
+const int kExprOut[TL_EXPR_COUNT] = {3, 9, 27, 3, 3, 3, 9, 27, 81, 81, 81, 81, 6};
+const char* const kExprName[TL_EXPR_COUNT] = {
+    "assign1", "assign2", "assign3", "add1", "add2", "add3", "mult1",
+    "mult2", "mult3", "contract1", "contract2", "contract3", "kij"};
+int expr_nin(int id) {
+  int k = 0;
+  while (k < 4 && kExprIn[id][k] > 0) ++k;
+  return k;
+}
+}  // namespace
+
+tl_status tl_expr_shape(int32_t expr, int32_t* nin, int32_t* in_ncomp, int32_t* out_ncomp) {
+  if (expr < 0 || expr >= TL_EXPR_COUNT) return fail(TL_ERR_INVALID, "unknown expression %d", expr);
+  const int k = expr_nin(expr);
+  if (nin) *nin = k;
+  if (in_ncomp)
+    for (int f = 0; f < k; ++f) in_ncomp[f] = kExprIn[expr][f];
+  if (out_ncomp) *out_ncomp = kExprOut[expr];
+  return TL_OK;
+}
+
+tl_status tl_expr(int32_t expr, int64_t n, const tl_cfield* in, int32_t nin, tl_field out,
+                  void* stream, const tl_tune* tune) {
+  if (expr < 0 || expr >= TL_EXPR_COUNT) return fail(TL_ERR_INVALID, "unknown expression %d", expr);
+  const int k = expr_nin(expr);
+  if (nin != k) return fail(TL_ERR_INVALID, "%s takes %d inputs, got %d", kExprName[expr], k, nin);
+  if (n < 0) return fail(TL_ERR_SIZE, "n=%lld < 0", (long long)n);
+  if (n == 0) return TL_OK;
+  if (in == nullptr) return fail(TL_ERR_NULL, "in is NULL");
+  static const char* const names[4] = {"in[0]", "in[1]", "in[2]", "in[3]"};
+  Checker c(n);
+  for (int f = 0; f < k; ++f) c.field(names[f], in[f].ptr, in[f].ld, kExprIn[expr][f], false);
+  c.field("out", out.ptr, out.ld, kExprOut[expr], true);
+  if (c.overlaps() != TL_OK) return c.st;
+  tl::KArgs a = zero_args();
+  for (int f = 0; f < k; ++f) set_in(a, f, in[f]);
+  set_out(a, 0, out);
+  tl::Resolved r;
+  tl_status s = resolve(tl::KernelId::Chain, tune, c.vec_ok, n, &r);
+  if (s != TL_OK) return s;
+  hipError_t e = tl::launch_expr(expr, r, a, n, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "expression launch");
+  return TL_OK;
+}
+
 tl_status tl_bw_twin(int64_t n, int32_t nin, tl_cfield in, int32_t nout, tl_field out, void* stream,
                      const tl_tune* tune) {
   bool known = false;
@@ -578,11 +628,14 @@ tl_status tl_kernel_info(const char* kernel, const tl_tune* tune, tl_kernel_attr
   const tl::KernelId* id = nullptr;
   for (const auto& x : names)
     if (std::strcmp(x.name, kernel) == 0) id = &x.id;
-  if (id == nullptr) return fail(TL_ERR_INVALID, "unknown kernel '%s'", kernel);
+  int expr = -1;
+  for (int e = 0; e < TL_EXPR_COUNT; ++e)
+    if (std::strcmp(kExprName[e], kernel) == 0) expr = e;
+  if (id == nullptr && expr < 0) return fail(TL_ERR_INVALID, "unknown kernel '%s'", kernel);
   tl::Resolved r;
-  tl_status s = resolve(*id, tune, true, int64_t(1) << 24, &r);
+  tl_status s = resolve(id ? *id : tl::KernelId::Chain, tune, true, int64_t(1) << 24, &r);
   if (s != TL_OK) return s;
-  const void* fn = tl::kernel_address(*id, r);
+  const void* fn = id ? tl::kernel_address(*id, r) : tl::expr_address(expr, r);
   if (fn == nullptr) return fail(TL_ERR_INVALID, "no instantiation for this tuning");
   hipFuncAttributes attr;
   hipError_t e = hipFuncGetAttributes(&attr, fn);

@@ -56,6 +56,9 @@ hipError_t launch_kernel(KernelId k, const Resolved& r, const KArgs& a, int64_t 
 hipError_t launch_twin(int nin, int nout, const Resolved& r, const KArgs& a, int64_t n,
                        hipStream_t s);
 const void* kernel_address(KernelId k, const Resolved& r);
+// The benchmark expressions (ids as in tl_expr_id of tl.h).
+hipError_t launch_expr(int id, const Resolved& r, const KArgs& a, int64_t n, hipStream_t s);
+const void* expr_address(int id, const Resolved& r);
 hipError_t launch_batched(const Resolved& r, const BatchDomain* doms, const int64_t* start,
                           const int32_t* tile_dom, int64_t ntiles, int64_t grid, int64_t chunk,
                           hipStream_t s);

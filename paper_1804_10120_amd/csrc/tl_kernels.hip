@@ -1,161 +1,14 @@
-// Streaming point-wise kernels for gfx950 and their launchers.
-//
-// One lane owns PPT consecutive grid points.  It issues every load of its
-// points up front -- one coalesced stream per tensor component, 16-byte
-// vector loads when PPT == 2 -- runs the per-point body from tl_device.hpp in
-// registers and streams the results out.  No LDS and no MFMA: every point is
-// independent and the contractions are 3-long, so the kernels are bound by HBM
-// bandwidth, and the only levers are the bytes in flight per CU (PPT, block
-// size, occupancy) and cache policy (non-temporal loads/stores).
-//
-// A tile is BLOCK*PPT consecutive points; a block walks tiles
-// blockIdx.x, blockIdx.x + gridDim.x, ... so the same kernel serves a grid of
-// one tile per block and a persistent grid.  The batched kernel walks the
-// tiles of many subgrids, locating each tile's subgrid by a binary search of a
-// prefix-sum table (uniform per block, so it runs on scalar registers).
+// Kernels of the tensor-expression chain for gfx950 and their launchers:
+// the unfused steps, the fused chain and its adjoint (all through the
+// streaming template of tl_stream.hpp), the batched kernel over many
+// subgrids, the bandwidth twins and the streaming copy.
 #include <hip/hip_runtime.h>
 
 #include "tl_device.hpp"
 #include "tl_internal.hpp"
+#include "tl_stream.hpp"
 
 namespace tl {
-
-typedef double dbl2 __attribute__((ext_vector_type(2)));
-
-template <bool NT>
-__device__ inline double load1(const double* p) {
-  if constexpr (NT) return __builtin_nontemporal_load(p);
-  else return *p;
-}
-template <bool NT>
-__device__ inline dbl2 load2(const double* p) {
-  const dbl2* q = reinterpret_cast<const dbl2*>(p);
-  if constexpr (NT) return __builtin_nontemporal_load(q);
-  else return *q;
-}
-template <bool NT>
-__device__ inline void store1(double* p, double v) {
-  if constexpr (NT) __builtin_nontemporal_store(v, p);
-  else *p = v;
-}
-template <bool NT>
-__device__ inline void store2(double* p, dbl2 v) {
-  dbl2* q = reinterpret_cast<dbl2*>(p);
-  if constexpr (NT) __builtin_nontemporal_store(v, q);
-  else *q = v;
-}
-
-// Offsets of each field's first component in the gathered per-point vector.
-template <int NF>
-struct Offsets {
-  int v[NF + 1];
-};
-template <class Op>
-constexpr Offsets<Op::NF_IN> in_offsets() {
-  Offsets<Op::NF_IN> o{};
-  o.v[0] = 0;
-  for (int f = 0; f < Op::NF_IN; ++f) o.v[f + 1] = o.v[f] + Op::fin[f];
-  return o;
-}
-template <class Op>
-constexpr Offsets<Op::NF_OUT> out_offsets() {
-  Offsets<Op::NF_OUT> o{};
-  o.v[0] = 0;
-  for (int f = 0; f < Op::NF_OUT; ++f) o.v[f + 1] = o.v[f] + Op::fout[f];
-  return o;
-}
-
-// Points p .. p+PPT-1 of one tile, all in range.
-template <class Op, int PPT, bool NT>
-__device__ inline void points_full(const KArgs& a, int64_t p) {
-  constexpr auto io = in_offsets<Op>();
-  constexpr auto oo = out_offsets<Op>();
-  if constexpr (PPT == 1) {
-    double x[Op::NIN], y[Op::NOUT];
-#pragma unroll
-    for (int f = 0; f < Op::NF_IN; ++f)
-#pragma unroll
-      for (int c = 0; c < Op::fin[f]; ++c) x[io.v[f] + c] = load1<NT>(a.in[f] + c * a.ldin[f] + p);
-    Op::apply(x, y);
-#pragma unroll
-    for (int f = 0; f < Op::NF_OUT; ++f) {
-      if (a.out[f] == nullptr) continue;
-#pragma unroll
-      for (int c = 0; c < Op::fout[f]; ++c) store1<NT>(a.out[f] + c * a.ldout[f] + p, y[oo.v[f] + c]);
-    }
-  } else {
-    static_assert(PPT == 2, "PPT is 1 or 2");
-    dbl2 x2[Op::NIN];
-#pragma unroll
-    for (int f = 0; f < Op::NF_IN; ++f)
-#pragma unroll
-      for (int c = 0; c < Op::fin[f]; ++c) x2[io.v[f] + c] = load2<NT>(a.in[f] + c * a.ldin[f] + p);
-    double x[Op::NIN], y0[Op::NOUT], y1[Op::NOUT];
-#pragma unroll
-    for (int q = 0; q < Op::NIN; ++q) x[q] = x2[q].x;
-    Op::apply(x, y0);
-#pragma unroll
-    for (int q = 0; q < Op::NIN; ++q) x[q] = x2[q].y;
-    Op::apply(x, y1);
-#pragma unroll
-    for (int f = 0; f < Op::NF_OUT; ++f) {
-      if (a.out[f] == nullptr) continue;
-#pragma unroll
-      for (int c = 0; c < Op::fout[f]; ++c) {
-        dbl2 v;
-        v.x = y0[oo.v[f] + c];
-        v.y = y1[oo.v[f] + c];
-        store2<NT>(a.out[f] + c * a.ldout[f] + p, v);
-      }
-    }
-  }
-}
-
-// Points p .. min(p+PPT, n)-1, scalar accesses (the ragged tail).
-template <class Op, int PPT>
-__device__ inline void points_tail(const KArgs& a, int64_t p, int64_t n) {
-  constexpr auto io = in_offsets<Op>();
-  constexpr auto oo = out_offsets<Op>();
-  for (int k = 0; k < PPT; ++k) {
-    const int64_t q = p + k;
-    if (q >= n) break;
-    double x[Op::NIN], y[Op::NOUT];
-#pragma unroll
-    for (int f = 0; f < Op::NF_IN; ++f)
-#pragma unroll
-      for (int c = 0; c < Op::fin[f]; ++c) x[io.v[f] + c] = a.in[f][c * a.ldin[f] + q];
-    Op::apply(x, y);
-#pragma unroll
-    for (int f = 0; f < Op::NF_OUT; ++f) {
-      if (a.out[f] == nullptr) continue;
-#pragma unroll
-      for (int c = 0; c < Op::fout[f]; ++c) a.out[f][c * a.ldout[f] + q] = y[oo.v[f] + c];
-    }
-  }
-}
-
-template <class Op, int BLOCK, int PPT, bool NT>
-__device__ inline void tile(const KArgs& a, int64_t n, int64_t t) {
-  const int64_t p = (t * BLOCK + threadIdx.x) * PPT;
-  if (p + PPT <= n) points_full<Op, PPT, NT>(a, p);
-  else if (p < n) points_tail<Op, PPT>(a, p, n);
-}
-
-// Logical block index.  Workgroups are dispatched to the 8 XCDs round-robin
-// (block b runs on XCD b % 8); with `xcd` set (and gridDim.x a multiple of
-// 8) the blocks of one XCD take a contiguous run of tiles instead of every
-// 8th tile, so each XCD streams through its own contiguous address ranges.
-__device__ inline int64_t logical_block(int32_t xcd) {
-  const int64_t b = blockIdx.x;
-  if (!xcd) return b;
-  const int64_t per = gridDim.x >> 3;
-  return (b & 7) * per + (b >> 3);
-}
-
-template <class Op, int BLOCK, int PPT, bool NT>
-__global__ __launch_bounds__(BLOCK) void k_points(KArgs a, int64_t n, int64_t ntiles, int32_t xcd) {
-  for (int64_t t = logical_block(xcd); t < ntiles; t += gridDim.x) tile<Op, BLOCK, PPT, NT>(a, n, t);
-}
 
 // Many subgrids: global tile t belongs to subgrid d = tile_dom[t] and is that
 // subgrid's tile t - start[d] (block-uniform loads, so scalar).  Block lb
@@ -197,64 +50,6 @@ __global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst,
       if (i + 1 < n) dst[i + 1] = src[i + 1];
     }
   }
-}
-
-// ---------------------------------------------------------------- dispatch
-
-template <class Op, int BLOCK, int PPT, bool NT>
-static const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&k_points<Op, BLOCK, PPT, NT>);
-}
-
-template <class Op, int BLOCK, int PPT, bool NT>
-static hipError_t launch_one(const KArgs& a, int64_t n, int64_t ntiles, int64_t grid, int32_t xcd,
-                             hipStream_t s) {
-  hipLaunchKernelGGL((k_points<Op, BLOCK, PPT, NT>), dim3(static_cast<unsigned>(grid)),
-                     dim3(BLOCK), 0, s, a, n, ntiles, xcd);
-  return hipGetLastError();
-}
-
-template <class Op, int BLOCK>
-static hipError_t launch_b(const Resolved& r, const KArgs& a, int64_t n, int64_t ntiles,
-                           int64_t grid, hipStream_t s) {
-  const int32_t x = r.xcd ? 1 : 0;
-  if (r.ppt == 2)
-    return r.nt ? launch_one<Op, BLOCK, 2, true>(a, n, ntiles, grid, x, s)
-                : launch_one<Op, BLOCK, 2, false>(a, n, ntiles, grid, x, s);
-  return r.nt ? launch_one<Op, BLOCK, 1, true>(a, n, ntiles, grid, x, s)
-              : launch_one<Op, BLOCK, 1, false>(a, n, ntiles, grid, x, s);
-}
-
-template <class Op>
-static hipError_t launch_op(const Resolved& r, const KArgs& a, int64_t n, hipStream_t s) {
-  const int64_t per = static_cast<int64_t>(r.block) * r.ppt;
-  const int64_t ntiles = (n + per - 1) / per;
-  const int64_t grid = grid_size(r, ntiles);
-  switch (r.block) {
-    case 64: return launch_b<Op, 64>(r, a, n, ntiles, grid, s);
-    case 128: return launch_b<Op, 128>(r, a, n, ntiles, grid, s);
-    case 256: return launch_b<Op, 256>(r, a, n, ntiles, grid, s);
-    case 512: return launch_b<Op, 512>(r, a, n, ntiles, grid, s);
-    case 1024: return launch_b<Op, 1024>(r, a, n, ntiles, grid, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <class Op>
-static const void* ptr_op(const Resolved& r) {
-#define TL_PTR(B)                                                                       \
-  case B:                                                                               \
-    return r.ppt == 2 ? (r.nt ? kernel_ptr<Op, B, 2, true>() : kernel_ptr<Op, B, 2, false>()) \
-                      : (r.nt ? kernel_ptr<Op, B, 1, true>() : kernel_ptr<Op, B, 1, false>());
-  switch (r.block) {
-    TL_PTR(64)
-    TL_PTR(128)
-    TL_PTR(256)
-    TL_PTR(512)
-    TL_PTR(1024)
-    default: return nullptr;
-  }
-#undef TL_PTR
 }
 
 template <int BLOCK, int PPT, bool NT>

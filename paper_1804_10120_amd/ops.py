@@ -279,6 +279,38 @@ def tl_bw_twin(src, nout, dst=None, *, stream=None, tune=None):
     return dst
 
 
+def tl_expr_shape(expr):
+    """(input component counts, output component count) of a Sec. 5.1
+    benchmark expression, by name ("assign1" ... "kij") or id."""
+    eid = _abi.EXPRS.index(expr) if isinstance(expr, str) else int(expr)
+    nin, oc = ctypes.c_int32(), ctypes.c_int32()
+    ic = (ctypes.c_int32 * 4)()
+    check(lib().tl_expr_shape(eid, ctypes.byref(nin), ic, ctypes.byref(oc)))
+    return tuple(ic[:nin.value]), oc.value
+
+
+def tl_expr(expr, *inputs, out=None, stream=None, tune=None):
+    """A Sec. 5.1 benchmark expression over [C, n] device fields given in the
+    order of its right-hand side; returns (or fills) the left-hand side."""
+    eid = _abi.EXPRS.index(expr) if isinstance(expr, str) else int(expr)
+    ic, oc = tl_expr_shape(eid)
+    if len(inputs) != len(ic):
+        raise ValueError(f"{_abi.EXPRS[eid]}: expected {len(ic)} inputs, got {len(inputs)}")
+    c = _Call()
+    for k, (t, nc) in enumerate(zip(inputs, ic)):
+        c.add(t, f"in[{k}]", nc)
+    out = c.out(out, "out", inputs[-1], oc)
+    arr = (CField * len(inputs))(*[_cf(t, nc) for t, nc in zip(inputs, ic)])
+    with torch.cuda.device(c.device):
+        full = (eid, c.n, arr, len(inputs), _f(out, oc), _stream(c.device, stream),
+                make_tune(tune))
+        if _recorder is not None:
+            _recorder.append(Prepared(lib().tl_expr, full, c.keep + [arr], c.device))
+        else:
+            check(lib().tl_expr(*full))
+    return out
+
+
 def tl_kernel_info(kernel, tune=None):
     """Attributes (registers, scratch, ...) of the kernel a call would run."""
     a = KernelAttr()
@@ -352,4 +384,5 @@ class BatchPlan:
 
 
 __all__ = ["record", "Prepared", "tl_sym_inverse", "tl_christoffel", "tl_cov_deriv", "tl_dtg", "tl_dtg_chain",
-           "tl_dtg_chain_bwd", "tl_bw_copy", "tl_bw_twin", "tl_kernel_info", "BatchPlan", "TLError"]
+           "tl_dtg_chain_bwd", "tl_bw_copy", "tl_bw_twin", "tl_expr", "tl_expr_shape",
+           "tl_kernel_info", "BatchPlan", "TLError"]

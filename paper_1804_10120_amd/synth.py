@@ -71,3 +71,25 @@ def domain_edges(ndom: int = 256, lo: int = 8, hi: int = 48, seed: int = BASE_SE
     lo..hi; subgrid d has edges[d]**3 points."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
     return rng.integers(lo, hi + 1, size=ndom)
+
+
+# Component counts of the right-hand-side tensors of the Sec. 5.1 benchmark
+# expressions, in the order they are written.
+EXPR_INPUTS = {"assign1": (3,), "assign2": (9,), "assign3": (27,), "add1": (3, 3),
+               "add2": (3, 3, 3), "add3": (3, 3, 3, 3), "mult1": (3, 3), "mult2": (3, 3, 3),
+               "mult3": (3, 3, 3, 3), "contract1": (9, 81), "contract2": (9, 9, 81),
+               "contract3": (9, 9, 9, 81), "kij": (1, 6, 3)}
+
+
+def make_expr_inputs(name, n, seed=BASE_SEED):
+    """Seeded inputs of benchmark expression ``name``: every tensor component
+    i.i.d. U[-1,1], except the lapse of K_ij (U[0.5,1.5]).  One generator per
+    input, spawned from ``SeedSequence(seed)``."""
+    comps = EXPR_INPUTS[name]
+    seqs = np.random.SeedSequence(seed).spawn(len(comps))
+    out = []
+    for k, (c, sq) in enumerate(zip(comps, seqs)):
+        rng = np.random.Generator(np.random.PCG64(sq))
+        lo, hi = (0.5, 1.5) if (name == "kij" and k == 0) else (-1.0, 1.0)
+        out.append(np.ascontiguousarray(rng.uniform(lo, hi, size=(c, int(n)))))
+    return out

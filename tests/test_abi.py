@@ -197,3 +197,23 @@ def test_python_binding_rejects_host_tensors():
 def test_twin_rejects_unknown_shapes(L):
     assert L.tl_bw_twin(16, 5, cf(BASE, 16), 5, f(BASE + MB, 16), None, None) == _abi.TL_ERR_INVALID
     assert L.tl_bw_twin(16, 43, cf(BASE, 16), 6, f(BASE + 8 * 16, 16), None, None) == _abi.TL_ERR_ALIAS
+
+
+def test_expr_shapes_match_the_oracle(L):
+    import oracle
+    from paper_1804_10120_amd import tl_expr_shape
+    for name in _abi.EXPRS:
+        assert tl_expr_shape(name) == oracle.expr_shape(name)
+
+
+def test_expr_validation(L):
+    n = 16
+    ins = (CField * 2)(cf(BASE, n), cf(BASE + MB, n))
+    assert L.tl_expr(99, n, ins, 2, f(BASE + 2 * MB, n), None, None) == _abi.TL_ERR_INVALID
+    assert L.tl_expr(_abi.EXPRS.index("contract1"), n, ins, 3, f(BASE + 2 * MB, n), None,
+                     None) == _abi.TL_ERR_INVALID
+    # contract1 reads 81 components of E: an output 1 MiB after E's base overlaps it
+    bad = (CField * 2)(cf(BASE, 4096), cf(BASE + MB, 4096))
+    assert L.tl_expr(_abi.EXPRS.index("contract1"), 4096, bad, 2, f(BASE + 2 * MB, 4096), None,
+                     None) == _abi.TL_ERR_ALIAS
+    assert L.tl_expr(0, 0, None, 1, f(None, 0), None, None) == _abi.TL_OK
