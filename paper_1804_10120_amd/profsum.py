@@ -23,17 +23,19 @@ import os
 from collections import defaultdict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ("tl_kernels.hip", "tl_device.hpp", "tl_internal.hpp", "tl_abi.cpp")
+CSRC = os.path.join(PKG, "csrc")
 OPS = {"dtg_chain": "tl::OpChain,", "dtg_chain_bwd": "tl::OpChainBwd,"}
 DOUBLES_READ = {"dtg_chain": 43, "dtg_chain_bwd": 40}
 DOUBLES_WRITTEN = {"dtg_chain": 6, "dtg_chain_bwd": 43}
 
 
 def sources_sha256():
+    """Hash of every source file of the library (kernels, bodies, ABI)."""
     h = hashlib.sha256()
-    for name in SOURCES:
-        with open(os.path.join(PKG, "csrc", name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
