@@ -43,7 +43,8 @@ _SIGS = {
     "tlo_dtg_chain_vjp": [_I] + [_P] * 13,
 }
 EXPRS = ("assign1", "assign2", "assign3", "add1", "add2", "add3", "mult1", "mult2", "mult3",
-         "contract1", "contract2", "contract3", "kij")
+         "contract1", "contract2", "contract3", "kij",
+         "lst_sym_contract", "lst_fixed_offset", "spacetime_g", "spacetime_beta")
 GRAD_KEYS = (("g", 6), ("dg", 18), ("beta", 3), ("dbeta", 9), ("K", 6), ("alpha", 1))
 
 
@@ -90,9 +91,12 @@ class Oracle:
             raise ValueError(name)
         return tuple(ic[:nin.value]), oc.value
 
-    def expr(self, name, *inputs):
-        """Benchmark expression ``name`` (Sec. 5.1) over [C, n] inputs given in
-        the order of its right-hand side -> [C_out, n]."""
+    def expr(self, name, *inputs, out=None):
+        """Expression ``name`` (the benchmark expressions of Sec. 5.1, the
+        examples of Sec. 4, the spacetime split of Sec. 2.2) over [C, n] inputs
+        given in the order of its right-hand side -> [C_out, n].  Components an
+        expression does not write keep their values from ``out`` (NaN if no
+        ``out`` is given)."""
         ic, oc = self.expr_shape(name)
         if len(inputs) != len(ic):
             raise ValueError(f"{name}: expected {len(ic)} inputs")
@@ -100,7 +104,9 @@ class Oracle:
         n = ins[0].shape[1]
         if any(a.shape[1] != n for a in ins):
             raise ValueError(f"{name}: inputs differ in n")
-        out = np.empty((oc, n))
+        out = np.full((oc, n), np.nan) if out is None else np.array(out, dtype=np.float64)
+        if out.shape != (oc, n):
+            raise ValueError(f"{name}: out must be [{oc}, {n}]")
         ptrs = (ctypes.c_void_p * len(ins))(*[a.ctypes.data for a in ins])
         if self.lib.tlo_expr(EXPRS.index(name), n, ptrs, _ptr(out)):
             raise ValueError(name)
@@ -224,8 +230,8 @@ def dtg_chain_vjp(inputs, W):
     return default().dtg_chain_vjp(inputs, W)
 
 
-def expr(name, *inputs):
-    return default().expr(name, *inputs)
+def expr(name, *inputs, out=None):
+    return default().expr(name, *inputs, out=out)
 
 
 def expr_shape(name):

@@ -358,7 +358,22 @@ void tlo_dtg_chain_vjp(int64_t n, const double* g, const double* dg, const doubl
 //   10  A_ijkl = C_j^n B_i^m E_mnkl             9 9 81                   81
 //   11  A_ijkl = D_k^o C_j^n B_i^m E_mnol       9 9 9 81                 81
 //   12  K_ij = 2 alpha g_ij + beta_i beta_j     1 6 3                    6
+//
+// And, with four-dimensional (spacetime) indices a,b,c = 0..3 and the
+// symmetric dimension-4 pair order of the same kind (00 01 02 03 11 12 13 22 23
+// 33), the examples of Sec. 4 and the spacetime split of Sec. 2.2:
+//   13  C_(ab) = sum_c A_ac B_cb  (symmetric LHS)    16 16     10
+//   14  D_(i0) = sum_c E_(i+1)c F_c0, i = 0..2       16 16     10 (3 written)
+//   15  g_ij = psi_(i+1)(j+1)                         10        6
+//   16  beta_i = psi_(i+1)0                           10        3
+// For a symmetric left-hand side with both slots free, the components with
+// a <= b are evaluated (ascending pairs, like the storage order).
 namespace {
+
+inline int sym4(int a, int b) {
+  static const int table[4][4] = {{0, 1, 2, 3}, {1, 4, 5, 6}, {2, 5, 7, 8}, {3, 6, 8, 9}};
+  return table[a][b];
+}
 
 int ipow3(int r) { return r == 0 ? 1 : 3 * ipow3(r - 1); }
 
@@ -445,21 +460,46 @@ void expr_point(int id, const std::vector<const double*>& in, double* out) {
           out[sym(i, j)] = 2.0 * alpha * in[1][sym(i, j)] + in[2][i] * in[2][j];
       break;
     }
+    case 13: {  // A = in[0], B = in[1], both 4x4 row-major
+      for (int a = 0; a < 4; ++a)
+        for (int b = a; b < 4; ++b) {
+          double sum = 0.0;
+          for (int c = 0; c < 4; ++c) sum += in[0][a * 4 + c] * in[1][c * 4 + b];
+          out[sym4(a, b)] = sum;
+        }
+      break;
+    }
+    case 14: {  // E = in[0], F = in[1], both 4x4 row-major; only D_(i0) is written
+      for (int i = 0; i < 3; ++i) {
+        double sum = 0.0;
+        for (int c = 0; c < 4; ++c) sum += in[0][(i + 1) * 4 + c] * in[1][c * 4 + 0];
+        out[sym4(i, 0)] = sum;
+      }
+      break;
+    }
+    case 15:
+      for (int i = 0; i < 3; ++i)
+        for (int j = i; j < 3; ++j) out[sym(i, j)] = in[0][sym4(i + 1, j + 1)];
+      break;
+    case 16:
+      for (int i = 0; i < 3; ++i) out[i] = in[0][sym4(i + 1, 0)];
+      break;
     default:
       break;
   }
 }
 
-const int kExprIn[13][4] = {{3}, {9}, {27}, {3, 3}, {3, 3, 3}, {3, 3, 3, 3}, {3, 3}, {3, 3, 3},
-                            {3, 3, 3, 3}, {9, 81}, {9, 9, 81}, {9, 9, 9, 81}, {1, 6, 3}};
-const int kExprOut[13] = {3, 9, 27, 3, 3, 3, 9, 27, 81, 81, 81, 81, 6};
+const int kExprIn[17][4] = {{3}, {9}, {27}, {3, 3}, {3, 3, 3}, {3, 3, 3, 3}, {3, 3}, {3, 3, 3},
+                            {3, 3, 3, 3}, {9, 81}, {9, 9, 81}, {9, 9, 9, 81}, {1, 6, 3},
+                            {16, 16}, {16, 16}, {10}, {10}};
+const int kExprOut[17] = {3, 9, 27, 3, 3, 3, 9, 27, 81, 81, 81, 81, 6, 10, 10, 6, 3};
 
 }  // namespace
 
 // Shape of expression `id`: number of inputs, their component counts and the
 // output's; returns 0, or -1 for an unknown id.
 int tlo_expr_shape(int id, int* nin, int* in_ncomp, int* out_ncomp) {
-  if (id < 0 || id > 12) return -1;
+  if (id < 0 || id > 16) return -1;
   int k = 0;
   while (k < 4 && kExprIn[id][k] > 0) {
     in_ncomp[k] = kExprIn[id][k];
@@ -484,6 +524,7 @@ int tlo_expr(int id, int64_t n, const double* const* in, double* out) {
       for (int c = 0; c < ic[f]; ++c) x[f][c] = in[f][c * n + p];
       xp[f] = x[f].data();
     }
+    for (int c = 0; c < oc; ++c) y[c] = out[c * n + p];  // components not written stay
     expr_point(id, xp, y.data());
     for (int c = 0; c < oc; ++c) out[c * n + p] = y[c];
   }

@@ -416,4 +416,47 @@ def pin_expr_kij(orc):
     _assert(np.array_equal(orc.expr("kij", 0 * al, g, b), bb), "kij alpha = 0")
 
 
+# --------------------------------------------------------------------------- Sec. 4 / Sec. 2.2
+
+S4 = np.array([[0, 1, 2, 3], [1, 4, 5, 6], [2, 5, 7, 8], [3, 6, 8, 9]])
+PAIRS4 = [(a, b) for a in range(4) for b in range(a, 4)]
+
+
+def pin_listing_examples(orc):
+    """C_(ab) = A_ac B_cb on ascending pairs, and D_(i0) = E_(i+1)c F_c0 with the
+    other seven components of D left alone (einsum on small integers)."""
+    n = 30
+    A, B = _ints((4, 4, n), 101, -5, 5), _ints((4, 4, n), 102, -5, 5)
+    full = np.einsum("acp,cbp->abp", A, B)
+    exp = np.stack([full[a, b] for a, b in PAIRS4])
+    _assert(np.array_equal(orc.expr("lst_sym_contract", A.reshape(16, n), B.reshape(16, n)), exp),
+            "symmetric contraction")
+    At = A.transpose(1, 0, 2).reshape(16, n)       # B = A^T: a symmetric product
+    got = orc.expr("lst_sym_contract", A.reshape(16, n), At)
+    aat = np.einsum("acp,bcp->abp", A, A)
+    _assert(np.array_equal(got, np.stack([aat[a, b] for a, b in PAIRS4])), "A A^T")
+    E, F = _ints((4, 4, n), 103, -5, 5), _ints((4, 4, n), 104, -5, 5)
+    prev = _ints((10, n), 105)
+    got = orc.expr("lst_fixed_offset", E.reshape(16, n), F.reshape(16, n), out=prev)
+    exp = prev.copy()
+    for i in range(3):
+        exp[S4[i, 0]] = np.einsum("cp,cp->p", E[i + 1], F[:, 0])
+    _assert(np.array_equal(got, exp), "fixed and offset indices")
+
+
+def pin_spacetime_split(orc):
+    """psi_ab assembled from a known spatial metric and shift gives them back."""
+    n = 25
+    rng = np.random.default_rng(110)
+    g, b = rng.standard_normal((6, n)), rng.standard_normal((3, n))
+    psi = np.zeros((10, n))
+    psi[S4[0, 0]] = rng.standard_normal(n)
+    for i in range(3):
+        psi[S4[i + 1, 0]] = b[i]
+        for j in range(i, 3):
+            psi[S4[i + 1, j + 1]] = g[cf.S[i, j]]
+    _assert(np.array_equal(orc.expr("spacetime_g", psi), g), "spatial metric")
+    _assert(np.array_equal(orc.expr("spacetime_beta", psi), b), "shift")
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_") and callable(v)]

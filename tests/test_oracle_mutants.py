@@ -59,6 +59,14 @@ MUTANTS = [
      "out[sym(i, j)] = alpha * in[1][sym(i, j)]"),
     ("kij_outer", "+ in[2][i] * in[2][j]", "+ in[2][i] * in[2][i]"),
     ("expr_table", "{9, 81}, {9, 9, 81}", "{9, 81}, {9, 81, 9}"),
+    ("sym4_table", "{1, 4, 5, 6}, {2, 5, 7, 8}", "{1, 4, 5, 6}, {2, 5, 8, 7}"),
+    ("lst_contract_order", "sum += in[0][a * 4 + c] * in[1][c * 4 + b]",
+     "sum += in[0][c * 4 + a] * in[1][c * 4 + b]"),
+    ("lst_offset", "in[0][(i + 1) * 4 + c]", "in[0][i * 4 + c]"),
+    ("lst_fixed", "in[1][c * 4 + 0]", "in[1][0 * 4 + c]"),
+    ("spacetime_offset", "out[sym(i, j)] = in[0][sym4(i + 1, j + 1)]",
+     "out[sym(i, j)] = in[0][sym4(i, j + 1)]"),
+    ("spacetime_shift", "out[i] = in[0][sym4(i + 1, 0)]", "out[i] = in[0][sym4(i + 1, 1)]"),
 ]
 
 
