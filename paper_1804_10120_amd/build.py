@@ -21,14 +21,14 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libtl.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["tl_kernels.hip", "tl_expr.hip", "tl_abi.cpp"]
+SOURCES = ["tl_kernels.hip", "tl_expr.hip", "generated/tlg_kernels.hip", "tl_abi.cpp"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
 def _compile(src, verbose):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    obj = os.path.join(BUILD, os.path.splitext(os.path.basename(src))[0] + ".o")
     cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".hip"):
         cmd.insert(1, "-Rpass-analysis=kernel-resource-usage")
@@ -39,7 +39,10 @@ def _compile(src, verbose):
 
 
 def build(verbose: bool = False) -> str:
-    """Compiles every translation unit (in parallel) and links libtl.so."""
+    """Regenerates the generated kernels from the registry, compiles every
+    translation unit (in parallel) and links libtl.so."""
+    from .codegen.__main__ import main as codegen
+    codegen([])
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
         results = list(pool.map(lambda s: _compile(s, verbose), SOURCES))

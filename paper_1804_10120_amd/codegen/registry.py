@@ -1,0 +1,79 @@
+"""The expressions compiled into the library by the code generator.
+
+Each is written the way the paper writes its TLoops expressions, with the
+citation of the passage it comes from.  The build regenerates
+csrc/generated/tlg_kernels.hip, include/tl_generated.h and generated.json from
+this list (``python -m paper_1804_10120_amd.codegen``).
+"""
+from __future__ import annotations
+
+from .dsl import Program, Sum, Tensor, indices
+
+
+def programs():
+    i, j, k, l, m = indices("i j k l m")
+    a, b, c = indices("a b c", 4)
+
+    # spatial tensors, layouts as in tl.h
+    g = Tensor("g", (3, 3), sym=[(0, 1)])
+    Invg = Tensor("Invg", (3, 3), sym=[(0, 1)])
+    dg = Tensor("dg", (3, 3, 3), sym=[(1, 2)])          # dg(k,i,j) = d_k g_ij
+    Gamma = Tensor("Gamma", (3, 3, 3), sym=[(1, 2)])    # Gamma(i,j,k) = Gamma^i_jk
+    beta = Tensor("beta", (3,))
+    dbeta = Tensor("dbeta", (3, 3))                     # dbeta(j,i) = d_j beta_i
+    nabla = Tensor("nabla", (3, 3))                     # nabla(j,i) = nabla_j beta_i
+    K = Tensor("K", (3, 3), sym=[(0, 1)])
+    alpha = Tensor("alpha", ())
+    dtg = Tensor("dtg", (3, 3), sym=[(0, 1)])
+
+    christoffel = (0.5 * Sum(l, Invg[i, l] * (dg[k, j, l] + dg[j, l, k] - dg[l, j, k])))
+    out = []
+
+    out.append(Program("christoffel", "Christoffel symbols from g^ij and d_k g_ij "
+                                      "(Sec. 1, eq:SpatialChristoffel)")
+               .let(Gamma[i, j, k], christoffel))
+    out.append(Program("cov_deriv", "covariant derivative of the shift (Sec. 1, footnote)")
+               .let(nabla[j, i], dbeta[j, i] - Sum(k, Gamma[k, i, j] * beta[k])))
+    out.append(Program("dtg", "metric evolution from nabla beta (Sec. 1, eq:dtg_ij)")
+               .let(dtg[i, j], -2.0 * alpha[()] * K[i, j] + nabla[i, j] + nabla[j, i]))
+    out.append(Program("dtg_chain_invg",
+                       "Christoffel symbols, covariant derivative and metric evolution in one "
+                       "kernel, Gamma and nabla beta in registers (Sec. 1)")
+               .temp(Gamma, nabla)
+               .let(Gamma[i, j, k], christoffel)
+               .let(nabla[j, i], dbeta[j, i] - Sum(k, Gamma[k, i, j] * beta[k]))
+               .let(dtg[i, j], -2.0 * alpha[()] * K[i, j] + nabla[i, j] + nabla[j, i]))
+
+    Kout = Tensor("K", (3, 3), sym=[(0, 1)])
+    out.append(Program("kij", "K_ij = 2 alpha g_ij + beta_i beta_j (Sec. 5.1, eq:Kij)")
+               .let(Kout[i, j], 2.0 * alpha[()] * g[i, j] + beta[i] * beta[j]))
+
+    B = Tensor("B", (3, 3))
+    E = Tensor("E", (3, 3, 3, 3))
+    A4 = Tensor("A", (3, 3, 3, 3))
+    out.append(Program("contract1", "A_ijkl = B_i^m E_mjkl (Sec. 5.1, eq:Contract1)")
+               .let(A4[i, j, k, l], Sum(m, B[i, m] * E[m, j, k, l])))
+
+    # the examples of Sec. 4 (dimension-4 indices a, b, c; fixed and offset indices)
+    A = Tensor("A", (4, 4))
+    Bm = Tensor("B", (4, 4))
+    C = Tensor("C", (4, 4), sym=[(0, 1)])
+    out.append(Program("lst_sym_contract", "C_(ab) = sum_c A_ac B_cb, symmetric left-hand "
+                                           "side (Sec. 4, rank 2 contraction example)")
+               .let(C[a, b], Sum(c, A[a, c] * Bm[c, b])))
+    D = Tensor("D", (4, 4), sym=[(0, 1)])
+    E4 = Tensor("E", (4, 4))
+    F = Tensor("F", (4, 4))
+    out.append(Program("lst_fixed_offset", "D_(i0) = sum_c E_(i+1)c F_c0, fixed and offset "
+                                           "indices (Sec. 4, second contraction example)")
+               .let(D[i, 0], Sum(c, E4[i + 1, c] * F[c, 0])))
+
+    # spacetime split (Sec. 2.2): g_ij = psi_(i+1)(j+1), beta_i = psi_(i+1)0
+    psi = Tensor("psi", (4, 4), sym=[(0, 1)])
+    gs = Tensor("g", (3, 3), sym=[(0, 1)])
+    bs = Tensor("beta", (3,))
+    out.append(Program("spacetime_split", "spatial metric and shift from the spacetime "
+                                          "metric psi_ab (Sec. 2.2)")
+               .let(gs[i, j], psi[i + 1, j + 1])
+               .let(bs[i], psi[i + 1, 0]))
+    return out

@@ -1,0 +1,795 @@
+// Generated from index notation by paper_1804_10120_amd/codegen (regenerate
+// with `python -m paper_1804_10120_amd.codegen`, do not edit by hand).
+// Streaming per-point bodies for gfx950 and their C-ABI entry points; see
+// include/tl_generated.h for the expressions.
+#include <hip/hip_runtime.h>
+
+#include "../../../include/tl_generated.h"
+#include "../tl_internal.hpp"
+#include "../tl_stream.hpp"
+
+namespace tl {
+
+// christoffel: Christoffel symbols from g^ij and d_k g_ij (Sec. 1, eq:SpatialChristoffel)
+struct Gen_christoffel {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 2, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {6, 18};
+  static constexpr int fout[NF_OUT] = {18};
+  static constexpr int NIN = 24, NOUT = 18;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    const double x0_3 = ld(0, 3);
+    const double x0_4 = ld(0, 4);
+    const double x0_5 = ld(0, 5);
+    const double x1_0 = ld(1, 0);
+    const double x1_1 = ld(1, 1);
+    const double x1_2 = ld(1, 2);
+    const double x1_3 = ld(1, 3);
+    const double x1_4 = ld(1, 4);
+    const double x1_5 = ld(1, 5);
+    const double x1_6 = ld(1, 6);
+    const double x1_7 = ld(1, 7);
+    const double x1_8 = ld(1, 8);
+    const double x1_9 = ld(1, 9);
+    const double x1_10 = ld(1, 10);
+    const double x1_11 = ld(1, 11);
+    const double x1_12 = ld(1, 12);
+    const double x1_13 = ld(1, 13);
+    const double x1_14 = ld(1, 14);
+    const double x1_15 = ld(1, 15);
+    const double x1_16 = ld(1, 16);
+    const double x1_17 = ld(1, 17);
+    // Gamma(i,j,k) = (0.5 * Sum(l, (Invg(i,l) * ((dg(k,j,l) + dg(j,l,k)) - dg(l,j,k)))))
+    double o0_0 = (0.5 * ((x0_0 * ((x1_0 + x1_0) - x1_0)) + (x0_1 * ((x1_1 + x1_1) - x1_6)) + (x0_2 * ((x1_2 + x1_2) - x1_12))));
+    st(0, 0, o0_0);
+    double o0_1 = (0.5 * ((x0_0 * ((x1_6 + x1_1) - x1_1)) + (x0_1 * ((x1_7 + x1_3) - x1_7)) + (x0_2 * ((x1_8 + x1_4) - x1_13))));
+    st(0, 1, o0_1);
+    double o0_2 = (0.5 * ((x0_0 * ((x1_12 + x1_2) - x1_2)) + (x0_1 * ((x1_13 + x1_4) - x1_8)) + (x0_2 * ((x1_14 + x1_5) - x1_14))));
+    st(0, 2, o0_2);
+    double o0_3 = (0.5 * ((x0_0 * ((x1_7 + x1_7) - x1_3)) + (x0_1 * ((x1_9 + x1_9) - x1_9)) + (x0_2 * ((x1_10 + x1_10) - x1_15))));
+    st(0, 3, o0_3);
+    double o0_4 = (0.5 * ((x0_0 * ((x1_13 + x1_8) - x1_4)) + (x0_1 * ((x1_15 + x1_10) - x1_10)) + (x0_2 * ((x1_16 + x1_11) - x1_16))));
+    st(0, 4, o0_4);
+    double o0_5 = (0.5 * ((x0_0 * ((x1_14 + x1_14) - x1_5)) + (x0_1 * ((x1_16 + x1_16) - x1_11)) + (x0_2 * ((x1_17 + x1_17) - x1_17))));
+    st(0, 5, o0_5);
+    double o0_6 = (0.5 * ((x0_1 * ((x1_0 + x1_0) - x1_0)) + (x0_3 * ((x1_1 + x1_1) - x1_6)) + (x0_4 * ((x1_2 + x1_2) - x1_12))));
+    st(0, 6, o0_6);
+    double o0_7 = (0.5 * ((x0_1 * ((x1_6 + x1_1) - x1_1)) + (x0_3 * ((x1_7 + x1_3) - x1_7)) + (x0_4 * ((x1_8 + x1_4) - x1_13))));
+    st(0, 7, o0_7);
+    double o0_8 = (0.5 * ((x0_1 * ((x1_12 + x1_2) - x1_2)) + (x0_3 * ((x1_13 + x1_4) - x1_8)) + (x0_4 * ((x1_14 + x1_5) - x1_14))));
+    st(0, 8, o0_8);
+    double o0_9 = (0.5 * ((x0_1 * ((x1_7 + x1_7) - x1_3)) + (x0_3 * ((x1_9 + x1_9) - x1_9)) + (x0_4 * ((x1_10 + x1_10) - x1_15))));
+    st(0, 9, o0_9);
+    double o0_10 = (0.5 * ((x0_1 * ((x1_13 + x1_8) - x1_4)) + (x0_3 * ((x1_15 + x1_10) - x1_10)) + (x0_4 * ((x1_16 + x1_11) - x1_16))));
+    st(0, 10, o0_10);
+    double o0_11 = (0.5 * ((x0_1 * ((x1_14 + x1_14) - x1_5)) + (x0_3 * ((x1_16 + x1_16) - x1_11)) + (x0_4 * ((x1_17 + x1_17) - x1_17))));
+    st(0, 11, o0_11);
+    double o0_12 = (0.5 * ((x0_2 * ((x1_0 + x1_0) - x1_0)) + (x0_4 * ((x1_1 + x1_1) - x1_6)) + (x0_5 * ((x1_2 + x1_2) - x1_12))));
+    st(0, 12, o0_12);
+    double o0_13 = (0.5 * ((x0_2 * ((x1_6 + x1_1) - x1_1)) + (x0_4 * ((x1_7 + x1_3) - x1_7)) + (x0_5 * ((x1_8 + x1_4) - x1_13))));
+    st(0, 13, o0_13);
+    double o0_14 = (0.5 * ((x0_2 * ((x1_12 + x1_2) - x1_2)) + (x0_4 * ((x1_13 + x1_4) - x1_8)) + (x0_5 * ((x1_14 + x1_5) - x1_14))));
+    st(0, 14, o0_14);
+    double o0_15 = (0.5 * ((x0_2 * ((x1_7 + x1_7) - x1_3)) + (x0_4 * ((x1_9 + x1_9) - x1_9)) + (x0_5 * ((x1_10 + x1_10) - x1_15))));
+    st(0, 15, o0_15);
+    double o0_16 = (0.5 * ((x0_2 * ((x1_13 + x1_8) - x1_4)) + (x0_4 * ((x1_15 + x1_10) - x1_10)) + (x0_5 * ((x1_16 + x1_11) - x1_16))));
+    st(0, 16, o0_16);
+    double o0_17 = (0.5 * ((x0_2 * ((x1_14 + x1_14) - x1_5)) + (x0_4 * ((x1_16 + x1_16) - x1_11)) + (x0_5 * ((x1_17 + x1_17) - x1_17))));
+    st(0, 17, o0_17);
+  }
+};
+
+// cov_deriv: covariant derivative of the shift (Sec. 1, footnote)
+struct Gen_cov_deriv {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 3, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {9, 18, 3};
+  static constexpr int fout[NF_OUT] = {9};
+  static constexpr int NIN = 30, NOUT = 9;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    const double x0_3 = ld(0, 3);
+    const double x0_4 = ld(0, 4);
+    const double x0_5 = ld(0, 5);
+    const double x0_6 = ld(0, 6);
+    const double x0_7 = ld(0, 7);
+    const double x0_8 = ld(0, 8);
+    const double x1_0 = ld(1, 0);
+    const double x1_1 = ld(1, 1);
+    const double x1_2 = ld(1, 2);
+    const double x1_3 = ld(1, 3);
+    const double x1_4 = ld(1, 4);
+    const double x1_5 = ld(1, 5);
+    const double x1_6 = ld(1, 6);
+    const double x1_7 = ld(1, 7);
+    const double x1_8 = ld(1, 8);
+    const double x1_9 = ld(1, 9);
+    const double x1_10 = ld(1, 10);
+    const double x1_11 = ld(1, 11);
+    const double x1_12 = ld(1, 12);
+    const double x1_13 = ld(1, 13);
+    const double x1_14 = ld(1, 14);
+    const double x1_15 = ld(1, 15);
+    const double x1_16 = ld(1, 16);
+    const double x1_17 = ld(1, 17);
+    const double x2_0 = ld(2, 0);
+    const double x2_1 = ld(2, 1);
+    const double x2_2 = ld(2, 2);
+    // nabla(j,i) = (dbeta(j,i) - Sum(k, (Gamma(k,i,j) * beta(k))))
+    double o0_0 = (x0_0 - ((x1_0 * x2_0) + (x1_6 * x2_1) + (x1_12 * x2_2)));
+    st(0, 0, o0_0);
+    double o0_1 = (x0_1 - ((x1_1 * x2_0) + (x1_7 * x2_1) + (x1_13 * x2_2)));
+    st(0, 1, o0_1);
+    double o0_2 = (x0_2 - ((x1_2 * x2_0) + (x1_8 * x2_1) + (x1_14 * x2_2)));
+    st(0, 2, o0_2);
+    double o0_3 = (x0_3 - ((x1_1 * x2_0) + (x1_7 * x2_1) + (x1_13 * x2_2)));
+    st(0, 3, o0_3);
+    double o0_4 = (x0_4 - ((x1_3 * x2_0) + (x1_9 * x2_1) + (x1_15 * x2_2)));
+    st(0, 4, o0_4);
+    double o0_5 = (x0_5 - ((x1_4 * x2_0) + (x1_10 * x2_1) + (x1_16 * x2_2)));
+    st(0, 5, o0_5);
+    double o0_6 = (x0_6 - ((x1_2 * x2_0) + (x1_8 * x2_1) + (x1_14 * x2_2)));
+    st(0, 6, o0_6);
+    double o0_7 = (x0_7 - ((x1_4 * x2_0) + (x1_10 * x2_1) + (x1_16 * x2_2)));
+    st(0, 7, o0_7);
+    double o0_8 = (x0_8 - ((x1_5 * x2_0) + (x1_11 * x2_1) + (x1_17 * x2_2)));
+    st(0, 8, o0_8);
+  }
+};
+
+// dtg: metric evolution from nabla beta (Sec. 1, eq:dtg_ij)
+struct Gen_dtg {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 3, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {1, 6, 9};
+  static constexpr int fout[NF_OUT] = {6};
+  static constexpr int NIN = 16, NOUT = 6;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x1_0 = ld(1, 0);
+    const double x1_1 = ld(1, 1);
+    const double x1_2 = ld(1, 2);
+    const double x1_3 = ld(1, 3);
+    const double x1_4 = ld(1, 4);
+    const double x1_5 = ld(1, 5);
+    const double x2_0 = ld(2, 0);
+    const double x2_1 = ld(2, 1);
+    const double x2_2 = ld(2, 2);
+    const double x2_3 = ld(2, 3);
+    const double x2_4 = ld(2, 4);
+    const double x2_5 = ld(2, 5);
+    const double x2_6 = ld(2, 6);
+    const double x2_7 = ld(2, 7);
+    const double x2_8 = ld(2, 8);
+    // dtg(i,j) = ((((-2.0 * alpha()) * K(i,j)) + nabla(i,j)) + nabla(j,i))
+    double o0_0 = ((((-2.0 * x0_0) * x1_0) + x2_0) + x2_0);
+    st(0, 0, o0_0);
+    double o0_1 = ((((-2.0 * x0_0) * x1_1) + x2_1) + x2_3);
+    st(0, 1, o0_1);
+    double o0_2 = ((((-2.0 * x0_0) * x1_2) + x2_2) + x2_6);
+    st(0, 2, o0_2);
+    double o0_3 = ((((-2.0 * x0_0) * x1_3) + x2_4) + x2_4);
+    st(0, 3, o0_3);
+    double o0_4 = ((((-2.0 * x0_0) * x1_4) + x2_5) + x2_7);
+    st(0, 4, o0_4);
+    double o0_5 = ((((-2.0 * x0_0) * x1_5) + x2_8) + x2_8);
+    st(0, 5, o0_5);
+  }
+};
+
+// dtg_chain_invg: Christoffel symbols, covariant derivative and metric evolution in one kernel, Gamma and nabla beta in registers (Sec. 1)
+struct Gen_dtg_chain_invg {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 6, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {6, 18, 9, 3, 1, 6};
+  static constexpr int fout[NF_OUT] = {6};
+  static constexpr int NIN = 43, NOUT = 6;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    double t_Gamma[18];
+    double t_nabla[9];
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    const double x0_3 = ld(0, 3);
+    const double x0_4 = ld(0, 4);
+    const double x0_5 = ld(0, 5);
+    const double x1_0 = ld(1, 0);
+    const double x1_1 = ld(1, 1);
+    const double x1_2 = ld(1, 2);
+    const double x1_3 = ld(1, 3);
+    const double x1_4 = ld(1, 4);
+    const double x1_5 = ld(1, 5);
+    const double x1_6 = ld(1, 6);
+    const double x1_7 = ld(1, 7);
+    const double x1_8 = ld(1, 8);
+    const double x1_9 = ld(1, 9);
+    const double x1_10 = ld(1, 10);
+    const double x1_11 = ld(1, 11);
+    const double x1_12 = ld(1, 12);
+    const double x1_13 = ld(1, 13);
+    const double x1_14 = ld(1, 14);
+    const double x1_15 = ld(1, 15);
+    const double x1_16 = ld(1, 16);
+    const double x1_17 = ld(1, 17);
+    const double x2_0 = ld(2, 0);
+    const double x2_1 = ld(2, 1);
+    const double x2_2 = ld(2, 2);
+    const double x2_3 = ld(2, 3);
+    const double x2_4 = ld(2, 4);
+    const double x2_5 = ld(2, 5);
+    const double x2_6 = ld(2, 6);
+    const double x2_7 = ld(2, 7);
+    const double x2_8 = ld(2, 8);
+    const double x3_0 = ld(3, 0);
+    const double x3_1 = ld(3, 1);
+    const double x3_2 = ld(3, 2);
+    const double x4_0 = ld(4, 0);
+    const double x5_0 = ld(5, 0);
+    const double x5_1 = ld(5, 1);
+    const double x5_2 = ld(5, 2);
+    const double x5_3 = ld(5, 3);
+    const double x5_4 = ld(5, 4);
+    const double x5_5 = ld(5, 5);
+    // Gamma(i,j,k) = (0.5 * Sum(l, (Invg(i,l) * ((dg(k,j,l) + dg(j,l,k)) - dg(l,j,k)))))
+    t_Gamma[0] = (0.5 * ((x0_0 * ((x1_0 + x1_0) - x1_0)) + (x0_1 * ((x1_1 + x1_1) - x1_6)) + (x0_2 * ((x1_2 + x1_2) - x1_12))));
+    t_Gamma[1] = (0.5 * ((x0_0 * ((x1_6 + x1_1) - x1_1)) + (x0_1 * ((x1_7 + x1_3) - x1_7)) + (x0_2 * ((x1_8 + x1_4) - x1_13))));
+    t_Gamma[2] = (0.5 * ((x0_0 * ((x1_12 + x1_2) - x1_2)) + (x0_1 * ((x1_13 + x1_4) - x1_8)) + (x0_2 * ((x1_14 + x1_5) - x1_14))));
+    t_Gamma[3] = (0.5 * ((x0_0 * ((x1_7 + x1_7) - x1_3)) + (x0_1 * ((x1_9 + x1_9) - x1_9)) + (x0_2 * ((x1_10 + x1_10) - x1_15))));
+    t_Gamma[4] = (0.5 * ((x0_0 * ((x1_13 + x1_8) - x1_4)) + (x0_1 * ((x1_15 + x1_10) - x1_10)) + (x0_2 * ((x1_16 + x1_11) - x1_16))));
+    t_Gamma[5] = (0.5 * ((x0_0 * ((x1_14 + x1_14) - x1_5)) + (x0_1 * ((x1_16 + x1_16) - x1_11)) + (x0_2 * ((x1_17 + x1_17) - x1_17))));
+    t_Gamma[6] = (0.5 * ((x0_1 * ((x1_0 + x1_0) - x1_0)) + (x0_3 * ((x1_1 + x1_1) - x1_6)) + (x0_4 * ((x1_2 + x1_2) - x1_12))));
+    t_Gamma[7] = (0.5 * ((x0_1 * ((x1_6 + x1_1) - x1_1)) + (x0_3 * ((x1_7 + x1_3) - x1_7)) + (x0_4 * ((x1_8 + x1_4) - x1_13))));
+    t_Gamma[8] = (0.5 * ((x0_1 * ((x1_12 + x1_2) - x1_2)) + (x0_3 * ((x1_13 + x1_4) - x1_8)) + (x0_4 * ((x1_14 + x1_5) - x1_14))));
+    t_Gamma[9] = (0.5 * ((x0_1 * ((x1_7 + x1_7) - x1_3)) + (x0_3 * ((x1_9 + x1_9) - x1_9)) + (x0_4 * ((x1_10 + x1_10) - x1_15))));
+    t_Gamma[10] = (0.5 * ((x0_1 * ((x1_13 + x1_8) - x1_4)) + (x0_3 * ((x1_15 + x1_10) - x1_10)) + (x0_4 * ((x1_16 + x1_11) - x1_16))));
+    t_Gamma[11] = (0.5 * ((x0_1 * ((x1_14 + x1_14) - x1_5)) + (x0_3 * ((x1_16 + x1_16) - x1_11)) + (x0_4 * ((x1_17 + x1_17) - x1_17))));
+    t_Gamma[12] = (0.5 * ((x0_2 * ((x1_0 + x1_0) - x1_0)) + (x0_4 * ((x1_1 + x1_1) - x1_6)) + (x0_5 * ((x1_2 + x1_2) - x1_12))));
+    t_Gamma[13] = (0.5 * ((x0_2 * ((x1_6 + x1_1) - x1_1)) + (x0_4 * ((x1_7 + x1_3) - x1_7)) + (x0_5 * ((x1_8 + x1_4) - x1_13))));
+    t_Gamma[14] = (0.5 * ((x0_2 * ((x1_12 + x1_2) - x1_2)) + (x0_4 * ((x1_13 + x1_4) - x1_8)) + (x0_5 * ((x1_14 + x1_5) - x1_14))));
+    t_Gamma[15] = (0.5 * ((x0_2 * ((x1_7 + x1_7) - x1_3)) + (x0_4 * ((x1_9 + x1_9) - x1_9)) + (x0_5 * ((x1_10 + x1_10) - x1_15))));
+    t_Gamma[16] = (0.5 * ((x0_2 * ((x1_13 + x1_8) - x1_4)) + (x0_4 * ((x1_15 + x1_10) - x1_10)) + (x0_5 * ((x1_16 + x1_11) - x1_16))));
+    t_Gamma[17] = (0.5 * ((x0_2 * ((x1_14 + x1_14) - x1_5)) + (x0_4 * ((x1_16 + x1_16) - x1_11)) + (x0_5 * ((x1_17 + x1_17) - x1_17))));
+    // nabla(j,i) = (dbeta(j,i) - Sum(k, (Gamma(k,i,j) * beta(k))))
+    t_nabla[0] = (x2_0 - ((t_Gamma[0] * x3_0) + (t_Gamma[6] * x3_1) + (t_Gamma[12] * x3_2)));
+    t_nabla[1] = (x2_1 - ((t_Gamma[1] * x3_0) + (t_Gamma[7] * x3_1) + (t_Gamma[13] * x3_2)));
+    t_nabla[2] = (x2_2 - ((t_Gamma[2] * x3_0) + (t_Gamma[8] * x3_1) + (t_Gamma[14] * x3_2)));
+    t_nabla[3] = (x2_3 - ((t_Gamma[1] * x3_0) + (t_Gamma[7] * x3_1) + (t_Gamma[13] * x3_2)));
+    t_nabla[4] = (x2_4 - ((t_Gamma[3] * x3_0) + (t_Gamma[9] * x3_1) + (t_Gamma[15] * x3_2)));
+    t_nabla[5] = (x2_5 - ((t_Gamma[4] * x3_0) + (t_Gamma[10] * x3_1) + (t_Gamma[16] * x3_2)));
+    t_nabla[6] = (x2_6 - ((t_Gamma[2] * x3_0) + (t_Gamma[8] * x3_1) + (t_Gamma[14] * x3_2)));
+    t_nabla[7] = (x2_7 - ((t_Gamma[4] * x3_0) + (t_Gamma[10] * x3_1) + (t_Gamma[16] * x3_2)));
+    t_nabla[8] = (x2_8 - ((t_Gamma[5] * x3_0) + (t_Gamma[11] * x3_1) + (t_Gamma[17] * x3_2)));
+    // dtg(i,j) = ((((-2.0 * alpha()) * K(i,j)) + nabla(i,j)) + nabla(j,i))
+    double o0_0 = ((((-2.0 * x4_0) * x5_0) + t_nabla[0]) + t_nabla[0]);
+    st(0, 0, o0_0);
+    double o0_1 = ((((-2.0 * x4_0) * x5_1) + t_nabla[1]) + t_nabla[3]);
+    st(0, 1, o0_1);
+    double o0_2 = ((((-2.0 * x4_0) * x5_2) + t_nabla[2]) + t_nabla[6]);
+    st(0, 2, o0_2);
+    double o0_3 = ((((-2.0 * x4_0) * x5_3) + t_nabla[4]) + t_nabla[4]);
+    st(0, 3, o0_3);
+    double o0_4 = ((((-2.0 * x4_0) * x5_4) + t_nabla[5]) + t_nabla[7]);
+    st(0, 4, o0_4);
+    double o0_5 = ((((-2.0 * x4_0) * x5_5) + t_nabla[8]) + t_nabla[8]);
+    st(0, 5, o0_5);
+  }
+};
+
+// kij: K_ij = 2 alpha g_ij + beta_i beta_j (Sec. 5.1, eq:Kij)
+struct Gen_kij {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 3, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {1, 6, 3};
+  static constexpr int fout[NF_OUT] = {6};
+  static constexpr int NIN = 10, NOUT = 6;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x1_0 = ld(1, 0);
+    const double x1_1 = ld(1, 1);
+    const double x1_2 = ld(1, 2);
+    const double x1_3 = ld(1, 3);
+    const double x1_4 = ld(1, 4);
+    const double x1_5 = ld(1, 5);
+    const double x2_0 = ld(2, 0);
+    const double x2_1 = ld(2, 1);
+    const double x2_2 = ld(2, 2);
+    // K(i,j) = (((2.0 * alpha()) * g(i,j)) + (beta(i) * beta(j)))
+    double o0_0 = (((2.0 * x0_0) * x1_0) + (x2_0 * x2_0));
+    st(0, 0, o0_0);
+    double o0_1 = (((2.0 * x0_0) * x1_1) + (x2_0 * x2_1));
+    st(0, 1, o0_1);
+    double o0_2 = (((2.0 * x0_0) * x1_2) + (x2_0 * x2_2));
+    st(0, 2, o0_2);
+    double o0_3 = (((2.0 * x0_0) * x1_3) + (x2_1 * x2_1));
+    st(0, 3, o0_3);
+    double o0_4 = (((2.0 * x0_0) * x1_4) + (x2_1 * x2_2));
+    st(0, 4, o0_4);
+    double o0_5 = (((2.0 * x0_0) * x1_5) + (x2_2 * x2_2));
+    st(0, 5, o0_5);
+  }
+};
+
+// contract1: A_ijkl = B_i^m E_mjkl (Sec. 5.1, eq:Contract1)
+struct Gen_contract1 {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 2, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {9, 81};
+  static constexpr int fout[NF_OUT] = {81};
+  static constexpr int NIN = 90, NOUT = 81;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    const double x0_3 = ld(0, 3);
+    const double x0_4 = ld(0, 4);
+    const double x0_5 = ld(0, 5);
+    const double x0_6 = ld(0, 6);
+    const double x0_7 = ld(0, 7);
+    const double x0_8 = ld(0, 8);
+    const double x1_0 = ld(1, 0);
+    const double x1_1 = ld(1, 1);
+    const double x1_2 = ld(1, 2);
+    const double x1_3 = ld(1, 3);
+    const double x1_4 = ld(1, 4);
+    const double x1_5 = ld(1, 5);
+    const double x1_6 = ld(1, 6);
+    const double x1_7 = ld(1, 7);
+    const double x1_8 = ld(1, 8);
+    const double x1_9 = ld(1, 9);
+    const double x1_10 = ld(1, 10);
+    const double x1_11 = ld(1, 11);
+    const double x1_12 = ld(1, 12);
+    const double x1_13 = ld(1, 13);
+    const double x1_14 = ld(1, 14);
+    const double x1_15 = ld(1, 15);
+    const double x1_16 = ld(1, 16);
+    const double x1_17 = ld(1, 17);
+    const double x1_18 = ld(1, 18);
+    const double x1_19 = ld(1, 19);
+    const double x1_20 = ld(1, 20);
+    const double x1_21 = ld(1, 21);
+    const double x1_22 = ld(1, 22);
+    const double x1_23 = ld(1, 23);
+    const double x1_24 = ld(1, 24);
+    const double x1_25 = ld(1, 25);
+    const double x1_26 = ld(1, 26);
+    const double x1_27 = ld(1, 27);
+    const double x1_28 = ld(1, 28);
+    const double x1_29 = ld(1, 29);
+    const double x1_30 = ld(1, 30);
+    const double x1_31 = ld(1, 31);
+    const double x1_32 = ld(1, 32);
+    const double x1_33 = ld(1, 33);
+    const double x1_34 = ld(1, 34);
+    const double x1_35 = ld(1, 35);
+    const double x1_36 = ld(1, 36);
+    const double x1_37 = ld(1, 37);
+    const double x1_38 = ld(1, 38);
+    const double x1_39 = ld(1, 39);
+    const double x1_40 = ld(1, 40);
+    const double x1_41 = ld(1, 41);
+    const double x1_42 = ld(1, 42);
+    const double x1_43 = ld(1, 43);
+    const double x1_44 = ld(1, 44);
+    const double x1_45 = ld(1, 45);
+    const double x1_46 = ld(1, 46);
+    const double x1_47 = ld(1, 47);
+    const double x1_48 = ld(1, 48);
+    const double x1_49 = ld(1, 49);
+    const double x1_50 = ld(1, 50);
+    const double x1_51 = ld(1, 51);
+    const double x1_52 = ld(1, 52);
+    const double x1_53 = ld(1, 53);
+    const double x1_54 = ld(1, 54);
+    const double x1_55 = ld(1, 55);
+    const double x1_56 = ld(1, 56);
+    const double x1_57 = ld(1, 57);
+    const double x1_58 = ld(1, 58);
+    const double x1_59 = ld(1, 59);
+    const double x1_60 = ld(1, 60);
+    const double x1_61 = ld(1, 61);
+    const double x1_62 = ld(1, 62);
+    const double x1_63 = ld(1, 63);
+    const double x1_64 = ld(1, 64);
+    const double x1_65 = ld(1, 65);
+    const double x1_66 = ld(1, 66);
+    const double x1_67 = ld(1, 67);
+    const double x1_68 = ld(1, 68);
+    const double x1_69 = ld(1, 69);
+    const double x1_70 = ld(1, 70);
+    const double x1_71 = ld(1, 71);
+    const double x1_72 = ld(1, 72);
+    const double x1_73 = ld(1, 73);
+    const double x1_74 = ld(1, 74);
+    const double x1_75 = ld(1, 75);
+    const double x1_76 = ld(1, 76);
+    const double x1_77 = ld(1, 77);
+    const double x1_78 = ld(1, 78);
+    const double x1_79 = ld(1, 79);
+    const double x1_80 = ld(1, 80);
+    // A(i,j,k,l) = Sum(m, (B(i,m) * E(m,j,k,l)))
+    double o0_0 = ((x0_0 * x1_0) + (x0_1 * x1_27) + (x0_2 * x1_54));
+    st(0, 0, o0_0);
+    double o0_1 = ((x0_0 * x1_1) + (x0_1 * x1_28) + (x0_2 * x1_55));
+    st(0, 1, o0_1);
+    double o0_2 = ((x0_0 * x1_2) + (x0_1 * x1_29) + (x0_2 * x1_56));
+    st(0, 2, o0_2);
+    double o0_3 = ((x0_0 * x1_3) + (x0_1 * x1_30) + (x0_2 * x1_57));
+    st(0, 3, o0_3);
+    double o0_4 = ((x0_0 * x1_4) + (x0_1 * x1_31) + (x0_2 * x1_58));
+    st(0, 4, o0_4);
+    double o0_5 = ((x0_0 * x1_5) + (x0_1 * x1_32) + (x0_2 * x1_59));
+    st(0, 5, o0_5);
+    double o0_6 = ((x0_0 * x1_6) + (x0_1 * x1_33) + (x0_2 * x1_60));
+    st(0, 6, o0_6);
+    double o0_7 = ((x0_0 * x1_7) + (x0_1 * x1_34) + (x0_2 * x1_61));
+    st(0, 7, o0_7);
+    double o0_8 = ((x0_0 * x1_8) + (x0_1 * x1_35) + (x0_2 * x1_62));
+    st(0, 8, o0_8);
+    double o0_9 = ((x0_0 * x1_9) + (x0_1 * x1_36) + (x0_2 * x1_63));
+    st(0, 9, o0_9);
+    double o0_10 = ((x0_0 * x1_10) + (x0_1 * x1_37) + (x0_2 * x1_64));
+    st(0, 10, o0_10);
+    double o0_11 = ((x0_0 * x1_11) + (x0_1 * x1_38) + (x0_2 * x1_65));
+    st(0, 11, o0_11);
+    double o0_12 = ((x0_0 * x1_12) + (x0_1 * x1_39) + (x0_2 * x1_66));
+    st(0, 12, o0_12);
+    double o0_13 = ((x0_0 * x1_13) + (x0_1 * x1_40) + (x0_2 * x1_67));
+    st(0, 13, o0_13);
+    double o0_14 = ((x0_0 * x1_14) + (x0_1 * x1_41) + (x0_2 * x1_68));
+    st(0, 14, o0_14);
+    double o0_15 = ((x0_0 * x1_15) + (x0_1 * x1_42) + (x0_2 * x1_69));
+    st(0, 15, o0_15);
+    double o0_16 = ((x0_0 * x1_16) + (x0_1 * x1_43) + (x0_2 * x1_70));
+    st(0, 16, o0_16);
+    double o0_17 = ((x0_0 * x1_17) + (x0_1 * x1_44) + (x0_2 * x1_71));
+    st(0, 17, o0_17);
+    double o0_18 = ((x0_0 * x1_18) + (x0_1 * x1_45) + (x0_2 * x1_72));
+    st(0, 18, o0_18);
+    double o0_19 = ((x0_0 * x1_19) + (x0_1 * x1_46) + (x0_2 * x1_73));
+    st(0, 19, o0_19);
+    double o0_20 = ((x0_0 * x1_20) + (x0_1 * x1_47) + (x0_2 * x1_74));
+    st(0, 20, o0_20);
+    double o0_21 = ((x0_0 * x1_21) + (x0_1 * x1_48) + (x0_2 * x1_75));
+    st(0, 21, o0_21);
+    double o0_22 = ((x0_0 * x1_22) + (x0_1 * x1_49) + (x0_2 * x1_76));
+    st(0, 22, o0_22);
+    double o0_23 = ((x0_0 * x1_23) + (x0_1 * x1_50) + (x0_2 * x1_77));
+    st(0, 23, o0_23);
+    double o0_24 = ((x0_0 * x1_24) + (x0_1 * x1_51) + (x0_2 * x1_78));
+    st(0, 24, o0_24);
+    double o0_25 = ((x0_0 * x1_25) + (x0_1 * x1_52) + (x0_2 * x1_79));
+    st(0, 25, o0_25);
+    double o0_26 = ((x0_0 * x1_26) + (x0_1 * x1_53) + (x0_2 * x1_80));
+    st(0, 26, o0_26);
+    double o0_27 = ((x0_3 * x1_0) + (x0_4 * x1_27) + (x0_5 * x1_54));
+    st(0, 27, o0_27);
+    double o0_28 = ((x0_3 * x1_1) + (x0_4 * x1_28) + (x0_5 * x1_55));
+    st(0, 28, o0_28);
+    double o0_29 = ((x0_3 * x1_2) + (x0_4 * x1_29) + (x0_5 * x1_56));
+    st(0, 29, o0_29);
+    double o0_30 = ((x0_3 * x1_3) + (x0_4 * x1_30) + (x0_5 * x1_57));
+    st(0, 30, o0_30);
+    double o0_31 = ((x0_3 * x1_4) + (x0_4 * x1_31) + (x0_5 * x1_58));
+    st(0, 31, o0_31);
+    double o0_32 = ((x0_3 * x1_5) + (x0_4 * x1_32) + (x0_5 * x1_59));
+    st(0, 32, o0_32);
+    double o0_33 = ((x0_3 * x1_6) + (x0_4 * x1_33) + (x0_5 * x1_60));
+    st(0, 33, o0_33);
+    double o0_34 = ((x0_3 * x1_7) + (x0_4 * x1_34) + (x0_5 * x1_61));
+    st(0, 34, o0_34);
+    double o0_35 = ((x0_3 * x1_8) + (x0_4 * x1_35) + (x0_5 * x1_62));
+    st(0, 35, o0_35);
+    double o0_36 = ((x0_3 * x1_9) + (x0_4 * x1_36) + (x0_5 * x1_63));
+    st(0, 36, o0_36);
+    double o0_37 = ((x0_3 * x1_10) + (x0_4 * x1_37) + (x0_5 * x1_64));
+    st(0, 37, o0_37);
+    double o0_38 = ((x0_3 * x1_11) + (x0_4 * x1_38) + (x0_5 * x1_65));
+    st(0, 38, o0_38);
+    double o0_39 = ((x0_3 * x1_12) + (x0_4 * x1_39) + (x0_5 * x1_66));
+    st(0, 39, o0_39);
+    double o0_40 = ((x0_3 * x1_13) + (x0_4 * x1_40) + (x0_5 * x1_67));
+    st(0, 40, o0_40);
+    double o0_41 = ((x0_3 * x1_14) + (x0_4 * x1_41) + (x0_5 * x1_68));
+    st(0, 41, o0_41);
+    double o0_42 = ((x0_3 * x1_15) + (x0_4 * x1_42) + (x0_5 * x1_69));
+    st(0, 42, o0_42);
+    double o0_43 = ((x0_3 * x1_16) + (x0_4 * x1_43) + (x0_5 * x1_70));
+    st(0, 43, o0_43);
+    double o0_44 = ((x0_3 * x1_17) + (x0_4 * x1_44) + (x0_5 * x1_71));
+    st(0, 44, o0_44);
+    double o0_45 = ((x0_3 * x1_18) + (x0_4 * x1_45) + (x0_5 * x1_72));
+    st(0, 45, o0_45);
+    double o0_46 = ((x0_3 * x1_19) + (x0_4 * x1_46) + (x0_5 * x1_73));
+    st(0, 46, o0_46);
+    double o0_47 = ((x0_3 * x1_20) + (x0_4 * x1_47) + (x0_5 * x1_74));
+    st(0, 47, o0_47);
+    double o0_48 = ((x0_3 * x1_21) + (x0_4 * x1_48) + (x0_5 * x1_75));
+    st(0, 48, o0_48);
+    double o0_49 = ((x0_3 * x1_22) + (x0_4 * x1_49) + (x0_5 * x1_76));
+    st(0, 49, o0_49);
+    double o0_50 = ((x0_3 * x1_23) + (x0_4 * x1_50) + (x0_5 * x1_77));
+    st(0, 50, o0_50);
+    double o0_51 = ((x0_3 * x1_24) + (x0_4 * x1_51) + (x0_5 * x1_78));
+    st(0, 51, o0_51);
+    double o0_52 = ((x0_3 * x1_25) + (x0_4 * x1_52) + (x0_5 * x1_79));
+    st(0, 52, o0_52);
+    double o0_53 = ((x0_3 * x1_26) + (x0_4 * x1_53) + (x0_5 * x1_80));
+    st(0, 53, o0_53);
+    double o0_54 = ((x0_6 * x1_0) + (x0_7 * x1_27) + (x0_8 * x1_54));
+    st(0, 54, o0_54);
+    double o0_55 = ((x0_6 * x1_1) + (x0_7 * x1_28) + (x0_8 * x1_55));
+    st(0, 55, o0_55);
+    double o0_56 = ((x0_6 * x1_2) + (x0_7 * x1_29) + (x0_8 * x1_56));
+    st(0, 56, o0_56);
+    double o0_57 = ((x0_6 * x1_3) + (x0_7 * x1_30) + (x0_8 * x1_57));
+    st(0, 57, o0_57);
+    double o0_58 = ((x0_6 * x1_4) + (x0_7 * x1_31) + (x0_8 * x1_58));
+    st(0, 58, o0_58);
+    double o0_59 = ((x0_6 * x1_5) + (x0_7 * x1_32) + (x0_8 * x1_59));
+    st(0, 59, o0_59);
+    double o0_60 = ((x0_6 * x1_6) + (x0_7 * x1_33) + (x0_8 * x1_60));
+    st(0, 60, o0_60);
+    double o0_61 = ((x0_6 * x1_7) + (x0_7 * x1_34) + (x0_8 * x1_61));
+    st(0, 61, o0_61);
+    double o0_62 = ((x0_6 * x1_8) + (x0_7 * x1_35) + (x0_8 * x1_62));
+    st(0, 62, o0_62);
+    double o0_63 = ((x0_6 * x1_9) + (x0_7 * x1_36) + (x0_8 * x1_63));
+    st(0, 63, o0_63);
+    double o0_64 = ((x0_6 * x1_10) + (x0_7 * x1_37) + (x0_8 * x1_64));
+    st(0, 64, o0_64);
+    double o0_65 = ((x0_6 * x1_11) + (x0_7 * x1_38) + (x0_8 * x1_65));
+    st(0, 65, o0_65);
+    double o0_66 = ((x0_6 * x1_12) + (x0_7 * x1_39) + (x0_8 * x1_66));
+    st(0, 66, o0_66);
+    double o0_67 = ((x0_6 * x1_13) + (x0_7 * x1_40) + (x0_8 * x1_67));
+    st(0, 67, o0_67);
+    double o0_68 = ((x0_6 * x1_14) + (x0_7 * x1_41) + (x0_8 * x1_68));
+    st(0, 68, o0_68);
+    double o0_69 = ((x0_6 * x1_15) + (x0_7 * x1_42) + (x0_8 * x1_69));
+    st(0, 69, o0_69);
+    double o0_70 = ((x0_6 * x1_16) + (x0_7 * x1_43) + (x0_8 * x1_70));
+    st(0, 70, o0_70);
+    double o0_71 = ((x0_6 * x1_17) + (x0_7 * x1_44) + (x0_8 * x1_71));
+    st(0, 71, o0_71);
+    double o0_72 = ((x0_6 * x1_18) + (x0_7 * x1_45) + (x0_8 * x1_72));
+    st(0, 72, o0_72);
+    double o0_73 = ((x0_6 * x1_19) + (x0_7 * x1_46) + (x0_8 * x1_73));
+    st(0, 73, o0_73);
+    double o0_74 = ((x0_6 * x1_20) + (x0_7 * x1_47) + (x0_8 * x1_74));
+    st(0, 74, o0_74);
+    double o0_75 = ((x0_6 * x1_21) + (x0_7 * x1_48) + (x0_8 * x1_75));
+    st(0, 75, o0_75);
+    double o0_76 = ((x0_6 * x1_22) + (x0_7 * x1_49) + (x0_8 * x1_76));
+    st(0, 76, o0_76);
+    double o0_77 = ((x0_6 * x1_23) + (x0_7 * x1_50) + (x0_8 * x1_77));
+    st(0, 77, o0_77);
+    double o0_78 = ((x0_6 * x1_24) + (x0_7 * x1_51) + (x0_8 * x1_78));
+    st(0, 78, o0_78);
+    double o0_79 = ((x0_6 * x1_25) + (x0_7 * x1_52) + (x0_8 * x1_79));
+    st(0, 79, o0_79);
+    double o0_80 = ((x0_6 * x1_26) + (x0_7 * x1_53) + (x0_8 * x1_80));
+    st(0, 80, o0_80);
+  }
+};
+
+// lst_sym_contract: C_(ab) = sum_c A_ac B_cb, symmetric left-hand side (Sec. 4, rank 2 contraction example)
+struct Gen_lst_sym_contract {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 2, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {16, 16};
+  static constexpr int fout[NF_OUT] = {10};
+  static constexpr int NIN = 32, NOUT = 10;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    const double x0_3 = ld(0, 3);
+    const double x0_4 = ld(0, 4);
+    const double x0_5 = ld(0, 5);
+    const double x0_6 = ld(0, 6);
+    const double x0_7 = ld(0, 7);
+    const double x0_8 = ld(0, 8);
+    const double x0_9 = ld(0, 9);
+    const double x0_10 = ld(0, 10);
+    const double x0_11 = ld(0, 11);
+    const double x0_12 = ld(0, 12);
+    const double x0_13 = ld(0, 13);
+    const double x0_14 = ld(0, 14);
+    const double x0_15 = ld(0, 15);
+    const double x1_0 = ld(1, 0);
+    const double x1_1 = ld(1, 1);
+    const double x1_2 = ld(1, 2);
+    const double x1_3 = ld(1, 3);
+    const double x1_4 = ld(1, 4);
+    const double x1_5 = ld(1, 5);
+    const double x1_6 = ld(1, 6);
+    const double x1_7 = ld(1, 7);
+    const double x1_8 = ld(1, 8);
+    const double x1_9 = ld(1, 9);
+    const double x1_10 = ld(1, 10);
+    const double x1_11 = ld(1, 11);
+    const double x1_12 = ld(1, 12);
+    const double x1_13 = ld(1, 13);
+    const double x1_14 = ld(1, 14);
+    const double x1_15 = ld(1, 15);
+    // C(a,b) = Sum(c, (A(a,c) * B(c,b)))
+    double o0_0 = ((x0_0 * x1_0) + (x0_1 * x1_4) + (x0_2 * x1_8) + (x0_3 * x1_12));
+    st(0, 0, o0_0);
+    double o0_1 = ((x0_0 * x1_1) + (x0_1 * x1_5) + (x0_2 * x1_9) + (x0_3 * x1_13));
+    st(0, 1, o0_1);
+    double o0_2 = ((x0_0 * x1_2) + (x0_1 * x1_6) + (x0_2 * x1_10) + (x0_3 * x1_14));
+    st(0, 2, o0_2);
+    double o0_3 = ((x0_0 * x1_3) + (x0_1 * x1_7) + (x0_2 * x1_11) + (x0_3 * x1_15));
+    st(0, 3, o0_3);
+    double o0_4 = ((x0_4 * x1_1) + (x0_5 * x1_5) + (x0_6 * x1_9) + (x0_7 * x1_13));
+    st(0, 4, o0_4);
+    double o0_5 = ((x0_4 * x1_2) + (x0_5 * x1_6) + (x0_6 * x1_10) + (x0_7 * x1_14));
+    st(0, 5, o0_5);
+    double o0_6 = ((x0_4 * x1_3) + (x0_5 * x1_7) + (x0_6 * x1_11) + (x0_7 * x1_15));
+    st(0, 6, o0_6);
+    double o0_7 = ((x0_8 * x1_2) + (x0_9 * x1_6) + (x0_10 * x1_10) + (x0_11 * x1_14));
+    st(0, 7, o0_7);
+    double o0_8 = ((x0_8 * x1_3) + (x0_9 * x1_7) + (x0_10 * x1_11) + (x0_11 * x1_15));
+    st(0, 8, o0_8);
+    double o0_9 = ((x0_12 * x1_3) + (x0_13 * x1_7) + (x0_14 * x1_11) + (x0_15 * x1_15));
+    st(0, 9, o0_9);
+  }
+};
+
+// lst_fixed_offset: D_(i0) = sum_c E_(i+1)c F_c0, fixed and offset indices (Sec. 4, second contraction example)
+struct Gen_lst_fixed_offset {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 2, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {16, 16};
+  static constexpr int fout[NF_OUT] = {10};
+  static constexpr int NIN = 32, NOUT = 10;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_4 = ld(0, 4);
+    const double x0_5 = ld(0, 5);
+    const double x0_6 = ld(0, 6);
+    const double x0_7 = ld(0, 7);
+    const double x0_8 = ld(0, 8);
+    const double x0_9 = ld(0, 9);
+    const double x0_10 = ld(0, 10);
+    const double x0_11 = ld(0, 11);
+    const double x0_12 = ld(0, 12);
+    const double x0_13 = ld(0, 13);
+    const double x0_14 = ld(0, 14);
+    const double x0_15 = ld(0, 15);
+    const double x1_0 = ld(1, 0);
+    const double x1_4 = ld(1, 4);
+    const double x1_8 = ld(1, 8);
+    const double x1_12 = ld(1, 12);
+    // D(i,0) = Sum(c, (E(i+1,c) * F(c,0)))
+    double o0_0 = ((x0_4 * x1_0) + (x0_5 * x1_4) + (x0_6 * x1_8) + (x0_7 * x1_12));
+    st(0, 0, o0_0);
+    double o0_1 = ((x0_8 * x1_0) + (x0_9 * x1_4) + (x0_10 * x1_8) + (x0_11 * x1_12));
+    st(0, 1, o0_1);
+    double o0_2 = ((x0_12 * x1_0) + (x0_13 * x1_4) + (x0_14 * x1_8) + (x0_15 * x1_12));
+    st(0, 2, o0_2);
+  }
+};
+
+// spacetime_split: spatial metric and shift from the spacetime metric psi_ab (Sec. 2.2)
+struct Gen_spacetime_split {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 1, NF_OUT = 2;
+  static constexpr int fin[NF_IN] = {10};
+  static constexpr int fout[NF_OUT] = {6, 3};
+  static constexpr int NIN = 10, NOUT = 9;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    const double x0_3 = ld(0, 3);
+    const double x0_4 = ld(0, 4);
+    const double x0_5 = ld(0, 5);
+    const double x0_6 = ld(0, 6);
+    const double x0_7 = ld(0, 7);
+    const double x0_8 = ld(0, 8);
+    const double x0_9 = ld(0, 9);
+    // g(i,j) = psi(i+1,j+1)
+    double o0_0 = x0_4;
+    st(0, 0, o0_0);
+    double o0_1 = x0_5;
+    st(0, 1, o0_1);
+    double o0_2 = x0_6;
+    st(0, 2, o0_2);
+    double o0_3 = x0_7;
+    st(0, 3, o0_3);
+    double o0_4 = x0_8;
+    st(0, 4, o0_4);
+    double o0_5 = x0_9;
+    st(0, 5, o0_5);
+    // beta(i) = psi(i+1,0)
+    double o1_0 = x0_1;
+    st(1, 0, o1_0);
+    double o1_1 = x0_2;
+    st(1, 1, o1_1);
+    double o1_2 = x0_3;
+    st(1, 2, o1_2);
+  }
+};
+
+}  // namespace tl
+
+extern "C" {
+
+tl_status tlg_christoffel(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {6, 18};
+  static const int32_t kOut[] = {18};
+  return tl::run_generated("christoffel", n, in, nin, kIn, 2, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_christoffel>);
+}
+
+tl_status tlg_cov_deriv(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {9, 18, 3};
+  static const int32_t kOut[] = {9};
+  return tl::run_generated("cov_deriv", n, in, nin, kIn, 3, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_cov_deriv>);
+}
+
+tl_status tlg_dtg(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {1, 6, 9};
+  static const int32_t kOut[] = {6};
+  return tl::run_generated("dtg", n, in, nin, kIn, 3, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_dtg>);
+}
+
+tl_status tlg_dtg_chain_invg(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {6, 18, 9, 3, 1, 6};
+  static const int32_t kOut[] = {6};
+  return tl::run_generated("dtg_chain_invg", n, in, nin, kIn, 6, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_dtg_chain_invg>);
+}
+
+tl_status tlg_kij(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {1, 6, 3};
+  static const int32_t kOut[] = {6};
+  return tl::run_generated("kij", n, in, nin, kIn, 3, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_kij>);
+}
+
+tl_status tlg_contract1(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {9, 81};
+  static const int32_t kOut[] = {81};
+  return tl::run_generated("contract1", n, in, nin, kIn, 2, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_contract1>);
+}
+
+tl_status tlg_lst_sym_contract(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {16, 16};
+  static const int32_t kOut[] = {10};
+  return tl::run_generated("lst_sym_contract", n, in, nin, kIn, 2, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_lst_sym_contract>);
+}
+
+tl_status tlg_lst_fixed_offset(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {16, 16};
+  static const int32_t kOut[] = {10};
+  return tl::run_generated("lst_fixed_offset", n, in, nin, kIn, 2, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_lst_fixed_offset>);
+}
+
+tl_status tlg_spacetime_split(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {10};
+  static const int32_t kOut[] = {6, 3};
+  return tl::run_generated("spacetime_split", n, in, nin, kIn, 1, out, nout, kOut,
+                           2, stream, tune, &tl::launch_op<tl::Gen_spacetime_split>);
+}
+
+}  // extern "C"

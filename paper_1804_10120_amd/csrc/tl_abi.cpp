@@ -200,6 +200,42 @@ struct tl_batch_plan {
   hipGraphExec_t exec = nullptr;
 };
 
+namespace tl {
+
+tl_status run_generated(const char* name, int64_t n, const tl_cfield* in, int32_t nin,
+                        const int32_t* in_ncomp, int32_t nin_expected, const tl_field* out,
+                        int32_t nout, const int32_t* out_ncomp, int32_t nout_expected,
+                        void* stream, const tl_tune* tune, LaunchFn launch) {
+  if (nin != nin_expected || nout != nout_expected)
+    return fail(TL_ERR_INVALID, "%s takes %d inputs and %d outputs, got %d and %d", name,
+                nin_expected, nout_expected, nin, nout);
+  if (nin > kMaxFields || nout > kMaxFields)
+    return fail(TL_ERR_INVALID, "%s: more than %d fields", name, kMaxFields);
+  if (n < 0) return fail(TL_ERR_SIZE, "n=%lld < 0", (long long)n);
+  if (n == 0) return TL_OK;
+  if (in == nullptr || out == nullptr) return fail(TL_ERR_NULL, "in or out is NULL");
+  static const char* const in_names[kMaxFields] = {"in[0]", "in[1]", "in[2]", "in[3]",
+                                                   "in[4]", "in[5]", "in[6]", "in[7]"};
+  static const char* const out_names[kMaxFields] = {"out[0]", "out[1]", "out[2]", "out[3]",
+                                                    "out[4]", "out[5]", "out[6]", "out[7]"};
+  Checker c(n);
+  for (int f = 0; f < nin; ++f) c.field(in_names[f], in[f].ptr, in[f].ld, in_ncomp[f], false);
+  for (int f = 0; f < nout; ++f)
+    c.field(out_names[f], out[f].ptr, out[f].ld, out_ncomp[f], true);
+  if (c.overlaps() != TL_OK) return c.st;
+  KArgs a = zero_args();
+  for (int f = 0; f < nin; ++f) set_in(a, f, in[f]);
+  for (int f = 0; f < nout; ++f) set_out(a, f, out[f]);
+  Resolved r;
+  tl_status s = resolve(KernelId::Chain, tune, c.vec_ok, n, &r);
+  if (s != TL_OK) return s;
+  hipError_t e = launch(r, a, n, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "generated kernel launch");
+  return TL_OK;
+}
+
+}  // namespace tl
+
 extern "C" {
 
 int tl_abi_version(void) { return TL_ABI_VERSION; }

@@ -6,7 +6,7 @@
 // as B[i*3+m]; K_ij and g_ij are symmetric (s(i,j)).  Inputs are the
 // right-hand-side tensors in the order they are written; the output is the
 // left-hand side.  Bodies with 81 outputs are streaming bodies (kStream): they
-// get a loader ld(field, component) and a storer st(component, value) and
+// get a loader ld(field, component) and a storer st(field, component, value) and
 // interleave loads, arithmetic and stores in program order, so that only one
 // group of outputs is live at a time.
 #pragma once
@@ -98,7 +98,7 @@ struct OpMult4 {
         for (int k = 0; k < 3; ++k) {
           const double bcd = bc * D[k];
 #pragma unroll
-          for (int l = 0; l < 3; ++l) st(((i * 3 + j) * 3 + k) * 3 + l, bcd * E[l]);
+          for (int l = 0; l < 3; ++l) st(0, ((i * 3 + j) * 3 + k) * 3 + l, bcd * E[l]);
         }
       }
   }
@@ -158,7 +158,7 @@ struct OpContract {
                          e2 = ld(fE, e(2, j, k, l));
 #pragma unroll
             for (int i = 0; i < 3; ++i)
-              st(e(i, j, k, l), B[i * 3 + 0] * e0 + B[i * 3 + 1] * e1 + B[i * 3 + 2] * e2);
+              st(0, e(i, j, k, l), B[i * 3 + 0] * e0 + B[i * 3 + 1] * e1 + B[i * 3 + 2] * e2);
           }
     } else {
       constexpr int fC = M - 2;
@@ -179,7 +179,7 @@ struct OpContract {
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
-              for (int j = 0; j < 3; ++j) st(e(i, j, k, l), Y[i * 3 + j]);
+              for (int j = 0; j < 3; ++j) st(0, e(i, j, k, l), Y[i * 3 + j]);
           }
       } else {
         double D[9];
@@ -201,7 +201,7 @@ struct OpContract {
           for (int k = 0; k < 3; ++k)
 #pragma unroll
             for (int q = 0; q < 9; ++q)
-              st(e(q / 3, q % 3, k, l),
+              st(0, e(q / 3, q % 3, k, l),
                  D[k * 3 + 0] * Mo[0][q] + D[k * 3 + 1] * Mo[1][q] + D[k * 3 + 2] * Mo[2][q]);
         }
       }

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "../../include/tl.h"
+
 namespace tl {
 
 constexpr int kMaxFields = 8;
@@ -59,6 +61,14 @@ const void* kernel_address(KernelId k, const Resolved& r);
 // The benchmark expressions (ids as in tl_expr_id of tl.h).
 hipError_t launch_expr(int id, const Resolved& r, const KArgs& a, int64_t n, hipStream_t s);
 const void* expr_address(int id, const Resolved& r);
+// Validation, tuning and launch for a generated entry point: nin/nout and
+// the fields' component counts are checked against the expected ones.
+typedef hipError_t (*LaunchFn)(const Resolved&, const KArgs&, int64_t, hipStream_t);
+tl_status run_generated(const char* name, int64_t n, const tl_cfield* in, int32_t nin,
+                        const int32_t* in_ncomp, int32_t nin_expected, const tl_field* out,
+                        int32_t nout, const int32_t* out_ncomp, int32_t nout_expected,
+                        void* stream, const tl_tune* tune, LaunchFn launch);
+
 hipError_t launch_batched(const Resolved& r, const BatchDomain* doms, const int64_t* start,
                           const int32_t* tile_dom, int64_t ntiles, int64_t grid, int64_t chunk,
                           hipStream_t s);

@@ -11,9 +11,10 @@
 // stores) and the order in which tiles meet the memory system (XCD order).
 //
 // A body with more outputs than registers comfortably hold (kStream) is
-// instead given a loader and a storer and interleaves its own loads, math and
-// stores in program order, one point per lane; stores are never moved above
-// later loads, so only one group of outputs is live at a time.
+// instead given a loader ld(field, component) and a storer st(field,
+// component, value) and interleaves its own loads, math and stores in program
+// order, one point per lane; stores are never moved above later loads, so
+// only one group of outputs is live at a time.
 //
 // A tile is BLOCK*PPT consecutive points; a block walks tiles
 // logical_block, logical_block + gridDim.x, ... so the same kernel serves a
@@ -82,7 +83,7 @@ struct is_stream<Op, std::void_t<decltype(Op::kStream)>> : std::bool_constant<Op
 template <class Op, bool NT>
 __device__ inline void point_stream(const KArgs& a, int64_t p) {
   Op::stream([&](int f, int c) { return load1<NT>(a.in[f] + c * a.ldin[f] + p); },
-             [&](int c, double v) { store1<NT>(a.out[0] + c * a.ldout[0] + p, v); });
+             [&](int f, int c, double v) { store1<NT>(a.out[f] + c * a.ldout[f] + p, v); });
 }
 
 // Points p .. p+PPT-1 of one tile, all in range.

@@ -1,0 +1,110 @@
+"""The index-notation code generator on the CPU: index rules, storage layouts,
+element counts against the paper's printed examples, and freshness of the
+committed generated files."""
+import json
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+from paper_1804_10120_amd.codegen import CodegenError, Program, Sum, Tensor, indices
+from paper_1804_10120_amd.codegen import registry
+from paper_1804_10120_amd.codegen.__main__ import FILES
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden", "bweff_examples.txt")
+
+
+def golden():
+    out = {}
+    for line in open(GOLDEN):
+        if line.strip() and not line.startswith("#"):
+            name, ne = line.split()[:2]
+            out[name] = int(ne)
+    return out
+
+
+def test_element_counts_match_the_papers_examples():
+    progs = {p.name: p for p in registry.programs()}
+    for name, ne in golden().items():
+        assert progs[name].elements() == ne, name
+
+
+def test_other_element_counts():
+    progs = {p.name: p for p in registry.programs()}
+    # the hand-written rows' byte counts: 42, 39, 22, 49 doubles per point
+    assert progs["christoffel"].elements() == 42
+    assert progs["cov_deriv"].elements() == 39
+    assert progs["dtg"].elements() == 22
+    assert progs["dtg_chain_invg"].elements() == 49
+
+
+def test_layouts_match_the_library_conventions():
+    g = Tensor("g", (3, 3), sym=[(0, 1)])
+    assert g.components == [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    assert g.comp((2, 1)) == g.comp((1, 2)) == 4
+    dg = Tensor("dg", (3, 3, 3), sym=[(1, 2)])
+    for k in range(3):
+        for i in range(3):
+            for j in range(3):
+                assert dg.comp((k, i, j)) == k * 6 + g.comp((i, j))
+    db = Tensor("db", (3, 3))
+    assert db.comp((2, 1)) == 2 * 3 + 1
+    psi = Tensor("psi", (4, 4), sym=[(0, 1)])
+    assert psi.ncomp == 10 and psi.comp((3, 0)) == 3 and psi.comp((1, 1)) == 4
+
+
+def test_index_rules():
+    i, j, k = indices("i j k")
+    a, = indices("a", 4)
+    A, B = Tensor("A", (3, 3)), Tensor("B", (3, 3))
+    v = Tensor("v", (3,))
+    with pytest.raises(CodegenError, match="repeats outside a Sum"):
+        Program("p").let(A[i, k], A[i, j] * B[j, k])
+    with pytest.raises(CodegenError, match="different free indices"):
+        Program("p").let(A[i, j], A[i, j] + v[i])
+    with pytest.raises(CodegenError, match="does not appear"):
+        Sum(k, v[i]).free()
+    with pytest.raises(CodegenError, match="leaves"):
+        A[i + 1, j]
+    with pytest.raises(CodegenError, match="ranges over 4"):
+        v[a]
+    with pytest.raises(CodegenError, match="differ from"):
+        Program("p").let(A[i, j], B[i, k])
+    p = Program("p").temp(B).let(A[i, j], B[i, j])
+    with pytest.raises(CodegenError, match="read before"):
+        p.check()
+    assert Program("ok").let(A[i, k], Sum(j, A[i, j] * B[j, k])).statements
+
+
+def test_symmetric_lhs_written_once_per_component():
+    i, j = indices("i j")
+    S, M = Tensor("S", (3, 3), sym=[(0, 1)]), Tensor("M", (3, 3))
+    st = Program("p").let(S[i, j], M[i, j]).statements[0]
+    tuples = [tuple(env[x] for x in (i, j)) for _, env in st.assignments()]
+    assert tuples == [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+
+
+def test_committed_generated_files_are_fresh():
+    r = subprocess.run([sys.executable, "-m", "paper_1804_10120_amd.codegen", "--check"],
+                       cwd=ROOT, capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+
+
+def test_generated_entry_points_are_exported_and_validate():
+    import ctypes
+    from paper_1804_10120_amd import _abi, generated
+    L = _abi.lib()
+    hdr = open(FILES["header"]).read()
+    declared = set(re.findall(r"\b(tlg_[a-z_0-9]+)\s*\(", hdr))
+    assert declared == {f"tlg_{n}" for n in generated.programs()}
+    for name in declared:
+        assert hasattr(L, name)
+    fn = generated._fn("christoffel")
+    cin = (_abi.CField * 1)(_abi.CField(1 << 40, 8))
+    cout = (_abi.Field * 1)(_abi.Field((1 << 40) + (1 << 20), 8))
+    assert fn(8, cin, 1, cout, 1, None, None) == _abi.TL_ERR_INVALID     # nin must be 2
+    man = json.load(open(FILES["manifest"]))
+    assert [p["name"] for p in man["programs"]] == [p.name for p in registry.programs()]
