@@ -323,6 +323,23 @@ def main():
         shape = "40r43w" if dom == "dtg_chain_bwd" else "43r6w"
         res["roofline"]["frac_of_twin"] = achieved / twins[shape]
 
+        log("[bench] kernels generated from index notation")
+        from paper_1804_10120_amd.generated import call as gen_call
+        gi = tl_sym_inverse(d["g"])
+        gam_g = torch.empty(18, n, dtype=torch.float64, device=device)
+        dtg_g = torch.empty(6, n, dtype=torch.float64, device=device)
+        with record() as gl:
+            gen_call("christoffel", gi, d["dg"], outs=[gam_g])
+            gen_call("dtg_chain_invg", gi, d["dg"], d["dbeta"], d["beta"], d["alpha"], d["K"],
+                     outs=[dtg_g])
+        _, (ms_gc, ms_gf) = time_calls([gl], 20, 3)
+        rows["generated"] = {
+            "christoffel": {"us": ms_gc * 1e3, "GB_s": rate(BYTES["christoffel"] * n, ms_gc),
+                            "hand_written_us": rows["christoffel"]["us"]},
+            "dtg_chain_invg": {"us": ms_gf * 1e3, "GB_s": rate(BYTES["dtg_chain"] * n, ms_gf),
+                               "hand_written_fused_us": ms_fwd * 1e3}}
+        del gl, gi, gam_g, dtg_g
+
         log("[bench] Christoffel symbols at 16^3 points")
         n16 = 16 ** 3
         (_, e16), = device_sets(n16, 1, device, config_seed(1))
