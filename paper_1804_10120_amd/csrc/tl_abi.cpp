@@ -7,6 +7,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -88,15 +89,20 @@ struct Checker {
   }
 };
 
+// Compute units of the current device (cached per device; calls may come
+// from several threads).
 int num_cus() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;
-  static int cache[64] = {0};
-  if (dev >= 0 && dev < 64 && cache[dev] > 0) return cache[dev];
+  static std::atomic<int> cache[64];
+  if (dev >= 0 && dev < 64) {
+    const int c = cache[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+  }
   int cu = 0;
   if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
     cu = 256;
-  if (dev >= 0 && dev < 64) cache[dev] = cu;
+  if (dev >= 0 && dev < 64) cache[dev].store(cu, std::memory_order_relaxed);
   return cu;
 }
 

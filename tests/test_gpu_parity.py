@@ -206,3 +206,20 @@ def test_graph_capture_replays():
         assert torch.equal(out, eager), f"replay {rep}"
         assert torch.equal(ginv, ginv_e), f"replay {rep}"
     assert_close(out, _oracle_chain(f), what="graph replay vs oracle")
+
+
+def test_autotuner_picks_a_valid_shape(tmp_path, monkeypatch):
+    """The autotuner times candidate shapes and caches the fastest; the cached
+    shape gives the same results."""
+    from paper_1804_10120_amd import autotune
+    monkeypatch.setenv("TLMI_TUNE_CACHE", str(tmp_path / "tune.json"))
+    n = 1 << 16
+    cands = list(autotune.candidates(blocks=(64, 256), ppts=(1, 2), nts=(True,), xcds=(False,),
+                                     grid_mults=(0,)))
+    res = autotune.tune("dtg_chain", n, tunes=cands, reps=5)
+    assert res["tune"] in cands and len(res["table"]) == len(cands)
+    assert autotune.lookup("dtg_chain", n) == res["tune"]
+    f = _fields(4097, seed=17)
+    out = tl_dtg_chain(*[dev(f[k]) for k in ("g", "dg", "beta", "dbeta", "K", "alpha")],
+                       tune=res["tune"])
+    assert_close(out, _oracle_chain(f), what="tuned shape")

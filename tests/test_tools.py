@@ -1,0 +1,80 @@
+"""Host-side tools: the profile summariser, the benchmark's command line, the
+synthetic input generators."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _write(path, header, rows):
+    with open(path, "w") as f:
+        f.write(",".join(f'"{h}"' for h in header) + "\n")
+        for r in rows:
+            f.write(",".join(f'"{x}"' if isinstance(x, str) else str(x) for x in r) + "\n")
+
+
+def test_profsum_scales_counters_by_the_copy_kernel(tmp_path):
+    from paper_1804_10120_amd import profsum
+    n = 1000
+    trace, fetch, write, out = (tmp_path / d for d in ("trace", "fetch", "write", "out"))
+    for d in (trace, fetch, write):
+        d.mkdir()
+    bwd = "void tl::k_points<tl::OpChainBwd, 256, 1, true>(tl::KArgs, long, long, int)"
+    fwd = "void tl::k_points<tl::OpChain, 256, 1, true>(tl::KArgs, long, long, int)"
+    copy = "tl::k_copy(double const*, double*, long)"
+    _write(trace / "t_kernel_stats.csv", ["Name", "Calls", "TotalDurationNs", "AverageNs",
+                                          "Percentage"], [[bwd, 2, 200.0, 100.0, 60.0]])
+    _write(trace / "t_kernel_trace.csv", ["Kernel_Name", "Grid_Size_X", "Start_Timestamp",
+                                          "End_Timestamp", "VGPR_Count", "Accum_VGPR_Count"],
+           [[bwd, 1024, 0, 100, 89, 0], [bwd, 1024, 200, 300, 89, 0]])
+    copy_doubles = 4096
+    hdr = ["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"]
+    # the counter sees half the fetched bytes and all the written ones
+    _write(fetch / "f_counter_collection.csv", hdr,
+           [[copy, 2048, "FETCH_SIZE", 8 * copy_doubles / 1024 / 2],
+            [bwd, 1024, "FETCH_SIZE", 8 * 40 * n / 1024 / 2],
+            [fwd, 1024, "FETCH_SIZE", 8 * 43 * n / 1024 / 2]])
+    _write(write / "w_counter_collection.csv", hdr,
+           [[copy, 2048, "WRITE_SIZE", 8 * copy_doubles / 1024],
+            [bwd, 1024, "WRITE_SIZE", 8 * 43 * n / 1024],
+            [fwd, 1024, "WRITE_SIZE", 8 * 6 * n / 1024]])
+    r = subprocess.run([sys.executable, "-m", "paper_1804_10120_amd.profsum", "--trace",
+                        str(trace), "--fetch", str(fetch), "--write", str(write), "--cmd", "x",
+                        "--points", str(n), "--copy-doubles", str(copy_doubles), "--workload",
+                        "w", "--out", str(out)], cwd=ROOT, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    rec = {}
+    for line in open(out / "pmc_dtg_chain_bwd.md"):
+        if ":" in line and not line.startswith(("#", "|", " ")):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    assert float(rec["traffic_bytes_per_launch"]) == 8 * 83 * n
+    assert rec["sources_sha256"] == profsum.sources_sha256()
+    assert "| 2 | 0.10 |" in open(out / "kernel_stats_w.md").read()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=ROOT,
+                       capture_output=True, text=True)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_synthetic_fields_are_seeded_and_in_range():
+    from paper_1804_10120_amd.synth import domain_edges, make_expr_inputs, make_fields
+    a, b = make_fields(1000, seed=3), make_fields(1000, seed=3)
+    assert all(np.array_equal(a[k], b[k]) for k in a)
+    c = make_fields(1000, seed=3, fields=("dg",))
+    assert np.array_equal(c["dg"], a["dg"])            # a field does not depend on the others
+    g = a["g"]
+    full = np.array([[g[0], g[1], g[2]], [g[1], g[3], g[4]], [g[2], g[4], g[5]]])
+    ev = np.linalg.eigvalsh(full.transpose(2, 0, 1))
+    assert ev.min() >= 0.7 - 1e-12 and ev.max() <= 1.3 + 1e-12
+    assert 0.5 <= a["alpha"].min() and a["alpha"].max() <= 1.5
+    assert np.abs(a["beta"]).max() <= 0.5
+    e = domain_edges(256)
+    assert e.min() >= 8 and e.max() <= 48 and len(e) == 256
+    x = make_expr_inputs("kij", 100, seed=1)
+    assert [v.shape[0] for v in x] == [1, 6, 3] and x[0].min() >= 0.5
