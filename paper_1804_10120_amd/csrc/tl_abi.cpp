@@ -7,6 +7,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdarg>
 #include <cstdio>
@@ -78,14 +79,38 @@ struct Checker {
 
   tl_status overlaps() {
     if (st != TL_OK) return st;
-    for (size_t i = 0; i < spans.size(); ++i)
-      for (size_t j = i + 1; j < spans.size(); ++j) {
-        const Span &x = spans[i], &y = spans[j];
-        if (!x.output && !y.output) continue;
-        if (x.lo < y.hi && y.lo < x.hi)
-          return st = fail(TL_ERR_ALIAS, "%s overlaps %s", x.name, y.name);
-      }
+    const Span* a = nullptr;
+    const Span* b = nullptr;
+    if (find_overlap(spans, &a, &b))
+      return st = fail(TL_ERR_ALIAS, "%s overlaps %s", a->name, b->name);
     return st;
+  }
+
+  // Finds a pair of overlapping spans of which at least one is an output
+  // (inputs may overlap each other).  Sort by start, then sweep: a span that
+  // starts before the furthest end of the outputs seen so far overlaps an
+  // output; an output that starts before the furthest end of any span seen so
+  // far overlaps that span.  O(S log S).
+  static bool find_overlap(std::vector<Span>& v, const Span** x, const Span** y) {
+    std::sort(v.begin(), v.end(), [](const Span& p, const Span& q) { return p.lo < q.lo; });
+    const Span* far_out = nullptr;  // output with the largest end so far
+    const Span* far_any = nullptr;  // span with the largest end so far
+    for (const Span& s : v) {
+      if (s.hi == s.lo) continue;
+      if (far_out && s.lo < far_out->hi) {
+        *x = far_out;
+        *y = &s;
+        return true;
+      }
+      if (s.output && far_any && s.lo < far_any->hi) {
+        *x = far_any;
+        *y = &s;
+        return true;
+      }
+      if (!far_any || s.hi > far_any->hi) far_any = &s;
+      if (s.output && (!far_out || s.hi > far_out->hi)) far_out = &s;
+    }
+    return false;
   }
 };
 
@@ -517,15 +542,10 @@ tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tun
     points += x.n;
   }
   {
-    std::vector<size_t> outs;
-    for (size_t i = 0; i < all.size(); ++i)
-      if (all[i].output) outs.push_back(i);
-    for (size_t oi : outs)
-      for (size_t j = 0; j < all.size(); ++j) {
-        if (j == oi) continue;
-        if (all[oi].lo < all[j].hi && all[j].lo < all[oi].hi)
-          return fail(TL_ERR_ALIAS, "a domain's dtg overlaps another field of the batch");
-      }
+    const Span* a = nullptr;
+    const Span* b = nullptr;
+    if (Checker::find_overlap(all, &a, &b))
+      return fail(TL_ERR_ALIAS, "%s of one domain overlaps %s of another", a->name, b->name);
   }
 
   tl::Resolved r;

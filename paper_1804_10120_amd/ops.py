@@ -93,7 +93,8 @@ def _stream(device, stream):
 def make_tune(tune):
     """None (library default), a Tune, a dict with keys block, ppt, nt, xcd,
     grid_mult (missing numbers mean the default; flags default to off), or a
-    tuple (block, ppt, flags, grid_mult) -> Tune pointer or None."""
+    tuple (block, ppt, flags, grid_mult) -> Tune pointer or None.  (The tl_*
+    functions also accept tune="auto", the autotuner's cached shape.)"""
     if tune is None:
         return None
     if isinstance(tune, Tune):
@@ -149,7 +150,19 @@ class record:
         return False
 
 
-def _run(fn, c, *args, stream=None, tune=None):
+def _auto(tune, kernel, n):
+    """tune="auto": the autotuner's cached shape for (kernel, size class), or
+    the library default when nothing is cached."""
+    if isinstance(tune, str):
+        if tune != "auto":
+            raise ValueError(f"tune={tune!r}: expected None, 'auto', a dict, a tuple or a Tune")
+        from . import autotune
+        return autotune.lookup(kernel, n)
+    return tune
+
+
+def _run(fn, c, *args, stream=None, tune=None, kernel=None):
+    tune = _auto(tune, kernel, c.n)
     with torch.cuda.device(c.device):
         full = (c.n, *args, _stream(c.device, stream), make_tune(tune))
         if _recorder is not None:
@@ -163,7 +176,8 @@ def tl_sym_inverse(g, ginv=None, *, stream=None, tune=None):
     c = _Call()
     c.add(g, "g")
     ginv = c.out(ginv, "ginv", g)
-    _run(lib().tl_sym_inverse, c, _cf(g, 6), _f(ginv, 6), stream=stream, tune=tune)
+    _run(lib().tl_sym_inverse, c, _cf(g, 6), _f(ginv, 6), stream=stream, tune=tune,
+         kernel="sym_inverse")
     return ginv
 
 
@@ -174,7 +188,8 @@ def tl_christoffel(ginv, dg, gamma=None, *, stream=None, tune=None):
     c.add(dg, "dg")
     gamma = c.out(gamma, "gamma", dg)
     _run(lib().tl_christoffel, c, _cf(ginv, 6), _cf(dg, 18), _f(gamma, 18), stream=stream,
-         tune=tune)
+         tune=tune,
+         kernel="christoffel")
     return gamma
 
 
@@ -186,7 +201,8 @@ def tl_cov_deriv(gamma, beta, dbeta, nabla_beta=None, *, stream=None, tune=None)
     c.add(dbeta, "dbeta")
     nabla_beta = c.out(nabla_beta, "nabla_beta", dbeta)
     _run(lib().tl_cov_deriv, c, _cf(gamma, 18), _cf(beta, 3), _cf(dbeta, 9), _f(nabla_beta, 9),
-         stream=stream, tune=tune)
+         stream=stream, tune=tune,
+         kernel="cov_deriv")
     return nabla_beta
 
 
@@ -198,7 +214,8 @@ def tl_dtg(alpha, K, nabla_beta, dtg=None, *, stream=None, tune=None):
     c.add(nabla_beta, "nabla_beta")
     dtg = c.out(dtg, "dtg", K)
     _run(lib().tl_dtg, c, _cf(alpha, 1), _cf(K, 6), _cf(nabla_beta, 9), _f(dtg, 6),
-         stream=stream, tune=tune)
+         stream=stream, tune=tune,
+         kernel="dtg")
     return dtg
 
 
@@ -210,7 +227,8 @@ def tl_dtg_chain(g, dg, beta, dbeta, K, alpha, dtg=None, *, stream=None, tune=No
         c.add(t, name)
     dtg = c.out(dtg, "dtg", K)
     _run(lib().tl_dtg_chain, c, _cf(g, 6), _cf(dg, 18), _cf(beta, 3), _cf(dbeta, 9), _cf(K, 6),
-         _cf(alpha, 1), _f(dtg, 6), stream=stream, tune=tune)
+         _cf(alpha, 1), _f(dtg, 6), stream=stream, tune=tune,
+         kernel="dtg_chain")
     return dtg
 
 
@@ -240,7 +258,8 @@ def tl_dtg_chain_bwd(g, dg, beta, K, alpha, w, g_bar=None, dg_bar=None, beta_bar
         raise ValueError("tl_dtg_chain_bwd: no gradient requested")
     fields = [_f(o, nc) for o, nc in zip(outs, ncomp)]
     _run(lib().tl_dtg_chain_bwd, c, _cf(g, 6), _cf(dg, 18), _cf(beta, 3), _cf(K, 6),
-         _cf(alpha, 1), _cf(w, 6), *fields, stream=stream, tune=tune)
+         _cf(alpha, 1), _cf(w, 6), *fields, stream=stream, tune=tune,
+         kernel="dtg_chain_bwd")
     return tuple(outs)
 
 

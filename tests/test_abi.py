@@ -217,3 +217,21 @@ def test_expr_validation(L):
     assert L.tl_expr(_abi.EXPRS.index("contract1"), 4096, bad, 2, f(BASE + 2 * MB, 4096), None,
                      None) == _abi.TL_ERR_ALIAS
     assert L.tl_expr(0, 0, None, 1, f(None, 0), None, None) == _abi.TL_OK
+
+
+def test_batch_overlap_check_scales(L):
+    """20000 subgrids (140000 fields): the overlap check is a sort and a sweep,
+    and it finds the one output that overlaps another subgrid's input."""
+    import time
+    nd, n = 20000, 64
+    doms = (Domain * nd)()
+    stride = 64 * 1024
+    for d in range(nd):
+        base = BASE + d * 8 * stride
+        doms[d] = Domain(n, *[cf(base + f * stride, n) for f in range(6)], f(base + 6 * stride, n))
+    doms[nd - 1].dtg = Field(doms[0].dbeta.ptr + 8, n)
+    plan = ctypes.c_void_p()
+    t0 = time.perf_counter()
+    assert L.tl_batch_plan_create(doms, nd, None, ctypes.byref(plan)) == _abi.TL_ERR_ALIAS
+    assert time.perf_counter() - t0 < 5.0
+    assert b"dtg" in L.tl_last_error() and b"dbeta" in L.tl_last_error()

@@ -223,3 +223,21 @@ def test_autotuner_picks_a_valid_shape(tmp_path, monkeypatch):
     out = tl_dtg_chain(*[dev(f[k]) for k in ("g", "dg", "beta", "dbeta", "K", "alpha")],
                        tune=res["tune"])
     assert_close(out, _oracle_chain(f), what="tuned shape")
+
+
+def test_auto_tune_uses_the_cache(tmp_path, monkeypatch):
+    import json
+    from paper_1804_10120_amd import autotune
+    monkeypatch.setenv("TLMI_TUNE_CACHE", str(tmp_path / "tune.json"))
+    n = 3000
+    f = _fields(n, seed=19)
+    ref = tl_sym_inverse(dev(f["g"]))                      # nothing cached: default shape
+    assert torch.equal(tl_sym_inverse(dev(f["g"]), tune="auto"), ref)
+    with open(tmp_path / "tune.json", "w") as fh:
+        json.dump({autotune.cache_key("sym_inverse", n):
+                   {"tune": {"block": 128, "ppt": 2, "nt": True}, "us": 1.0, "GB_s": 1.0}}, fh)
+    assert autotune.lookup("sym_inverse", n) == {"block": 128, "ppt": 2, "nt": True}
+    assert_close(tl_sym_inverse(dev(f["g"]), tune="auto"), oracle.sym_inverse(f["g"]),
+                 what="auto-tuned inverse")
+    with pytest.raises(ValueError, match="auto"):
+        tl_sym_inverse(dev(f["g"]), tune="fast")
