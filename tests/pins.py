@@ -355,6 +355,93 @@ def pin_jvp_finite_difference(orc, n=128, h=1e-6):
     _close(jv, fd, 1e-6, "JVP vs central differences")
 
 
+# --------------------------------------------------------------------------- exact arithmetic
+
+def _fr_solve(A, B):
+    """Gauss-Jordan elimination in exact rationals: A is m x m, B is m x r."""
+    m = len(A)
+    M = [list(A[i]) + list(B[i]) for i in range(m)]
+    for c in range(m):
+        p = next(r for r in range(c, m) if M[r][c] != 0)
+        M[c], M[p] = M[p], M[c]
+        piv = M[c][c]
+        M[c] = [x / piv for x in M[c]]
+        for r in range(m):
+            if r != c and M[r][c] != 0:
+                fac = M[r][c]
+                M[r] = [a - fac * b for a, b in zip(M[r], M[c])]
+    return [row[m:] for row in M]
+
+
+def exact_chain_point(f, p):
+    """g^ij, Gamma^i_jk, nabla_j beta_i and d_t g_ij at point p in exact
+    rational arithmetic, from the double inputs taken exactly, by routes that
+    avoid the oracle's formulas: the inverse by elimination, Gamma as the
+    solution of the metric-compatibility system, nabla beta through the raised
+    shift beta^k, and d_t g as -2 alpha K plus the Lie derivative of g."""
+    from fractions import Fraction as Fr
+    R = range(3)
+    sym = lambda a, b: cf.S[a, b]
+    G = [[Fr(float(f["g"][sym(i, j), p])) for j in R] for i in R]
+    D = [[[Fr(float(f["dg"][k * 6 + sym(i, j), p])) for j in R] for i in R] for k in R]
+    b = [Fr(float(f["beta"][i, p])) for i in R]
+    db = [[Fr(float(f["dbeta"][j * 3 + i, p])) for i in R] for j in R]     # [j][i]
+    K = [[Fr(float(f["K"][sym(i, j), p])) for j in R] for i in R]
+    al = Fr(float(f["alpha"][0, p]))
+    Gi = _fr_solve(G, [[Fr(int(i == j)) for j in R] for i in R])
+    unk = [(l, j, k) for l in R for j, k in cf.PAIRS]
+    col = {u: c for c, u in enumerate(unk)}
+    ci = lambda l, a, c: col[(l, min(a, c), max(a, c))]
+    A = [[Fr(0)] * 18 for _ in range(18)]
+    rhs = []
+    for k in R:
+        for i, j in cf.PAIRS:
+            row = len(rhs)
+            for l in R:
+                A[row][ci(l, j, k)] += G[i][l]
+                A[row][ci(l, i, k)] += G[j][l]
+            rhs.append([D[k][i][j]])
+    x = _fr_solve(A, rhs)
+    gam = [[[x[ci(l, j, k)][0] for k in R] for j in R] for l in R]
+    bu = [sum(Gi[k][l] * b[l] for l in R) for k in R]
+    # d_j beta^k = g^kl d_j beta_l - g^ka (d_j g_ab) beta^b
+    dbu = [[sum(Gi[k][l] * db[j][l] for l in R)
+            - sum(Gi[k][a] * D[j][a][c] * bu[c] for a in R for c in R) for k in R] for j in R]
+    cov_up = [[dbu[j][k] + sum(gam[k][j][l] * bu[l] for l in R) for k in R] for j in R]
+    nab = [[sum(G[i][k] * cov_up[j][k] for k in R) for i in R] for j in R]    # [j][i]
+    lie = [[sum(bu[k] * D[k][i][j] + G[k][j] * dbu[i][k] + G[i][k] * dbu[j][k] for k in R)
+            for j in R] for i in R]
+    dtg = [[-2 * al * K[i][j] + lie[i][j] for j in R] for i in R]
+    return Gi, gam, nab, dtg
+
+
+def pin_exact_rational(orc):
+    """Every step of the chain against exact rational arithmetic on a few
+    points (random metrics with condition number <= 1.86, and general SPD
+    metrics): the oracle is within a small multiple of eps * kappa of the exact
+    value, which a float32 step, a dropped term or a wrong index would not be."""
+    sets = [(_random(5, seed=120), 1.86)]
+    f = _random(4, seed=121)
+    f["g"], M = _spd(4, seed=122)
+    sets.append((f, np.linalg.cond(M).max()))
+    for f, kappa in sets:
+        n = f["g"].shape[1]
+        ex = [exact_chain_point(f, p) for p in range(n)]
+        Gi = orc.sym_inverse(f["g"])
+        gam = orc.christoffel(Gi, f["dg"], full=True)
+        nab = _nabla(orc, f["g"], f["dg"], f["beta"], f["dbeta"])
+        dtg = _chain(orc, f)
+        col = lambda get, comps: np.array([[float(get(ex[p], *c)) for p in range(n)] for c in comps])
+        pairs = cf.PAIRS
+        trip = [(i, j, k) for i in range(3) for j in range(3) for k in range(3)]
+        jis = [(j, i) for j in range(3) for i in range(3)]
+        tol = 16 * EPS * kappa
+        _close(Gi, col(lambda e, i, j: e[0][i][j], pairs), 4 * EPS * kappa, "inverse vs exact")
+        _close(gam, col(lambda e, i, j, k: e[1][i][j][k], trip), tol, "Gamma vs exact")
+        _close(nab, col(lambda e, j, i: e[2][j][i], jis), 4 * tol, "nabla beta vs exact")
+        _close(dtg, col(lambda e, i, j: e[3][i][j], pairs), 4 * tol, "d_t g vs exact")
+
+
 # --------------------------------------------------------------------------- Sec. 5.1 family
 
 def _ints(shape, seed, lo=-8, hi=8):
