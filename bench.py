@@ -36,6 +36,7 @@ KEYS = ("g", "dg", "beta", "dbeta", "K", "alpha")
 # the fields).
 BYTES = {"sym_inverse": 8 * 12, "christoffel": 8 * 42, "cov_deriv": 8 * 39, "dtg": 8 * 22,
          "dtg_chain": 8 * 49, "dtg_chain_bwd": 8 * 83, "dtg_chain_batched": 8 * 49,
+         "dtg_chain_fwd_bwd": 8 * 98,
          "unfused_chain": 8 * 115}
 METRIC = "grid points/s + achieved HBM GB/s, fused FP64 chain fwd and fwd+bwd"
 
@@ -117,26 +118,65 @@ def copy_ceiling(device, reps=20):
     return rate(16 * n, ms)
 
 
-def cpu_baseline(f, budget_s):
-    """The serial oracle (forward chain + reverse-mode gradients) on one host
-    core, over consecutive 16^3-point slices of the benchmark's fields until
-    ``budget_s`` seconds have passed."""
+def host_cpu():
+    """Model name of the host CPU and the number of cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def _oracle_slices(f, budget_s, first, step):
+    """Runs the oracle (forward chain + reverse-mode gradients) over the
+    4096-point slices first, first + step, ... of the benchmark's fields until
+    ``budget_s`` seconds have passed; returns the number of points done."""
     import numpy as np
     import oracle
     n = f["g"].shape[1]
     chunk = min(n, 4096)
-    done, t0 = 0, time.perf_counter()
+    nslices = (n + chunk - 1) // chunk
+    done, k, t0 = 0, first, time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
-        lo = done % n
+        lo = (k % nslices) * chunk
         hi = min(n, lo + chunk)
-        ins = tuple(np.ascontiguousarray(f[k][:, lo:hi]) for k in KEYS)
+        ins = tuple(np.ascontiguousarray(f[key][:, lo:hi]) for key in KEYS)
         oracle.dtg_chain(*ins)
         oracle.dtg_chain_vjp(ins, np.ascontiguousarray(f["W"][:, lo:hi]))
         done += hi - lo
+        k += step
+    return done
+
+
+def cpu_baseline(f, budget_s):
+    """The serial oracle on one host core, over consecutive 16^3-point slices
+    of the benchmark's fields, for about ``budget_s`` seconds."""
+    t0 = time.perf_counter()
+    done = _oracle_slices(f, budget_s, 0, 1)
     dt = time.perf_counter() - t0
+    model, ncpu = host_cpu()
     return {"value": done / dt, "unit": "grid points/s", "cores": 1, "kind": "oracle",
             "sample": f"serial oracle (forward chain + tape VJP) on {done} points of the "
-                      f"benchmark fields, in 4096-point slices, {dt:.1f} s on one host core"}
+                      f"benchmark fields, in 4096-point slices, {dt:.1f} s on one host core",
+            "host_cpu": model, "host_cores": ncpu}
+
+
+def cpu_all_cores(f, budget_s, threads):
+    """The same oracle, unchanged, on ``threads`` host threads at once (each
+    takes every threads-th slice; the oracle's C entry points run without the
+    interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        done = sum(pool.map(lambda i: _oracle_slices(f, budget_s, i, threads), range(threads)))
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "grid points/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} points in 4096-point slices over {dt:.1f} s"}
 
 
 SWEEP_SIZES = tuple(32 * 4 ** k for k in range(9)) + (2 ** 21,)
@@ -233,7 +273,8 @@ def main():
 
     import torch
     from paper_1804_10120_amd import (BatchPlan, tl_christoffel, tl_cov_deriv, tl_dtg,
-                                      tl_dtg_chain, tl_dtg_chain_bwd, tl_sym_inverse)
+                                      tl_dtg_chain, tl_dtg_chain_bwd, tl_dtg_chain_fwd_bwd,
+                                      tl_sym_inverse)
     from paper_1804_10120_amd.ops import record
     from paper_1804_10120_amd.synth import config_seed, domain_edges, make_fields
 
@@ -291,6 +332,18 @@ def main():
 
     if not args.no_rows:
         rows = {}
+        log("[bench] forward + adjoint in one kernel (cotangent known up front)")
+        ref = [d["dtg"].clone()] + [x.clone() for x in d["grads"]]
+        with record() as fb:
+            tl_dtg_chain_fwd_bwd(*[d[k] for k in KEYS], d["W"], d["dtg"], d["grads"])
+        _, (ms_fb,) = time_calls([fb], args.steps, args.warmup)
+        diff = max(float(((a - b).abs().max() / b.abs().max().clamp_min(1e-300)).item())
+                   for a, b in zip([d["dtg"], *d["grads"]], ref))
+        rows["fwd_bwd_one_kernel"] = {"us": ms_fb * 1e3, "points_per_s": n / (ms_fb * 1e-3),
+                                      "GB_s": rate(BYTES["dtg_chain_fwd_bwd"] * n, ms_fb),
+                                      "speedup_vs_two_kernels": ms_step / ms_fb,
+                                      "max_rel_diff_vs_two_kernels": diff}
+        del ref, fb
         log("[bench] unfused steps")
         with record() as unf:
             ginv = tl_sym_inverse(d["g"])
@@ -375,12 +428,14 @@ def main():
                 tl_dtg_chain_bwd(e["g"], e["dg"], e["beta"], e["K"], e["alpha"], e["W"])
             lists.append(c)
         ms64, (f64, b64) = time_calls(lists, 100, 10)
+        _, (wf64, wb64) = time_calls(lists[:1], 100, 10)     # one set: cache-resident
         rows["fwd_bwd_64cubed"] = {"points": n64, "us": ms64 * 1e3,
                                    "points_per_s": n64 / (ms64 * 1e-3),
                                    "fwd_us": f64 * 1e3,
                                    "fwd_GB_s": rate(BYTES["dtg_chain"] * n64, f64),
                                    "bwd_us": b64 * 1e3,
-                                   "bwd_GB_s": rate(BYTES["dtg_chain_bwd"] * n64, b64)}
+                                   "bwd_GB_s": rate(BYTES["dtg_chain_bwd"] * n64, b64),
+                                   "warm_fwd_us": wf64 * 1e3, "warm_bwd_us": wb64 * 1e3}
         del s64, lists
 
         log("[bench] 256 subgrids")
@@ -396,14 +451,24 @@ def main():
             for e in doms:
                 tl_dtg_chain(*[e[k] for k in KEYS])
         ms_many, _ = time_calls([many], 10, 2)
+        outs = [torch.empty_like(e["K"]) for e in doms]
+        graph256 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph256):    # the 256 plain launches, captured
+            for e, o in zip(doms, outs):
+                tl_dtg_chain(*[e[k] for k in KEYS], o)
+        _, (ms_g256,) = time_calls([[graph256.replay]], 20, 3)
+        same = all(torch.equal(a, b) for a, b in zip(outs, plan.outputs))
         rows["dtg_chain_batched"] = {
             "subgrids": 256, "points": npts, "us": ms_graph * 1e3,
             "points_per_s": npts / (ms_graph * 1e-3),
             "GB_s": rate(BYTES["dtg_chain_batched"] * npts, ms_graph),
             "separate_launches_us": ms_many * 1e3,
-            "separate_launches_points_per_s": npts / (ms_many * 1e-3)}
+            "separate_launches_points_per_s": npts / (ms_many * 1e-3),
+            "separate_launches_graph_us": ms_g256 * 1e3,
+            "separate_launches_graph_points_per_s": npts / (ms_g256 * 1e-3),
+            "separate_launches_match_batched": same}
         plan.close()
-        del doms, many
+        del doms, many, outs, graph256
         log("[bench] the paper's benchmark expressions, grid-size sweep")
         table = paper_family(device, SWEEP_SIZES)
         rows["paper_family"] = family_summary(table)
@@ -415,6 +480,10 @@ def main():
     if not args.no_cpu:
         log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         res["cpu_baseline"] = cpu_baseline(f, args.cpu_seconds)
+        if "rows" in res:
+            threads = min(16, res["cpu_baseline"]["host_cores"])
+            log(f"[bench] CPU oracle on {threads} threads (~{args.cpu_seconds / 2:.0f} s)")
+            res["rows"]["cpu_oracle_all_cores"] = cpu_all_cores(f, args.cpu_seconds / 2, threads)
     else:
         res["cpu_baseline"] = None
     print(json.dumps(res), flush=True)

@@ -61,6 +61,8 @@ SIGNATURES = {
     "tl_dtg": [_I64, _C, _C, _C, _F, _S, _T],
     "tl_dtg_chain": [_I64, _C, _C, _C, _C, _C, _C, _F, _S, _T],
     "tl_dtg_chain_bwd": [_I64, _C, _C, _C, _C, _C, _C, _F, _F, _F, _F, _F, _F, _S, _T],
+    "tl_dtg_chain_fwd_bwd": [_I64, _C, _C, _C, _C, _C, _C, _C, _F, _F, _F, _F, _F, _F, _F, _S,
+                             _T],
     "tl_batch_plan_create": [ctypes.POINTER(Domain), ctypes.c_int32, _T, ctypes.POINTER(ctypes.c_void_p)],
     "tl_batch_plan_launch": [ctypes.c_void_p, _S],
     "tl_batch_plan_launch_direct": [ctypes.c_void_p, _S],

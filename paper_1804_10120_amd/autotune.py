@@ -18,10 +18,11 @@ import os
 import torch
 
 from .ops import (record, tl_christoffel, tl_cov_deriv, tl_dtg, tl_dtg_chain, tl_dtg_chain_bwd,
-                  tl_sym_inverse)
+                  tl_dtg_chain_fwd_bwd, tl_sym_inverse)
 from .synth import make_fields
 
-KERNELS = ("sym_inverse", "christoffel", "cov_deriv", "dtg", "dtg_chain", "dtg_chain_bwd")
+KERNELS = ("sym_inverse", "christoffel", "cov_deriv", "dtg", "dtg_chain", "dtg_chain_bwd",
+           "dtg_chain_fwd_bwd")
 BLOCKS = (64, 128, 256, 512, 1024)
 PPTS = (1, 2)
 NTS = (False, True)
@@ -29,7 +30,7 @@ XCDS = (False, True)
 GRID_MULTS = (0, 1, 2, 4, 8)
 # stored doubles read + written per point
 DOUBLES = {"sym_inverse": 12, "christoffel": 42, "cov_deriv": 39, "dtg": 22, "dtg_chain": 49,
-           "dtg_chain_bwd": 83}
+           "dtg_chain_bwd": 83, "dtg_chain_fwd_bwd": 98}
 CACHE_BYTES = 256 << 20
 
 
@@ -96,6 +97,9 @@ def _calls(kernel, d, tune):
         elif kernel == "dtg_chain_bwd":
             tl_dtg_chain_bwd(d["g"], d["dg"], d["beta"], d["K"], d["alpha"], d["W"], *d["_grads"],
                              tune=tune)
+        elif kernel == "dtg_chain_fwd_bwd":
+            tl_dtg_chain_fwd_bwd(d["g"], d["dg"], d["beta"], d["dbeta"], d["K"], d["alpha"],
+                                 d["W"], d["_o6"], d["_grads"], tune=tune)
         else:
             raise KeyError(kernel)
     return calls[0]

@@ -428,6 +428,52 @@ tl_status tl_dtg_chain_bwd(int64_t n, tl_cfield g, tl_cfield dg, tl_cfield beta,
   return run(tl::KernelId::ChainBwd, c, tune, a, stream);
 }
 
+tl_status tl_dtg_chain_fwd_bwd(int64_t n, tl_cfield g, tl_cfield dg, tl_cfield beta,
+                           tl_cfield dbeta, tl_cfield K, tl_cfield alpha, tl_cfield w,
+                           tl_field dtg, tl_field g_bar, tl_field dg_bar, tl_field beta_bar,
+                           tl_field dbeta_bar, tl_field K_bar, tl_field alpha_bar, void* stream,
+                           const tl_tune* tune) {
+  if (n < 0) return fail(TL_ERR_SIZE, "n=%lld < 0", (long long)n);
+  if (n == 0) return TL_OK;
+  if (!dtg.ptr && !g_bar.ptr && !dg_bar.ptr && !beta_bar.ptr && !dbeta_bar.ptr && !K_bar.ptr &&
+      !alpha_bar.ptr)
+    return fail(TL_ERR_NULL, "every output is NULL");
+  Checker c(n);
+  c.field("g", g.ptr, g.ld, 6, false);
+  c.field("dg", dg.ptr, dg.ld, 18, false);
+  c.field("beta", beta.ptr, beta.ld, 3, false);
+  c.field("dbeta", dbeta.ptr, dbeta.ld, 9, false);
+  c.field("K", K.ptr, K.ld, 6, false);
+  c.field("alpha", alpha.ptr, alpha.ld, 1, false);
+  c.field("w", w.ptr, w.ld, 6, false);
+  c.field("dtg", dtg.ptr, dtg.ld, 6, true, true);
+  c.field("g_bar", g_bar.ptr, g_bar.ld, 6, true, true);
+  c.field("dg_bar", dg_bar.ptr, dg_bar.ld, 18, true, true);
+  c.field("beta_bar", beta_bar.ptr, beta_bar.ld, 3, true, true);
+  c.field("dbeta_bar", dbeta_bar.ptr, dbeta_bar.ld, 9, true, true);
+  c.field("K_bar", K_bar.ptr, K_bar.ld, 6, true, true);
+  c.field("alpha_bar", alpha_bar.ptr, alpha_bar.ld, 1, true, true);
+  if (c.overlaps() != TL_OK) return c.st;
+  tl::KArgs a = zero_args();
+  set_in(a, 0, g);
+  set_in(a, 1, dg);
+  set_in(a, 2, beta);
+  set_in(a, 3, dbeta);
+  set_in(a, 4, K);
+  set_in(a, 5, alpha);
+  a.ldin[5] = 0;
+  set_in(a, 6, w);
+  set_out(a, 0, dtg);
+  set_out(a, 1, g_bar);
+  set_out(a, 2, dg_bar);
+  set_out(a, 3, beta_bar);
+  set_out(a, 4, dbeta_bar);
+  set_out(a, 5, K_bar);
+  set_out(a, 6, alpha_bar);
+  a.ldout[6] = 0;
+  return run(tl::KernelId::ChainFwdBwd, c, tune, a, stream);
+}
+
 namespace {
 // Input component counts (0-terminated) and output count of each expression.
 const int kExprIn[TL_EXPR_COUNT][5] = {{3}, {9}, {27}, {3, 3}, {3, 3, 3}, {3, 3, 3, 3}, {3, 3},
@@ -686,7 +732,8 @@ tl_status tl_kernel_info(const char* kernel, const tl_tune* tune, tl_kernel_attr
   } names[] = {{"sym_inverse", tl::KernelId::SymInverse}, {"christoffel", tl::KernelId::Christoffel},
                {"cov_deriv", tl::KernelId::CovDeriv},     {"dtg", tl::KernelId::Dtg},
                {"dtg_chain", tl::KernelId::Chain},        {"dtg_chain_bwd", tl::KernelId::ChainBwd},
-               {"dtg_chain_batched", tl::KernelId::ChainBatched}};
+               {"dtg_chain_batched", tl::KernelId::ChainBatched},
+               {"dtg_chain_fwd_bwd", tl::KernelId::ChainFwdBwd}};
   const tl::KernelId* id = nullptr;
   for (const auto& x : names)
     if (std::strcmp(x.name, kernel) == 0) id = &x.id;

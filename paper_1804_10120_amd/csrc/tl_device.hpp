@@ -268,6 +268,26 @@ struct OpChainBwd {
   }
 };
 
+// ---------------------------------------------------------------- value and gradient
+// d_t g and its vector-Jacobian product for a cotangent w that is known when
+// the chain is evaluated (a loss linear in d_t g, such as sum_s w_s d_t g_s):
+// OpChain and OpChainBwd on one read of the shared inputs.  Inputs: g 6, dg 18,
+// beta 3, dbeta 9, K 6, alpha 1, w 6.  Outputs: d_t g 6, then the six
+// gradients of OpChainBwd in its order.
+struct OpChainFwdBwd {
+  static constexpr int NF_IN = 7, NF_OUT = 7;
+  static constexpr int fin[NF_IN] = {6, 18, 3, 9, 6, 1, 6};
+  static constexpr int fout[NF_OUT] = {6, 6, 18, 3, 9, 6, 1};
+  static constexpr int NIN = 49, NOUT = 49;
+  __device__ static inline void apply(const double* x, double* y) {
+    OpChain::apply(x, y);
+    double cof[6], r, b[3];
+    OpChainBwd::phase1(x, x + 24, x + 36, x[42], x + 43, cof, r, b, y + 12, y + 33, y + 42,
+                       y + 48);
+    OpChainBwd::phase2(x + 6, x + 43, cof, r, b, y + 6, y + 30);
+  }
+};
+
 // ---------------------------------------------------------------- twin
 // Bandwidth twin of a row: reads NI component streams and writes NO, with no
 // arithmetic beyond a sum (each output is the sum of the inputs plus its own

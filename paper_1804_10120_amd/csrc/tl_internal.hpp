@@ -27,7 +27,8 @@ struct alignas(64) BatchDomain {
   int64_t n;
 };
 
-enum class KernelId { SymInverse, Christoffel, CovDeriv, Dtg, Chain, ChainBwd, ChainBatched };
+enum class KernelId { SymInverse, Christoffel, CovDeriv, Dtg, Chain, ChainBwd, ChainBatched,
+                      ChainFwdBwd };
 
 // A tuning request resolved to one compiled instantiation.
 struct Resolved {

@@ -91,6 +91,7 @@ hipError_t launch_kernel(KernelId k, const Resolved& r, const KArgs& a, int64_t 
     case KernelId::Dtg: return launch_op<OpDtg>(r, a, n, s);
     case KernelId::Chain: return launch_op<OpChain>(r, a, n, s);
     case KernelId::ChainBwd: return launch_op<OpChainBwd>(r, a, n, s);
+    case KernelId::ChainFwdBwd: return launch_op<OpChainFwdBwd>(r, a, n, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -103,6 +104,7 @@ const void* kernel_address(KernelId k, const Resolved& r) {
     case KernelId::Dtg: return ptr_op<OpDtg>(r);
     case KernelId::Chain: return ptr_op<OpChain>(r);
     case KernelId::ChainBwd: return ptr_op<OpChainBwd>(r);
+    case KernelId::ChainFwdBwd: return ptr_op<OpChainFwdBwd>(r);
     case KernelId::ChainBatched: return ptr_batched(r);
     default: return nullptr;
   }

@@ -263,6 +263,41 @@ def tl_dtg_chain_bwd(g, dg, beta, K, alpha, w, g_bar=None, dg_bar=None, beta_bar
     return tuple(outs)
 
 
+def tl_dtg_chain_fwd_bwd(g, dg, beta, dbeta, K, alpha, w, dtg=None, grads=None, *, want=None,
+                         stream=None, tune=None):
+    """tl_dtg_chain and tl_dtg_chain_bwd in one pass, for a cotangent w [6,n]
+    known up front (a loss linear in d_t g).
+
+    Returns (dtg, (g_bar, dg_bar, beta_bar, dbeta_bar, K_bar, alpha_bar)).
+    ``grads`` optionally gives the six gradient outputs (None entries are
+    allocated when wanted); ``want`` is a 7-tuple of booleans for d_t g and the
+    six gradients; an unwanted output is not written and comes back as None.
+    """
+    c = _Call()
+    for t, name in ((g, "g"), (dg, "dg"), (beta, "beta"), (dbeta, "dbeta"), (K, "K"),
+                    (alpha, "alpha"), (w, "w")):
+        c.add(t, name)
+    want = (True,) * 7 if want is None else tuple(bool(x) for x in want)
+    if len(want) != 7:
+        raise ValueError("tl_dtg_chain_fwd_bwd: want has 7 entries")
+    outs = [dtg] + (list(grads) if grads is not None else [None] * 6)
+    if len(outs) != 7:
+        raise ValueError("tl_dtg_chain_fwd_bwd: grads has 6 entries")
+    ncomp = (6, 6, 18, 3, 9, 6, 1)
+    likes = (K, g, dg, beta, dbeta, K, alpha)
+    names = ("dtg",) + tuple(x + "_bar" for x in GRAD_NAMES)
+    for i in range(7):
+        if outs[i] is not None or want[i]:
+            outs[i] = c.out(outs[i], names[i], likes[i], ncomp[i])
+    if all(o is None for o in outs):
+        raise ValueError("tl_dtg_chain_fwd_bwd: no output requested")
+    fields = [_f(o, nc) for o, nc in zip(outs, ncomp)]
+    _run(lib().tl_dtg_chain_fwd_bwd, c, _cf(g, 6), _cf(dg, 18), _cf(beta, 3), _cf(dbeta, 9),
+         _cf(K, 6), _cf(alpha, 1), _cf(w, 6), *fields, stream=stream, tune=tune,
+         kernel="dtg_chain_fwd_bwd")
+    return outs[0], tuple(outs[1:])
+
+
 def tl_bw_copy(src, dst=None, *, stream=None):
     """dst = src for a contiguous float64 device tensor (bandwidth reference)."""
     if src.dtype != torch.float64 or not src.is_contiguous() or src.device.type != "cuda":

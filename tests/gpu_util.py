@@ -57,7 +57,8 @@ def dev(host, **kw):
 
 
 def assert_close(x, r, tol=TOL, what=""):
-    x = x.cpu().numpy() if isinstance(x, torch.Tensor) else np.asarray(x)
+    x = x.detach().cpu().numpy() if isinstance(x, torch.Tensor) else np.asarray(x)
+    r = r.detach().cpu().numpy() if isinstance(r, torch.Tensor) else np.asarray(r)
     e = rel_err(x, r)
     assert e <= tol, f"{what}: relative error {e:.3e} > {tol:.1e}"
     return e

@@ -34,7 +34,7 @@ def L():
 def test_header_declares_the_hot_path():
     names = declared()
     for n in ("tl_sym_inverse", "tl_christoffel", "tl_cov_deriv", "tl_dtg", "tl_dtg_chain",
-              "tl_dtg_chain_bwd", "tl_batch_plan_create", "tl_batch_plan_launch",
+              "tl_dtg_chain_bwd", "tl_dtg_chain_fwd_bwd", "tl_batch_plan_create", "tl_batch_plan_launch",
               "tl_batch_plan_destroy"):
         assert n in names
 
@@ -151,6 +151,26 @@ def test_bwd_outputs_may_not_overlap(L):
     ins = [cf(BASE + i * MB, n) for i in range(6)]
     outs = [f(BASE + 10 * MB, n), f(BASE + 10 * MB + 8 * 40, n)] + [f(None, 0)] * 4
     assert L.tl_dtg_chain_bwd(n, *ins, *outs, None, None) == _abi.TL_ERR_ALIAS
+
+
+def test_fwd_bwd_validation(L):
+    n = 32
+    ins = [cf(BASE + i * MB, n) for i in range(7)]
+    none = [f(None, 0)] * 7
+    assert L.tl_dtg_chain_fwd_bwd(n, *ins, *none, None, None) == _abi.TL_ERR_NULL
+    outs = [f(BASE + 10 * MB, n)] + [f(None, 0)] * 6
+    bad = list(ins)
+    bad[6] = cf(None, n)                             # the cotangent w
+    assert L.tl_dtg_chain_fwd_bwd(n, *bad, *outs, None, None) == _abi.TL_ERR_NULL
+    assert b"w" in L.tl_last_error()
+    # d_t g overlapping g_bar
+    outs = [f(BASE + 10 * MB, n), f(BASE + 10 * MB + 8 * 100, n)] + [f(None, 0)] * 5
+    assert L.tl_dtg_chain_fwd_bwd(n, *ins, *outs, None, None) == _abi.TL_ERR_ALIAS
+    # d beta (read here, unlike in the adjoint) overlapping an output
+    outs = [f(BASE + 3 * MB + 8, n)] + [f(None, 0)] * 6
+    assert L.tl_dtg_chain_fwd_bwd(n, *ins, *outs, None, None) == _abi.TL_ERR_ALIAS
+    assert L.tl_dtg_chain_fwd_bwd(-2, *ins, *outs, None, None) == _abi.TL_ERR_SIZE
+    assert L.tl_dtg_chain_fwd_bwd(0, *ins, *none, None, None) == _abi.TL_OK
 
 
 def test_unfused_validation(L):

@@ -6,7 +6,7 @@ import torch
 
 import oracle
 from gpu_util import DevField, assert_close, dev, need_gpu
-from paper_1804_10120_amd import dtg_chain, tl_dtg_chain, tl_dtg_chain_bwd
+from paper_1804_10120_amd import dtg_chain, tl_dtg_chain, tl_dtg_chain_bwd, tl_dtg_chain_fwd_bwd
 from paper_1804_10120_amd.synth import config_seed, make_fields
 
 pytestmark = pytest.mark.gpu
@@ -144,3 +144,82 @@ def test_finite_differences_8cubed():
             fm[k][c] -= h
             fd[c] = (loss(fp) - loss(fm)) / (2 * h)
         assert_close(got[k], fd, tol=1e-6, what=f"FD {k}")
+
+
+# --------------------------------------------------------------------------- fused forward + adjoint
+
+def _fwd_bwd(f, tune=None, want=None, **kw):
+    return tl_dtg_chain_fwd_bwd(*[dev(f[k]) for k in KEYS], dev(f["W"]), want=want, tune=tune,
+                                **kw)
+
+
+@pytest.mark.parametrize("n", [1, 3, 64, 1000, 4097, 40001])
+@pytest.mark.parametrize("tune", TUNES, ids=_tid)
+def test_fwd_bwd_vs_oracle(n, tune):
+    f = make_fields(n, seed=300 + n)
+    ref = _vjp_ref(f)
+    dtg, grads = _fwd_bwd(f, tune)
+    assert_close(dtg, oracle.dtg_chain(*[f[k] for k in KEYS]), what="d_t g")
+    for k, x in zip(KEYS, grads):
+        assert_close(x, ref[k], what=f"{k}_bar")
+
+
+def test_fwd_bwd_matches_the_two_kernels():
+    """Same values as tl_dtg_chain followed by tl_dtg_chain_bwd (the same
+    per-point arithmetic, though the compiler may contract it differently)."""
+    n = 20000
+    f = make_fields(n, seed=31)
+    dtg, grads = _fwd_bwd(f)
+    assert_close(dtg, tl_dtg_chain(*[dev(f[k]) for k in KEYS]), what="d_t g vs forward kernel")
+    for k, a, b in zip(KEYS, grads, _bwd(f)):
+        assert_close(a, b, what=f"{k}_bar vs adjoint kernel")
+
+
+@pytest.mark.parametrize("want", [(1, 0, 0, 0, 0, 0, 0), (0, 1, 1, 0, 0, 0, 0),
+                                  (0, 0, 0, 1, 1, 1, 1), (1, 0, 1, 0, 1, 0, 1)])
+def test_fwd_bwd_output_subsets(want):
+    n = 777
+    f = make_fields(n, seed=37)
+    ref = _vjp_ref(f)
+    dtg, grads = _fwd_bwd(f, want=want)
+    if want[0]:
+        assert_close(dtg, oracle.dtg_chain(*[f[k] for k in KEYS]), what="d_t g subset")
+    else:
+        assert dtg is None
+    for k, w, x in zip(KEYS, want[1:], grads):
+        if w:
+            assert_close(x, ref[k], what=f"{k}_bar subset")
+        else:
+            assert x is None
+
+
+def test_fwd_bwd_guard_bands_and_padding():
+    n = 2111
+    f = make_fields(n, seed=41)
+    ref = _vjp_ref(f)
+    ins = [DevField(f[k], pad=5, offset=3) for k in KEYS + ("W",)]
+    dtg = DevField.empty(6, n, pad=2, offset=1)
+    outs = [DevField.empty(c, n, pad=3, offset=1) for c in (6, 18, 3, 9, 6, 1)]
+    tl_dtg_chain_fwd_bwd(*[x.view for x in ins], dtg.view, [o.view for o in outs])
+    torch.cuda.synchronize()
+    assert_close(dtg.view, oracle.dtg_chain(*[f[k] for k in KEYS]), what="d_t g padded")
+    assert dtg.canaries_intact()
+    for k, o in zip(KEYS, outs):
+        assert_close(o.view, ref[k], what=f"{k}_bar padded")
+        assert o.canaries_intact()
+
+
+def test_fwd_bwd_full_size_sampled():
+    """128^3 points in the benchmark's launch shape; the oracle checks 4096
+    sampled points (each output point depends only on its own inputs)."""
+    n = 128 ** 3
+    f = make_fields(n, seed=config_seed(3), fields=KEYS + ("W",))
+    dtg, grads = _fwd_bwd(f)
+    idx = np.sort(np.random.default_rng(5).choice(n, 4096, replace=False))
+    idx[-1] = n - 1
+    sub = {k: np.ascontiguousarray(v[:, idx]) for k, v in f.items()}
+    ref = _vjp_ref(sub)
+    ti = torch.from_numpy(idx).cuda()
+    assert_close(dtg[:, ti], oracle.dtg_chain(*[sub[k] for k in KEYS]), what="d_t g 128^3")
+    for k, x in zip(KEYS, grads):
+        assert_close(x[:, ti], ref[k], what=f"{k}_bar 128^3")
