@@ -274,7 +274,7 @@ def main():
     import torch
     from paper_1804_10120_amd import (BatchPlan, tl_christoffel, tl_cov_deriv, tl_dtg,
                                       tl_dtg_chain, tl_dtg_chain_bwd, tl_dtg_chain_fwd_bwd,
-                                      tl_sym_inverse)
+                                      tl_sym_inverse, empty_field, to_field)
     from paper_1804_10120_amd.ops import record
     from paper_1804_10120_amd.synth import config_seed, domain_edges, make_fields
 
@@ -440,18 +440,25 @@ def main():
 
         log("[bench] 256 subgrids")
         edges = domain_edges(256, seed=config_seed(4))
-        doms = []
-        for i, e in enumerate(edges):
-            fe = make_fields(int(e) ** 3, seed=config_seed(4) * 1000 + i, fields=KEYS)
-            doms.append({k: torch.from_numpy(v).to(device) for k, v in fe.items()})
+        hosts = [make_fields(int(e) ** 3, seed=config_seed(4) * 1000 + i, fields=KEYS)
+                 for i, e in enumerate(edges)]
         npts = sum(int(e) ** 3 for e in edges)
+        # the same subgrids with ld = n (contiguous [C, n] tensors)
+        flat = [{k: torch.from_numpy(v).to(device) for k, v in fe.items()} for fe in hosts]
+        plan = BatchPlan(flat)
+        _, (ms_flat,) = time_calls([[plan.run]], 20, 3)
+        plan.close()
+        del flat, plan
+        # each subgrid's fields with ld padded to a multiple of 16 doubles
+        doms = [{k: to_field(v, device=device) for k, v in fe.items()} for fe in hosts]
+        del hosts
         plan = BatchPlan(doms)
         _, (ms_graph,) = time_calls([[plan.run]], 20, 3)
+        outs = [empty_field(6, e["K"].shape[1], device=device) for e in doms]
         with record() as many:
-            for e in doms:
-                tl_dtg_chain(*[e[k] for k in KEYS])
+            for e, o in zip(doms, outs):
+                tl_dtg_chain(*[e[k] for k in KEYS], o)
         ms_many, _ = time_calls([many], 10, 2)
-        outs = [torch.empty_like(e["K"]) for e in doms]
         graph256 = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph256):    # the 256 plain launches, captured
             for e, o in zip(doms, outs):
@@ -466,7 +473,9 @@ def main():
             "separate_launches_points_per_s": npts / (ms_many * 1e-3),
             "separate_launches_graph_us": ms_g256 * 1e3,
             "separate_launches_graph_points_per_s": npts / (ms_g256 * 1e-3),
-            "separate_launches_match_batched": same}
+            "separate_launches_match_batched": same,
+            "ld_unpadded_us": ms_flat * 1e3,
+            "ld_unpadded_GB_s": rate(BYTES["dtg_chain_batched"] * npts, ms_flat)}
         plan.close()
         del doms, many, outs, graph256
         log("[bench] the paper's benchmark expressions, grid-size sweep")

@@ -255,3 +255,17 @@ def test_batch_overlap_check_scales(L):
     assert L.tl_batch_plan_create(doms, nd, None, ctypes.byref(plan)) == _abi.TL_ERR_ALIAS
     assert time.perf_counter() - t0 < 5.0
     assert b"dtg" in L.tl_last_error() and b"dbeta" in L.tl_last_error()
+
+
+def test_padded_fields():
+    import numpy as np
+    import torch
+    from paper_1804_10120_amd import empty_field, padded_ld, to_field
+    assert [padded_ld(n) for n in (0, 1, 16, 17, 19683)] == [16, 16, 16, 32, 19696]
+    f = empty_field(18, 1000)
+    assert f.shape == (18, 1000) and f.stride() == (1008, 1) and f.dtype == torch.float64
+    x = np.random.default_rng(0).standard_normal((6, 27 ** 3))
+    t = to_field(x)
+    assert t.stride(0) % 16 == 0 and np.array_equal(t.numpy(), x)
+    a = to_field(np.arange(5.0))
+    assert a.shape == (1, 5) and a.stride(0) == 16

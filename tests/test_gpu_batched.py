@@ -121,3 +121,19 @@ def test_full_multidomain_workload():
         if not torch.equal(plain, plan.outputs[d]):
             assert_close(plan.outputs[d], plain.cpu().numpy(), what=f"subgrid {d} vs plain")
     plan.close()
+
+
+def test_padded_subgrids():
+    """Subgrids in fields whose leading dimension is padded to 16 doubles (the
+    layout the benchmark uses), outputs allocated by the plan the same way."""
+    from paper_1804_10120_amd import to_field
+    sizes = [27, 1000, 4913, 17 ** 3, 1, 16]
+    hosts = [make_fields(n, seed=5000 + d) for d, n in enumerate(sizes)]
+    devs = [{k: to_field(f[k], device="cuda") for k in KEYS} for f in hosts]
+    plan = BatchPlan(devs)
+    plan.run()
+    torch.cuda.synchronize()
+    for out, n in zip(plan.outputs, sizes):
+        assert out.shape == (6, n) and out.stride(0) % 16 == 0
+    _check(plan, hosts, devs)
+    plan.close()
