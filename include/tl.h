@@ -76,12 +76,18 @@ typedef struct { double* ptr; int64_t ld; } tl_field;
  *   flags      TL_TUNE_NT: non-temporal (streaming) loads and stores;
  *              TL_TUNE_XCD: the blocks resident on one XCD (workgroups go to
  *              the 8 XCDs round-robin) take consecutive tiles, so each XCD
- *              streams through contiguous address ranges
+ *              streams through contiguous address ranges;
+ *              TL_TUNE_PTR64: address every component with a 64-bit pointer.
+ *              Without it, a call whose fields each span less than 4 GiB
+ *              and that uses TL_TUNE_NT addresses them through one buffer
+ *              descriptor per field and 32-bit offsets (fewer instructions
+ *              per access; the results are identical)
  *   grid_mult  0: one tile of block*ppt points per block; k > 0: a persistent
  *              grid of k blocks per compute unit striding over the tiles   */
 typedef struct { int32_t block, ppt, flags, grid_mult; } tl_tune;
 #define TL_TUNE_NT 1
 #define TL_TUNE_XCD 2
+#define TL_TUNE_PTR64 4
 
 /* ---- Unfused steps ------------------------------------------------------ */
 

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(PKG, "libtl.so")
 TL_OK, TL_ERR_NULL, TL_ERR_SIZE, TL_ERR_ALIAS, TL_ERR_ALIGN, TL_ERR_HIP, TL_ERR_INVALID = range(7)
 TL_TUNE_NT = 1
 TL_TUNE_XCD = 2
+TL_TUNE_PTR64 = 4
 EXPRS = ("assign1", "assign2", "assign3", "add1", "add2", "add3", "mult1", "mult2", "mult3",
          "contract1", "contract2", "contract3", "kij")
 TWIN_SHAPES = ((1, 1), (6, 6), (24, 18), (30, 9), (16, 6), (43, 6), (40, 43))

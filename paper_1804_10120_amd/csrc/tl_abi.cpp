@@ -46,6 +46,7 @@ struct Checker {
   int64_t n;
   std::vector<Span> spans;
   bool vec_ok = true;  // every field 16-byte aligned with even ld (for ppt = 2)
+  bool buf_ok = true;  // every field spans less than 4 GiB (32-bit buffer offsets)
   tl_status st = TL_OK;
 
   explicit Checker(int64_t n_) : n(n_) {}
@@ -74,6 +75,7 @@ struct Checker {
     }
     if (a % 16 != 0 || (ncomp > 1 && ld % 2 != 0)) vec_ok = false;
     const uintptr_t bytes = static_cast<uintptr_t>((ncomp - 1) * ld + n) * 8u;
+    if (bytes > 0xFFFFFFFFull) buf_ok = false;
     spans.push_back({name, a, a + bytes, output});
   }
 
@@ -164,7 +166,8 @@ tl::Resolved defaults(tl::KernelId k, int64_t n) {
   return r;
 }
 
-tl_status resolve(tl::KernelId k, const tl_tune* t, bool vec_ok, int64_t n, tl::Resolved* out) {
+tl_status resolve(tl::KernelId k, const tl_tune* t, bool vec_ok, bool buf_ok, int64_t n,
+                  tl::Resolved* out) {
   tl::Resolved r = defaults(k, n);
   if (t != nullptr) {
     if (t->block != 0) {
@@ -177,15 +180,17 @@ tl_status resolve(tl::KernelId k, const tl_tune* t, bool vec_ok, int64_t n, tl::
       if (t->ppt != 1 && t->ppt != 2) return fail(TL_ERR_INVALID, "tune.ppt=%d not in {1,2}", t->ppt);
       r.ppt = t->ppt;
     }
-    if (t->flags & ~(TL_TUNE_NT | TL_TUNE_XCD))
+    if (t->flags & ~(TL_TUNE_NT | TL_TUNE_XCD | TL_TUNE_PTR64))
       return fail(TL_ERR_INVALID, "tune.flags=%d has unknown bits", t->flags);
     r.nt = (t->flags & TL_TUNE_NT) != 0;
     r.xcd = (t->flags & TL_TUNE_XCD) != 0;
+    if (t->flags & TL_TUNE_PTR64) buf_ok = false;
     if (t->grid_mult < 0 || t->grid_mult > 1024)
       return fail(TL_ERR_INVALID, "tune.grid_mult=%d not in [0,1024]", t->grid_mult);
     r.grid_mult = t->grid_mult;
   }
   if (!vec_ok) r.ppt = 1;
+  r.buf = buf_ok;
   r.num_cu = num_cus();
   *out = r;
   return TL_OK;
@@ -194,7 +199,7 @@ tl_status resolve(tl::KernelId k, const tl_tune* t, bool vec_ok, int64_t n, tl::
 tl_status run(tl::KernelId k, const Checker& c, const tl_tune* tune, const tl::KArgs& a,
               void* stream) {
   tl::Resolved r;
-  tl_status s = resolve(k, tune, c.vec_ok, c.n, &r);
+  tl_status s = resolve(k, tune, c.vec_ok, c.buf_ok, c.n, &r);
   if (s != TL_OK) return s;
   hipError_t e = tl::launch_kernel(k, r, a, c.n, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -258,7 +263,7 @@ tl_status run_generated(const char* name, int64_t n, const tl_cfield* in, int32_
   for (int f = 0; f < nin; ++f) set_in(a, f, in[f]);
   for (int f = 0; f < nout; ++f) set_out(a, f, out[f]);
   Resolved r;
-  tl_status s = resolve(KernelId::Chain, tune, c.vec_ok, n, &r);
+  tl_status s = resolve(KernelId::Chain, tune, c.vec_ok, c.buf_ok, n, &r);
   if (s != TL_OK) return s;
   hipError_t e = launch(r, a, n, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "generated kernel launch");
@@ -517,7 +522,7 @@ tl_status tl_expr(int32_t expr, int64_t n, const tl_cfield* in, int32_t nin, tl_
   for (int f = 0; f < k; ++f) set_in(a, f, in[f]);
   set_out(a, 0, out);
   tl::Resolved r;
-  tl_status s = resolve(tl::KernelId::Chain, tune, c.vec_ok, n, &r);
+  tl_status s = resolve(tl::KernelId::Chain, tune, c.vec_ok, c.buf_ok, n, &r);
   if (s != TL_OK) return s;
   hipError_t e = tl::launch_expr(expr, r, a, n, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "expression launch");
@@ -541,7 +546,7 @@ tl_status tl_bw_twin(int64_t n, int32_t nin, tl_cfield in, int32_t nout, tl_fiel
   set_in(a, 0, in);
   set_out(a, 0, out);
   tl::Resolved r;
-  tl_status s = resolve(tl::KernelId::Chain, tune, c.vec_ok, n, &r);
+  tl_status s = resolve(tl::KernelId::Chain, tune, c.vec_ok, c.buf_ok, n, &r);
   if (s != TL_OK) return s;
   hipError_t e = tl::launch_twin(nin, nout, r, a, n, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "twin launch");
@@ -574,7 +579,7 @@ tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tun
   // Per-domain validation, then overlap of every output with every field of
   // every domain.
   std::vector<Span> all;
-  bool vec_ok = true;
+  bool vec_ok = true, buf_ok = true;
   int64_t points = 0;
   for (int32_t d = 0; d < ndom; ++d) {
     const tl_domain& x = doms[d];
@@ -584,6 +589,7 @@ tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tun
     chain_fields(c, "", x.g, x.dg, x.beta, x.dbeta, x.K, x.alpha, x.dtg);
     if (c.overlaps() != TL_OK) return fail(c.st, "domain %d: %s", d, g_last_error.c_str());
     vec_ok = vec_ok && c.vec_ok;
+    buf_ok = buf_ok && c.buf_ok;
     all.insert(all.end(), c.spans.begin(), c.spans.end());
     points += x.n;
   }
@@ -595,7 +601,7 @@ tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tun
   }
 
   tl::Resolved r;
-  tl_status s = resolve(tl::KernelId::ChainBatched, tune, vec_ok, points, &r);
+  tl_status s = resolve(tl::KernelId::ChainBatched, tune, vec_ok, buf_ok, points, &r);
   if (s != TL_OK) return s;
 
   std::vector<tl::BatchDomain> h(ndom);
@@ -742,7 +748,7 @@ tl_status tl_kernel_info(const char* kernel, const tl_tune* tune, tl_kernel_attr
     if (std::strcmp(kExprName[e], kernel) == 0) expr = e;
   if (id == nullptr && expr < 0) return fail(TL_ERR_INVALID, "unknown kernel '%s'", kernel);
   tl::Resolved r;
-  tl_status s = resolve(id ? *id : tl::KernelId::Chain, tune, true, int64_t(1) << 24, &r);
+  tl_status s = resolve(id ? *id : tl::KernelId::Chain, tune, true, true, int64_t(1) << 24, &r);
   if (s != TL_OK) return s;
   const void* fn = id ? tl::kernel_address(*id, r) : tl::expr_address(expr, r);
   if (fn == nullptr) return fail(TL_ERR_INVALID, "no instantiation for this tuning");

@@ -100,6 +100,10 @@ struct OpMult4 {
 #pragma unroll
           for (int l = 0; l < 3; ++l) st(0, ((i * 3 + j) * 3 + k) * 3 + l, bcd * E[l]);
         }
+        // Keep the scheduler from forming many outputs ahead of their stores:
+        // the kernel is bound by its 81 store streams, and registers held by
+        // early products cost occupancy.
+        __builtin_amdgcn_sched_barrier(0);
       }
   }
 };

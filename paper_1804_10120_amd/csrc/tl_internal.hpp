@@ -38,6 +38,7 @@ struct Resolved {
   bool xcd = false;  // XCD-contiguous tile order (grid is then a multiple of 8)
   int grid_mult = 0;
   int num_cu = 256;
+  bool buf = false;  // buffer addressing (every field's extent below 4 GiB)
 };
 
 inline int64_t grid_size(const Resolved& r, int64_t ntiles) {

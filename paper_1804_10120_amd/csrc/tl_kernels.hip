@@ -16,7 +16,7 @@ namespace tl {
 // consecutive tiles of a block are mostly in the same subgrid and its
 // descriptor is fetched again only when the subgrid changes.  With chunk = 1
 // and one block per tile this is a plain (non-persistent) launch.
-template <int BLOCK, int PPT, bool NT>
+template <int BLOCK, int PPT, bool NT, bool BUF>
 __global__ __launch_bounds__(BLOCK) void k_chain_batched(const BatchDomain* __restrict__ doms,
                                                           const int64_t* __restrict__ start,
                                                           const int32_t* __restrict__ tile_dom,
@@ -26,6 +26,7 @@ __global__ __launch_bounds__(BLOCK) void k_chain_batched(const BatchDomain* __re
   const int64_t t1 = t0 + chunk < ntiles ? t0 + chunk : ntiles;
   int32_t cur = -1;
   KArgs a;
+  Bufs<OpChain> b;
   int64_t n = 0, s0 = 0;
   for (int64_t t = t0; t < t1; ++t) {
     const int32_t d = tile_dom[t];
@@ -34,8 +35,10 @@ __global__ __launch_bounds__(BLOCK) void k_chain_batched(const BatchDomain* __re
       a = doms[d].args;
       n = doms[d].n;
       s0 = start[d];
+      if constexpr (BUF) b = make_bufs<OpChain>(a, n);
     }
-    tile<OpChain, BLOCK, PPT, NT>(a, n, t - s0);
+    if constexpr (BUF) tile_buf<OpChain, BLOCK, PPT, NT>(a, b, n, t - s0);
+    else tile<OpChain, BLOCK, PPT, NT>(a, n, t - s0);
   }
 }
 
@@ -52,16 +55,21 @@ __global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst,
   }
 }
 
-template <int BLOCK, int PPT, bool NT>
+template <int BLOCK, int PPT, bool NT, bool BUF>
 static const void* batched_ptr() {
-  return reinterpret_cast<const void*>(&k_chain_batched<BLOCK, PPT, NT>);
+  return reinterpret_cast<const void*>(&k_chain_batched<BLOCK, PPT, NT, BUF>);
+}
+
+template <int BLOCK, int PPT>
+static const void* batched_ptr_p(const Resolved& r) {
+  if (!r.nt) return batched_ptr<BLOCK, PPT, false, false>();
+  return r.buf ? batched_ptr<BLOCK, PPT, true, true>() : batched_ptr<BLOCK, PPT, true, false>();
 }
 
 static const void* ptr_batched(const Resolved& r) {
-#define TL_PTR(B)                                                                         \
-  case B:                                                                                 \
-    return r.ppt == 2 ? (r.nt ? batched_ptr<B, 2, true>() : batched_ptr<B, 2, false>()) \
-                      : (r.nt ? batched_ptr<B, 1, true>() : batched_ptr<B, 1, false>());
+#define TL_PTR(B) \
+  case B:         \
+    return r.ppt == 2 ? batched_ptr_p<B, 2>(r) : batched_ptr_p<B, 1>(r);
   switch (r.block) {
     TL_PTR(64)
     TL_PTR(128)

@@ -54,6 +54,45 @@ __device__ inline void store2(double* p, dbl2 v) {
   else *q = v;
 }
 
+// ---- Buffer addressing.  A wave of a wide body addresses up to 83 component
+// streams; with 64-bit pointers every one costs a 64-bit scalar multiply-add
+// and the live addresses overflow the scalar registers.  Instead each field
+// gets one buffer descriptor (base and extent in bytes) and every access is
+// base + lane offset (p * 8, a vector register shared by all components) +
+// component offset (c * ld * 8, a 32-bit scalar).  Used when every field's
+// extent is below 4 GiB (checked by the host).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // raw (unstructured) buffer, gfx9 family
+constexpr int kCpolNT = 2;              // the non-temporal cache-policy bit
+
+__device__ inline rsrc_t make_rsrc(const double* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), 0,
+                                           static_cast<int>(static_cast<uint32_t>(bytes)),
+                                           kRsrcWord3);
+}
+template <bool NT>
+__device__ inline double bload1(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double,
+                            __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, NT ? kCpolNT : 0));
+}
+template <bool NT>
+__device__ inline dbl2 bload2(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(dbl2,
+                            __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, NT ? kCpolNT : 0));
+}
+template <bool NT>
+__device__ inline void bstore1(rsrc_t r, uint32_t voff, uint32_t soff, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff,
+                                        NT ? kCpolNT : 0);
+}
+template <bool NT>
+__device__ inline void bstore2(rsrc_t r, uint32_t voff, uint32_t soff, dbl2 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff,
+                                         NT ? kCpolNT : 0);
+}
+
 // Offsets of each field's first component in the gathered per-point vector.
 template <int NF>
 struct Offsets {
@@ -155,6 +194,93 @@ __device__ inline void points_tail(const KArgs& a, int64_t p, int64_t n) {
   }
 }
 
+// One descriptor and one component stride (bytes) per field.
+template <class Op>
+struct Bufs {
+  rsrc_t in[Op::NF_IN], out[Op::NF_OUT];
+  uint32_t ldin8[Op::NF_IN], ldout8[Op::NF_OUT];
+};
+
+template <class Op>
+__device__ inline Bufs<Op> make_bufs(const KArgs& a, int64_t n) {
+  Bufs<Op> b;
+#pragma unroll
+  for (int f = 0; f < Op::NF_IN; ++f) {
+    b.in[f] = make_rsrc(a.in[f], ((Op::fin[f] - 1) * a.ldin[f] + n) * 8);
+    b.ldin8[f] = static_cast<uint32_t>(a.ldin[f] * 8);
+  }
+#pragma unroll
+  for (int f = 0; f < Op::NF_OUT; ++f) {
+    b.out[f] = make_rsrc(a.out[f], ((Op::fout[f] - 1) * a.ldout[f] + n) * 8);
+    b.ldout8[f] = static_cast<uint32_t>(a.ldout[f] * 8);
+  }
+  return b;
+}
+
+template <class Op, bool NT>
+__device__ inline void point_stream_buf(const Bufs<Op>& b, uint32_t p8) {
+  Op::stream([&](int f, int c) { return bload1<NT>(b.in[f], p8, c * b.ldin8[f]); },
+             [&](int f, int c, double v) { bstore1<NT>(b.out[f], p8, c * b.ldout8[f], v); });
+}
+
+template <class Op, int PPT, bool NT>
+__device__ inline void points_full_buf(const KArgs& a, const Bufs<Op>& b, uint32_t p8) {
+  constexpr auto io = in_offsets<Op>();
+  constexpr auto oo = out_offsets<Op>();
+  if constexpr (PPT == 1) {
+    double x[Op::NIN], y[Op::NOUT];
+#pragma unroll
+    for (int f = 0; f < Op::NF_IN; ++f)
+#pragma unroll
+      for (int c = 0; c < Op::fin[f]; ++c) x[io.v[f] + c] = bload1<NT>(b.in[f], p8, c * b.ldin8[f]);
+    Op::apply(x, y);
+#pragma unroll
+    for (int f = 0; f < Op::NF_OUT; ++f) {
+      if (a.out[f] == nullptr) continue;
+#pragma unroll
+      for (int c = 0; c < Op::fout[f]; ++c)
+        bstore1<NT>(b.out[f], p8, c * b.ldout8[f], y[oo.v[f] + c]);
+    }
+  } else {
+    static_assert(PPT == 2, "PPT is 1 or 2");
+    dbl2 x2[Op::NIN];
+#pragma unroll
+    for (int f = 0; f < Op::NF_IN; ++f)
+#pragma unroll
+      for (int c = 0; c < Op::fin[f]; ++c) x2[io.v[f] + c] = bload2<NT>(b.in[f], p8, c * b.ldin8[f]);
+    double x[Op::NIN], y0[Op::NOUT], y1[Op::NOUT];
+#pragma unroll
+    for (int q = 0; q < Op::NIN; ++q) x[q] = x2[q].x;
+    Op::apply(x, y0);
+#pragma unroll
+    for (int q = 0; q < Op::NIN; ++q) x[q] = x2[q].y;
+    Op::apply(x, y1);
+#pragma unroll
+    for (int f = 0; f < Op::NF_OUT; ++f) {
+      if (a.out[f] == nullptr) continue;
+#pragma unroll
+      for (int c = 0; c < Op::fout[f]; ++c) {
+        dbl2 v;
+        v.x = y0[oo.v[f] + c];
+        v.y = y1[oo.v[f] + c];
+        bstore2<NT>(b.out[f], p8, c * b.ldout8[f], v);
+      }
+    }
+  }
+}
+
+template <class Op, int BLOCK, int PPT, bool NT>
+__device__ inline void tile_buf(const KArgs& a, const Bufs<Op>& b, int64_t n, int64_t t) {
+  const int64_t p = (t * BLOCK + threadIdx.x) * PPT;
+  if constexpr (is_stream<Op>::value) {
+    static_assert(PPT == 1, "streaming bodies take one point per lane");
+    if (p < n) point_stream_buf<Op, NT>(b, static_cast<uint32_t>(p * 8));
+  } else {
+    if (p + PPT <= n) points_full_buf<Op, PPT, NT>(a, b, static_cast<uint32_t>(p * 8));
+    else if (p < n) points_tail<Op, PPT>(a, p, n);
+  }
+}
+
 template <class Op, int BLOCK, int PPT, bool NT>
 __device__ inline void tile(const KArgs& a, int64_t n, int64_t t) {
   const int64_t p = (t * BLOCK + threadIdx.x) * PPT;
@@ -178,23 +304,42 @@ __device__ inline int64_t logical_block(int32_t xcd) {
   return (b & 7) * per + (b >> 3);
 }
 
-template <class Op, int BLOCK, int PPT, bool NT>
+// BUF: buffer addressing (every field's extent below 4 GiB); otherwise 64-bit
+// pointers.
+template <class Op, int BLOCK, int PPT, bool NT, bool BUF>
 __global__ __launch_bounds__(BLOCK) void k_points(KArgs a, int64_t n, int64_t ntiles, int32_t xcd) {
-  for (int64_t t = logical_block(xcd); t < ntiles; t += gridDim.x) tile<Op, BLOCK, PPT, NT>(a, n, t);
+  if constexpr (BUF) {
+    const Bufs<Op> b = make_bufs<Op>(a, n);
+    for (int64_t t = logical_block(xcd); t < ntiles; t += gridDim.x)
+      tile_buf<Op, BLOCK, PPT, NT>(a, b, n, t);
+  } else {
+    for (int64_t t = logical_block(xcd); t < ntiles; t += gridDim.x)
+      tile<Op, BLOCK, PPT, NT>(a, n, t);
+  }
 }
 
 
-template <class Op, int BLOCK, int PPT, bool NT>
+template <class Op, int BLOCK, int PPT, bool NT, bool BUF>
 static const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&k_points<Op, BLOCK, PPT, NT>);
+  return reinterpret_cast<const void*>(&k_points<Op, BLOCK, PPT, NT, BUF>);
 }
 
-template <class Op, int BLOCK, int PPT, bool NT>
+template <class Op, int BLOCK, int PPT, bool NT, bool BUF>
 static hipError_t launch_one(const KArgs& a, int64_t n, int64_t ntiles, int64_t grid, int32_t xcd,
                              hipStream_t s) {
-  hipLaunchKernelGGL((k_points<Op, BLOCK, PPT, NT>), dim3(static_cast<unsigned>(grid)),
+  hipLaunchKernelGGL((k_points<Op, BLOCK, PPT, NT, BUF>), dim3(static_cast<unsigned>(grid)),
                      dim3(BLOCK), 0, s, a, n, ntiles, xcd);
   return hipGetLastError();
+}
+
+// Buffer addressing is instantiated with the non-temporal hint only (the
+// default); a request without it takes the pointer path.
+template <class Op, int BLOCK, int PPT>
+static hipError_t launch_p(const Resolved& r, const KArgs& a, int64_t n, int64_t ntiles,
+                           int64_t grid, int32_t x, hipStream_t s) {
+  if (!r.nt) return launch_one<Op, BLOCK, PPT, false, false>(a, n, ntiles, grid, x, s);
+  return r.buf ? launch_one<Op, BLOCK, PPT, true, true>(a, n, ntiles, grid, x, s)
+               : launch_one<Op, BLOCK, PPT, true, false>(a, n, ntiles, grid, x, s);
 }
 
 template <class Op, int BLOCK>
@@ -202,14 +347,10 @@ static hipError_t launch_b(const Resolved& r, const KArgs& a, int64_t n, int64_t
                            int64_t grid, hipStream_t s) {
   const int32_t x = r.xcd ? 1 : 0;
   if constexpr (is_stream<Op>::value) {
-    return r.nt ? launch_one<Op, BLOCK, 1, true>(a, n, ntiles, grid, x, s)
-                : launch_one<Op, BLOCK, 1, false>(a, n, ntiles, grid, x, s);
+    return launch_p<Op, BLOCK, 1>(r, a, n, ntiles, grid, x, s);
   } else {
-    if (r.ppt == 2)
-      return r.nt ? launch_one<Op, BLOCK, 2, true>(a, n, ntiles, grid, x, s)
-                  : launch_one<Op, BLOCK, 2, false>(a, n, ntiles, grid, x, s);
-    return r.nt ? launch_one<Op, BLOCK, 1, true>(a, n, ntiles, grid, x, s)
-                : launch_one<Op, BLOCK, 1, false>(a, n, ntiles, grid, x, s);
+    if (r.ppt == 2) return launch_p<Op, BLOCK, 2>(r, a, n, ntiles, grid, x, s);
+    return launch_p<Op, BLOCK, 1>(r, a, n, ntiles, grid, x, s);
   }
 }
 
@@ -228,13 +369,18 @@ static hipError_t launch_op(const Resolved& r, const KArgs& a, int64_t n, hipStr
   }
 }
 
+template <class Op, int BLOCK, int PPT>
+static const void* ptr_p(const Resolved& r) {
+  if (!r.nt) return kernel_ptr<Op, BLOCK, PPT, false, false>();
+  return r.buf ? kernel_ptr<Op, BLOCK, PPT, true, true>() : kernel_ptr<Op, BLOCK, PPT, true, false>();
+}
+
 template <class Op>
 static const void* ptr_op(const Resolved& r) {
   constexpr int P2 = is_stream<Op>::value ? 1 : 2;
-#define TL_PTR(B)                                                                         \
-  case B:                                                                                 \
-    return r.ppt == 2 ? (r.nt ? kernel_ptr<Op, B, P2, true>() : kernel_ptr<Op, B, P2, false>()) \
-                      : (r.nt ? kernel_ptr<Op, B, 1, true>() : kernel_ptr<Op, B, 1, false>());
+#define TL_PTR(B) \
+  case B:         \
+    return r.ppt == 2 ? ptr_p<Op, B, P2>(r) : ptr_p<Op, B, 1>(r);
   switch (r.block) {
     TL_PTR(64)
     TL_PTR(128)

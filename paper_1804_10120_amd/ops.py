@@ -121,7 +121,7 @@ def _stream(device, stream):
 
 def make_tune(tune):
     """None (library default), a Tune, a dict with keys block, ppt, nt, xcd,
-    grid_mult (missing numbers mean the default; flags default to off), or a
+    ptr64, grid_mult (missing numbers mean the default; flags default to off), or a
     tuple (block, ppt, flags, grid_mult) -> Tune pointer or None.  (The tl_*
     functions also accept tune="auto", the autotuner's cached shape.)"""
     if tune is None:
@@ -131,7 +131,8 @@ def make_tune(tune):
     elif isinstance(tune, dict):
         t = Tune(int(tune.get("block", 0)), int(tune.get("ppt", 0)),
                  int(tune.get("flags", 0)) | (_abi.TL_TUNE_NT if tune.get("nt") else 0)
-                 | (_abi.TL_TUNE_XCD if tune.get("xcd") else 0),
+                 | (_abi.TL_TUNE_XCD if tune.get("xcd") else 0)
+                 | (_abi.TL_TUNE_PTR64 if tune.get("ptr64") else 0),
                  int(tune.get("grid_mult", 0)))
     else:
         t = Tune(*[int(v) for v in tune])

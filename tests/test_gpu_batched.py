@@ -40,8 +40,9 @@ def _check(plan, hosts, devs, tune=None):
 @pytest.mark.parametrize("tune", [None, dict(block=64, ppt=1, grid_mult=1),
                                   dict(block=256, ppt=2, nt=True, grid_mult=2),
                                   dict(block=128, ppt=1, grid_mult=0),
-                                  dict(block=64, ppt=1, nt=True, xcd=True, grid_mult=1)],
-                         ids=["default", "b64", "b256ppt2nt", "b128grid", "b64xcd"])
+                                  dict(block=64, ppt=1, nt=True, xcd=True, grid_mult=1),
+                                  dict(block=128, ppt=1, nt=True, ptr64=True)],
+                         ids=["default", "b64", "b256ppt2nt", "b128grid", "b64xcd", "b128ptr64"])
 def test_small_batch(tune):
     sizes = [1, 0, 63, 64, 65, 512, 1000, 4097, 0, 27, 8 ** 3, 12 ** 3, 3]
     hosts, devs = _domains(sizes, seed=1)

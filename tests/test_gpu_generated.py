@@ -13,7 +13,8 @@ from paper_1804_10120_amd.synth import make_expr_inputs, make_fields
 pytestmark = pytest.mark.gpu
 
 SIZES = [1, 65, 1000, 4097]
-TUNES = [None, dict(block=64, nt=True), dict(block=512, nt=True, xcd=True, grid_mult=1)]
+TUNES = [None, dict(block=64, nt=True), dict(block=512, nt=True, xcd=True, grid_mult=1),
+         dict(block=256, nt=True, xcd=True, ptr64=True)]
 
 
 @pytest.fixture(scope="module", autouse=True)
