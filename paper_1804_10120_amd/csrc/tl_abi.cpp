@@ -158,6 +158,12 @@ tl::Resolved defaults(tl::KernelId k, int64_t n) {
     r.block = 64;
     r.ppt = 1;
     r.xcd = false;
+  } else if (k == tl::KernelId::Chain) {
+    // measured: with buffer addressing the fused forward needs 62 registers
+    // at one point per lane (8 waves per SIMD) but 166 at two (3 waves)
+    r.block = 256;
+    r.ppt = 1;
+    r.xcd = false;
   } else {
     r.block = 512;
     r.ppt = 2;
