@@ -418,6 +418,26 @@ def main():
         assert torch.equal(gi_g, gi16)
         del graph, cs, gi16, e16, gi_g, ga_g
 
+        log("[bench] per-launch floor at tiny grids")
+        from paper_1804_10120_amd import tl_bw_copy, tl_expr
+        (_, e32), = device_sets(4096, 1, device, config_seed(1))
+        tiny = {}
+        for npt in (32, 4096):
+            cp_src = torch.rand(npt, dtype=torch.float64, device=device)
+            b3 = torch.rand(3, npt, dtype=torch.float64, device=device)
+            with record() as fl:
+                tl_bw_copy(cp_src)
+                tl_expr("assign1", b3)
+                tl_dtg_chain(*[e32[k][:, :npt] for k in KEYS])
+            _, per = time_calls([fl], 200, 20)
+            tiny[str(npt)] = dict(zip(("copy_us", "assign1_us", "dtg_chain_us"),
+                                      (ms * 1e3 for ms in per)))
+        tiny["note"] = ("one load and one store per point (copy), 3 and 3 (assign1) or 43 and 6 "
+                        "(dtg_chain) take about the same time per launch: a round trip to "
+                        "memory and the launch, not the lanes in flight, set the time")
+        rows["tiny_grid_floor"] = tiny
+        del e32, fl
+
         log("[bench] 64^3 with 4 rotating buffer sets")
         n64 = 64 ** 3
         s64 = device_sets(n64, 4, device, config_seed(2))
