@@ -38,6 +38,8 @@ BYTES = {"sym_inverse": 8 * 12, "christoffel": 8 * 42, "cov_deriv": 8 * 39, "dtg
          "dtg_chain": 8 * 49, "dtg_chain_bwd": 8 * 83, "dtg_chain_batched": 8 * 49,
          "dtg_chain_fwd_bwd": 8 * 98,
          "unfused_chain": 8 * 115}
+# (read, written) doubles per point of the kernels the step runs
+RW_DOUBLES = {"dtg_chain": (43, 6), "dtg_chain_bwd": (40, 43), "dtg_chain_fwd_bwd": (49, 49)}
 METRIC = "grid points/s + achieved HBM GB/s, fused FP64 chain fwd and fwd+bwd"
 
 
@@ -116,6 +118,30 @@ def copy_ceiling(device, reps=20):
     _, (ms,) = time_calls([calls], reps, 3)
     assert torch.equal(src[:4096], dst[:4096]) and torch.equal(src[-4096:], dst[-4096:])
     return rate(16 * n, ms)
+
+
+def direction_ceilings(device, reps=20):
+    """GB/s of the library's read-only and write-only references over 1 GiB."""
+    import torch
+    from paper_1804_10120_amd import tl_bw_read, tl_bw_write
+    from paper_1804_10120_amd.ops import record
+    n = 128 * 1024 * 1024
+    buf = torch.rand(n, dtype=torch.float64, device=device)
+    with record() as rd:
+        part = tl_bw_read(buf)
+    with record() as wr:
+        tl_bw_write(buf)
+    _, (ms_r,) = time_calls([rd], reps, 3)
+    _, (ms_w,) = time_calls([wr], reps, 3)
+    del part
+    return rate(8 * n, ms_r), rate(8 * n, ms_w)
+
+
+def rw_model(read_doubles, write_doubles, read_gbs, write_gbs):
+    """Ceiling of a kernel that reads and writes the given doubles per point if
+    its reads ran at the read-only rate and its writes at the write-only rate,
+    one after the other (the streaming copy matches this model)."""
+    return (read_doubles + write_doubles) / (read_doubles / read_gbs + write_doubles / write_gbs)
 
 
 def host_cpu():
@@ -325,10 +351,17 @@ def main():
                        "algorithmic_bytes_per_launch": BYTES[dom] * n,
                        "duration_us": ms_dom * 1e3}
 
-    log("[bench] copy ceiling")
+    log("[bench] copy, read-only and write-only ceilings")
     cgbs = copy_ceiling(device)
     res["copy_GB_s"] = cgbs
     res["roofline"]["frac_of_copy"] = achieved / cgbs
+    rgbs, wgbs = direction_ceilings(device)
+    res["read_only_GB_s"], res["write_only_GB_s"] = rgbs, wgbs
+    rd, wr = RW_DOUBLES[dom]
+    res["roofline"]["rw_model_GB_s"] = rw_model(rd, wr, rgbs, wgbs)
+    res["roofline"]["frac_of_rw_model"] = achieved / res["roofline"]["rw_model_GB_s"]
+    res["fwd"]["frac_of_rw_model"] = res["fwd"]["GB_s"] / rw_model(*RW_DOUBLES["dtg_chain"],
+                                                                   rgbs, wgbs)
 
     if not args.no_rows:
         rows = {}
@@ -342,7 +375,9 @@ def main():
         rows["fwd_bwd_one_kernel"] = {"us": ms_fb * 1e3, "points_per_s": n / (ms_fb * 1e-3),
                                       "GB_s": rate(BYTES["dtg_chain_fwd_bwd"] * n, ms_fb),
                                       "speedup_vs_two_kernels": ms_step / ms_fb,
-                                      "max_rel_diff_vs_two_kernels": diff}
+                                      "max_rel_diff_vs_two_kernels": diff,
+                                      "frac_of_rw_model": rate(BYTES["dtg_chain_fwd_bwd"] * n, ms_fb)
+                                      / rw_model(*RW_DOUBLES["dtg_chain_fwd_bwd"], rgbs, wgbs)}
         del ref, fb
         log("[bench] unfused steps")
         with record() as unf:

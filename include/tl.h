@@ -223,6 +223,19 @@ tl_status tl_expr_shape(int32_t expr, int32_t* nin, int32_t* in_ncomp, int32_t* 
  * a device bandwidth test (Sec. 4, measured bandwidth).  Non-overlapping. */
 tl_status tl_bw_copy(int64_t n, const double* src, double* dst, void* stream);
 
+/* Read-only and write-only references: with tl_bw_copy, the measured
+ * ceilings of each direction of traffic.  TL_BW_READ reads src[0..n) with
+ * 16-byte non-temporal loads; each of its blocks (at most TL_BW_READ_BLOCKS)
+ * writes the sum of its share of src to dst[block], so dst must hold
+ * TL_BW_READ_BLOCKS doubles, and the sum of those partial sums is the sum of
+ * src up to rounding (entries past the number of blocks are not written).
+ * TL_BW_WRITE writes dst[i] = 1 for i < n; src is ignored.  Another kind:
+ * TL_ERR_INVALID. */
+#define TL_BW_READ 1
+#define TL_BW_WRITE 2
+#define TL_BW_READ_BLOCKS 2048
+tl_status tl_bw_stream(int64_t n, int32_t kind, const double* src, double* dst, void* stream);
+
 /* Bandwidth twin of a row's access shape: reads the first nin components of
  * `in` and writes the first nout components of `out` (out_c = sum of the
  * inputs + c) with the library's launch machinery and tuning, and no other

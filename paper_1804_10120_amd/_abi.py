@@ -15,6 +15,9 @@ TL_OK, TL_ERR_NULL, TL_ERR_SIZE, TL_ERR_ALIAS, TL_ERR_ALIGN, TL_ERR_HIP, TL_ERR_
 TL_TUNE_NT = 1
 TL_TUNE_XCD = 2
 TL_TUNE_PTR64 = 4
+TL_BW_READ = 1
+TL_BW_WRITE = 2
+TL_BW_READ_BLOCKS = 2048
 EXPRS = ("assign1", "assign2", "assign3", "add1", "add2", "add3", "mult1", "mult2", "mult3",
          "contract1", "contract2", "contract3", "kij")
 TWIN_SHAPES = ((1, 1), (6, 6), (24, 18), (30, 9), (16, 6), (43, 6), (40, 43))
@@ -71,6 +74,7 @@ SIGNATURES = {
                            ctypes.POINTER(_I64)],
     "tl_batch_plan_destroy": [ctypes.c_void_p],
     "tl_bw_copy": [_I64, ctypes.c_void_p, ctypes.c_void_p, _S],
+    "tl_bw_stream": [_I64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, _S],
     "tl_bw_twin": [_I64, ctypes.c_int32, _C, ctypes.c_int32, _F, _S, _T],
     "tl_expr": [ctypes.c_int32, _I64, ctypes.POINTER(CField), ctypes.c_int32, _F, _S, _T],
     "tl_expr_shape": [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),

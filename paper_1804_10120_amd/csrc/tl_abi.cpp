@@ -573,6 +573,37 @@ tl_status tl_bw_copy(int64_t n, const double* src, double* dst, void* stream) {
   return TL_OK;
 }
 
+tl_status tl_bw_stream(int64_t n, int32_t kind, const double* src, double* dst, void* stream) {
+  if (kind != TL_BW_READ && kind != TL_BW_WRITE)
+    return fail(TL_ERR_INVALID, "kind=%d is neither TL_BW_READ nor TL_BW_WRITE", kind);
+  if (n < 0) return fail(TL_ERR_SIZE, "n=%lld < 0", (long long)n);
+  if (n == 0) return TL_OK;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (kind == TL_BW_READ) {
+    Checker c(n);
+    c.field("src", src, n, 1, false);
+    if (c.st != TL_OK) return c.st;
+    Checker p(TL_BW_READ_BLOCKS);
+    p.field("partial", dst, TL_BW_READ_BLOCKS, 1, true);
+    if (p.st != TL_OK) return p.st;
+    c.spans.insert(c.spans.end(), p.spans.begin(), p.spans.end());
+    if (c.overlaps() != TL_OK) return c.st;
+    int64_t grid = (n + 511) / 512;
+    if (grid > TL_BW_READ_BLOCKS) grid = TL_BW_READ_BLOCKS;
+    e = tl::launch_read(src, dst, n, grid, reinterpret_cast<uintptr_t>(src) % 16 == 0, s);
+  } else {
+    Checker c(n);
+    c.field("dst", dst, n, 1, true);
+    if (c.st != TL_OK) return c.st;
+    int64_t grid = (n + 511) / 512;
+    if (grid > 32768) grid = 32768;
+    e = tl::launch_write(dst, n, grid, reinterpret_cast<uintptr_t>(dst) % 16 == 0, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "bandwidth reference launch");
+  return TL_OK;
+}
+
 // ---------------------------------------------------------------- batch plans
 
 tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tune* tune,

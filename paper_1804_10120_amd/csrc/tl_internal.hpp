@@ -75,5 +75,8 @@ hipError_t launch_batched(const Resolved& r, const BatchDomain* doms, const int6
                           const int32_t* tile_dom, int64_t ntiles, int64_t grid, int64_t chunk,
                           hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, int64_t n, int64_t grid, hipStream_t s);
+hipError_t launch_read(const double* src, double* partial, int64_t n, int64_t grid, bool vec,
+                       hipStream_t s);
+hipError_t launch_write(double* dst, int64_t n, int64_t grid, bool vec, hipStream_t s);
 
 }  // namespace tl

@@ -55,6 +55,48 @@ __global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst,
   }
 }
 
+// Read-only reference: every block sums a grid-stride share of src (16-byte
+// non-temporal loads) and writes its partial sum to partial[blockIdx.x].
+__global__ __launch_bounds__(256) void k_read(const double* __restrict__ src,
+                                             double* __restrict__ partial, int64_t n,
+                                             int32_t vec) {
+  const int64_t tid = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t nth = static_cast<int64_t>(gridDim.x) * 256;
+  double s = 0.0;
+  if (vec) {
+    const int64_t n2 = n / 2;
+    for (int64_t i = tid; i < n2; i += nth) {
+      const dbl2 v = load2<true>(src + 2 * i);
+      s += v.x + v.y;
+    }
+    if (tid == 0 && (n & 1)) s += src[n - 1];
+  } else {
+    for (int64_t i = tid; i < n; i += nth) s += load1<true>(src + i);
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (static_cast<int>(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// Write-only reference: dst[i] = 1 (16-byte non-temporal stores).
+__global__ __launch_bounds__(256) void k_write(double* __restrict__ dst, int64_t n, int32_t vec) {
+  const int64_t tid = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t nth = static_cast<int64_t>(gridDim.x) * 256;
+  if (vec) {
+    const int64_t n2 = n / 2;
+    const dbl2 one = {1.0, 1.0};
+    for (int64_t i = tid; i < n2; i += nth) store2<true>(dst + 2 * i, one);
+    if (tid == 0 && (n & 1)) dst[n - 1] = 1.0;
+  } else {
+    for (int64_t i = tid; i < n; i += nth) store1<true>(dst + i, 1.0);
+  }
+}
+
 template <int BLOCK, int PPT, bool NT, bool BUF>
 static const void* batched_ptr() {
   return reinterpret_cast<const void*>(&k_chain_batched<BLOCK, PPT, NT, BUF>);
@@ -133,6 +175,19 @@ hipError_t launch_batched(const Resolved& r, const BatchDomain* doms, const int6
 
 hipError_t launch_copy(const double* src, double* dst, int64_t n, int64_t grid, hipStream_t s) {
   hipLaunchKernelGGL(k_copy, dim3(static_cast<unsigned>(grid)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_read(const double* src, double* partial, int64_t n, int64_t grid, bool vec,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_read, dim3(static_cast<unsigned>(grid)), dim3(256), 0, s, src, partial, n,
+                     vec ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_write(double* dst, int64_t n, int64_t grid, bool vec, hipStream_t s) {
+  hipLaunchKernelGGL(k_write, dim3(static_cast<unsigned>(grid)), dim3(256), 0, s, dst, n,
+                     vec ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -346,6 +346,43 @@ def tl_bw_copy(src, dst=None, *, stream=None):
     return dst
 
 
+def tl_bw_read(src, partial=None, *, stream=None):
+    """Reads a contiguous float64 device tensor (the read-only bandwidth
+    reference); returns the per-block partial sums [TL_BW_READ_BLOCKS]
+    (entries past the number of blocks are left as they were)."""
+    if src.dtype != torch.float64 or not src.is_contiguous() or src.device.type != "cuda":
+        raise ValueError("tl_bw_read: src must be a contiguous float64 device tensor")
+    if partial is None:
+        partial = torch.zeros(_abi.TL_BW_READ_BLOCKS, dtype=torch.float64, device=src.device)
+    if partial.numel() < _abi.TL_BW_READ_BLOCKS or not partial.is_contiguous() \
+            or partial.dtype != torch.float64 or partial.device != src.device:
+        raise ValueError("tl_bw_read: partial must be a contiguous float64 tensor of "
+                         f"{_abi.TL_BW_READ_BLOCKS} elements on src's device")
+    _bw_stream(src.numel(), _abi.TL_BW_READ, src, partial, stream)
+    return partial
+
+
+def tl_bw_write(dst, *, stream=None):
+    """dst[:] = 1 for a contiguous float64 device tensor (the write-only
+    bandwidth reference)."""
+    if dst.dtype != torch.float64 or not dst.is_contiguous() or dst.device.type != "cuda":
+        raise ValueError("tl_bw_write: dst must be a contiguous float64 device tensor")
+    _bw_stream(dst.numel(), _abi.TL_BW_WRITE, None, dst, stream)
+    return dst
+
+
+def _bw_stream(n, kind, src, dst, stream):
+    dev = dst.device
+    keep = [t for t in (src, dst) if t is not None]
+    with torch.cuda.device(dev):
+        args = (n, kind, ctypes.c_void_p(src.data_ptr() if src is not None else None),
+                ctypes.c_void_p(dst.data_ptr()), _stream(dev, stream))
+        if _recorder is not None:
+            _recorder.append(Prepared(lib().tl_bw_stream, args, keep, dev))
+            return
+        check(lib().tl_bw_stream(*args))
+
+
 def tl_bw_twin(src, nout, dst=None, *, stream=None, tune=None):
     """Bandwidth twin: reads every component of ``src`` [nin, n], writes
     ``nout`` components (out_c = sum of the inputs + c)."""

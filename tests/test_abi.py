@@ -269,3 +269,16 @@ def test_padded_fields():
     assert t.stride(0) % 16 == 0 and np.array_equal(t.numpy(), x)
     a = to_field(np.arange(5.0))
     assert a.shape == (1, 5) and a.stride(0) == 16
+
+
+def test_bw_stream_validation(L):
+    n = 4096
+    assert L.tl_bw_stream(n, 3, BASE, BASE + MB, None) == _abi.TL_ERR_INVALID
+    assert L.tl_bw_stream(-1, _abi.TL_BW_READ, BASE, BASE + MB, None) == _abi.TL_ERR_SIZE
+    assert L.tl_bw_stream(n, _abi.TL_BW_READ, None, BASE + MB, None) == _abi.TL_ERR_NULL
+    assert L.tl_bw_stream(n, _abi.TL_BW_READ, BASE, None, None) == _abi.TL_ERR_NULL
+    # the partial sums may not overlap the source
+    assert L.tl_bw_stream(n, _abi.TL_BW_READ, BASE, BASE + 8 * 100, None) == _abi.TL_ERR_ALIAS
+    assert L.tl_bw_stream(n, _abi.TL_BW_WRITE, None, None, None) == _abi.TL_ERR_NULL
+    assert L.tl_bw_stream(n, _abi.TL_BW_WRITE, None, BASE + 4, None) == _abi.TL_ERR_ALIGN
+    assert L.tl_bw_stream(0, _abi.TL_BW_WRITE, None, None, None) == _abi.TL_OK

@@ -37,3 +37,30 @@ def test_twin(nin, nout, n, tune):
 def test_copy(n):
     src = torch.randn(n, dtype=torch.float64, device="cuda")
     assert torch.equal(tl_bw_copy(src), src)
+
+
+@pytest.mark.parametrize("n", [1, 2, 511, 513, 4097, 1 << 22])
+@pytest.mark.parametrize("offset", [0, 1])
+def test_read_reference(n, offset):
+    from paper_1804_10120_amd import tl_bw_read
+    buf = torch.rand(n + offset, dtype=torch.float64, device="cuda")
+    src = buf[offset:]
+    partial = torch.full((2048,), 7.0, dtype=torch.float64, device="cuda")
+    tl_bw_read(src, partial)
+    nblk = min(2048, (n + 511) // 512)
+    got = partial[:nblk].sum().item()
+    ref = src.double().sum().item()
+    assert abs(got - ref) <= 1e-12 * abs(ref)
+    assert torch.all(partial[nblk:] == 7.0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 511, 4097, 1 << 22])
+@pytest.mark.parametrize("offset", [0, 1])
+def test_write_reference(n, offset):
+    from paper_1804_10120_amd import tl_bw_write
+    buf = DevField.empty(1, n + offset, pad=0, offset=0)
+    dst = buf.buf[offset:offset + n]
+    tl_bw_write(dst)
+    torch.cuda.synchronize()
+    assert torch.all(dst == 1.0)
+    assert buf.buf[:offset].eq(1234.5678e300).all() and buf.buf[offset + n:].eq(1234.5678e300).all()
