@@ -179,7 +179,8 @@ tl_status tl_batch_plan_launch_direct(tl_batch_plan* plan, void* stream);
 /* Total points, tiles and grid size of a plan (any pointer may be NULL). */
 tl_status tl_batch_plan_info(const tl_batch_plan* plan, int64_t* points, int64_t* tiles,
                              int64_t* blocks);
-/* Waits for the plan's work, then frees it; NULL is a no-op. */
+/* Waits for all work on the plan's device, then frees the plan (from any
+ * current device; the current device is restored); NULL is a no-op. */
 tl_status tl_batch_plan_destroy(tl_batch_plan* plan);
 
 /* ---- The paper's benchmark expressions (Sec. 5.1) ------------------------- */

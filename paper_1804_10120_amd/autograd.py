@@ -4,11 +4,13 @@ Only the inputs are saved; the backward kernel recomputes g^ij and b^l = g^lk
 beta_k instead of storing them.  Gradients are taken with respect to the
 stored components (a [6, n] symmetric field gets the sum of the (i,j) and (j,i)
 partials in an off-diagonal slot), which is what torch's autograd and finite
-differences on the [6, n] storage both measure.
+differences on the [6, n] storage both measure.  The backward is not itself
+differentiable (second derivatives raise).
 """
 from __future__ import annotations
 
 import torch
+from torch.autograd.function import once_differentiable
 
 from .ops import tl_dtg_chain, tl_dtg_chain_bwd
 
@@ -22,6 +24,7 @@ class DtgChainFn(torch.autograd.Function):
         return out
 
     @staticmethod
+    @once_differentiable
     def backward(ctx, w):
         g, dg, beta, K, alpha = ctx.saved_tensors
         want = ctx.needs_input_grad[:6]

@@ -753,6 +753,12 @@ tl_status tl_batch_plan_destroy(tl_batch_plan* p) {
   auto keep = [&](hipError_t e) {
     if (first == hipSuccess && e != hipSuccess) first = e;
   };
+  // Work on the plan's device (the caller's current device may differ), and
+  // wait for its launches before freeing what they read.
+  int prev = -1;
+  keep(hipGetDevice(&prev));
+  const bool switched = prev >= 0 && prev != p->device;
+  if (switched) keep(hipSetDevice(p->device));
   if (p->d_doms || p->d_start || p->d_tile_dom || p->exec) keep(hipDeviceSynchronize());
   if (p->exec) keep(hipGraphExecDestroy(p->exec));
   if (p->graph) keep(hipGraphDestroy(p->graph));
@@ -760,6 +766,7 @@ tl_status tl_batch_plan_destroy(tl_batch_plan* p) {
   if (p->d_doms) keep(hipFree(p->d_doms));
   if (p->d_start) keep(hipFree(p->d_start));
   if (p->d_tile_dom) keep(hipFree(p->d_tile_dom));
+  if (switched) keep(hipSetDevice(prev));
   delete p;
   if (first != hipSuccess) return hip_fail(first, "plan destroy");
   return TL_OK;
