@@ -238,3 +238,22 @@ def test_fwd_bwd_full_size_sampled():
     assert_close(dtg[:, ti], oracle.dtg_chain(*[sub[k] for k in KEYS]), what="d_t g 128^3")
     for k, x in zip(KEYS, grads):
         assert_close(x[:, ti], ref[k], what=f"{k}_bar 128^3")
+
+
+def test_bwd_output_spanning_more_than_4_GiB():
+    """dg_bar in a buffer whose 18 components span more than 4 GiB: the call
+    takes the 64-bit pointer path; values match the oracle and nothing outside
+    the written components changes."""
+    n = 2049
+    ld = (1 << 25) + 32
+    f = make_fields(n, seed=43)
+    big = torch.full((18 * ld,), 3.25, dtype=torch.float64, device="cuda")
+    dgb = big.view(18, ld)[:, :n]
+    tl_dtg_chain_bwd(dev(f["g"]), dev(f["dg"]), dev(f["beta"]), dev(f["K"]), dev(f["alpha"]),
+                     dev(f["W"]), dg_bar=dgb, want=(0, 1, 0, 0, 0, 0))
+    torch.cuda.synchronize()
+    assert_close(dgb, _vjp_ref(f)["dg"], what="dg_bar over 4 GiB")
+    rest = big.view(18, ld)[:, n:n + 4096]
+    assert bool((rest == 3.25).all())
+    del big, dgb, rest
+    torch.cuda.empty_cache()

@@ -242,3 +242,26 @@ def test_auto_tune_uses_the_cache(tmp_path, monkeypatch):
                  what="auto-tuned inverse")
     with pytest.raises(ValueError, match="auto"):
         tl_sym_inverse(dev(f["g"]), tune="fast")
+
+
+def test_fields_spanning_more_than_4_GiB():
+    """A field whose components are spread over more than 4 GiB (a large
+    leading dimension) cannot use 32-bit buffer offsets: the call must take the
+    64-bit pointer path and still match the oracle; its neighbours with small
+    extents in the same call are unaffected."""
+    n = 3001
+    ld = (1 << 25) + 64                       # 18 components span 4.3 GiB
+    f = _fields(n, seed=77)
+    big = torch.empty(18 * ld, dtype=torch.float64, device="cuda")
+    dg = big.view(18, ld)[:, :n]
+    dg.copy_(torch.from_numpy(f["dg"]))
+    assert (17 * ld + n) * 8 > 1 << 32
+    ins = [dev(f[k]) for k in ("g", "beta", "dbeta", "K", "alpha")]
+    out = tl_dtg_chain(ins[0], dg, *ins[1:])
+    assert_close(out, _oracle_chain(f), what="chain, dg over 4 GiB")
+    gi = tl_sym_inverse(ins[0])
+    gam = tl_christoffel(gi, dg)
+    assert_close(gam, oracle.christoffel(oracle.sym_inverse(f["g"]), f["dg"]),
+                 what="christoffel, dg over 4 GiB")
+    del big, dg
+    torch.cuda.empty_cache()
