@@ -508,6 +508,11 @@ def main():
         doms = [{k: to_field(v, device=device) for k, v in fe.items()} for fe in hosts]
         del hosts
         plan = BatchPlan(doms)
+        _, (ms_default,) = time_calls([[plan.run]], 20, 3)
+        plan.close()
+        from paper_1804_10120_amd import autotune
+        tuned = autotune.tune_plan(doms, save=False)
+        plan = BatchPlan(doms, tune=tuned["tune"])
         _, (ms_graph,) = time_calls([[plan.run]], 20, 3)
         outs = [empty_field(6, e["K"].shape[1], device=device) for e in doms]
         with record() as many:
@@ -522,6 +527,7 @@ def main():
         same = all(torch.equal(a, b) for a, b in zip(outs, plan.outputs))
         rows["dtg_chain_batched"] = {
             "subgrids": 256, "points": npts, "us": ms_graph * 1e3,
+            "tune": tuned["tune"], "default_tune_us": ms_default * 1e3,
             "points_per_s": npts / (ms_graph * 1e-3),
             "GB_s": rate(BYTES["dtg_chain_batched"] * npts, ms_graph),
             "separate_launches_us": ms_many * 1e3,

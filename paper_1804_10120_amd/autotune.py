@@ -157,3 +157,66 @@ def tune(kernel, n, tunes=None, reps=20, save=True, device="cuda"):
         c[cache_key(kernel, n)] = {k: res[k] for k in ("tune", "us", "GB_s")}
         save_cache(c)
     return res
+
+
+# --------------------------------------------------------------------------- batch plans
+
+PLAN_BLOCKS = (64, 128, 256, 512)
+PLAN_GRID_MULTS = (0, 2, 4, 8)
+
+
+def plan_candidates(blocks=PLAN_BLOCKS, ppts=PPTS, xcds=XCDS, grid_mults=PLAN_GRID_MULTS):
+    """Shapes of a batch plan: threads per block, points per lane, XCD order,
+    one block per tile (grid_mult 0) or a persistent grid; all non-temporal."""
+    for b, p, x, gm in itertools.product(blocks, ppts, xcds, grid_mults):
+        yield {"block": b, "ppt": p, "nt": True, "xcd": x, "grid_mult": gm}
+
+
+def plan_key(domains):
+    """Cache key of a set of subgrids: architecture, number of subgrids and the
+    size class of the total and of the mean subgrid."""
+    sizes = [int(d["K"].shape[-1]) for d in domains]
+    total = max(1, sum(sizes))
+    mean = max(1, total // max(1, len(sizes)))
+    return (f"batch_plan|{_arch()}|ndom={len(sizes)}|log2n={int(math.log2(total))}"
+            f"|log2mean={int(math.log2(mean))}")
+
+
+def lookup_plan(domains):
+    """The cached best shape for subgrids like ``domains``, or None."""
+    e = load_cache().get(plan_key(domains))
+    return None if e is None else e["tune"]
+
+
+def tune_plan(domains, tunes=None, reps=10, warmup=2, save=True):
+    """Builds a plan over ``domains`` for every candidate shape, times its graph
+    replay with HIP events (median of ``reps``) and returns {"tune", "us",
+    "table"} for the fastest; caches it under plan_key(domains)."""
+    from .ops import BatchPlan
+    tunes = list(plan_candidates()) if tunes is None else list(tunes)
+    us = []
+    for t in tunes:
+        plan = BatchPlan(domains, tune=t)
+        try:
+            for _ in range(warmup):
+                plan.run()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(reps)]
+            for a, b in ev:
+                a.record()
+                plan.run()
+                b.record()
+            torch.cuda.synchronize()
+            ts = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
+            us.append(ts[len(ts) // 2])
+        finally:
+            plan.close()
+    table = sorted(zip(us, range(len(tunes))))
+    best_us, bi = table[0]
+    res = {"tune": tunes[bi], "us": best_us,
+           "table": [{"tune": tunes[i], "us": u} for u, i in table]}
+    if save:
+        c = load_cache()
+        c[plan_key(domains)] = {"tune": res["tune"], "us": best_us}
+        save_cache(c)
+    return res

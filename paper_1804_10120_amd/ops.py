@@ -444,13 +444,22 @@ class BatchPlan:
 
     ``domains`` is a sequence of dicts with the tensors g, dg, beta, dbeta, K,
     alpha and (optionally) dtg of one subgrid each; missing outputs are
-    allocated with empty_field (leading dimension padded to 16 doubles).  The plan keeps references to every tensor, so the buffers it
+    allocated with empty_field (leading dimension padded to 16 doubles).
+    ``tune="auto"`` takes the autotuner's cached shape for subgrids like these
+    (autotune.plan_key), tuning them first if nothing is cached.  The plan keeps references to every tensor, so the buffers it
     borrows outlive it.
     """
 
     def __init__(self, domains, tune=None):
         self._plan = None
         self.domains = []
+        if isinstance(tune, str):
+            if tune != "auto":
+                raise ValueError(f"tune={tune!r}: expected None, 'auto', a dict, a tuple or a Tune")
+            from . import autotune
+            tune = autotune.lookup_plan(domains)
+            if tune is None:
+                tune = autotune.tune_plan(domains)["tune"]
         arr = (Domain * len(domains))()
         device = None
         for i, d in enumerate(domains):

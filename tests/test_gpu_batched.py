@@ -138,3 +138,32 @@ def test_padded_subgrids():
         assert out.shape == (6, n) and out.stride(0) % 16 == 0
     _check(plan, hosts, devs)
     plan.close()
+
+
+def test_autotuned_plan(tmp_path, monkeypatch):
+    """The autotuner picks one of the candidate shapes for a set of subgrids,
+    caches it, and tune="auto" builds the plan from the cache; the outputs
+    equal the default plan's (same per-point body)."""
+    from paper_1804_10120_amd import autotune
+    monkeypatch.setenv("TLMI_TUNE_CACHE", str(tmp_path / "tune.json"))
+    sizes = [8 ** 3, 13 ** 3, 1000, 65, 20 ** 3, 1]
+    hosts, devs = _domains(sizes, seed=9)
+    cands = [dict(block=128, ppt=1, nt=True), dict(block=256, ppt=1, nt=True, xcd=True),
+             dict(block=64, ppt=2, nt=True, grid_mult=2)]
+    res = autotune.tune_plan(devs, tunes=cands, reps=3, warmup=1)
+    assert res["tune"] in cands and len(res["table"]) == 3
+    assert autotune.lookup_plan(devs) == res["tune"]
+
+    def no_retune(*a, **k):
+        raise AssertionError("tune='auto' re-tuned although the shape is cached")
+    monkeypatch.setattr(autotune, "tune_plan", no_retune)
+    auto = BatchPlan(devs, tune="auto")
+    ref = BatchPlan(devs)
+    auto.run()
+    ref.run()
+    torch.cuda.synchronize()
+    for a, b in zip(auto.outputs, ref.outputs):
+        assert torch.equal(a, b)
+    _check(auto, hosts, devs)
+    auto.close()
+    ref.close()
