@@ -1,0 +1,23 @@
+"""The C ABI used from C++ without Python or torch (tests/c_abi_driver.cpp):
+forward, adjoint, both in one pass and an unfused step against the oracle, and
+argument errors."""
+import os
+import subprocess
+
+import pytest
+
+from gpu_util import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+DRIVER = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_build", "c_abi_driver")
+
+
+def test_c_driver():
+    need_gpu()
+    if not os.path.exists(DRIVER):
+        pytest.fail("tests/_build/c_abi_driver is missing: run __graft_entry__.build() first")
+    r = subprocess.run([DRIVER], capture_output=True, text=True, timeout=120)
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "c_abi_driver: ok" in r.stdout
