@@ -484,14 +484,27 @@ def main():
             lists.append(c)
         ms64, (f64, b64) = time_calls(lists, 100, 10)
         _, (wf64, wb64) = time_calls(lists[:1], 100, 10)     # one set: cache-resident
+        # the same forward + adjoint pairs over the 4 sets, twice, replayed from one graph
+        outs64 = [(torch.empty(6, n64, dtype=torch.float64, device=device),
+                   [torch.empty(c, n64, dtype=torch.float64, device=device)
+                    for c in (6, 18, 3, 9, 6, 1)]) for _ in s64]
+        g64 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g64):
+            for _ in range(2):
+                for (_, e), (o, gr) in zip(s64, outs64):
+                    tl_dtg_chain(*[e[k] for k in KEYS], o)
+                    tl_dtg_chain_bwd(e["g"], e["dg"], e["beta"], e["K"], e["alpha"], e["W"], *gr)
+        _, (ms_g64,) = time_calls([[g64.replay]], 20, 3)
         rows["fwd_bwd_64cubed"] = {"points": n64, "us": ms64 * 1e3,
                                    "points_per_s": n64 / (ms64 * 1e-3),
                                    "fwd_us": f64 * 1e3,
                                    "fwd_GB_s": rate(BYTES["dtg_chain"] * n64, f64),
                                    "bwd_us": b64 * 1e3,
                                    "bwd_GB_s": rate(BYTES["dtg_chain_bwd"] * n64, b64),
-                                   "warm_fwd_us": wf64 * 1e3, "warm_bwd_us": wb64 * 1e3}
-        del s64, lists
+                                   "warm_fwd_us": wf64 * 1e3, "warm_bwd_us": wb64 * 1e3,
+                                   "graph_us_per_pair": ms_g64 * 1e3 / 8,
+                                   "graph_points_per_s": n64 / (ms_g64 * 1e-3 / 8)}
+        del s64, lists, outs64, g64
 
         log("[bench] 256 subgrids")
         edges = domain_edges(256, seed=config_seed(4))
