@@ -211,11 +211,13 @@ SWEEP_SIZES = tuple(32 * 4 ** k for k in range(9)) + (2 ** 21,)
 def paper_family(device, sizes, reps=21):
     """BW_eff (the paper's effective bandwidth: 8 B x elements x N / t) of the
     Sec. 5.1 benchmark expressions, the Christoffel symbols (g^ij given, as in
-    the paper) and the fused chain, at each grid size.  Each size: ``reps``
+    the paper), the fused chain and the same chain as four launches, at each
+    grid size.  Each size: ``reps``
     launches timed with HIP events, the first discarded, the median kept (the
     paper's method).  Smaller grids are views of the largest fields."""
     import torch
-    from paper_1804_10120_amd import tl_christoffel, tl_dtg_chain, tl_expr, tl_expr_shape
+    from paper_1804_10120_amd import (tl_christoffel, tl_cov_deriv, tl_dtg, tl_dtg_chain,
+                                      tl_expr, tl_expr_shape, tl_sym_inverse)
     from paper_1804_10120_amd.ops import record
     from paper_1804_10120_amd.synth import EXPR_INPUTS, make_expr_inputs, make_fields
     nmax = max(sizes)
@@ -226,12 +228,12 @@ def paper_family(device, sizes, reps=21):
         for n in sizes:
             with record() as calls:
                 launch(n)
-            c = calls[0]
             ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                   for _ in range(reps)]
             for a, b in ev:
                 a.record()
-                c()
+                for c in calls:
+                    c()
                 b.record()
             torch.cuda.synchronize()
             ts = sorted(a.elapsed_time(b) for a, b in ev[1:])
@@ -251,7 +253,18 @@ def paper_family(device, sizes, reps=21):
     run("christoffel", 42, lambda n: tl_christoffel(f["g"][:, :n], f["dg"][:, :n], gam[:, :n]))
     dtg = torch.empty(6, nmax, dtype=torch.float64, device=device)
     run("dtg_chain", 49, lambda n: tl_dtg_chain(*[f[k][:, :n] for k in KEYS], dtg[:, :n]))
-    del f, gam, dtg
+    # the same d_t g as four launches (a1-a4), counted with the fused chain's 49 elements:
+    # the paper's comparison of one kernel per expression with several (Sec. 5.5)
+    gi = torch.empty(6, nmax, dtype=torch.float64, device=device)
+    nb = torch.empty(9, nmax, dtype=torch.float64, device=device)
+
+    def unfused(n):
+        tl_sym_inverse(f["g"][:, :n], gi[:, :n])
+        tl_christoffel(gi[:, :n], f["dg"][:, :n], gam[:, :n])
+        tl_cov_deriv(gam[:, :n], f["beta"][:, :n], f["dbeta"][:, :n], nb[:, :n])
+        tl_dtg(f["alpha"][:, :n], f["K"][:, :n], nb[:, :n], dtg[:, :n])
+    run("dtg_chain_4_launches", 49, unfused)
+    del f, gam, dtg, gi, nb
     torch.cuda.empty_cache()
     return table
 
