@@ -32,9 +32,10 @@
  * returned synchronously: a NULL pointer while n > 0 (TL_ERR_NULL); n < 0 or
  * ld < n (TL_ERR_SIZE); a pointer that is not 8-byte aligned (TL_ERR_ALIGN);
  * an output whose address range overlaps an input's or another output's
- * (TL_ERR_ALIAS; a field's range is the whole span from its first to its last
- * element, gaps between components included, so two fields interleaved in one
- * buffer count as overlapping; inputs may overlap each other); an invalid
+ * (TL_ERR_ALIAS: an element of an output is also an element of another
+ * field -- fields interleaved in one buffer without sharing an element, such
+ * as point ranges of one large field, are accepted; inputs may overlap each
+ * other); an invalid
  * tuning or plan argument (TL_ERR_INVALID).  A
  * launch failure reported by the HIP runtime returns TL_ERR_HIP.  For every
  * error a message is available from tl_last_error() (per calling thread).

@@ -35,11 +35,15 @@ tl_status hip_fail(hipError_t e, const char* what) {
   return fail(TL_ERR_HIP, "%s: %s (%d)", what, hipGetErrorString(e), static_cast<int>(e));
 }
 
-// A field as validated: byte range [lo, hi) for overlap checks.
+// A field as validated: byte range [lo, hi) from its first to its last
+// element, and the layout inside it (ncomp components of comp bytes, stride
+// bytes apart) for the exact check.
 struct Span {
   const char* name;
   uintptr_t lo, hi;
   bool output;
+  uintptr_t comp, stride;
+  int ncomp;
 };
 
 struct Checker {
@@ -76,16 +80,38 @@ struct Checker {
     if (a % 16 != 0 || (ncomp > 1 && ld % 2 != 0)) vec_ok = false;
     const uintptr_t bytes = static_cast<uintptr_t>((ncomp - 1) * ld + n) * 8u;
     if (bytes > 0xFFFFFFFFull) buf_ok = false;
-    spans.push_back({name, a, a + bytes, output});
+    spans.push_back({name, a, a + bytes, output, static_cast<uintptr_t>(n) * 8u,
+                     static_cast<uintptr_t>(ld) * 8u, ncomp});
   }
 
   tl_status overlaps() {
     if (st != TL_OK) return st;
     const Span* a = nullptr;
     const Span* b = nullptr;
-    if (find_overlap(spans, &a, &b))
-      return st = fail(TL_ERR_ALIAS, "%s overlaps %s", a->name, b->name);
+    const char* x = nullptr;
+    const char* y = nullptr;
+    if (overlapping(spans, &x, &y)) return st = fail(TL_ERR_ALIAS, "%s overlaps %s", x, y);
     return st;
+  }
+
+  // Whether an output shares a byte with another field.  The whole spans are
+  // compared first; only if two of them meet are the individual components
+  // compared, so fields interleaved in one buffer (e.g. point ranges of one
+  // large field) are accepted when no element is shared.
+  static bool overlapping(std::vector<Span>& v, const char** x, const char** y) {
+    const Span* a = nullptr;
+    const Span* b = nullptr;
+    if (!find_overlap(v, &a, &b)) return false;
+    std::vector<Span> parts;
+    for (const Span& s : v)
+      for (int c = 0; c < s.ncomp; ++c) {
+        const uintptr_t lo = s.lo + static_cast<uintptr_t>(c) * s.stride;
+        parts.push_back({s.name, lo, lo + s.comp, s.output, s.comp, 0, 1});
+      }
+    if (!find_overlap(parts, &a, &b)) return false;
+    *x = a->name;
+    *y = b->name;
+    return true;
   }
 
   // Finds a pair of overlapping spans of which at least one is an output
@@ -631,10 +657,10 @@ tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tun
     points += x.n;
   }
   {
-    const Span* a = nullptr;
-    const Span* b = nullptr;
-    if (Checker::find_overlap(all, &a, &b))
-      return fail(TL_ERR_ALIAS, "%s of one domain overlaps %s of another", a->name, b->name);
+    const char* a = nullptr;
+    const char* b = nullptr;
+    if (Checker::overlapping(all, &a, &b))
+      return fail(TL_ERR_ALIAS, "%s of one domain overlaps %s of another", a, b);
   }
 
   tl::Resolved r;

@@ -168,18 +168,19 @@ int main() {
   e = rel_err(ginv.get(), rinv, 6, n);
   expect(e <= 1e-12, "sym_inverse vs oracle");
 
-  // a batch plan over three subgrids whose inputs are point ranges of the same
-  // fields ([0, 5000), [5000, 5001) and [7000, 20011); inputs may overlap one
-  // another), each writing its own output field
+  // a batch plan over three subgrids that are point ranges of the same fields
+  // ([0, 5000), [5000, 5001) and [7000, 20011)), inputs and outputs alike: the
+  // outputs interleave in one buffer without sharing an element
   {
     const int64_t lo[3] = {0, 5000, 7000}, cnt[3] = {5000, 1, n - 7000};
-    std::vector<Dev*> outs;
+    Dev outb(6 * n);
+    std::vector<double> fill(6 * n, -7.0);
+    outb.put(fill);
     tl_domain doms[3];
     for (int k = 0; k < 3; ++k) {
-      outs.push_back(new Dev(6 * cnt[k]));
       auto sub = [&](int f) { return tl_cfield{d[f]->p + lo[k], n}; };
       doms[k] = tl_domain{cnt[k], sub(0), sub(1), sub(2), sub(3), sub(4), sub(5),
-                          tl_field{outs[k]->p, cnt[k]}};
+                          tl_field{outb.p + lo[k], n}};
     }
     tl_batch_plan* plan = nullptr;
     expect(tl_batch_plan_create(doms, 3, nullptr, &plan) == TL_OK && plan != nullptr,
@@ -187,19 +188,28 @@ int main() {
     if (plan) {
       expect(tl_batch_plan_launch(plan, s) == TL_OK, "tl_batch_plan_launch");
       expect(hipStreamSynchronize(s) == hipSuccess, "plan sync");
-      double worst = 0.0;
-      for (int k = 0; k < 3; ++k) {
-        const std::vector<double> got = outs[k]->get();
-        std::vector<double> want(6 * cnt[k]);
-        for (int c = 0; c < 6; ++c)
-          for (int64_t p = 0; p < cnt[k]; ++p) want[c * cnt[k] + p] = ref[c * n + lo[k] + p];
-        worst = std::fmax(worst, rel_err(got, want, 6, cnt[k]));
-      }
-      std::printf("batch plan rel err %.3e\n", worst);
-      expect(worst <= 1e-12, "batch plan vs oracle");
+      const std::vector<double> got = outb.get();
+      std::vector<double> want(6 * n);
+      bool untouched = true;
+      for (int c = 0; c < 6; ++c)
+        for (int64_t p = 0; p < n; ++p) {
+          const bool in_domain = p < 5001 || p >= 7000;
+          want[c * n + p] = in_domain ? ref[c * n + p] : -7.0;
+          if (!in_domain && got[c * n + p] != -7.0) untouched = false;
+        }
+      e = rel_err(got, want, 6, n);
+      std::printf("batch plan rel err %.3e\n", e);
+      expect(e <= 1e-12, "batch plan vs oracle");
+      expect(untouched, "points outside every subgrid untouched");
       expect(tl_batch_plan_destroy(plan) == TL_OK, "tl_batch_plan_destroy");
     }
-    for (auto* x : outs) delete x;
+    // two subgrids sharing an output element are refused
+    tl_domain clash[2] = {doms[0], doms[0]};
+    clash[1].n = 10;
+    clash[1].dtg.ptr = outb.p + 4995;
+    tl_batch_plan* bad = nullptr;
+    expect(tl_batch_plan_create(clash, 2, nullptr, &bad) == TL_ERR_ALIAS && bad == nullptr,
+           "overlapping subgrid outputs refused");
   }
 
   // argument errors come back before any launch

@@ -282,3 +282,19 @@ def test_bw_stream_validation(L):
     assert L.tl_bw_stream(n, _abi.TL_BW_WRITE, None, None, None) == _abi.TL_ERR_NULL
     assert L.tl_bw_stream(n, _abi.TL_BW_WRITE, None, BASE + 4, None) == _abi.TL_ERR_ALIGN
     assert L.tl_bw_stream(0, _abi.TL_BW_WRITE, None, None, None) == _abi.TL_OK
+
+
+def test_interleaved_fields_are_not_overlapping(L):
+    """Fields interleaved in one buffer (components of one in the gaps of the
+    other's leading dimension) share no element and are accepted; the call
+    then stops at the invalid tuning, before any launch.  A single shared
+    element is still caught."""
+    n = 100
+    a = [cf(BASE + i * 64 * MB, n) for i in range(6)]
+    a[1] = cf(BASE + 7 * 64 * MB, 2 * n)                    # dg, ld = 2n
+    bad = ctypes.pointer(Tune(96, 0, 0, 0))
+    out = f(BASE + 7 * 64 * MB + 8 * n, 2 * n)              # dtg in dg's gaps
+    assert call_chain(L, n, a, out, bad) == _abi.TL_ERR_INVALID
+    out = f(BASE + 7 * 64 * MB + 8 * (n - 1), 2 * n)        # one element of dg shared
+    assert call_chain(L, n, a, out, bad) == _abi.TL_ERR_ALIAS
+    assert b"dtg" in L.tl_last_error() and b"dg" in L.tl_last_error()
