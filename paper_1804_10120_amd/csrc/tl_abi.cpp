@@ -160,14 +160,17 @@ int num_cus() {
 }
 
 // Default launch shapes, measured on MI355X with the library's autotuner.
-// Every kernel streams, so one rule serves all of them: non-temporal loads
-// and stores always; for large grids one point per lane in blocks of 256 with
-// XCD-contiguous tiles; below 2^20 points (where the whole grid is in flight
-// at once and the XCD order buys nothing) two points per lane in blocks of
-// 512; below 2^16 points (a few memory round trips in all) one point per lane
-// in blocks of 64, to spread the grid over as many compute units as possible.  The batched kernel: one block of 128 per tile in plain order (its
-// subgrids are already contiguous runs of tiles; a persistent grid measured
-// 20% slower than letting the dispatcher balance the uneven subgrids).
+// Every kernel streams, so one rule serves nearly all of them: non-temporal
+// loads and stores always; for large grids one point per lane in blocks of 256
+// with XCD-contiguous tiles; below 2^20 points (where the whole grid is in
+// flight at once and the XCD order buys nothing) two points per lane in
+// blocks of 512, except the fused forward, which keeps one point per lane in
+// blocks of 256 (62 registers against 166 at two points); below 2^16 points
+// (a few memory round trips in all) one point per lane in blocks of 64, to
+// spread the grid over as many compute units as possible.  The batched
+// kernel: one block of 128 per tile in plain order (its subgrids are already
+// contiguous runs of tiles; a persistent grid measured 20% slower than
+// letting the dispatcher balance the uneven subgrids).
 tl::Resolved defaults(tl::KernelId k, int64_t n) {
   tl::Resolved r;
   r.nt = true;
@@ -185,8 +188,6 @@ tl::Resolved defaults(tl::KernelId k, int64_t n) {
     r.ppt = 1;
     r.xcd = false;
   } else if (k == tl::KernelId::Chain) {
-    // measured: with buffer addressing the fused forward needs 62 registers
-    // at one point per lane (8 waves per SIMD) but 166 at two (3 waves)
     r.block = 256;
     r.ppt = 1;
     r.xcd = false;

@@ -8,7 +8,8 @@
 // MFMA: every point is independent and the contractions are 3 long, so the
 // kernels are bound by HBM bandwidth, and the levers are the bytes in flight
 // per CU (PPT, block size, occupancy), the cache policy (non-temporal loads and
-// stores) and the order in which tiles meet the memory system (XCD order).
+// stores), the order in which tiles meet the memory system (XCD order) and
+// the instructions spent on addresses (buffer addressing, below).
 //
 // A body with more outputs than registers comfortably hold (kStream) is
 // instead given a loader ld(field, component) and a storer st(field,
