@@ -60,8 +60,8 @@ def call(name, *inputs, outs=None, stream=None, tune=None):
     with torch.cuda.device(c.device):
         full = (c.n, cin, len(inputs), cout, len(outs), ops._stream(c.device, stream),
                 ops.make_tune(tune))
-        if ops._recorder is not None:
-            ops._recorder.append(ops.Prepared(_fn(name), full, c.keep + [cin, cout], c.device))
+        if ops._recording() is not None:
+            ops._recording().append(ops.Prepared(_fn(name), full, c.keep + [cin, cout], c.device))
         else:
             check(_fn(name)(*full))
     return tuple(outs)

@@ -10,6 +10,7 @@ computation runs in the library's HIP kernels.
 from __future__ import annotations
 
 import ctypes
+import threading
 
 import torch
 
@@ -155,12 +156,17 @@ class Prepared:
             check(st)
 
 
-_recorder = None
+_local = threading.local()     # per thread: the list being recorded into, or None
+
+
+def _recording():
+    return getattr(_local, "calls", None)
 
 
 class record:
-    """Context manager: tl_* calls made inside are marshalled into Prepared
-    objects (outputs are still allocated) instead of being launched.
+    """Context manager: tl_* calls made inside, on this thread, are marshalled
+    into Prepared objects (outputs are still allocated) instead of being
+    launched; other threads are unaffected.
 
         with record() as calls:
             tl_dtg_chain(...)
@@ -168,15 +174,13 @@ class record:
     """
 
     def __enter__(self):
-        global _recorder
-        if _recorder is not None:
+        if _recording() is not None:
             raise RuntimeError("record() does not nest")
-        _recorder = []
-        return _recorder
+        _local.calls = []
+        return _local.calls
 
     def __exit__(self, *exc):
-        global _recorder
-        _recorder = None
+        _local.calls = None
         return False
 
 
@@ -195,8 +199,8 @@ def _run(fn, c, *args, stream=None, tune=None, kernel=None):
     tune = _auto(tune, kernel, c.n)
     with torch.cuda.device(c.device):
         full = (c.n, *args, _stream(c.device, stream), make_tune(tune))
-        if _recorder is not None:
-            _recorder.append(Prepared(fn, full, c.keep, c.device))
+        if _recording() is not None:
+            _recording().append(Prepared(fn, full, c.keep, c.device))
             return
         check(fn(*full))
 
@@ -339,8 +343,8 @@ def tl_bw_copy(src, dst=None, *, stream=None):
     with torch.cuda.device(src.device):
         args = (src.numel(), ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
                 _stream(src.device, stream))
-        if _recorder is not None:
-            _recorder.append(Prepared(lib().tl_bw_copy, args, [src, dst], src.device))
+        if _recording() is not None:
+            _recording().append(Prepared(lib().tl_bw_copy, args, [src, dst], src.device))
         else:
             check(lib().tl_bw_copy(*args))
     return dst
@@ -377,8 +381,8 @@ def _bw_stream(n, kind, src, dst, stream):
     with torch.cuda.device(dev):
         args = (n, kind, ctypes.c_void_p(src.data_ptr() if src is not None else None),
                 ctypes.c_void_p(dst.data_ptr()), _stream(dev, stream))
-        if _recorder is not None:
-            _recorder.append(Prepared(lib().tl_bw_stream, args, keep, dev))
+        if _recording() is not None:
+            _recording().append(Prepared(lib().tl_bw_stream, args, keep, dev))
             return
         check(lib().tl_bw_stream(*args))
 
@@ -393,8 +397,8 @@ def tl_bw_twin(src, nout, dst=None, *, stream=None, tune=None):
     with torch.cuda.device(c.device):
         full = (c.n, nin, _cf(src, nin), nout, _f(dst, nout), _stream(c.device, stream),
                 make_tune(tune))
-        if _recorder is not None:
-            _recorder.append(Prepared(lib().tl_bw_twin, full, c.keep, c.device))
+        if _recording() is not None:
+            _recording().append(Prepared(lib().tl_bw_twin, full, c.keep, c.device))
         else:
             check(lib().tl_bw_twin(*full))
     return dst
@@ -425,8 +429,8 @@ def tl_expr(expr, *inputs, out=None, stream=None, tune=None):
     with torch.cuda.device(c.device):
         full = (eid, c.n, arr, len(inputs), _f(out, oc), _stream(c.device, stream),
                 make_tune(tune))
-        if _recorder is not None:
-            _recorder.append(Prepared(lib().tl_expr, full, c.keep + [arr], c.device))
+        if _recording() is not None:
+            _recording().append(Prepared(lib().tl_expr, full, c.keep + [arr], c.device))
         else:
             check(lib().tl_expr(*full))
     return out

@@ -78,3 +78,21 @@ def test_synthetic_fields_are_seeded_and_in_range():
     assert e.min() >= 8 and e.max() <= 48 and len(e) == 256
     x = make_expr_inputs("kij", 100, seed=1)
     assert [v.shape[0] for v in x] == [1, 6, 3] and x[0].min() >= 0.5
+
+
+def test_record_is_per_thread():
+    """A recording on one thread does not capture another thread's calls."""
+    import threading
+    from paper_1804_10120_amd import ops
+    seen = {}
+
+    def other():
+        seen["other"] = ops._recording()
+
+    with ops.record() as calls:
+        t = threading.Thread(target=other)
+        t.start()
+        t.join()
+        assert ops._recording() is calls
+    assert seen["other"] is None
+    assert ops._recording() is None
