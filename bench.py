@@ -251,6 +251,11 @@ def paper_family(device, sizes, reps=21):
          make_fields(nmax, seed=7, fields=KEYS).items()}
     gam = torch.empty(18, nmax, dtype=torch.float64, device=device)
     run("christoffel", 42, lambda n: tl_christoffel(f["g"][:, :n], f["dg"][:, :n], gam[:, :n]))
+    # the paper's parallelisation over left-hand-side components: 3 and 18 lanes per point
+    for lanes in (3, 18):
+        run(f"christoffel_{lanes}_lanes", 42,
+            lambda n: tl_christoffel(f["g"][:, :n], f["dg"][:, :n], gam[:, :n],
+                                     tune=dict(block=64, lanes=lanes)))
     dtg = torch.empty(6, nmax, dtype=torch.float64, device=device)
     run("dtg_chain", 49, lambda n: tl_dtg_chain(*[f[k][:, :n] for k in KEYS], dtg[:, :n]))
     # the same d_t g as four launches (a1-a4), counted with the fused chain's 49 elements:

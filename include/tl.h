@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define TL_ABI_VERSION 1
+#define TL_ABI_VERSION 2
 
 typedef enum {
   TL_OK = 0,
@@ -87,8 +87,18 @@ typedef struct { double* ptr; int64_t ld; } tl_field;
  *              descriptor per field and 32-bit offsets (fewer instructions
  *              per access; the results are identical)
  *   grid_mult  0: one tile of block*ppt points per block; k > 0: a persistent
- *              grid of k blocks per compute unit striding over the tiles   */
-typedef struct { int32_t block, ppt, flags, grid_mult; } tl_tune;
+ *              grid of k blocks per compute unit striding over the tiles
+ *   lanes      lanes per grid point, 0 or 1 (one lane computes all components
+ *              of its point) or, for tl_christoffel only, 2, 3, 6, 9 or 18:
+ *              the 18 stored components of a point are spread over that many
+ *              neighbouring lanes (lane r of a point stores the components
+ *              q with q mod lanes == r; every lane loads the point's inputs),
+ *              the paper's parallelisation over left-hand-side components.
+ *              ppt and grid_mult are then ignored; results agree with the
+ *              one-lane kernel's to rounding.
+ *              Other values, or lanes > 1 for another entry point:
+ *              TL_ERR_INVALID.                                              */
+typedef struct { int32_t block, ppt, flags, grid_mult, lanes; } tl_tune;
 #define TL_TUNE_NT 1
 #define TL_TUNE_XCD 2
 #define TL_TUNE_PTR64 4

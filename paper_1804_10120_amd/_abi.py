@@ -21,7 +21,7 @@ TL_BW_READ_BLOCKS = 2048
 EXPRS = ("assign1", "assign2", "assign3", "add1", "add2", "add3", "mult1", "mult2", "mult3",
          "contract1", "contract2", "contract3", "kij")
 TWIN_SHAPES = ((1, 1), (6, 6), (24, 18), (30, 9), (16, 6), (43, 6), (40, 43))
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 
 class CField(ctypes.Structure):
@@ -34,7 +34,7 @@ class Field(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("ppt", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("grid_mult", ctypes.c_int32)]
+                ("grid_mult", ctypes.c_int32), ("lanes", ctypes.c_int32)]
 
 
 class Domain(ctypes.Structure):

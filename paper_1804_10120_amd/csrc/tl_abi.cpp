@@ -203,6 +203,12 @@ tl_status resolve(tl::KernelId k, const tl_tune* t, bool vec_ok, bool buf_ok, in
                   tl::Resolved* out) {
   tl::Resolved r = defaults(k, n);
   if (t != nullptr) {
+    const int l = t->lanes;
+    if (l != 0 && l != 1 && l != 2 && l != 3 && l != 6 && l != 9 && l != 18)
+      return fail(TL_ERR_INVALID, "tune.lanes=%d not in {0,1,2,3,6,9,18}", l);
+    if (l > 1 && k != tl::KernelId::Christoffel)
+      return fail(TL_ERR_INVALID, "tune.lanes=%d: only tl_christoffel spreads a point over lanes", l);
+    r.lanes = l > 1 ? l : 1;
     if (t->block != 0) {
       if (t->block != 64 && t->block != 128 && t->block != 256 && t->block != 512 &&
           t->block != 1024)
@@ -234,7 +240,9 @@ tl_status run(tl::KernelId k, const Checker& c, const tl_tune* tune, const tl::K
   tl::Resolved r;
   tl_status s = resolve(k, tune, c.vec_ok, c.buf_ok, c.n, &r);
   if (s != TL_OK) return s;
-  hipError_t e = tl::launch_kernel(k, r, a, c.n, static_cast<hipStream_t>(stream));
+  hipError_t e = r.lanes > 1
+                     ? tl::launch_christoffel_lanes(r, a, c.n, static_cast<hipStream_t>(stream))
+                     : tl::launch_kernel(k, r, a, c.n, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return TL_OK;
 }

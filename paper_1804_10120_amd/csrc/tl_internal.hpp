@@ -39,6 +39,7 @@ struct Resolved {
   int grid_mult = 0;
   int num_cu = 256;
   bool buf = false;  // buffer addressing (every field's extent below 4 GiB)
+  int lanes = 1;     // lanes per grid point (tl_christoffel only)
 };
 
 inline int64_t grid_size(const Resolved& r, int64_t ntiles) {
@@ -78,5 +79,6 @@ hipError_t launch_copy(const double* src, double* dst, int64_t n, int64_t grid, 
 hipError_t launch_read(const double* src, double* partial, int64_t n, int64_t grid, bool vec,
                        hipStream_t s);
 hipError_t launch_write(double* dst, int64_t n, int64_t grid, bool vec, hipStream_t s);
+hipError_t launch_christoffel_lanes(const Resolved& r, const KArgs& a, int64_t n, hipStream_t s);
 
 }  // namespace tl

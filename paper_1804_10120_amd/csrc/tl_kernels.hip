@@ -97,6 +97,49 @@ __global__ __launch_bounds__(256) void k_write(double* __restrict__ dst, int64_t
   }
 }
 
+// Christoffel symbols with P neighbouring lanes per grid point: every lane
+// loads its point's 24 inputs and evaluates the same body, and stores the
+// components q with q mod P == its rank.
+template <int P, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_christoffel_lanes(KArgs a, int64_t n) {
+  const int64_t gid = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+  const int64_t p = gid / P;
+  const int rank = static_cast<int>(gid - p * P);
+  if (p >= n) return;
+  double x[OpChristoffel::NIN], y[OpChristoffel::NOUT];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) x[c] = load1<true>(a.in[0] + c * a.ldin[0] + p);
+#pragma unroll
+  for (int c = 0; c < 18; ++c) x[6 + c] = load1<true>(a.in[1] + c * a.ldin[1] + p);
+  OpChristoffel::apply(x, y);
+#pragma unroll
+  for (int q = 0; q < 18; ++q)
+    if (q % P == rank) store1<true>(a.out[0] + q * a.ldout[0] + p, y[q]);
+}
+
+template <int P>
+static const void* lanes_ptr(int block) {
+  switch (block) {
+    case 64: return reinterpret_cast<const void*>(&k_christoffel_lanes<P, 64>);
+    case 128: return reinterpret_cast<const void*>(&k_christoffel_lanes<P, 128>);
+    case 256: return reinterpret_cast<const void*>(&k_christoffel_lanes<P, 256>);
+    case 512: return reinterpret_cast<const void*>(&k_christoffel_lanes<P, 512>);
+    case 1024: return reinterpret_cast<const void*>(&k_christoffel_lanes<P, 1024>);
+    default: return nullptr;
+  }
+}
+
+static const void* ptr_christoffel_lanes(const Resolved& r) {
+  switch (r.lanes) {
+    case 2: return lanes_ptr<2>(r.block);
+    case 3: return lanes_ptr<3>(r.block);
+    case 6: return lanes_ptr<6>(r.block);
+    case 9: return lanes_ptr<9>(r.block);
+    case 18: return lanes_ptr<18>(r.block);
+    default: return nullptr;
+  }
+}
+
 template <int BLOCK, int PPT, bool NT, bool BUF>
 static const void* batched_ptr() {
   return reinterpret_cast<const void*>(&k_chain_batched<BLOCK, PPT, NT, BUF>);
@@ -149,7 +192,8 @@ hipError_t launch_kernel(KernelId k, const Resolved& r, const KArgs& a, int64_t 
 const void* kernel_address(KernelId k, const Resolved& r) {
   switch (k) {
     case KernelId::SymInverse: return ptr_op<OpSymInverse>(r);
-    case KernelId::Christoffel: return ptr_op<OpChristoffel>(r);
+    case KernelId::Christoffel:
+      return r.lanes > 1 ? ptr_christoffel_lanes(r) : ptr_op<OpChristoffel>(r);
     case KernelId::CovDeriv: return ptr_op<OpCovDeriv>(r);
     case KernelId::Dtg: return ptr_op<OpDtg>(r);
     case KernelId::Chain: return ptr_op<OpChain>(r);
@@ -175,6 +219,19 @@ hipError_t launch_batched(const Resolved& r, const BatchDomain* doms, const int6
 
 hipError_t launch_copy(const double* src, double* dst, int64_t n, int64_t grid, hipStream_t s) {
   hipLaunchKernelGGL(k_copy, dim3(static_cast<unsigned>(grid)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_christoffel_lanes(const Resolved& r, const KArgs& a, int64_t n, hipStream_t s) {
+  const void* fn = ptr_christoffel_lanes(r);
+  if (fn == nullptr) return hipErrorInvalidValue;
+  const int64_t grid = (n * r.lanes + r.block - 1) / r.block;
+  if (grid > 0x7fffffff) return hipErrorInvalidConfiguration;
+  KArgs args = a;
+  int64_t npts = n;
+  void* kargs[] = {&args, &npts};
+  hipError_t e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(grid)), dim3(r.block), kargs, 0, s);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

@@ -122,8 +122,8 @@ def _stream(device, stream):
 
 def make_tune(tune):
     """None (library default), a Tune, a dict with keys block, ppt, nt, xcd,
-    ptr64, grid_mult (missing numbers mean the default; flags default to off), or a
-    tuple (block, ppt, flags, grid_mult) -> Tune pointer or None.  (The tl_*
+    ptr64, grid_mult, lanes (missing numbers mean the default; flags default to
+    off), or a tuple (block, ppt, flags, grid_mult[, lanes]) -> Tune pointer or None.  (The tl_*
     functions also accept tune="auto", the autotuner's cached shape.)"""
     if tune is None:
         return None
@@ -134,7 +134,7 @@ def make_tune(tune):
                  int(tune.get("flags", 0)) | (_abi.TL_TUNE_NT if tune.get("nt") else 0)
                  | (_abi.TL_TUNE_XCD if tune.get("xcd") else 0)
                  | (_abi.TL_TUNE_PTR64 if tune.get("ptr64") else 0),
-                 int(tune.get("grid_mult", 0)))
+                 int(tune.get("grid_mult", 0)), int(tune.get("lanes", 0)))
     else:
         t = Tune(*[int(v) for v in tune])
     return ctypes.pointer(t)

@@ -133,7 +133,8 @@ def test_inputs_may_alias_each_other(L):
     assert call_chain(L, n, a, out, bad) == _abi.TL_ERR_INVALID
 
 
-@pytest.mark.parametrize("tune", [(96, 0, 0, 0), (256, 3, 0, 0), (256, 1, 8, 0), (256, 1, 0, -1)])
+@pytest.mark.parametrize("tune", [(96, 0, 0, 0), (256, 3, 0, 0), (256, 1, 8, 0), (256, 1, 0, -1),
+                                  (256, 1, 0, 0, 4), (256, 1, 0, 0, 3)])
 def test_invalid_tuning(L, tune):
     a, out = chain_args(64)
     assert call_chain(L, 64, a, out, ctypes.pointer(Tune(*tune))) == _abi.TL_ERR_INVALID
@@ -298,3 +299,17 @@ def test_interleaved_fields_are_not_overlapping(L):
     out = f(BASE + 7 * 64 * MB + 8 * (n - 1), 2 * n)        # one element of dg shared
     assert call_chain(L, n, a, out, bad) == _abi.TL_ERR_ALIAS
     assert b"dtg" in L.tl_last_error() and b"dg" in L.tl_last_error()
+
+
+def test_lanes_only_for_christoffel(L):
+    """lanes > 1 passes tl_christoffel's checks (the call then stops at the
+    invalid block size, which is checked after lanes) and is refused by
+    every other entry point."""
+    n = 64
+    lanes6_bad_block = ctypes.pointer(Tune(96, 0, 0, 0, 6))
+    assert L.tl_christoffel(n, cf(BASE, n), cf(BASE + MB, n), f(BASE + 2 * MB, n), None,
+                            lanes6_bad_block) == _abi.TL_ERR_INVALID
+    assert b"block" in L.tl_last_error()
+    a, out = chain_args(n)
+    assert call_chain(L, n, a, out, lanes6_bad_block) == _abi.TL_ERR_INVALID
+    assert b"lanes" in L.tl_last_error()

@@ -265,3 +265,22 @@ def test_fields_spanning_more_than_4_GiB():
                  what="christoffel, dg over 4 GiB")
     del big, dg
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("lanes", [2, 3, 6, 9, 18])
+@pytest.mark.parametrize("n", [1, 7, 64, 65, 1553, 4097])
+@pytest.mark.parametrize("block", [64, 256, 1024])
+def test_christoffel_lanes_per_point(lanes, n, block):
+    """The 18 components of a point spread over `lanes` lanes: the one-lane
+    kernel's result and the oracle's, to 1e-12 (the same per-point body, which
+    the compiler may contract differently in the two kernels)."""
+    f = _fields(n, seed=91)
+    gi = oracle.sym_inverse(f["g"])
+    ginv, dg = dev(gi), dev(f["dg"])
+    out = DevField.empty(18, n, pad=3, offset=1)
+    tl_christoffel(ginv, dg, out.view, tune=dict(block=block, lanes=lanes))
+    one = tl_christoffel(ginv, dg)
+    torch.cuda.synchronize()
+    assert_close(out.view, one, what=f"christoffel lanes={lanes} vs one lane")
+    assert out.canaries_intact()
+    assert_close(out.view, oracle.christoffel(gi, f["dg"]), what=f"christoffel lanes={lanes}")
