@@ -17,11 +17,10 @@ def test_c_driver():
     need_gpu()
     if not os.path.exists(DRIVER):
         pytest.fail("tests/_build/c_abi_driver is missing: run __graft_entry__.build() first")
-    root = os.path.dirname(os.path.dirname(DRIVER))
-    srcs = [os.path.join(root, "c_abi_driver.cpp"),
-            os.path.join(os.path.dirname(root), "include", "tl.h")]
-    if any(os.path.getmtime(x) > os.path.getmtime(DRIVER) for x in srcs):
-        pytest.fail("tests/_build/c_abi_driver is older than its sources: run "
+    import build_c_driver
+    stamp = open(build_c_driver.STAMP).read() if os.path.exists(build_c_driver.STAMP) else ""
+    if stamp != build_c_driver.sources_digest():
+        pytest.fail("tests/_build/c_abi_driver was built from other sources: run "
                     "__graft_entry__.build() again")
     r = subprocess.run([DRIVER], capture_output=True, text=True, timeout=120)
     print(r.stdout)
