@@ -145,7 +145,12 @@ def time_tunes(kernel, n, tunes, reps=20, warmup=3, device="cuda", sets=None):
 def tune(kernel, n, tunes=None, reps=20, save=True, device="cuda"):
     """Times every candidate shape of ``kernel`` at ``n`` points; returns
     {"tune": best, "us": time, "GB_s": algorithmic bandwidth, "table": [...]}."""
-    tunes = list(candidates()) if tunes is None else list(tunes)
+    if tunes is None:
+        tunes = list(candidates())
+        if kernel == "christoffel":     # components of a point spread over lanes
+            tunes += [{"block": b, "nt": True, "lanes": la}
+                      for b in (64, 256) for la in (2, 3, 6, 9, 18)]
+    tunes = list(tunes)
     us = time_tunes(kernel, n, tunes, reps=reps, device=device)
     table = sorted(zip(us, range(len(tunes))))
     best_us, bi = table[0]
