@@ -31,13 +31,11 @@
  * Errors.  Argument errors are detected before anything is launched and are
  * returned synchronously: a NULL pointer while n > 0 (TL_ERR_NULL); n < 0 or
  * ld < n (TL_ERR_SIZE); a pointer that is not 8-byte aligned (TL_ERR_ALIGN);
- * an output whose address range overlaps an input's or another output's
- * (TL_ERR_ALIAS: an element of an output is also an element of another
- * field -- fields interleaved in one buffer without sharing an element, such
- * as point ranges of one large field, are accepted; inputs may overlap each
- * other); an invalid
- * tuning or plan argument (TL_ERR_INVALID).  A
- * launch failure reported by the HIP runtime returns TL_ERR_HIP.  For every
+ * an output that shares an element with an input or another output
+ * (TL_ERR_ALIAS; fields interleaved in one buffer without sharing an element,
+ * such as point ranges of one large field, are accepted, and inputs may
+ * overlap each other); an invalid tuning or plan argument (TL_ERR_INVALID).
+ * A launch failure reported by the HIP runtime returns TL_ERR_HIP.  For every
  * error a message is available from tl_last_error() (per calling thread).
  * n == 0 returns TL_OK without launching.  Numerical conditions are not
  * reported: a singular metric propagates IEEE inf/NaN.  No C++ exception
@@ -178,12 +176,14 @@ typedef struct tl_batch_plan tl_batch_plan;
 /* Builds a plan that evaluates tl_dtg_chain on every domain with one kernel
  * launch over the tiles of all domains, captured once into a HIP graph (by
  * default one block per tile; tune->grid_mult > 0 makes it persistent, each
- * block walking a contiguous chunk of tiles).  The plan copies
- * the domain table to device memory (the only allocation it makes) and
- * borrows the domains' buffers, which must outlive it; if any pointer
- * changes, destroy the plan and create a new one.  ndom >= 1; domains with
- * n == 0 are allowed.  Validation is as for tl_dtg_chain, per domain, plus:
- * no domain's output may overlap any domain's input or output. */
+ * block walking a contiguous chunk of tiles).  The plan copies the domain
+ * table and its tile tables to device memory (its only device allocations,
+ * freed by tl_batch_plan_destroy) and borrows the domains' buffers, which
+ * must outlive it; if any pointer changes, destroy the plan and create a new
+ * one.  ndom >= 1; domains with n == 0 are allowed.  Validation is as for
+ * tl_dtg_chain, per domain, plus: no domain's output may share an element
+ * with any domain's input or output (domains that are point ranges of the
+ * same fields are accepted). */
 tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tune* tune,
                                tl_batch_plan** out);
 /* Replays the captured launch on `stream` (asynchronous). */
