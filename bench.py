@@ -397,6 +397,32 @@ def main():
                                       "frac_of_rw_model": rate(BYTES["dtg_chain_fwd_bwd"] * n, ms_fb)
                                       / rw_model(*RW_DOUBLES["dtg_chain_fwd_bwd"], rgbs, wgbs)}
         del ref, fb
+        log("[bench] the autograd step (torch.autograd.Function), eager and captured")
+        from paper_1804_10120_amd import dtg_chain
+        leaf = {k: d[k].detach().clone().requires_grad_(True) for k in KEYS}
+        wt = d["W"]
+
+        def ag_step():
+            for t in leaf.values():
+                t.grad = None
+            dtg_chain(*[leaf[k] for k in KEYS]).backward(wt)
+        ms_ag, _ = time_calls([[ag_step]], args.steps, args.warmup)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(2):
+                ag_step()
+        torch.cuda.current_stream().wait_stream(side)
+        for t in leaf.values():
+            t.grad = None
+        ag_graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(ag_graph):
+            dtg_chain(*[leaf[k] for k in KEYS]).backward(wt)
+        ms_agg, _ = time_calls([[ag_graph.replay]], args.steps, args.warmup)
+        rows["autograd_step"] = {"eager_us": ms_ag * 1e3, "eager_points_per_s": n / (ms_ag * 1e-3),
+                                 "graph_us": ms_agg * 1e3,
+                                 "graph_points_per_s": n / (ms_agg * 1e-3)}
+        del leaf, ag_graph
         log("[bench] unfused steps")
         with record() as unf:
             ginv = tl_sym_inverse(d["g"])
