@@ -595,7 +595,28 @@ def main():
             "ld_unpadded_us": ms_flat * 1e3,
             "ld_unpadded_GB_s": rate(BYTES["dtg_chain_batched"] * npts, ms_flat)}
         plan.close()
-        del doms, many, outs, graph256
+        del many, outs, graph256
+
+        log("[bench] 256 subgrids, the adjoint")
+        for i, (e, d) in enumerate(zip(edges, doms)):
+            w = make_fields(int(e) ** 3, seed=config_seed(4) * 1000 + i, fields=("W",))["W"]
+            d["W"] = to_field(w, device=device)
+        bdoms = [{k: d[k] for k in ("g", "dg", "beta", "K", "alpha", "W")} for d in doms]
+        tuned_b = autotune.tune_plan(bdoms, kind="bwd", save=False)
+        bplan = BatchPlan(bdoms, tune=tuned_b["tune"], kind="bwd")
+        _, (ms_bplan,) = time_calls([[bplan.run]], 20, 3)
+        with record() as bmany:
+            for d, gr in zip(bdoms, bplan.outputs):
+                tl_dtg_chain_bwd(d["g"], d["dg"], d["beta"], d["K"], d["alpha"], d["W"], *gr)
+        ms_bmany, _ = time_calls([bmany], 10, 2)
+        rows["dtg_chain_bwd_batched"] = {
+            "subgrids": 256, "points": npts, "us": ms_bplan * 1e3, "tune": tuned_b["tune"],
+            "points_per_s": npts / (ms_bplan * 1e-3),
+            "GB_s": rate(BYTES["dtg_chain_bwd"] * npts, ms_bplan),
+            "separate_launches_us": ms_bmany * 1e3,
+            "separate_launches_points_per_s": npts / (ms_bmany * 1e-3)}
+        bplan.close()
+        del doms, bdoms, bplan, bmany
         log("[bench] the paper's benchmark expressions, grid-size sweep")
         table = paper_family(device, SWEEP_SIZES)
         rows["paper_family"] = family_summary(table)

@@ -186,6 +186,21 @@ typedef struct tl_batch_plan tl_batch_plan;
  * same fields are accepted). */
 tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tune* tune,
                                tl_batch_plan** out);
+/* One subgrid of the adjoint: n points, the inputs of tl_dtg_chain_bwd and
+ * its gradient outputs (an output whose ptr is NULL is skipped; at least one
+ * must be non-NULL when n > 0). */
+typedef struct {
+  int64_t n;
+  tl_cfield g, dg, beta, K, alpha, w;
+  tl_field g_bar, dg_bar, beta_bar, dbeta_bar, K_bar, alpha_bar;
+} tl_domain_bwd;
+
+/* The same for the adjoint: a plan that evaluates tl_dtg_chain_bwd on every
+ * domain with one captured launch.  Ownership, validation and the functions
+ * below (launch, info, destroy) are as for tl_batch_plan_create. */
+tl_status tl_batch_plan_bwd_create(const tl_domain_bwd* doms, int32_t ndom, const tl_tune* tune,
+                                   tl_batch_plan** out);
+
 /* Replays the captured launch on `stream` (asynchronous). */
 tl_status tl_batch_plan_launch(tl_batch_plan* plan, void* stream);
 /* Launches the same kernel directly, without the graph (asynchronous). */

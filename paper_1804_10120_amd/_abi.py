@@ -42,6 +42,13 @@ class Domain(ctypes.Structure):
                 ("dbeta", CField), ("K", CField), ("alpha", CField), ("dtg", Field)]
 
 
+class DomainBwd(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("g", CField), ("dg", CField), ("beta", CField),
+                ("K", CField), ("alpha", CField), ("w", CField), ("g_bar", Field),
+                ("dg_bar", Field), ("beta_bar", Field), ("dbeta_bar", Field), ("K_bar", Field),
+                ("alpha_bar", Field)]
+
+
 class KernelAttr(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("ppt", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("num_regs", ctypes.c_int32), ("local_bytes", ctypes.c_int32),
@@ -68,6 +75,8 @@ SIGNATURES = {
     "tl_dtg_chain_fwd_bwd": [_I64, _C, _C, _C, _C, _C, _C, _C, _F, _F, _F, _F, _F, _F, _F, _S,
                              _T],
     "tl_batch_plan_create": [ctypes.POINTER(Domain), ctypes.c_int32, _T, ctypes.POINTER(ctypes.c_void_p)],
+    "tl_batch_plan_bwd_create": [ctypes.POINTER(DomainBwd), ctypes.c_int32, _T,
+                                 ctypes.POINTER(ctypes.c_void_p)],
     "tl_batch_plan_launch": [ctypes.c_void_p, _S],
     "tl_batch_plan_launch_direct": [ctypes.c_void_p, _S],
     "tl_batch_plan_info": [ctypes.c_void_p, ctypes.POINTER(_I64), ctypes.POINTER(_I64),

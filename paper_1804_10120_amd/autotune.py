@@ -177,31 +177,31 @@ def plan_candidates(blocks=PLAN_BLOCKS, ppts=PPTS, xcds=XCDS, grid_mults=PLAN_GR
         yield {"block": b, "ppt": p, "nt": True, "xcd": x, "grid_mult": gm}
 
 
-def plan_key(domains):
-    """Cache key of a set of subgrids: architecture, number of subgrids and the
-    size class of the total and of the mean subgrid."""
+def plan_key(domains, kind="fwd"):
+    """Cache key of a set of subgrids: plan kind, architecture, number of
+    subgrids and the size class of the total and of the mean subgrid."""
     sizes = [int(d["K"].shape[-1]) for d in domains]
     total = max(1, sum(sizes))
     mean = max(1, total // max(1, len(sizes)))
-    return (f"batch_plan|{_arch()}|ndom={len(sizes)}|log2n={int(math.log2(total))}"
+    return (f"batch_plan_{kind}|{_arch()}|ndom={len(sizes)}|log2n={int(math.log2(total))}"
             f"|log2mean={int(math.log2(mean))}")
 
 
-def lookup_plan(domains):
+def lookup_plan(domains, kind="fwd"):
     """The cached best shape for subgrids like ``domains``, or None."""
-    e = load_cache().get(plan_key(domains))
+    e = load_cache().get(plan_key(domains, kind))
     return None if e is None else e["tune"]
 
 
-def tune_plan(domains, tunes=None, reps=10, warmup=2, save=True):
-    """Builds a plan over ``domains`` for every candidate shape, times its graph
-    replay with HIP events (median of ``reps``) and returns {"tune", "us",
-    "table"} for the fastest; caches it under plan_key(domains)."""
+def tune_plan(domains, tunes=None, reps=10, warmup=2, save=True, kind="fwd", want=None):
+    """Builds a plan of ``kind`` over ``domains`` for every candidate shape,
+    times its graph replay with HIP events (median of ``reps``) and returns
+    {"tune", "us", "table"} for the fastest; caches it under plan_key."""
     from .ops import BatchPlan
     tunes = list(plan_candidates()) if tunes is None else list(tunes)
     us = []
     for t in tunes:
-        plan = BatchPlan(domains, tune=t)
+        plan = BatchPlan(domains, tune=t, kind=kind, want=want)
         try:
             for _ in range(warmup):
                 plan.run()
@@ -222,6 +222,6 @@ def tune_plan(domains, tunes=None, reps=10, warmup=2, save=True):
            "table": [{"tune": tunes[i], "us": u} for u, i in table]}
     if save:
         c = load_cache()
-        c[plan_key(domains)] = {"tune": res["tune"], "us": best_us}
+        c[plan_key(domains, kind)] = {"tune": res["tune"], "us": best_us}
         save_cache(c)
     return res

@@ -175,7 +175,7 @@ tl::Resolved defaults(tl::KernelId k, int64_t n) {
   tl::Resolved r;
   r.nt = true;
   r.grid_mult = 0;
-  if (k == tl::KernelId::ChainBatched) {
+  if (k == tl::KernelId::ChainBatched || k == tl::KernelId::ChainBwdBatched) {
     r.block = 128;
     r.ppt = 1;
     r.xcd = false;
@@ -266,6 +266,7 @@ void set_out(tl::KArgs& a, int f, tl_field x) {
 
 struct tl_batch_plan {
   int device = 0;
+  tl::KernelId kid = tl::KernelId::ChainBatched;
   tl::Resolved r;
   int32_t ndom = 0;
   int64_t points = 0, ntiles = 0, grid = 0, chunk = 1;
@@ -434,15 +435,13 @@ tl_status tl_dtg_chain(int64_t n, tl_cfield g, tl_cfield dg, tl_cfield beta, tl_
   return run(tl::KernelId::Chain, c, tune, chain_args(g, dg, beta, dbeta, K, alpha, dtg), stream);
 }
 
-tl_status tl_dtg_chain_bwd(int64_t n, tl_cfield g, tl_cfield dg, tl_cfield beta, tl_cfield K,
-                           tl_cfield alpha, tl_cfield w, tl_field g_bar, tl_field dg_bar,
-                           tl_field beta_bar, tl_field dbeta_bar, tl_field K_bar,
-                           tl_field alpha_bar, void* stream, const tl_tune* tune) {
-  if (n < 0) return fail(TL_ERR_SIZE, "n=%lld < 0", (long long)n);
-  if (n == 0) return TL_OK;
-  if (!g_bar.ptr && !dg_bar.ptr && !beta_bar.ptr && !dbeta_bar.ptr && !K_bar.ptr && !alpha_bar.ptr)
-    return fail(TL_ERR_NULL, "every gradient output is NULL");
-  Checker c(n);
+static bool all_null(tl_field a, tl_field b, tl_field c, tl_field d, tl_field e, tl_field f) {
+  return !a.ptr && !b.ptr && !c.ptr && !d.ptr && !e.ptr && !f.ptr;
+}
+
+static void bwd_fields(Checker& c, tl_cfield g, tl_cfield dg, tl_cfield beta, tl_cfield K,
+                       tl_cfield alpha, tl_cfield w, tl_field g_bar, tl_field dg_bar,
+                       tl_field beta_bar, tl_field dbeta_bar, tl_field K_bar, tl_field alpha_bar) {
   c.field("g", g.ptr, g.ld, 6, false);
   c.field("dg", dg.ptr, dg.ld, 18, false);
   c.field("beta", beta.ptr, beta.ld, 3, false);
@@ -455,7 +454,12 @@ tl_status tl_dtg_chain_bwd(int64_t n, tl_cfield g, tl_cfield dg, tl_cfield beta,
   c.field("dbeta_bar", dbeta_bar.ptr, dbeta_bar.ld, 9, true, true);
   c.field("K_bar", K_bar.ptr, K_bar.ld, 6, true, true);
   c.field("alpha_bar", alpha_bar.ptr, alpha_bar.ld, 1, true, true);
-  if (c.overlaps() != TL_OK) return c.st;
+}
+
+static tl::KArgs bwd_args(tl_cfield g, tl_cfield dg, tl_cfield beta, tl_cfield K,
+                          tl_cfield alpha, tl_cfield w, tl_field g_bar, tl_field dg_bar,
+                          tl_field beta_bar, tl_field dbeta_bar, tl_field K_bar,
+                          tl_field alpha_bar) {
   tl::KArgs a = zero_args();
   set_in(a, 0, g);
   set_in(a, 1, dg);
@@ -471,7 +475,24 @@ tl_status tl_dtg_chain_bwd(int64_t n, tl_cfield g, tl_cfield dg, tl_cfield beta,
   set_out(a, 4, K_bar);
   set_out(a, 5, alpha_bar);
   a.ldout[5] = 0;
-  return run(tl::KernelId::ChainBwd, c, tune, a, stream);
+  return a;
+}
+
+tl_status tl_dtg_chain_bwd(int64_t n, tl_cfield g, tl_cfield dg, tl_cfield beta, tl_cfield K,
+                           tl_cfield alpha, tl_cfield w, tl_field g_bar, tl_field dg_bar,
+                           tl_field beta_bar, tl_field dbeta_bar, tl_field K_bar,
+                           tl_field alpha_bar, void* stream, const tl_tune* tune) {
+  if (n < 0) return fail(TL_ERR_SIZE, "n=%lld < 0", (long long)n);
+  if (n == 0) return TL_OK;
+  if (all_null(g_bar, dg_bar, beta_bar, dbeta_bar, K_bar, alpha_bar))
+    return fail(TL_ERR_NULL, "every gradient output is NULL");
+  Checker c(n);
+  bwd_fields(c, g, dg, beta, K, alpha, w, g_bar, dg_bar, beta_bar, dbeta_bar, K_bar, alpha_bar);
+  if (c.overlaps() != TL_OK) return c.st;
+  return run(tl::KernelId::ChainBwd, c, tune,
+             bwd_args(g, dg, beta, K, alpha, w, g_bar, dg_bar, beta_bar, dbeta_bar, K_bar,
+                      alpha_bar),
+             stream);
 }
 
 tl_status tl_dtg_chain_fwd_bwd(int64_t n, tl_cfield g, tl_cfield dg, tl_cfield beta,
@@ -641,60 +662,60 @@ tl_status tl_bw_stream(int64_t n, int32_t kind, const double* src, double* dst, 
 
 // ---------------------------------------------------------------- batch plans
 
-tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tune* tune,
-                               tl_batch_plan** out) {
-  if (out == nullptr) return fail(TL_ERR_NULL, "out is NULL");
-  *out = nullptr;
-  if (doms == nullptr) return fail(TL_ERR_NULL, "doms is NULL");
-  if (ndom < 1) return fail(TL_ERR_SIZE, "ndom=%d < 1", ndom);
+namespace {
 
-  // Per-domain validation, then overlap of every output with every field of
-  // every domain.
-  std::vector<Span> all;
+// What a plan is built from: each domain's n and kernel arguments, the spans
+// of all its fields (already validated per domain) and the layout facts.
+struct PlanInput {
+  std::vector<int64_t> n;
+  std::vector<tl::KArgs> args;
+  std::vector<Span> spans;
   bool vec_ok = true, buf_ok = true;
   int64_t points = 0;
-  for (int32_t d = 0; d < ndom; ++d) {
-    const tl_domain& x = doms[d];
-    if (x.n < 0) return fail(TL_ERR_SIZE, "domain %d: n=%lld < 0", d, (long long)x.n);
-    if (x.n == 0) continue;
-    Checker c(x.n);
-    chain_fields(c, "", x.g, x.dg, x.beta, x.dbeta, x.K, x.alpha, x.dtg);
-    if (c.overlaps() != TL_OK) return fail(c.st, "domain %d: %s", d, g_last_error.c_str());
+  void add(int64_t nd, const tl::KArgs& a, const Checker& c) {
+    n.push_back(nd);
+    args.push_back(a);
+    if (nd == 0) return;
+    spans.insert(spans.end(), c.spans.begin(), c.spans.end());
     vec_ok = vec_ok && c.vec_ok;
     buf_ok = buf_ok && c.buf_ok;
-    all.insert(all.end(), c.spans.begin(), c.spans.end());
-    points += x.n;
+    points += nd;
   }
+};
+
+// Checks the outputs of all domains against every field of every domain,
+// builds the tile tables, copies them to the device and captures the launch.
+tl_status build_plan(tl::KernelId kid, PlanInput& in, const tl_tune* tune, tl_batch_plan** out) {
   {
     const char* a = nullptr;
     const char* b = nullptr;
-    if (Checker::overlapping(all, &a, &b))
+    if (Checker::overlapping(in.spans, &a, &b))
       return fail(TL_ERR_ALIAS, "%s of one domain overlaps %s of another", a, b);
   }
-
   tl::Resolved r;
-  tl_status s = resolve(tl::KernelId::ChainBatched, tune, vec_ok, buf_ok, points, &r);
+  tl_status s = resolve(kid, tune, in.vec_ok, in.buf_ok, in.points, &r);
   if (s != TL_OK) return s;
 
+  const int32_t ndom = static_cast<int32_t>(in.n.size());
   std::vector<tl::BatchDomain> h(ndom);
   std::vector<int64_t> start(ndom + 1);
   std::vector<int32_t> tile_dom;
   const int64_t per = static_cast<int64_t>(r.block) * r.ppt;
   start[0] = 0;
   for (int32_t d = 0; d < ndom; ++d) {
-    const tl_domain& x = doms[d];
     std::memset(&h[d], 0, sizeof(tl::BatchDomain));
-    h[d].n = x.n;
-    if (x.n > 0) h[d].args = chain_args(x.g, x.dg, x.beta, x.dbeta, x.K, x.alpha, x.dtg);
-    start[d + 1] = start[d] + (x.n + per - 1) / per;
+    h[d].n = in.n[d];
+    if (in.n[d] > 0) h[d].args = in.args[d];
+    start[d + 1] = start[d] + (in.n[d] + per - 1) / per;
     tile_dom.insert(tile_dom.end(), static_cast<size_t>(start[d + 1] - start[d]), d);
   }
 
   tl_batch_plan* p = new (std::nothrow) tl_batch_plan;
   if (p == nullptr) return fail(TL_ERR_INVALID, "out of host memory");
+  p->kid = kid;
   p->r = r;
   p->ndom = ndom;
-  p->points = points;
+  p->points = in.points;
   p->ntiles = start[ndom];
   hipError_t e = hipGetDevice(&p->device);
   // Grid: one block per tile (grid_mult 0, the default), or a persistent grid
@@ -735,8 +756,8 @@ tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tun
     if (e != hipSuccess) return cleanup(e, "hipStreamCreate");
     e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return cleanup(e, "hipStreamBeginCapture");
-    hipError_t le = tl::launch_batched(p->r, p->d_doms, p->d_start, p->d_tile_dom, p->ntiles,
-                                       p->grid, p->chunk, p->cap);
+    hipError_t le = tl::launch_batched(p->kid, p->r, p->d_doms, p->d_start, p->d_tile_dom,
+                                       p->ntiles, p->grid, p->chunk, p->cap);
     e = hipStreamEndCapture(p->cap, &p->graph);
     if (le != hipSuccess) return cleanup(le, "captured launch");
     if (e != hipSuccess) return cleanup(e, "hipStreamEndCapture");
@@ -745,6 +766,60 @@ tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tun
   }
   *out = p;
   return TL_OK;
+}
+
+tl_status plan_preamble(const void* doms, int32_t ndom, tl_batch_plan** out) {
+  if (out == nullptr) return fail(TL_ERR_NULL, "out is NULL");
+  *out = nullptr;
+  if (doms == nullptr) return fail(TL_ERR_NULL, "doms is NULL");
+  if (ndom < 1) return fail(TL_ERR_SIZE, "ndom=%d < 1", ndom);
+  return TL_OK;
+}
+
+}  // namespace
+
+tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tune* tune,
+                               tl_batch_plan** out) {
+  const tl_status s0 = plan_preamble(doms, ndom, out);
+  if (s0 != TL_OK) return s0;
+  PlanInput in;
+  for (int32_t d = 0; d < ndom; ++d) {
+    const tl_domain& x = doms[d];
+    if (x.n < 0) return fail(TL_ERR_SIZE, "domain %d: n=%lld < 0", d, (long long)x.n);
+    Checker c(x.n);
+    if (x.n > 0) {
+      chain_fields(c, "", x.g, x.dg, x.beta, x.dbeta, x.K, x.alpha, x.dtg);
+      if (c.overlaps() != TL_OK) return fail(c.st, "domain %d: %s", d, g_last_error.c_str());
+    }
+    in.add(x.n, x.n > 0 ? chain_args(x.g, x.dg, x.beta, x.dbeta, x.K, x.alpha, x.dtg)
+                        : zero_args(), c);
+  }
+  return build_plan(tl::KernelId::ChainBatched, in, tune, out);
+}
+
+tl_status tl_batch_plan_bwd_create(const tl_domain_bwd* doms, int32_t ndom, const tl_tune* tune,
+                                   tl_batch_plan** out) {
+  const tl_status s0 = plan_preamble(doms, ndom, out);
+  if (s0 != TL_OK) return s0;
+  PlanInput in;
+  for (int32_t d = 0; d < ndom; ++d) {
+    const tl_domain_bwd& x = doms[d];
+    if (x.n < 0) return fail(TL_ERR_SIZE, "domain %d: n=%lld < 0", d, (long long)x.n);
+    Checker c(x.n);
+    if (x.n > 0) {
+      if (all_null(x.g_bar, x.dg_bar, x.beta_bar, x.dbeta_bar, x.K_bar, x.alpha_bar))
+        return fail(TL_ERR_NULL, "domain %d: every gradient output is NULL", d);
+      bwd_fields(c, x.g, x.dg, x.beta, x.K, x.alpha, x.w, x.g_bar, x.dg_bar, x.beta_bar,
+                 x.dbeta_bar, x.K_bar, x.alpha_bar);
+      if (c.overlaps() != TL_OK) return fail(c.st, "domain %d: %s", d, g_last_error.c_str());
+    }
+    in.add(x.n,
+           x.n > 0 ? bwd_args(x.g, x.dg, x.beta, x.K, x.alpha, x.w, x.g_bar, x.dg_bar,
+                              x.beta_bar, x.dbeta_bar, x.K_bar, x.alpha_bar)
+                   : zero_args(),
+           c);
+  }
+  return build_plan(tl::KernelId::ChainBwdBatched, in, tune, out);
 }
 
 static tl_status plan_device_check(const tl_batch_plan* p) {
@@ -767,8 +842,8 @@ tl_status tl_batch_plan_launch_direct(tl_batch_plan* p, void* stream) {
   if (p == nullptr) return fail(TL_ERR_NULL, "plan is NULL");
   if (plan_device_check(p) != TL_OK) return TL_ERR_INVALID;
   if (p->ntiles == 0) return TL_OK;
-  hipError_t e = tl::launch_batched(p->r, p->d_doms, p->d_start, p->d_tile_dom, p->ntiles,
-                                    p->grid, p->chunk, static_cast<hipStream_t>(stream));
+  hipError_t e = tl::launch_batched(p->kid, p->r, p->d_doms, p->d_start, p->d_tile_dom,
+                                    p->ntiles, p->grid, p->chunk, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "batched launch");
   return TL_OK;
 }
@@ -818,7 +893,8 @@ tl_status tl_kernel_info(const char* kernel, const tl_tune* tune, tl_kernel_attr
                {"cov_deriv", tl::KernelId::CovDeriv},     {"dtg", tl::KernelId::Dtg},
                {"dtg_chain", tl::KernelId::Chain},        {"dtg_chain_bwd", tl::KernelId::ChainBwd},
                {"dtg_chain_batched", tl::KernelId::ChainBatched},
-               {"dtg_chain_fwd_bwd", tl::KernelId::ChainFwdBwd}};
+               {"dtg_chain_fwd_bwd", tl::KernelId::ChainFwdBwd},
+               {"dtg_chain_bwd_batched", tl::KernelId::ChainBwdBatched}};
   const tl::KernelId* id = nullptr;
   for (const auto& x : names)
     if (std::strcmp(x.name, kernel) == 0) id = &x.id;

@@ -28,7 +28,7 @@ struct alignas(64) BatchDomain {
 };
 
 enum class KernelId { SymInverse, Christoffel, CovDeriv, Dtg, Chain, ChainBwd, ChainBatched,
-                      ChainFwdBwd };
+                      ChainFwdBwd, ChainBwdBatched };
 
 // A tuning request resolved to one compiled instantiation.
 struct Resolved {
@@ -72,7 +72,7 @@ tl_status run_generated(const char* name, int64_t n, const tl_cfield* in, int32_
                         int32_t nout, const int32_t* out_ncomp, int32_t nout_expected,
                         void* stream, const tl_tune* tune, LaunchFn launch);
 
-hipError_t launch_batched(const Resolved& r, const BatchDomain* doms, const int64_t* start,
+hipError_t launch_batched(KernelId k, const Resolved& r, const BatchDomain* doms, const int64_t* start,
                           const int32_t* tile_dom, int64_t ntiles, int64_t grid, int64_t chunk,
                           hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, int64_t n, int64_t grid, hipStream_t s);

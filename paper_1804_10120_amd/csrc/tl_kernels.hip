@@ -15,18 +15,18 @@ namespace tl {
 // walks the contiguous chunk of tiles [lb*chunk, (lb+1)*chunk), so
 // consecutive tiles of a block are mostly in the same subgrid and its
 // descriptor is fetched again only when the subgrid changes.  With chunk = 1
-// and one block per tile this is a plain (non-persistent) launch.
-template <int BLOCK, int PPT, bool NT, bool BUF>
-__global__ __launch_bounds__(BLOCK) void k_chain_batched(const BatchDomain* __restrict__ doms,
-                                                          const int64_t* __restrict__ start,
-                                                          const int32_t* __restrict__ tile_dom,
-                                                          int64_t ntiles, int64_t chunk,
-                                                          int32_t xcd) {
+// and one block per tile this is a plain (non-persistent) launch.  Op is the
+// per-point body: the fused chain (OpChain) or its adjoint (OpChainBwd).
+template <class Op, int BLOCK, int PPT, bool NT, bool BUF>
+__global__ __launch_bounds__(BLOCK) void k_batched(const BatchDomain* __restrict__ doms,
+                                                    const int64_t* __restrict__ start,
+                                                    const int32_t* __restrict__ tile_dom,
+                                                    int64_t ntiles, int64_t chunk, int32_t xcd) {
   const int64_t t0 = logical_block(xcd) * chunk;
   const int64_t t1 = t0 + chunk < ntiles ? t0 + chunk : ntiles;
   int32_t cur = -1;
   KArgs a;
-  Bufs<OpChain> b;
+  Bufs<Op> b;
   int64_t n = 0, s0 = 0;
   for (int64_t t = t0; t < t1; ++t) {
     const int32_t d = tile_dom[t];
@@ -35,10 +35,10 @@ __global__ __launch_bounds__(BLOCK) void k_chain_batched(const BatchDomain* __re
       a = doms[d].args;
       n = doms[d].n;
       s0 = start[d];
-      if constexpr (BUF) b = make_bufs<OpChain>(a, n);
+      if constexpr (BUF) b = make_bufs<Op>(a, n);
     }
-    if constexpr (BUF) tile_buf<OpChain, BLOCK, PPT, NT>(a, b, n, t - s0);
-    else tile<OpChain, BLOCK, PPT, NT>(a, n, t - s0);
+    if constexpr (BUF) tile_buf<Op, BLOCK, PPT, NT>(a, b, n, t - s0);
+    else tile<Op, BLOCK, PPT, NT>(a, n, t - s0);
   }
 }
 
@@ -140,21 +140,23 @@ static const void* ptr_christoffel_lanes(const Resolved& r) {
   }
 }
 
-template <int BLOCK, int PPT, bool NT, bool BUF>
+template <class Op, int BLOCK, int PPT, bool NT, bool BUF>
 static const void* batched_ptr() {
-  return reinterpret_cast<const void*>(&k_chain_batched<BLOCK, PPT, NT, BUF>);
+  return reinterpret_cast<const void*>(&k_batched<Op, BLOCK, PPT, NT, BUF>);
 }
 
-template <int BLOCK, int PPT>
+template <class Op, int BLOCK, int PPT>
 static const void* batched_ptr_p(const Resolved& r) {
-  if (!r.nt) return batched_ptr<BLOCK, PPT, false, false>();
-  return r.buf ? batched_ptr<BLOCK, PPT, true, true>() : batched_ptr<BLOCK, PPT, true, false>();
+  if (!r.nt) return batched_ptr<Op, BLOCK, PPT, false, false>();
+  return r.buf ? batched_ptr<Op, BLOCK, PPT, true, true>()
+               : batched_ptr<Op, BLOCK, PPT, true, false>();
 }
 
-static const void* ptr_batched(const Resolved& r) {
+template <class Op>
+static const void* ptr_batched_op(const Resolved& r) {
 #define TL_PTR(B) \
   case B:         \
-    return r.ppt == 2 ? batched_ptr_p<B, 2>(r) : batched_ptr_p<B, 1>(r);
+    return r.ppt == 2 ? batched_ptr_p<Op, B, 2>(r) : batched_ptr_p<Op, B, 1>(r);
   switch (r.block) {
     TL_PTR(64)
     TL_PTR(128)
@@ -164,6 +166,14 @@ static const void* ptr_batched(const Resolved& r) {
     default: return nullptr;
   }
 #undef TL_PTR
+}
+
+static const void* ptr_batched(KernelId k, const Resolved& r) {
+  switch (k) {
+    case KernelId::ChainBatched: return ptr_batched_op<OpChain>(r);
+    case KernelId::ChainBwdBatched: return ptr_batched_op<OpChainBwd>(r);
+    default: return nullptr;
+  }
 }
 
 hipError_t launch_twin(int nin, int nout, const Resolved& r, const KArgs& a, int64_t n,
@@ -199,15 +209,16 @@ const void* kernel_address(KernelId k, const Resolved& r) {
     case KernelId::Chain: return ptr_op<OpChain>(r);
     case KernelId::ChainBwd: return ptr_op<OpChainBwd>(r);
     case KernelId::ChainFwdBwd: return ptr_op<OpChainFwdBwd>(r);
-    case KernelId::ChainBatched: return ptr_batched(r);
+    case KernelId::ChainBatched:
+    case KernelId::ChainBwdBatched: return ptr_batched(k, r);
     default: return nullptr;
   }
 }
 
-hipError_t launch_batched(const Resolved& r, const BatchDomain* doms, const int64_t* start,
+hipError_t launch_batched(KernelId k, const Resolved& r, const BatchDomain* doms, const int64_t* start,
                           const int32_t* tile_dom, int64_t ntiles, int64_t grid, int64_t chunk,
                           hipStream_t s) {
-  const void* fn = ptr_batched(r);
+  const void* fn = ptr_batched(k, r);
   if (fn == nullptr) return hipErrorInvalidValue;
   int32_t xcd = r.xcd ? 1 : 0;
   void* args[] = {const_cast<BatchDomain**>(&doms), const_cast<int64_t**>(&start),

@@ -15,7 +15,7 @@ import threading
 import torch
 
 from . import _abi
-from ._abi import CField, Domain, Field, KernelAttr, TLError, Tune, check, lib
+from ._abi import CField, Domain, DomainBwd, Field, KernelAttr, TLError, Tune, check, lib
 
 NCOMP = {"g": 6, "ginv": 6, "K": 6, "dtg": 6, "w": 6, "dg": 18, "gamma": 18, "beta": 3,
          "dbeta": 9, "nabla_beta": 9, "alpha": 1}
@@ -444,48 +444,75 @@ def tl_kernel_info(kernel, tune=None):
 
 
 class BatchPlan:
-    """tl_batch_plan_*: d_t g over many subgrids in one graph-captured launch.
+    """tl_batch_plan_*: d_t g (kind="fwd") or its adjoint (kind="bwd") over
+    many subgrids in one graph-captured launch.
 
-    ``domains`` is a sequence of dicts with the tensors g, dg, beta, dbeta, K,
-    alpha and (optionally) dtg of one subgrid each; missing outputs are
-    allocated with empty_field (leading dimension padded to 16 doubles).
-    ``tune="auto"`` takes the autotuner's cached shape for subgrids like these
-    (autotune.plan_key), tuning them first if nothing is cached.  The plan keeps references to every tensor, so the buffers it
+    kind="fwd": ``domains`` is a sequence of dicts with the tensors g, dg,
+    beta, dbeta, K, alpha and (optionally) dtg of one subgrid each.
+    kind="bwd": dicts with g, dg, beta, K, alpha, the cotangent W and
+    (optionally) g_bar, dg_bar, beta_bar, dbeta_bar, K_bar, alpha_bar; ``want``
+    (6 booleans in that order) selects the gradients computed.
+    Missing outputs are allocated with empty_field (leading dimension padded
+    to 16 doubles).  ``tune="auto"`` takes the autotuner's cached shape for
+    subgrids like these (autotune.plan_key), tuning them first if nothing is
+    cached.  The plan keeps references to every tensor, so the buffers it
     borrows outlive it.
     """
 
-    def __init__(self, domains, tune=None):
+    def __init__(self, domains, tune=None, kind="fwd", want=None):
         self._plan = None
         self.domains = []
+        if kind not in ("fwd", "bwd"):
+            raise ValueError(f"kind={kind!r}: expected 'fwd' or 'bwd'")
+        self.kind = kind
         if isinstance(tune, str):
             if tune != "auto":
                 raise ValueError(f"tune={tune!r}: expected None, 'auto', a dict, a tuple or a Tune")
             from . import autotune
-            tune = autotune.lookup_plan(domains)
+            tune = autotune.lookup_plan(domains, kind=kind)
             if tune is None:
-                tune = autotune.tune_plan(domains)["tune"]
-        arr = (Domain * len(domains))()
+                tune = autotune.tune_plan(domains, kind=kind, want=want)["tune"]
+        want = (True,) * 6 if want is None else tuple(bool(x) for x in want)
+        if len(want) != 6 or not any(want):
+            raise ValueError("want: 6 booleans, at least one true")
+        arr = ((Domain if kind == "fwd" else DomainBwd) * len(domains))()
         device = None
         for i, d in enumerate(domains):
             c = _Call()
-            for name in ("g", "dg", "beta", "dbeta", "K", "alpha"):
-                c.add(d[name], name)
+            names = ("g", "dg", "beta", "dbeta", "K", "alpha") if kind == "fwd" else \
+                ("g", "dg", "beta", "K", "alpha", "W")
+            for name in names:
+                c.add(d[name], "w" if name == "W" else name)
             if device is None:
                 device = c.device
             elif c.device != device:
                 raise ValueError("all subgrids must be on one device")
-            out = d.get("dtg")
-            out = c.out(empty_field(6, c.n, device=c.device) if out is None else out, "dtg", d["K"])
-            dom = dict(d, dtg=out)
-            self.domains.append(dom)
-            arr[i] = Domain(c.n, _cf(d["g"], 6), _cf(d["dg"], 18), _cf(d["beta"], 3),
-                            _cf(d["dbeta"], 9), _cf(d["K"], 6), _cf(d["alpha"], 1), _f(out, 6))
+            if kind == "fwd":
+                out = d.get("dtg")
+                out = c.out(empty_field(6, c.n, device=c.device) if out is None else out, "dtg",
+                            d["K"])
+                self.domains.append(dict(d, dtg=out))
+                arr[i] = Domain(c.n, _cf(d["g"], 6), _cf(d["dg"], 18), _cf(d["beta"], 3),
+                                _cf(d["dbeta"], 9), _cf(d["K"], 6), _cf(d["alpha"], 1),
+                                _f(out, 6))
+            else:
+                grads = []
+                for k, nc, w in zip(GRAD_NAMES, (6, 18, 3, 9, 6, 1), want):
+                    o = d.get(k + "_bar")
+                    if o is None and w:
+                        o = empty_field(nc, c.n, device=c.device)
+                    grads.append(c.out(o, k + "_bar", d["K"], nc) if o is not None else None)
+                self.domains.append(dict(d, **{k + "_bar": o for k, o in zip(GRAD_NAMES, grads)}))
+                arr[i] = DomainBwd(c.n, _cf(d["g"], 6), _cf(d["dg"], 18), _cf(d["beta"], 3),
+                                   _cf(d["K"], 6), _cf(d["alpha"], 1), _cf(d["W"], 6),
+                                   *[_f(o, nc) for o, nc in zip(grads, (6, 18, 3, 9, 6, 1))])
         if device is None:
             raise ValueError("BatchPlan needs at least one subgrid")
         self.device = device
         plan = ctypes.c_void_p()
+        create = lib().tl_batch_plan_create if kind == "fwd" else lib().tl_batch_plan_bwd_create
         with torch.cuda.device(device):
-            check(lib().tl_batch_plan_create(arr, len(domains), make_tune(tune), ctypes.byref(plan)))
+            check(create(arr, len(domains), make_tune(tune), ctypes.byref(plan)))
         self._plan = plan
         p, t, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         check(lib().tl_batch_plan_info(plan, ctypes.byref(p), ctypes.byref(t), ctypes.byref(b)))
@@ -493,7 +520,12 @@ class BatchPlan:
 
     @property
     def outputs(self):
-        return [d["dtg"] for d in self.domains]
+        """kind="fwd": each subgrid's d_t g; kind="bwd": each subgrid's tuple
+        (g_bar, dg_bar, beta_bar, dbeta_bar, K_bar, alpha_bar), None where not
+        wanted."""
+        if self.kind == "fwd":
+            return [d["dtg"] for d in self.domains]
+        return [tuple(d[k + "_bar"] for k in GRAD_NAMES) for d in self.domains]
 
     def run(self, stream=None):
         """Replay the captured graph on ``stream`` (default: current stream)."""

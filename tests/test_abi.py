@@ -313,3 +313,32 @@ def test_lanes_only_for_christoffel(L):
     a, out = chain_args(n)
     assert call_chain(L, n, a, out, lanes6_bad_block) == _abi.TL_ERR_INVALID
     assert b"lanes" in L.tl_last_error()
+
+
+def test_bwd_plan_validation(L):
+    from paper_1804_10120_amd._abi import DomainBwd
+    n = 32
+    plan = ctypes.c_void_p()
+
+    def dom(base, outs=True, w=True):
+        ins = [cf(base + i * MB, n) for i in range(6)]
+        if not w:
+            ins[5] = cf(None, n)
+        grads = [f(base + (10 + i) * MB, n) if outs else f(None, 0) for i in range(6)]
+        return DomainBwd(n, *ins, *grads)
+
+    arr = (DomainBwd * 2)(dom(BASE), dom(BASE + 64 * MB))
+    assert L.tl_batch_plan_bwd_create(None, 2, None, ctypes.byref(plan)) == _abi.TL_ERR_NULL
+    assert L.tl_batch_plan_bwd_create(arr, 0, None, ctypes.byref(plan)) == _abi.TL_ERR_SIZE
+    bad = ctypes.pointer(Tune(96, 0, 0, 0))
+    assert L.tl_batch_plan_bwd_create(arr, 2, bad, ctypes.byref(plan)) == _abi.TL_ERR_INVALID
+    arr[1] = dom(BASE + 64 * MB, outs=False)
+    assert L.tl_batch_plan_bwd_create(arr, 2, bad, ctypes.byref(plan)) == _abi.TL_ERR_NULL
+    assert b"domain 1" in L.tl_last_error()
+    arr[1] = dom(BASE + 64 * MB, w=False)
+    assert L.tl_batch_plan_bwd_create(arr, 2, bad, ctypes.byref(plan)) == _abi.TL_ERR_NULL
+    # domain 1 writes its g_bar onto domain 0's dg
+    arr[1] = dom(BASE + 64 * MB)
+    arr[1].g_bar = Field(BASE + 1 * MB + 8, n)
+    assert L.tl_batch_plan_bwd_create(arr, 2, bad, ctypes.byref(plan)) == _abi.TL_ERR_ALIAS
+    assert not plan.value

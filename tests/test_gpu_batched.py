@@ -6,7 +6,7 @@ import torch
 
 import oracle
 from gpu_util import assert_close, dev, need_gpu
-from paper_1804_10120_amd import BatchPlan, tl_dtg_chain
+from paper_1804_10120_amd import BatchPlan, tl_dtg_chain, tl_dtg_chain_bwd
 from paper_1804_10120_amd.synth import config_seed, domain_edges, make_fields
 
 pytestmark = pytest.mark.gpu
@@ -167,3 +167,85 @@ def test_autotuned_plan(tmp_path, monkeypatch):
     _check(auto, hosts, devs)
     auto.close()
     ref.close()
+
+
+# --------------------------------------------------------------------------- the adjoint
+
+GRADS = ("g", "dg", "beta", "dbeta", "K", "alpha")
+
+
+def _bwd_domains(sizes, seed):
+    hosts, devs = [], []
+    for d, n in enumerate(sizes):
+        f = make_fields(int(n), seed=seed * 1000 + d)
+        hosts.append(f)
+        devs.append({k: dev(f[k]) for k in ("g", "dg", "beta", "K", "alpha", "W")})
+    return hosts, devs
+
+
+@pytest.mark.parametrize("tune", [None, dict(block=64, ppt=1, nt=True),
+                                  dict(block=256, ppt=2, nt=True, grid_mult=2),
+                                  dict(block=128, ppt=1, nt=True, xcd=True, ptr64=True)],
+                         ids=["default", "b64", "b256ppt2grid", "b128xcdptr64"])
+def test_bwd_plan_small_batch(tune):
+    """Each subgrid's gradients equal the oracle's VJP and the plain adjoint
+    kernel's (same per-point body)."""
+    sizes = [1, 0, 63, 64, 65, 1000, 4097, 0, 27, 9 ** 3, 3]
+    hosts, devs = _bwd_domains(sizes, seed=21)
+    plan = BatchPlan(devs, tune=tune, kind="bwd")
+    assert plan.points == sum(sizes)
+    plan.run()
+    torch.cuda.synchronize()
+    for f, d, outs in zip(hosts, devs, plan.outputs):
+        if f["g"].shape[1] == 0:
+            continue
+        ref = oracle.dtg_chain_vjp(tuple(f[k] for k in KEYS), f["W"])
+        plain = tl_dtg_chain_bwd(d["g"], d["dg"], d["beta"], d["K"], d["alpha"], d["W"])
+        for k, o, p in zip(GRADS, outs, plain):
+            assert_close(o, ref[k], what=f"batched {k}_bar n={f['g'].shape[1]}")
+            assert_close(o, p, what=f"batched vs plain {k}_bar")
+    plan.close()
+
+
+def test_bwd_plan_wanted_subset_and_graph_replay():
+    sizes = [500, 1, 2048, 77]
+    hosts, devs = _bwd_domains(sizes, seed=22)
+    want = (0, 1, 0, 0, 1, 1)
+    plan = BatchPlan(devs, kind="bwd", want=want)
+    for rep in range(3):                    # replays with eager work in between
+        for outs in plan.outputs:
+            for o in outs:
+                if o is not None:
+                    o.fill_(-1.0)
+        torch.cuda.synchronize()
+        plan.run()
+        torch.cuda.synchronize()
+        for f, outs in zip(hosts, plan.outputs):
+            ref = oracle.dtg_chain_vjp(tuple(f[k] for k in KEYS), f["W"])
+            for k, w, o in zip(GRADS, want, outs):
+                if w:
+                    assert_close(o, ref[k], what=f"replay {rep} {k}_bar")
+                else:
+                    assert o is None
+    plan.close()
+
+
+def test_bwd_plan_full_multidomain_workload():
+    """256 subgrids with edges uniform on 8..48: every subgrid against the plain
+    adjoint kernel, 16 of them against the oracle."""
+    edges = domain_edges(256, seed=config_seed(4))
+    sizes = [int(e) ** 3 for e in edges]
+    hosts, devs = _bwd_domains(sizes, seed=23)
+    plan = BatchPlan(devs, kind="bwd")
+    plan.run()
+    torch.cuda.synchronize()
+    check = set(np.random.default_rng(1).choice(256, 16, replace=False).tolist())
+    for i, (f, d, outs) in enumerate(zip(hosts, devs, plan.outputs)):
+        plain = tl_dtg_chain_bwd(d["g"], d["dg"], d["beta"], d["K"], d["alpha"], d["W"])
+        for k, o, p in zip(GRADS, outs, plain):
+            assert_close(o, p, what=f"subgrid {i} {k}_bar vs plain")
+        if i in check:
+            ref = oracle.dtg_chain_vjp(tuple(f[k] for k in KEYS), f["W"])
+            for k, o in zip(GRADS, outs):
+                assert_close(o, ref[k], what=f"subgrid {i} {k}_bar vs oracle")
+    plan.close()
