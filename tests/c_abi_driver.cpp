@@ -212,6 +212,45 @@ int main() {
            "overlapping subgrid outputs refused");
   }
 
+  // the adjoint over the same three point ranges, every gradient into one
+  // buffer per gradient field (point ranges of it)
+  {
+    const int64_t lo[3] = {0, 5000, 7000}, cnt[3] = {5000, 1, n - 7000};
+    std::vector<Dev*> gout;
+    for (int f = 0; f < 6; ++f) gout.push_back(new Dev(gc[f] * n));
+    tl_domain_bwd doms[3];
+    for (int k = 0; k < 3; ++k) {
+      auto sub = [&](int f) { return tl_cfield{d[f]->p + lo[k], n}; };
+      auto out = [&](int f) { return tl_field{gout[f]->p + lo[k], n}; };
+      doms[k] = tl_domain_bwd{cnt[k], sub(0), sub(1), sub(2), sub(4), sub(5), sub(6),
+                              out(0), out(1), out(2), out(3), out(4), out(5)};
+    }
+    tl_batch_plan* plan = nullptr;
+    expect(tl_batch_plan_bwd_create(doms, 3, nullptr, &plan) == TL_OK && plan != nullptr,
+           "tl_batch_plan_bwd_create");
+    if (plan) {
+      expect(tl_batch_plan_launch(plan, s) == TL_OK, "adjoint plan launch");
+      expect(hipStreamSynchronize(s) == hipSuccess, "adjoint plan sync");
+      double worst = 0.0;
+      for (int f = 0; f < 6; ++f) {
+        const std::vector<double> got = gout[f]->get();
+        std::vector<double> a, b;
+        for (int c = 0; c < gc[f]; ++c)
+          for (int k = 0; k < 3; ++k)
+            for (int64_t p = lo[k]; p < lo[k] + cnt[k]; ++p) {
+              a.push_back(got[c * n + p]);
+              b.push_back(rg[f][c * n + p]);
+            }
+        const int64_t m = static_cast<int64_t>(a.size()) / gc[f];
+        worst = std::fmax(worst, rel_err(a, b, gc[f], m));
+      }
+      std::printf("adjoint plan rel err %.3e\n", worst);
+      expect(worst <= 1e-12, "adjoint plan vs oracle");
+      expect(tl_batch_plan_destroy(plan) == TL_OK, "adjoint plan destroy");
+    }
+    for (auto* x : gout) delete x;
+  }
+
   // argument errors come back before any launch
   expect(tl_dtg_chain(n, tl_cfield{nullptr, n}, cf(1), cf(2), cf(3), cf(4), cf(5),
                       tl_field{dtg.p, n}, s, nullptr) == TL_ERR_NULL, "NULL input");
