@@ -176,10 +176,18 @@ def test_singular_metric_propagates_nonfinite():
 
 
 @pytest.mark.parametrize("kernel", ["sym_inverse", "christoffel", "cov_deriv", "dtg", "dtg_chain",
-                                    "dtg_chain_bwd", "dtg_chain_batched"])
+                                    "dtg_chain_bwd", "dtg_chain_batched", "dtg_chain_fwd_bwd",
+                                    "dtg_chain_bwd_batched", "assign1", "contract3", "kij"])
 def test_kernel_info(kernel):
     a = tl_kernel_info(kernel)
     assert a["num_regs"] > 0 and a["max_threads"] >= a["block"]
+    assert a["local_bytes"] == 0, f"{kernel} spills to scratch"
+
+
+@pytest.mark.parametrize("lanes", [2, 3, 6, 9, 18])
+def test_kernel_info_lanes(lanes):
+    a = tl_kernel_info("christoffel", tune=dict(block=64, lanes=lanes))
+    assert a["num_regs"] > 0 and a["block"] == 64 and a["local_bytes"] == 0
 
 
 def test_graph_capture_replays():
