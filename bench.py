@@ -471,6 +471,23 @@ def main():
             "dtg_chain_invg": {"us": ms_gf * 1e3, "GB_s": rate(BYTES["dtg_chain"] * n, ms_gf),
                                "hand_written_fused_us": ms_fwd * 1e3}}
         del gl, gi, gam_g, dtg_g
+        # the Sec. 5.1 family: hand-written (tl_expr) against generated (tlg_*)
+        from paper_1804_10120_amd import tl_expr, tl_expr_shape
+        from paper_1804_10120_amd.synth import EXPR_INPUTS, make_expr_inputs
+        fam = {}
+        for name in EXPR_INPUTS:
+            ic, oc = tl_expr_shape(name)
+            xs = [torch.from_numpy(x).to(device) for x in make_expr_inputs(name, n, seed=5)]
+            o1 = torch.empty(oc, n, dtype=torch.float64, device=device)
+            o2 = torch.empty(oc, n, dtype=torch.float64, device=device)
+            with record() as fc:
+                tl_expr(name, *xs, out=o1)
+                gen_call(name, *xs, outs=[o2])
+            _, (mh, mg) = time_calls([fc], 20, 3)
+            nb = 8 * (sum(ic) + oc) * n
+            fam[name] = {"hand_GB_s": rate(nb, mh), "generated_GB_s": rate(nb, mg)}
+            del xs, o1, o2, fc
+        rows["generated"]["family"] = fam
 
         log("[bench] Christoffel symbols at 16^3 points")
         n16 = 16 ** 3

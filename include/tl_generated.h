@@ -66,12 +66,89 @@ tl_status tlg_dtg_chain_invg(int64_t n, const tl_cfield* in, int32_t nin, const 
  * stored elements read + written per point (BW_eff N_e): 16 */
 tl_status tlg_kij(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune);
 
+/* assign1: A_i = B_i (Sec. 5.1, eq:Assign1)
+ *   A(i) = B(i)
+ * in:  B [3] (3)
+ * out: A [3] (3)
+ * stored elements read + written per point (BW_eff N_e): 6 */
+tl_status tlg_assign1(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune);
+
+/* assign2: A_ij = B_ij (Sec. 5.1, eq:Assign2)
+ *   A(i,j) = B(i,j)
+ * in:  B [9] (3x3)
+ * out: A [9] (3x3)
+ * stored elements read + written per point (BW_eff N_e): 18 */
+tl_status tlg_assign2(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune);
+
+/* assign3: A_ijk = B_ijk (Sec. 5.1, eq:Assign3)
+ *   A(i,j,k) = B(i,j,k)
+ * in:  B [27] (3x3x3)
+ * out: A [27] (3x3x3)
+ * stored elements read + written per point (BW_eff N_e): 54 */
+tl_status tlg_assign3(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune);
+
+/* add1: A_i = B_i + C_i (Sec. 5.1, eq:Add1)
+ *   A(i) = (B(i) + C(i))
+ * in:  B [3] (3); C [3] (3)
+ * out: A [3] (3)
+ * stored elements read + written per point (BW_eff N_e): 9 */
+tl_status tlg_add1(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune);
+
+/* add2: A_i = B_i + C_i + D_i (Sec. 5.1, eq:Add2)
+ *   A(i) = ((B(i) + C(i)) + D(i))
+ * in:  B [3] (3); C [3] (3); D [3] (3)
+ * out: A [3] (3)
+ * stored elements read + written per point (BW_eff N_e): 12 */
+tl_status tlg_add2(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune);
+
+/* add3: A_i = B_i + C_i + D_i + E_i (Sec. 5.1, eq:Add3)
+ *   A(i) = (((B(i) + C(i)) + D(i)) + E(i))
+ * in:  B [3] (3); C [3] (3); D [3] (3); E [3] (3)
+ * out: A [3] (3)
+ * stored elements read + written per point (BW_eff N_e): 15 */
+tl_status tlg_add3(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune);
+
+/* mult1: A_ij = B_i C_j (Sec. 5.1, eq:Mult1)
+ *   A(i,j) = (B(i) * C(j))
+ * in:  B [3] (3); C [3] (3)
+ * out: A [9] (3x3)
+ * stored elements read + written per point (BW_eff N_e): 15 */
+tl_status tlg_mult1(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune);
+
+/* mult2: A_ijk = B_i C_j D_k (Sec. 5.1, eq:Mult2)
+ *   A(i,j,k) = ((B(i) * C(j)) * D(k))
+ * in:  B [3] (3); C [3] (3); D [3] (3)
+ * out: A [27] (3x3x3)
+ * stored elements read + written per point (BW_eff N_e): 36 */
+tl_status tlg_mult2(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune);
+
+/* mult3: A_ijkl = B_i C_j D_k E_l (Sec. 5.1, eq:Mult3)
+ *   A(i,j,k,l) = (((B(i) * C(j)) * D(k)) * E(l))
+ * in:  B [3] (3); C [3] (3); D [3] (3); E [3] (3)
+ * out: A [81] (3x3x3x3)
+ * stored elements read + written per point (BW_eff N_e): 93 */
+tl_status tlg_mult3(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune);
+
 /* contract1: A_ijkl = B_i^m E_mjkl (Sec. 5.1, eq:Contract1)
  *   A(i,j,k,l) = Sum(m, (B(i,m) * E(m,j,k,l)))
  * in:  B [9] (3x3); E [81] (3x3x3x3)
  * out: A [81] (3x3x3x3)
  * stored elements read + written per point (BW_eff N_e): 171 */
 tl_status tlg_contract1(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune);
+
+/* contract2: A_ijkl = C_j^n B_i^m E_mnkl (Sec. 5.1, eq:Contract2)
+ *   A(i,j,k,l) = Sum(m, Sum(n, ((C(j,n) * B(i,m)) * E(m,n,k,l))))
+ * in:  C [9] (3x3); B [9] (3x3); E [81] (3x3x3x3)
+ * out: A [81] (3x3x3x3)
+ * stored elements read + written per point (BW_eff N_e): 180 */
+tl_status tlg_contract2(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune);
+
+/* contract3: A_ijkl = D_k^o C_j^n B_i^m E_mnol (Sec. 5.1, eq:Contract3)
+ *   A(i,j,k,l) = Sum(m, Sum(n, Sum(o, (((D(k,o) * C(j,n)) * B(i,m)) * E(m,n,o,l)))))
+ * in:  D [9] (3x3); C [9] (3x3); B [9] (3x3); E [81] (3x3x3x3)
+ * out: A [81] (3x3x3x3)
+ * stored elements read + written per point (BW_eff N_e): 189 */
+tl_status tlg_contract3(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune);
 
 /* lst_sym_contract: C_(ab) = sum_c A_ac B_cb, symmetric left-hand side (Sec. 4, rank 2 contraction example)
  *   C(a,b) = Sum(c, (A(a,c) * B(c,b)))

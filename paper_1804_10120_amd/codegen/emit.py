@@ -39,6 +39,12 @@ def tensor_text(t) -> str:
     return f"{t.name} [{t.ncomp}] ({dims}{sym})"
 
 
+# Programs with more input components than WIDE_INPUTS keep them all live and
+# run in blocks of at most WIDE_MAX_BLOCK threads, which their registers fit.
+WIDE_INPUTS = 100
+WIDE_MAX_BLOCK = 256
+
+
 class _Emitter:
     def __init__(self, prog: Program):
         prog.check()
@@ -109,9 +115,12 @@ class _Emitter:
         body = self.body()
         fin = ", ".join(str(t.ncomp) for t in self.ins)
         fout = ", ".join(str(t.ncomp) for t in self.outs)
+        nin = sum(t.ncomp for t in self.ins)
+        cap = (f"\n  static constexpr int kMaxBlock = {WIDE_MAX_BLOCK};  // more than "
+               f"{WIDE_INPUTS} inputs live" if nin > WIDE_INPUTS else "")
         return f"""// {p.name}: {p.doc}
 struct Gen_{p.name} {{
-  static constexpr bool kStream = true;
+  static constexpr bool kStream = true;{cap}
   static constexpr int NF_IN = {len(self.ins)}, NF_OUT = {len(self.outs)};
   static constexpr int fin[NF_IN] = {{{fin}}};
   static constexpr int fout[NF_OUT] = {{{fout}}};

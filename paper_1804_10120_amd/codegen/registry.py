@@ -48,11 +48,43 @@ def programs():
     out.append(Program("kij", "K_ij = 2 alpha g_ij + beta_i beta_j (Sec. 5.1, eq:Kij)")
                .let(Kout[i, j], 2.0 * alpha[()] * g[i, j] + beta[i] * beta[j]))
 
-    B = Tensor("B", (3, 3))
-    E = Tensor("E", (3, 3, 3, 3))
+    # the rest of the Sec. 5.1 benchmark family, inputs in the order written
+    n_, o_ = indices("n o")
+    B1, C1, D1, E1 = (Tensor(x, (3,)) for x in "BCDE")
+    A1 = Tensor("A", (3,))
+    A2 = Tensor("A", (3, 3))
+    A3 = Tensor("A", (3, 3, 3))
+    B2, B3 = Tensor("B", (3, 3)), Tensor("B", (3, 3, 3))
+    out.append(Program("assign1", "A_i = B_i (Sec. 5.1, eq:Assign1)").let(A1[i], B1[i]))
+    out.append(Program("assign2", "A_ij = B_ij (Sec. 5.1, eq:Assign2)").let(A2[i, j], B2[i, j]))
+    out.append(Program("assign3", "A_ijk = B_ijk (Sec. 5.1, eq:Assign3)")
+               .let(A3[i, j, k], B3[i, j, k]))
+    out.append(Program("add1", "A_i = B_i + C_i (Sec. 5.1, eq:Add1)")
+               .let(A1[i], B1[i] + C1[i]))
+    out.append(Program("add2", "A_i = B_i + C_i + D_i (Sec. 5.1, eq:Add2)")
+               .let(A1[i], B1[i] + C1[i] + D1[i]))
+    out.append(Program("add3", "A_i = B_i + C_i + D_i + E_i (Sec. 5.1, eq:Add3)")
+               .let(A1[i], B1[i] + C1[i] + D1[i] + E1[i]))
+    out.append(Program("mult1", "A_ij = B_i C_j (Sec. 5.1, eq:Mult1)")
+               .let(A2[i, j], B1[i] * C1[j]))
+    out.append(Program("mult2", "A_ijk = B_i C_j D_k (Sec. 5.1, eq:Mult2)")
+               .let(A3[i, j, k], B1[i] * C1[j] * D1[k]))
     A4 = Tensor("A", (3, 3, 3, 3))
+    out.append(Program("mult3", "A_ijkl = B_i C_j D_k E_l (Sec. 5.1, eq:Mult3)")
+               .let(A4[i, j, k, l], B1[i] * C1[j] * D1[k] * E1[l]))
+
+    B = Tensor("B", (3, 3))
+    C = Tensor("C", (3, 3))
+    Dm = Tensor("D", (3, 3))
+    E = Tensor("E", (3, 3, 3, 3))
     out.append(Program("contract1", "A_ijkl = B_i^m E_mjkl (Sec. 5.1, eq:Contract1)")
                .let(A4[i, j, k, l], Sum(m, B[i, m] * E[m, j, k, l])))
+    out.append(Program("contract2", "A_ijkl = C_j^n B_i^m E_mnkl (Sec. 5.1, eq:Contract2)")
+               .let(A4[i, j, k, l], Sum(m, Sum(n_, C[j, n_] * B[i, m] * E[m, n_, k, l]))))
+    out.append(Program("contract3", "A_ijkl = D_k^o C_j^n B_i^m E_mnol (Sec. 5.1, "
+                                    "eq:Contract3)")
+               .let(A4[i, j, k, l],
+                    Sum(m, Sum(n_, Sum(o_, Dm[k, o_] * C[j, n_] * B[i, m] * E[m, n_, o_, l])))))
 
     # the examples of Sec. 4 (dimension-4 indices a, b, c; fixed and offset indices)
     A = Tensor("A", (4, 4))

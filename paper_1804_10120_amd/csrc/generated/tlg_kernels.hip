@@ -319,6 +319,546 @@ struct Gen_kij {
   }
 };
 
+// assign1: A_i = B_i (Sec. 5.1, eq:Assign1)
+struct Gen_assign1 {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 1, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {3};
+  static constexpr int fout[NF_OUT] = {3};
+  static constexpr int NIN = 3, NOUT = 3;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    // A(i) = B(i)
+    double o0_0 = x0_0;
+    st(0, 0, o0_0);
+    double o0_1 = x0_1;
+    st(0, 1, o0_1);
+    double o0_2 = x0_2;
+    st(0, 2, o0_2);
+  }
+};
+
+// assign2: A_ij = B_ij (Sec. 5.1, eq:Assign2)
+struct Gen_assign2 {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 1, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {9};
+  static constexpr int fout[NF_OUT] = {9};
+  static constexpr int NIN = 9, NOUT = 9;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    const double x0_3 = ld(0, 3);
+    const double x0_4 = ld(0, 4);
+    const double x0_5 = ld(0, 5);
+    const double x0_6 = ld(0, 6);
+    const double x0_7 = ld(0, 7);
+    const double x0_8 = ld(0, 8);
+    // A(i,j) = B(i,j)
+    double o0_0 = x0_0;
+    st(0, 0, o0_0);
+    double o0_1 = x0_1;
+    st(0, 1, o0_1);
+    double o0_2 = x0_2;
+    st(0, 2, o0_2);
+    double o0_3 = x0_3;
+    st(0, 3, o0_3);
+    double o0_4 = x0_4;
+    st(0, 4, o0_4);
+    double o0_5 = x0_5;
+    st(0, 5, o0_5);
+    double o0_6 = x0_6;
+    st(0, 6, o0_6);
+    double o0_7 = x0_7;
+    st(0, 7, o0_7);
+    double o0_8 = x0_8;
+    st(0, 8, o0_8);
+  }
+};
+
+// assign3: A_ijk = B_ijk (Sec. 5.1, eq:Assign3)
+struct Gen_assign3 {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 1, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {27};
+  static constexpr int fout[NF_OUT] = {27};
+  static constexpr int NIN = 27, NOUT = 27;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    const double x0_3 = ld(0, 3);
+    const double x0_4 = ld(0, 4);
+    const double x0_5 = ld(0, 5);
+    const double x0_6 = ld(0, 6);
+    const double x0_7 = ld(0, 7);
+    const double x0_8 = ld(0, 8);
+    const double x0_9 = ld(0, 9);
+    const double x0_10 = ld(0, 10);
+    const double x0_11 = ld(0, 11);
+    const double x0_12 = ld(0, 12);
+    const double x0_13 = ld(0, 13);
+    const double x0_14 = ld(0, 14);
+    const double x0_15 = ld(0, 15);
+    const double x0_16 = ld(0, 16);
+    const double x0_17 = ld(0, 17);
+    const double x0_18 = ld(0, 18);
+    const double x0_19 = ld(0, 19);
+    const double x0_20 = ld(0, 20);
+    const double x0_21 = ld(0, 21);
+    const double x0_22 = ld(0, 22);
+    const double x0_23 = ld(0, 23);
+    const double x0_24 = ld(0, 24);
+    const double x0_25 = ld(0, 25);
+    const double x0_26 = ld(0, 26);
+    // A(i,j,k) = B(i,j,k)
+    double o0_0 = x0_0;
+    st(0, 0, o0_0);
+    double o0_1 = x0_1;
+    st(0, 1, o0_1);
+    double o0_2 = x0_2;
+    st(0, 2, o0_2);
+    double o0_3 = x0_3;
+    st(0, 3, o0_3);
+    double o0_4 = x0_4;
+    st(0, 4, o0_4);
+    double o0_5 = x0_5;
+    st(0, 5, o0_5);
+    double o0_6 = x0_6;
+    st(0, 6, o0_6);
+    double o0_7 = x0_7;
+    st(0, 7, o0_7);
+    double o0_8 = x0_8;
+    st(0, 8, o0_8);
+    double o0_9 = x0_9;
+    st(0, 9, o0_9);
+    double o0_10 = x0_10;
+    st(0, 10, o0_10);
+    double o0_11 = x0_11;
+    st(0, 11, o0_11);
+    double o0_12 = x0_12;
+    st(0, 12, o0_12);
+    double o0_13 = x0_13;
+    st(0, 13, o0_13);
+    double o0_14 = x0_14;
+    st(0, 14, o0_14);
+    double o0_15 = x0_15;
+    st(0, 15, o0_15);
+    double o0_16 = x0_16;
+    st(0, 16, o0_16);
+    double o0_17 = x0_17;
+    st(0, 17, o0_17);
+    double o0_18 = x0_18;
+    st(0, 18, o0_18);
+    double o0_19 = x0_19;
+    st(0, 19, o0_19);
+    double o0_20 = x0_20;
+    st(0, 20, o0_20);
+    double o0_21 = x0_21;
+    st(0, 21, o0_21);
+    double o0_22 = x0_22;
+    st(0, 22, o0_22);
+    double o0_23 = x0_23;
+    st(0, 23, o0_23);
+    double o0_24 = x0_24;
+    st(0, 24, o0_24);
+    double o0_25 = x0_25;
+    st(0, 25, o0_25);
+    double o0_26 = x0_26;
+    st(0, 26, o0_26);
+  }
+};
+
+// add1: A_i = B_i + C_i (Sec. 5.1, eq:Add1)
+struct Gen_add1 {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 2, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {3, 3};
+  static constexpr int fout[NF_OUT] = {3};
+  static constexpr int NIN = 6, NOUT = 3;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    const double x1_0 = ld(1, 0);
+    const double x1_1 = ld(1, 1);
+    const double x1_2 = ld(1, 2);
+    // A(i) = (B(i) + C(i))
+    double o0_0 = (x0_0 + x1_0);
+    st(0, 0, o0_0);
+    double o0_1 = (x0_1 + x1_1);
+    st(0, 1, o0_1);
+    double o0_2 = (x0_2 + x1_2);
+    st(0, 2, o0_2);
+  }
+};
+
+// add2: A_i = B_i + C_i + D_i (Sec. 5.1, eq:Add2)
+struct Gen_add2 {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 3, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {3, 3, 3};
+  static constexpr int fout[NF_OUT] = {3};
+  static constexpr int NIN = 9, NOUT = 3;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    const double x1_0 = ld(1, 0);
+    const double x1_1 = ld(1, 1);
+    const double x1_2 = ld(1, 2);
+    const double x2_0 = ld(2, 0);
+    const double x2_1 = ld(2, 1);
+    const double x2_2 = ld(2, 2);
+    // A(i) = ((B(i) + C(i)) + D(i))
+    double o0_0 = ((x0_0 + x1_0) + x2_0);
+    st(0, 0, o0_0);
+    double o0_1 = ((x0_1 + x1_1) + x2_1);
+    st(0, 1, o0_1);
+    double o0_2 = ((x0_2 + x1_2) + x2_2);
+    st(0, 2, o0_2);
+  }
+};
+
+// add3: A_i = B_i + C_i + D_i + E_i (Sec. 5.1, eq:Add3)
+struct Gen_add3 {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 4, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {3, 3, 3, 3};
+  static constexpr int fout[NF_OUT] = {3};
+  static constexpr int NIN = 12, NOUT = 3;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    const double x1_0 = ld(1, 0);
+    const double x1_1 = ld(1, 1);
+    const double x1_2 = ld(1, 2);
+    const double x2_0 = ld(2, 0);
+    const double x2_1 = ld(2, 1);
+    const double x2_2 = ld(2, 2);
+    const double x3_0 = ld(3, 0);
+    const double x3_1 = ld(3, 1);
+    const double x3_2 = ld(3, 2);
+    // A(i) = (((B(i) + C(i)) + D(i)) + E(i))
+    double o0_0 = (((x0_0 + x1_0) + x2_0) + x3_0);
+    st(0, 0, o0_0);
+    double o0_1 = (((x0_1 + x1_1) + x2_1) + x3_1);
+    st(0, 1, o0_1);
+    double o0_2 = (((x0_2 + x1_2) + x2_2) + x3_2);
+    st(0, 2, o0_2);
+  }
+};
+
+// mult1: A_ij = B_i C_j (Sec. 5.1, eq:Mult1)
+struct Gen_mult1 {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 2, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {3, 3};
+  static constexpr int fout[NF_OUT] = {9};
+  static constexpr int NIN = 6, NOUT = 9;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    const double x1_0 = ld(1, 0);
+    const double x1_1 = ld(1, 1);
+    const double x1_2 = ld(1, 2);
+    // A(i,j) = (B(i) * C(j))
+    double o0_0 = (x0_0 * x1_0);
+    st(0, 0, o0_0);
+    double o0_1 = (x0_0 * x1_1);
+    st(0, 1, o0_1);
+    double o0_2 = (x0_0 * x1_2);
+    st(0, 2, o0_2);
+    double o0_3 = (x0_1 * x1_0);
+    st(0, 3, o0_3);
+    double o0_4 = (x0_1 * x1_1);
+    st(0, 4, o0_4);
+    double o0_5 = (x0_1 * x1_2);
+    st(0, 5, o0_5);
+    double o0_6 = (x0_2 * x1_0);
+    st(0, 6, o0_6);
+    double o0_7 = (x0_2 * x1_1);
+    st(0, 7, o0_7);
+    double o0_8 = (x0_2 * x1_2);
+    st(0, 8, o0_8);
+  }
+};
+
+// mult2: A_ijk = B_i C_j D_k (Sec. 5.1, eq:Mult2)
+struct Gen_mult2 {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 3, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {3, 3, 3};
+  static constexpr int fout[NF_OUT] = {27};
+  static constexpr int NIN = 9, NOUT = 27;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    const double x1_0 = ld(1, 0);
+    const double x1_1 = ld(1, 1);
+    const double x1_2 = ld(1, 2);
+    const double x2_0 = ld(2, 0);
+    const double x2_1 = ld(2, 1);
+    const double x2_2 = ld(2, 2);
+    // A(i,j,k) = ((B(i) * C(j)) * D(k))
+    double o0_0 = ((x0_0 * x1_0) * x2_0);
+    st(0, 0, o0_0);
+    double o0_1 = ((x0_0 * x1_0) * x2_1);
+    st(0, 1, o0_1);
+    double o0_2 = ((x0_0 * x1_0) * x2_2);
+    st(0, 2, o0_2);
+    double o0_3 = ((x0_0 * x1_1) * x2_0);
+    st(0, 3, o0_3);
+    double o0_4 = ((x0_0 * x1_1) * x2_1);
+    st(0, 4, o0_4);
+    double o0_5 = ((x0_0 * x1_1) * x2_2);
+    st(0, 5, o0_5);
+    double o0_6 = ((x0_0 * x1_2) * x2_0);
+    st(0, 6, o0_6);
+    double o0_7 = ((x0_0 * x1_2) * x2_1);
+    st(0, 7, o0_7);
+    double o0_8 = ((x0_0 * x1_2) * x2_2);
+    st(0, 8, o0_8);
+    double o0_9 = ((x0_1 * x1_0) * x2_0);
+    st(0, 9, o0_9);
+    double o0_10 = ((x0_1 * x1_0) * x2_1);
+    st(0, 10, o0_10);
+    double o0_11 = ((x0_1 * x1_0) * x2_2);
+    st(0, 11, o0_11);
+    double o0_12 = ((x0_1 * x1_1) * x2_0);
+    st(0, 12, o0_12);
+    double o0_13 = ((x0_1 * x1_1) * x2_1);
+    st(0, 13, o0_13);
+    double o0_14 = ((x0_1 * x1_1) * x2_2);
+    st(0, 14, o0_14);
+    double o0_15 = ((x0_1 * x1_2) * x2_0);
+    st(0, 15, o0_15);
+    double o0_16 = ((x0_1 * x1_2) * x2_1);
+    st(0, 16, o0_16);
+    double o0_17 = ((x0_1 * x1_2) * x2_2);
+    st(0, 17, o0_17);
+    double o0_18 = ((x0_2 * x1_0) * x2_0);
+    st(0, 18, o0_18);
+    double o0_19 = ((x0_2 * x1_0) * x2_1);
+    st(0, 19, o0_19);
+    double o0_20 = ((x0_2 * x1_0) * x2_2);
+    st(0, 20, o0_20);
+    double o0_21 = ((x0_2 * x1_1) * x2_0);
+    st(0, 21, o0_21);
+    double o0_22 = ((x0_2 * x1_1) * x2_1);
+    st(0, 22, o0_22);
+    double o0_23 = ((x0_2 * x1_1) * x2_2);
+    st(0, 23, o0_23);
+    double o0_24 = ((x0_2 * x1_2) * x2_0);
+    st(0, 24, o0_24);
+    double o0_25 = ((x0_2 * x1_2) * x2_1);
+    st(0, 25, o0_25);
+    double o0_26 = ((x0_2 * x1_2) * x2_2);
+    st(0, 26, o0_26);
+  }
+};
+
+// mult3: A_ijkl = B_i C_j D_k E_l (Sec. 5.1, eq:Mult3)
+struct Gen_mult3 {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 4, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {3, 3, 3, 3};
+  static constexpr int fout[NF_OUT] = {81};
+  static constexpr int NIN = 12, NOUT = 81;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    const double x1_0 = ld(1, 0);
+    const double x1_1 = ld(1, 1);
+    const double x1_2 = ld(1, 2);
+    const double x2_0 = ld(2, 0);
+    const double x2_1 = ld(2, 1);
+    const double x2_2 = ld(2, 2);
+    const double x3_0 = ld(3, 0);
+    const double x3_1 = ld(3, 1);
+    const double x3_2 = ld(3, 2);
+    // A(i,j,k,l) = (((B(i) * C(j)) * D(k)) * E(l))
+    double o0_0 = (((x0_0 * x1_0) * x2_0) * x3_0);
+    st(0, 0, o0_0);
+    double o0_1 = (((x0_0 * x1_0) * x2_0) * x3_1);
+    st(0, 1, o0_1);
+    double o0_2 = (((x0_0 * x1_0) * x2_0) * x3_2);
+    st(0, 2, o0_2);
+    double o0_3 = (((x0_0 * x1_0) * x2_1) * x3_0);
+    st(0, 3, o0_3);
+    double o0_4 = (((x0_0 * x1_0) * x2_1) * x3_1);
+    st(0, 4, o0_4);
+    double o0_5 = (((x0_0 * x1_0) * x2_1) * x3_2);
+    st(0, 5, o0_5);
+    double o0_6 = (((x0_0 * x1_0) * x2_2) * x3_0);
+    st(0, 6, o0_6);
+    double o0_7 = (((x0_0 * x1_0) * x2_2) * x3_1);
+    st(0, 7, o0_7);
+    double o0_8 = (((x0_0 * x1_0) * x2_2) * x3_2);
+    st(0, 8, o0_8);
+    double o0_9 = (((x0_0 * x1_1) * x2_0) * x3_0);
+    st(0, 9, o0_9);
+    double o0_10 = (((x0_0 * x1_1) * x2_0) * x3_1);
+    st(0, 10, o0_10);
+    double o0_11 = (((x0_0 * x1_1) * x2_0) * x3_2);
+    st(0, 11, o0_11);
+    double o0_12 = (((x0_0 * x1_1) * x2_1) * x3_0);
+    st(0, 12, o0_12);
+    double o0_13 = (((x0_0 * x1_1) * x2_1) * x3_1);
+    st(0, 13, o0_13);
+    double o0_14 = (((x0_0 * x1_1) * x2_1) * x3_2);
+    st(0, 14, o0_14);
+    double o0_15 = (((x0_0 * x1_1) * x2_2) * x3_0);
+    st(0, 15, o0_15);
+    double o0_16 = (((x0_0 * x1_1) * x2_2) * x3_1);
+    st(0, 16, o0_16);
+    double o0_17 = (((x0_0 * x1_1) * x2_2) * x3_2);
+    st(0, 17, o0_17);
+    double o0_18 = (((x0_0 * x1_2) * x2_0) * x3_0);
+    st(0, 18, o0_18);
+    double o0_19 = (((x0_0 * x1_2) * x2_0) * x3_1);
+    st(0, 19, o0_19);
+    double o0_20 = (((x0_0 * x1_2) * x2_0) * x3_2);
+    st(0, 20, o0_20);
+    double o0_21 = (((x0_0 * x1_2) * x2_1) * x3_0);
+    st(0, 21, o0_21);
+    double o0_22 = (((x0_0 * x1_2) * x2_1) * x3_1);
+    st(0, 22, o0_22);
+    double o0_23 = (((x0_0 * x1_2) * x2_1) * x3_2);
+    st(0, 23, o0_23);
+    double o0_24 = (((x0_0 * x1_2) * x2_2) * x3_0);
+    st(0, 24, o0_24);
+    double o0_25 = (((x0_0 * x1_2) * x2_2) * x3_1);
+    st(0, 25, o0_25);
+    double o0_26 = (((x0_0 * x1_2) * x2_2) * x3_2);
+    st(0, 26, o0_26);
+    double o0_27 = (((x0_1 * x1_0) * x2_0) * x3_0);
+    st(0, 27, o0_27);
+    double o0_28 = (((x0_1 * x1_0) * x2_0) * x3_1);
+    st(0, 28, o0_28);
+    double o0_29 = (((x0_1 * x1_0) * x2_0) * x3_2);
+    st(0, 29, o0_29);
+    double o0_30 = (((x0_1 * x1_0) * x2_1) * x3_0);
+    st(0, 30, o0_30);
+    double o0_31 = (((x0_1 * x1_0) * x2_1) * x3_1);
+    st(0, 31, o0_31);
+    double o0_32 = (((x0_1 * x1_0) * x2_1) * x3_2);
+    st(0, 32, o0_32);
+    double o0_33 = (((x0_1 * x1_0) * x2_2) * x3_0);
+    st(0, 33, o0_33);
+    double o0_34 = (((x0_1 * x1_0) * x2_2) * x3_1);
+    st(0, 34, o0_34);
+    double o0_35 = (((x0_1 * x1_0) * x2_2) * x3_2);
+    st(0, 35, o0_35);
+    double o0_36 = (((x0_1 * x1_1) * x2_0) * x3_0);
+    st(0, 36, o0_36);
+    double o0_37 = (((x0_1 * x1_1) * x2_0) * x3_1);
+    st(0, 37, o0_37);
+    double o0_38 = (((x0_1 * x1_1) * x2_0) * x3_2);
+    st(0, 38, o0_38);
+    double o0_39 = (((x0_1 * x1_1) * x2_1) * x3_0);
+    st(0, 39, o0_39);
+    double o0_40 = (((x0_1 * x1_1) * x2_1) * x3_1);
+    st(0, 40, o0_40);
+    double o0_41 = (((x0_1 * x1_1) * x2_1) * x3_2);
+    st(0, 41, o0_41);
+    double o0_42 = (((x0_1 * x1_1) * x2_2) * x3_0);
+    st(0, 42, o0_42);
+    double o0_43 = (((x0_1 * x1_1) * x2_2) * x3_1);
+    st(0, 43, o0_43);
+    double o0_44 = (((x0_1 * x1_1) * x2_2) * x3_2);
+    st(0, 44, o0_44);
+    double o0_45 = (((x0_1 * x1_2) * x2_0) * x3_0);
+    st(0, 45, o0_45);
+    double o0_46 = (((x0_1 * x1_2) * x2_0) * x3_1);
+    st(0, 46, o0_46);
+    double o0_47 = (((x0_1 * x1_2) * x2_0) * x3_2);
+    st(0, 47, o0_47);
+    double o0_48 = (((x0_1 * x1_2) * x2_1) * x3_0);
+    st(0, 48, o0_48);
+    double o0_49 = (((x0_1 * x1_2) * x2_1) * x3_1);
+    st(0, 49, o0_49);
+    double o0_50 = (((x0_1 * x1_2) * x2_1) * x3_2);
+    st(0, 50, o0_50);
+    double o0_51 = (((x0_1 * x1_2) * x2_2) * x3_0);
+    st(0, 51, o0_51);
+    double o0_52 = (((x0_1 * x1_2) * x2_2) * x3_1);
+    st(0, 52, o0_52);
+    double o0_53 = (((x0_1 * x1_2) * x2_2) * x3_2);
+    st(0, 53, o0_53);
+    double o0_54 = (((x0_2 * x1_0) * x2_0) * x3_0);
+    st(0, 54, o0_54);
+    double o0_55 = (((x0_2 * x1_0) * x2_0) * x3_1);
+    st(0, 55, o0_55);
+    double o0_56 = (((x0_2 * x1_0) * x2_0) * x3_2);
+    st(0, 56, o0_56);
+    double o0_57 = (((x0_2 * x1_0) * x2_1) * x3_0);
+    st(0, 57, o0_57);
+    double o0_58 = (((x0_2 * x1_0) * x2_1) * x3_1);
+    st(0, 58, o0_58);
+    double o0_59 = (((x0_2 * x1_0) * x2_1) * x3_2);
+    st(0, 59, o0_59);
+    double o0_60 = (((x0_2 * x1_0) * x2_2) * x3_0);
+    st(0, 60, o0_60);
+    double o0_61 = (((x0_2 * x1_0) * x2_2) * x3_1);
+    st(0, 61, o0_61);
+    double o0_62 = (((x0_2 * x1_0) * x2_2) * x3_2);
+    st(0, 62, o0_62);
+    double o0_63 = (((x0_2 * x1_1) * x2_0) * x3_0);
+    st(0, 63, o0_63);
+    double o0_64 = (((x0_2 * x1_1) * x2_0) * x3_1);
+    st(0, 64, o0_64);
+    double o0_65 = (((x0_2 * x1_1) * x2_0) * x3_2);
+    st(0, 65, o0_65);
+    double o0_66 = (((x0_2 * x1_1) * x2_1) * x3_0);
+    st(0, 66, o0_66);
+    double o0_67 = (((x0_2 * x1_1) * x2_1) * x3_1);
+    st(0, 67, o0_67);
+    double o0_68 = (((x0_2 * x1_1) * x2_1) * x3_2);
+    st(0, 68, o0_68);
+    double o0_69 = (((x0_2 * x1_1) * x2_2) * x3_0);
+    st(0, 69, o0_69);
+    double o0_70 = (((x0_2 * x1_1) * x2_2) * x3_1);
+    st(0, 70, o0_70);
+    double o0_71 = (((x0_2 * x1_1) * x2_2) * x3_2);
+    st(0, 71, o0_71);
+    double o0_72 = (((x0_2 * x1_2) * x2_0) * x3_0);
+    st(0, 72, o0_72);
+    double o0_73 = (((x0_2 * x1_2) * x2_0) * x3_1);
+    st(0, 73, o0_73);
+    double o0_74 = (((x0_2 * x1_2) * x2_0) * x3_2);
+    st(0, 74, o0_74);
+    double o0_75 = (((x0_2 * x1_2) * x2_1) * x3_0);
+    st(0, 75, o0_75);
+    double o0_76 = (((x0_2 * x1_2) * x2_1) * x3_1);
+    st(0, 76, o0_76);
+    double o0_77 = (((x0_2 * x1_2) * x2_1) * x3_2);
+    st(0, 77, o0_77);
+    double o0_78 = (((x0_2 * x1_2) * x2_2) * x3_0);
+    st(0, 78, o0_78);
+    double o0_79 = (((x0_2 * x1_2) * x2_2) * x3_1);
+    st(0, 79, o0_79);
+    double o0_80 = (((x0_2 * x1_2) * x2_2) * x3_2);
+    st(0, 80, o0_80);
+  }
+};
+
 // contract1: A_ijkl = B_i^m E_mjkl (Sec. 5.1, eq:Contract1)
 struct Gen_contract1 {
   static constexpr bool kStream = true;
@@ -584,6 +1124,564 @@ struct Gen_contract1 {
   }
 };
 
+// contract2: A_ijkl = C_j^n B_i^m E_mnkl (Sec. 5.1, eq:Contract2)
+struct Gen_contract2 {
+  static constexpr bool kStream = true;
+  static constexpr int NF_IN = 3, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {9, 9, 81};
+  static constexpr int fout[NF_OUT] = {81};
+  static constexpr int NIN = 99, NOUT = 81;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    const double x0_3 = ld(0, 3);
+    const double x0_4 = ld(0, 4);
+    const double x0_5 = ld(0, 5);
+    const double x0_6 = ld(0, 6);
+    const double x0_7 = ld(0, 7);
+    const double x0_8 = ld(0, 8);
+    const double x1_0 = ld(1, 0);
+    const double x1_1 = ld(1, 1);
+    const double x1_2 = ld(1, 2);
+    const double x1_3 = ld(1, 3);
+    const double x1_4 = ld(1, 4);
+    const double x1_5 = ld(1, 5);
+    const double x1_6 = ld(1, 6);
+    const double x1_7 = ld(1, 7);
+    const double x1_8 = ld(1, 8);
+    const double x2_0 = ld(2, 0);
+    const double x2_1 = ld(2, 1);
+    const double x2_2 = ld(2, 2);
+    const double x2_3 = ld(2, 3);
+    const double x2_4 = ld(2, 4);
+    const double x2_5 = ld(2, 5);
+    const double x2_6 = ld(2, 6);
+    const double x2_7 = ld(2, 7);
+    const double x2_8 = ld(2, 8);
+    const double x2_9 = ld(2, 9);
+    const double x2_10 = ld(2, 10);
+    const double x2_11 = ld(2, 11);
+    const double x2_12 = ld(2, 12);
+    const double x2_13 = ld(2, 13);
+    const double x2_14 = ld(2, 14);
+    const double x2_15 = ld(2, 15);
+    const double x2_16 = ld(2, 16);
+    const double x2_17 = ld(2, 17);
+    const double x2_18 = ld(2, 18);
+    const double x2_19 = ld(2, 19);
+    const double x2_20 = ld(2, 20);
+    const double x2_21 = ld(2, 21);
+    const double x2_22 = ld(2, 22);
+    const double x2_23 = ld(2, 23);
+    const double x2_24 = ld(2, 24);
+    const double x2_25 = ld(2, 25);
+    const double x2_26 = ld(2, 26);
+    const double x2_27 = ld(2, 27);
+    const double x2_28 = ld(2, 28);
+    const double x2_29 = ld(2, 29);
+    const double x2_30 = ld(2, 30);
+    const double x2_31 = ld(2, 31);
+    const double x2_32 = ld(2, 32);
+    const double x2_33 = ld(2, 33);
+    const double x2_34 = ld(2, 34);
+    const double x2_35 = ld(2, 35);
+    const double x2_36 = ld(2, 36);
+    const double x2_37 = ld(2, 37);
+    const double x2_38 = ld(2, 38);
+    const double x2_39 = ld(2, 39);
+    const double x2_40 = ld(2, 40);
+    const double x2_41 = ld(2, 41);
+    const double x2_42 = ld(2, 42);
+    const double x2_43 = ld(2, 43);
+    const double x2_44 = ld(2, 44);
+    const double x2_45 = ld(2, 45);
+    const double x2_46 = ld(2, 46);
+    const double x2_47 = ld(2, 47);
+    const double x2_48 = ld(2, 48);
+    const double x2_49 = ld(2, 49);
+    const double x2_50 = ld(2, 50);
+    const double x2_51 = ld(2, 51);
+    const double x2_52 = ld(2, 52);
+    const double x2_53 = ld(2, 53);
+    const double x2_54 = ld(2, 54);
+    const double x2_55 = ld(2, 55);
+    const double x2_56 = ld(2, 56);
+    const double x2_57 = ld(2, 57);
+    const double x2_58 = ld(2, 58);
+    const double x2_59 = ld(2, 59);
+    const double x2_60 = ld(2, 60);
+    const double x2_61 = ld(2, 61);
+    const double x2_62 = ld(2, 62);
+    const double x2_63 = ld(2, 63);
+    const double x2_64 = ld(2, 64);
+    const double x2_65 = ld(2, 65);
+    const double x2_66 = ld(2, 66);
+    const double x2_67 = ld(2, 67);
+    const double x2_68 = ld(2, 68);
+    const double x2_69 = ld(2, 69);
+    const double x2_70 = ld(2, 70);
+    const double x2_71 = ld(2, 71);
+    const double x2_72 = ld(2, 72);
+    const double x2_73 = ld(2, 73);
+    const double x2_74 = ld(2, 74);
+    const double x2_75 = ld(2, 75);
+    const double x2_76 = ld(2, 76);
+    const double x2_77 = ld(2, 77);
+    const double x2_78 = ld(2, 78);
+    const double x2_79 = ld(2, 79);
+    const double x2_80 = ld(2, 80);
+    // A(i,j,k,l) = Sum(m, Sum(n, ((C(j,n) * B(i,m)) * E(m,n,k,l))))
+    double o0_0 = ((((x0_0 * x1_0) * x2_0) + ((x0_1 * x1_0) * x2_9) + ((x0_2 * x1_0) * x2_18)) + (((x0_0 * x1_1) * x2_27) + ((x0_1 * x1_1) * x2_36) + ((x0_2 * x1_1) * x2_45)) + (((x0_0 * x1_2) * x2_54) + ((x0_1 * x1_2) * x2_63) + ((x0_2 * x1_2) * x2_72)));
+    st(0, 0, o0_0);
+    double o0_1 = ((((x0_0 * x1_0) * x2_1) + ((x0_1 * x1_0) * x2_10) + ((x0_2 * x1_0) * x2_19)) + (((x0_0 * x1_1) * x2_28) + ((x0_1 * x1_1) * x2_37) + ((x0_2 * x1_1) * x2_46)) + (((x0_0 * x1_2) * x2_55) + ((x0_1 * x1_2) * x2_64) + ((x0_2 * x1_2) * x2_73)));
+    st(0, 1, o0_1);
+    double o0_2 = ((((x0_0 * x1_0) * x2_2) + ((x0_1 * x1_0) * x2_11) + ((x0_2 * x1_0) * x2_20)) + (((x0_0 * x1_1) * x2_29) + ((x0_1 * x1_1) * x2_38) + ((x0_2 * x1_1) * x2_47)) + (((x0_0 * x1_2) * x2_56) + ((x0_1 * x1_2) * x2_65) + ((x0_2 * x1_2) * x2_74)));
+    st(0, 2, o0_2);
+    double o0_3 = ((((x0_0 * x1_0) * x2_3) + ((x0_1 * x1_0) * x2_12) + ((x0_2 * x1_0) * x2_21)) + (((x0_0 * x1_1) * x2_30) + ((x0_1 * x1_1) * x2_39) + ((x0_2 * x1_1) * x2_48)) + (((x0_0 * x1_2) * x2_57) + ((x0_1 * x1_2) * x2_66) + ((x0_2 * x1_2) * x2_75)));
+    st(0, 3, o0_3);
+    double o0_4 = ((((x0_0 * x1_0) * x2_4) + ((x0_1 * x1_0) * x2_13) + ((x0_2 * x1_0) * x2_22)) + (((x0_0 * x1_1) * x2_31) + ((x0_1 * x1_1) * x2_40) + ((x0_2 * x1_1) * x2_49)) + (((x0_0 * x1_2) * x2_58) + ((x0_1 * x1_2) * x2_67) + ((x0_2 * x1_2) * x2_76)));
+    st(0, 4, o0_4);
+    double o0_5 = ((((x0_0 * x1_0) * x2_5) + ((x0_1 * x1_0) * x2_14) + ((x0_2 * x1_0) * x2_23)) + (((x0_0 * x1_1) * x2_32) + ((x0_1 * x1_1) * x2_41) + ((x0_2 * x1_1) * x2_50)) + (((x0_0 * x1_2) * x2_59) + ((x0_1 * x1_2) * x2_68) + ((x0_2 * x1_2) * x2_77)));
+    st(0, 5, o0_5);
+    double o0_6 = ((((x0_0 * x1_0) * x2_6) + ((x0_1 * x1_0) * x2_15) + ((x0_2 * x1_0) * x2_24)) + (((x0_0 * x1_1) * x2_33) + ((x0_1 * x1_1) * x2_42) + ((x0_2 * x1_1) * x2_51)) + (((x0_0 * x1_2) * x2_60) + ((x0_1 * x1_2) * x2_69) + ((x0_2 * x1_2) * x2_78)));
+    st(0, 6, o0_6);
+    double o0_7 = ((((x0_0 * x1_0) * x2_7) + ((x0_1 * x1_0) * x2_16) + ((x0_2 * x1_0) * x2_25)) + (((x0_0 * x1_1) * x2_34) + ((x0_1 * x1_1) * x2_43) + ((x0_2 * x1_1) * x2_52)) + (((x0_0 * x1_2) * x2_61) + ((x0_1 * x1_2) * x2_70) + ((x0_2 * x1_2) * x2_79)));
+    st(0, 7, o0_7);
+    double o0_8 = ((((x0_0 * x1_0) * x2_8) + ((x0_1 * x1_0) * x2_17) + ((x0_2 * x1_0) * x2_26)) + (((x0_0 * x1_1) * x2_35) + ((x0_1 * x1_1) * x2_44) + ((x0_2 * x1_1) * x2_53)) + (((x0_0 * x1_2) * x2_62) + ((x0_1 * x1_2) * x2_71) + ((x0_2 * x1_2) * x2_80)));
+    st(0, 8, o0_8);
+    double o0_9 = ((((x0_3 * x1_0) * x2_0) + ((x0_4 * x1_0) * x2_9) + ((x0_5 * x1_0) * x2_18)) + (((x0_3 * x1_1) * x2_27) + ((x0_4 * x1_1) * x2_36) + ((x0_5 * x1_1) * x2_45)) + (((x0_3 * x1_2) * x2_54) + ((x0_4 * x1_2) * x2_63) + ((x0_5 * x1_2) * x2_72)));
+    st(0, 9, o0_9);
+    double o0_10 = ((((x0_3 * x1_0) * x2_1) + ((x0_4 * x1_0) * x2_10) + ((x0_5 * x1_0) * x2_19)) + (((x0_3 * x1_1) * x2_28) + ((x0_4 * x1_1) * x2_37) + ((x0_5 * x1_1) * x2_46)) + (((x0_3 * x1_2) * x2_55) + ((x0_4 * x1_2) * x2_64) + ((x0_5 * x1_2) * x2_73)));
+    st(0, 10, o0_10);
+    double o0_11 = ((((x0_3 * x1_0) * x2_2) + ((x0_4 * x1_0) * x2_11) + ((x0_5 * x1_0) * x2_20)) + (((x0_3 * x1_1) * x2_29) + ((x0_4 * x1_1) * x2_38) + ((x0_5 * x1_1) * x2_47)) + (((x0_3 * x1_2) * x2_56) + ((x0_4 * x1_2) * x2_65) + ((x0_5 * x1_2) * x2_74)));
+    st(0, 11, o0_11);
+    double o0_12 = ((((x0_3 * x1_0) * x2_3) + ((x0_4 * x1_0) * x2_12) + ((x0_5 * x1_0) * x2_21)) + (((x0_3 * x1_1) * x2_30) + ((x0_4 * x1_1) * x2_39) + ((x0_5 * x1_1) * x2_48)) + (((x0_3 * x1_2) * x2_57) + ((x0_4 * x1_2) * x2_66) + ((x0_5 * x1_2) * x2_75)));
+    st(0, 12, o0_12);
+    double o0_13 = ((((x0_3 * x1_0) * x2_4) + ((x0_4 * x1_0) * x2_13) + ((x0_5 * x1_0) * x2_22)) + (((x0_3 * x1_1) * x2_31) + ((x0_4 * x1_1) * x2_40) + ((x0_5 * x1_1) * x2_49)) + (((x0_3 * x1_2) * x2_58) + ((x0_4 * x1_2) * x2_67) + ((x0_5 * x1_2) * x2_76)));
+    st(0, 13, o0_13);
+    double o0_14 = ((((x0_3 * x1_0) * x2_5) + ((x0_4 * x1_0) * x2_14) + ((x0_5 * x1_0) * x2_23)) + (((x0_3 * x1_1) * x2_32) + ((x0_4 * x1_1) * x2_41) + ((x0_5 * x1_1) * x2_50)) + (((x0_3 * x1_2) * x2_59) + ((x0_4 * x1_2) * x2_68) + ((x0_5 * x1_2) * x2_77)));
+    st(0, 14, o0_14);
+    double o0_15 = ((((x0_3 * x1_0) * x2_6) + ((x0_4 * x1_0) * x2_15) + ((x0_5 * x1_0) * x2_24)) + (((x0_3 * x1_1) * x2_33) + ((x0_4 * x1_1) * x2_42) + ((x0_5 * x1_1) * x2_51)) + (((x0_3 * x1_2) * x2_60) + ((x0_4 * x1_2) * x2_69) + ((x0_5 * x1_2) * x2_78)));
+    st(0, 15, o0_15);
+    double o0_16 = ((((x0_3 * x1_0) * x2_7) + ((x0_4 * x1_0) * x2_16) + ((x0_5 * x1_0) * x2_25)) + (((x0_3 * x1_1) * x2_34) + ((x0_4 * x1_1) * x2_43) + ((x0_5 * x1_1) * x2_52)) + (((x0_3 * x1_2) * x2_61) + ((x0_4 * x1_2) * x2_70) + ((x0_5 * x1_2) * x2_79)));
+    st(0, 16, o0_16);
+    double o0_17 = ((((x0_3 * x1_0) * x2_8) + ((x0_4 * x1_0) * x2_17) + ((x0_5 * x1_0) * x2_26)) + (((x0_3 * x1_1) * x2_35) + ((x0_4 * x1_1) * x2_44) + ((x0_5 * x1_1) * x2_53)) + (((x0_3 * x1_2) * x2_62) + ((x0_4 * x1_2) * x2_71) + ((x0_5 * x1_2) * x2_80)));
+    st(0, 17, o0_17);
+    double o0_18 = ((((x0_6 * x1_0) * x2_0) + ((x0_7 * x1_0) * x2_9) + ((x0_8 * x1_0) * x2_18)) + (((x0_6 * x1_1) * x2_27) + ((x0_7 * x1_1) * x2_36) + ((x0_8 * x1_1) * x2_45)) + (((x0_6 * x1_2) * x2_54) + ((x0_7 * x1_2) * x2_63) + ((x0_8 * x1_2) * x2_72)));
+    st(0, 18, o0_18);
+    double o0_19 = ((((x0_6 * x1_0) * x2_1) + ((x0_7 * x1_0) * x2_10) + ((x0_8 * x1_0) * x2_19)) + (((x0_6 * x1_1) * x2_28) + ((x0_7 * x1_1) * x2_37) + ((x0_8 * x1_1) * x2_46)) + (((x0_6 * x1_2) * x2_55) + ((x0_7 * x1_2) * x2_64) + ((x0_8 * x1_2) * x2_73)));
+    st(0, 19, o0_19);
+    double o0_20 = ((((x0_6 * x1_0) * x2_2) + ((x0_7 * x1_0) * x2_11) + ((x0_8 * x1_0) * x2_20)) + (((x0_6 * x1_1) * x2_29) + ((x0_7 * x1_1) * x2_38) + ((x0_8 * x1_1) * x2_47)) + (((x0_6 * x1_2) * x2_56) + ((x0_7 * x1_2) * x2_65) + ((x0_8 * x1_2) * x2_74)));
+    st(0, 20, o0_20);
+    double o0_21 = ((((x0_6 * x1_0) * x2_3) + ((x0_7 * x1_0) * x2_12) + ((x0_8 * x1_0) * x2_21)) + (((x0_6 * x1_1) * x2_30) + ((x0_7 * x1_1) * x2_39) + ((x0_8 * x1_1) * x2_48)) + (((x0_6 * x1_2) * x2_57) + ((x0_7 * x1_2) * x2_66) + ((x0_8 * x1_2) * x2_75)));
+    st(0, 21, o0_21);
+    double o0_22 = ((((x0_6 * x1_0) * x2_4) + ((x0_7 * x1_0) * x2_13) + ((x0_8 * x1_0) * x2_22)) + (((x0_6 * x1_1) * x2_31) + ((x0_7 * x1_1) * x2_40) + ((x0_8 * x1_1) * x2_49)) + (((x0_6 * x1_2) * x2_58) + ((x0_7 * x1_2) * x2_67) + ((x0_8 * x1_2) * x2_76)));
+    st(0, 22, o0_22);
+    double o0_23 = ((((x0_6 * x1_0) * x2_5) + ((x0_7 * x1_0) * x2_14) + ((x0_8 * x1_0) * x2_23)) + (((x0_6 * x1_1) * x2_32) + ((x0_7 * x1_1) * x2_41) + ((x0_8 * x1_1) * x2_50)) + (((x0_6 * x1_2) * x2_59) + ((x0_7 * x1_2) * x2_68) + ((x0_8 * x1_2) * x2_77)));
+    st(0, 23, o0_23);
+    double o0_24 = ((((x0_6 * x1_0) * x2_6) + ((x0_7 * x1_0) * x2_15) + ((x0_8 * x1_0) * x2_24)) + (((x0_6 * x1_1) * x2_33) + ((x0_7 * x1_1) * x2_42) + ((x0_8 * x1_1) * x2_51)) + (((x0_6 * x1_2) * x2_60) + ((x0_7 * x1_2) * x2_69) + ((x0_8 * x1_2) * x2_78)));
+    st(0, 24, o0_24);
+    double o0_25 = ((((x0_6 * x1_0) * x2_7) + ((x0_7 * x1_0) * x2_16) + ((x0_8 * x1_0) * x2_25)) + (((x0_6 * x1_1) * x2_34) + ((x0_7 * x1_1) * x2_43) + ((x0_8 * x1_1) * x2_52)) + (((x0_6 * x1_2) * x2_61) + ((x0_7 * x1_2) * x2_70) + ((x0_8 * x1_2) * x2_79)));
+    st(0, 25, o0_25);
+    double o0_26 = ((((x0_6 * x1_0) * x2_8) + ((x0_7 * x1_0) * x2_17) + ((x0_8 * x1_0) * x2_26)) + (((x0_6 * x1_1) * x2_35) + ((x0_7 * x1_1) * x2_44) + ((x0_8 * x1_1) * x2_53)) + (((x0_6 * x1_2) * x2_62) + ((x0_7 * x1_2) * x2_71) + ((x0_8 * x1_2) * x2_80)));
+    st(0, 26, o0_26);
+    double o0_27 = ((((x0_0 * x1_3) * x2_0) + ((x0_1 * x1_3) * x2_9) + ((x0_2 * x1_3) * x2_18)) + (((x0_0 * x1_4) * x2_27) + ((x0_1 * x1_4) * x2_36) + ((x0_2 * x1_4) * x2_45)) + (((x0_0 * x1_5) * x2_54) + ((x0_1 * x1_5) * x2_63) + ((x0_2 * x1_5) * x2_72)));
+    st(0, 27, o0_27);
+    double o0_28 = ((((x0_0 * x1_3) * x2_1) + ((x0_1 * x1_3) * x2_10) + ((x0_2 * x1_3) * x2_19)) + (((x0_0 * x1_4) * x2_28) + ((x0_1 * x1_4) * x2_37) + ((x0_2 * x1_4) * x2_46)) + (((x0_0 * x1_5) * x2_55) + ((x0_1 * x1_5) * x2_64) + ((x0_2 * x1_5) * x2_73)));
+    st(0, 28, o0_28);
+    double o0_29 = ((((x0_0 * x1_3) * x2_2) + ((x0_1 * x1_3) * x2_11) + ((x0_2 * x1_3) * x2_20)) + (((x0_0 * x1_4) * x2_29) + ((x0_1 * x1_4) * x2_38) + ((x0_2 * x1_4) * x2_47)) + (((x0_0 * x1_5) * x2_56) + ((x0_1 * x1_5) * x2_65) + ((x0_2 * x1_5) * x2_74)));
+    st(0, 29, o0_29);
+    double o0_30 = ((((x0_0 * x1_3) * x2_3) + ((x0_1 * x1_3) * x2_12) + ((x0_2 * x1_3) * x2_21)) + (((x0_0 * x1_4) * x2_30) + ((x0_1 * x1_4) * x2_39) + ((x0_2 * x1_4) * x2_48)) + (((x0_0 * x1_5) * x2_57) + ((x0_1 * x1_5) * x2_66) + ((x0_2 * x1_5) * x2_75)));
+    st(0, 30, o0_30);
+    double o0_31 = ((((x0_0 * x1_3) * x2_4) + ((x0_1 * x1_3) * x2_13) + ((x0_2 * x1_3) * x2_22)) + (((x0_0 * x1_4) * x2_31) + ((x0_1 * x1_4) * x2_40) + ((x0_2 * x1_4) * x2_49)) + (((x0_0 * x1_5) * x2_58) + ((x0_1 * x1_5) * x2_67) + ((x0_2 * x1_5) * x2_76)));
+    st(0, 31, o0_31);
+    double o0_32 = ((((x0_0 * x1_3) * x2_5) + ((x0_1 * x1_3) * x2_14) + ((x0_2 * x1_3) * x2_23)) + (((x0_0 * x1_4) * x2_32) + ((x0_1 * x1_4) * x2_41) + ((x0_2 * x1_4) * x2_50)) + (((x0_0 * x1_5) * x2_59) + ((x0_1 * x1_5) * x2_68) + ((x0_2 * x1_5) * x2_77)));
+    st(0, 32, o0_32);
+    double o0_33 = ((((x0_0 * x1_3) * x2_6) + ((x0_1 * x1_3) * x2_15) + ((x0_2 * x1_3) * x2_24)) + (((x0_0 * x1_4) * x2_33) + ((x0_1 * x1_4) * x2_42) + ((x0_2 * x1_4) * x2_51)) + (((x0_0 * x1_5) * x2_60) + ((x0_1 * x1_5) * x2_69) + ((x0_2 * x1_5) * x2_78)));
+    st(0, 33, o0_33);
+    double o0_34 = ((((x0_0 * x1_3) * x2_7) + ((x0_1 * x1_3) * x2_16) + ((x0_2 * x1_3) * x2_25)) + (((x0_0 * x1_4) * x2_34) + ((x0_1 * x1_4) * x2_43) + ((x0_2 * x1_4) * x2_52)) + (((x0_0 * x1_5) * x2_61) + ((x0_1 * x1_5) * x2_70) + ((x0_2 * x1_5) * x2_79)));
+    st(0, 34, o0_34);
+    double o0_35 = ((((x0_0 * x1_3) * x2_8) + ((x0_1 * x1_3) * x2_17) + ((x0_2 * x1_3) * x2_26)) + (((x0_0 * x1_4) * x2_35) + ((x0_1 * x1_4) * x2_44) + ((x0_2 * x1_4) * x2_53)) + (((x0_0 * x1_5) * x2_62) + ((x0_1 * x1_5) * x2_71) + ((x0_2 * x1_5) * x2_80)));
+    st(0, 35, o0_35);
+    double o0_36 = ((((x0_3 * x1_3) * x2_0) + ((x0_4 * x1_3) * x2_9) + ((x0_5 * x1_3) * x2_18)) + (((x0_3 * x1_4) * x2_27) + ((x0_4 * x1_4) * x2_36) + ((x0_5 * x1_4) * x2_45)) + (((x0_3 * x1_5) * x2_54) + ((x0_4 * x1_5) * x2_63) + ((x0_5 * x1_5) * x2_72)));
+    st(0, 36, o0_36);
+    double o0_37 = ((((x0_3 * x1_3) * x2_1) + ((x0_4 * x1_3) * x2_10) + ((x0_5 * x1_3) * x2_19)) + (((x0_3 * x1_4) * x2_28) + ((x0_4 * x1_4) * x2_37) + ((x0_5 * x1_4) * x2_46)) + (((x0_3 * x1_5) * x2_55) + ((x0_4 * x1_5) * x2_64) + ((x0_5 * x1_5) * x2_73)));
+    st(0, 37, o0_37);
+    double o0_38 = ((((x0_3 * x1_3) * x2_2) + ((x0_4 * x1_3) * x2_11) + ((x0_5 * x1_3) * x2_20)) + (((x0_3 * x1_4) * x2_29) + ((x0_4 * x1_4) * x2_38) + ((x0_5 * x1_4) * x2_47)) + (((x0_3 * x1_5) * x2_56) + ((x0_4 * x1_5) * x2_65) + ((x0_5 * x1_5) * x2_74)));
+    st(0, 38, o0_38);
+    double o0_39 = ((((x0_3 * x1_3) * x2_3) + ((x0_4 * x1_3) * x2_12) + ((x0_5 * x1_3) * x2_21)) + (((x0_3 * x1_4) * x2_30) + ((x0_4 * x1_4) * x2_39) + ((x0_5 * x1_4) * x2_48)) + (((x0_3 * x1_5) * x2_57) + ((x0_4 * x1_5) * x2_66) + ((x0_5 * x1_5) * x2_75)));
+    st(0, 39, o0_39);
+    double o0_40 = ((((x0_3 * x1_3) * x2_4) + ((x0_4 * x1_3) * x2_13) + ((x0_5 * x1_3) * x2_22)) + (((x0_3 * x1_4) * x2_31) + ((x0_4 * x1_4) * x2_40) + ((x0_5 * x1_4) * x2_49)) + (((x0_3 * x1_5) * x2_58) + ((x0_4 * x1_5) * x2_67) + ((x0_5 * x1_5) * x2_76)));
+    st(0, 40, o0_40);
+    double o0_41 = ((((x0_3 * x1_3) * x2_5) + ((x0_4 * x1_3) * x2_14) + ((x0_5 * x1_3) * x2_23)) + (((x0_3 * x1_4) * x2_32) + ((x0_4 * x1_4) * x2_41) + ((x0_5 * x1_4) * x2_50)) + (((x0_3 * x1_5) * x2_59) + ((x0_4 * x1_5) * x2_68) + ((x0_5 * x1_5) * x2_77)));
+    st(0, 41, o0_41);
+    double o0_42 = ((((x0_3 * x1_3) * x2_6) + ((x0_4 * x1_3) * x2_15) + ((x0_5 * x1_3) * x2_24)) + (((x0_3 * x1_4) * x2_33) + ((x0_4 * x1_4) * x2_42) + ((x0_5 * x1_4) * x2_51)) + (((x0_3 * x1_5) * x2_60) + ((x0_4 * x1_5) * x2_69) + ((x0_5 * x1_5) * x2_78)));
+    st(0, 42, o0_42);
+    double o0_43 = ((((x0_3 * x1_3) * x2_7) + ((x0_4 * x1_3) * x2_16) + ((x0_5 * x1_3) * x2_25)) + (((x0_3 * x1_4) * x2_34) + ((x0_4 * x1_4) * x2_43) + ((x0_5 * x1_4) * x2_52)) + (((x0_3 * x1_5) * x2_61) + ((x0_4 * x1_5) * x2_70) + ((x0_5 * x1_5) * x2_79)));
+    st(0, 43, o0_43);
+    double o0_44 = ((((x0_3 * x1_3) * x2_8) + ((x0_4 * x1_3) * x2_17) + ((x0_5 * x1_3) * x2_26)) + (((x0_3 * x1_4) * x2_35) + ((x0_4 * x1_4) * x2_44) + ((x0_5 * x1_4) * x2_53)) + (((x0_3 * x1_5) * x2_62) + ((x0_4 * x1_5) * x2_71) + ((x0_5 * x1_5) * x2_80)));
+    st(0, 44, o0_44);
+    double o0_45 = ((((x0_6 * x1_3) * x2_0) + ((x0_7 * x1_3) * x2_9) + ((x0_8 * x1_3) * x2_18)) + (((x0_6 * x1_4) * x2_27) + ((x0_7 * x1_4) * x2_36) + ((x0_8 * x1_4) * x2_45)) + (((x0_6 * x1_5) * x2_54) + ((x0_7 * x1_5) * x2_63) + ((x0_8 * x1_5) * x2_72)));
+    st(0, 45, o0_45);
+    double o0_46 = ((((x0_6 * x1_3) * x2_1) + ((x0_7 * x1_3) * x2_10) + ((x0_8 * x1_3) * x2_19)) + (((x0_6 * x1_4) * x2_28) + ((x0_7 * x1_4) * x2_37) + ((x0_8 * x1_4) * x2_46)) + (((x0_6 * x1_5) * x2_55) + ((x0_7 * x1_5) * x2_64) + ((x0_8 * x1_5) * x2_73)));
+    st(0, 46, o0_46);
+    double o0_47 = ((((x0_6 * x1_3) * x2_2) + ((x0_7 * x1_3) * x2_11) + ((x0_8 * x1_3) * x2_20)) + (((x0_6 * x1_4) * x2_29) + ((x0_7 * x1_4) * x2_38) + ((x0_8 * x1_4) * x2_47)) + (((x0_6 * x1_5) * x2_56) + ((x0_7 * x1_5) * x2_65) + ((x0_8 * x1_5) * x2_74)));
+    st(0, 47, o0_47);
+    double o0_48 = ((((x0_6 * x1_3) * x2_3) + ((x0_7 * x1_3) * x2_12) + ((x0_8 * x1_3) * x2_21)) + (((x0_6 * x1_4) * x2_30) + ((x0_7 * x1_4) * x2_39) + ((x0_8 * x1_4) * x2_48)) + (((x0_6 * x1_5) * x2_57) + ((x0_7 * x1_5) * x2_66) + ((x0_8 * x1_5) * x2_75)));
+    st(0, 48, o0_48);
+    double o0_49 = ((((x0_6 * x1_3) * x2_4) + ((x0_7 * x1_3) * x2_13) + ((x0_8 * x1_3) * x2_22)) + (((x0_6 * x1_4) * x2_31) + ((x0_7 * x1_4) * x2_40) + ((x0_8 * x1_4) * x2_49)) + (((x0_6 * x1_5) * x2_58) + ((x0_7 * x1_5) * x2_67) + ((x0_8 * x1_5) * x2_76)));
+    st(0, 49, o0_49);
+    double o0_50 = ((((x0_6 * x1_3) * x2_5) + ((x0_7 * x1_3) * x2_14) + ((x0_8 * x1_3) * x2_23)) + (((x0_6 * x1_4) * x2_32) + ((x0_7 * x1_4) * x2_41) + ((x0_8 * x1_4) * x2_50)) + (((x0_6 * x1_5) * x2_59) + ((x0_7 * x1_5) * x2_68) + ((x0_8 * x1_5) * x2_77)));
+    st(0, 50, o0_50);
+    double o0_51 = ((((x0_6 * x1_3) * x2_6) + ((x0_7 * x1_3) * x2_15) + ((x0_8 * x1_3) * x2_24)) + (((x0_6 * x1_4) * x2_33) + ((x0_7 * x1_4) * x2_42) + ((x0_8 * x1_4) * x2_51)) + (((x0_6 * x1_5) * x2_60) + ((x0_7 * x1_5) * x2_69) + ((x0_8 * x1_5) * x2_78)));
+    st(0, 51, o0_51);
+    double o0_52 = ((((x0_6 * x1_3) * x2_7) + ((x0_7 * x1_3) * x2_16) + ((x0_8 * x1_3) * x2_25)) + (((x0_6 * x1_4) * x2_34) + ((x0_7 * x1_4) * x2_43) + ((x0_8 * x1_4) * x2_52)) + (((x0_6 * x1_5) * x2_61) + ((x0_7 * x1_5) * x2_70) + ((x0_8 * x1_5) * x2_79)));
+    st(0, 52, o0_52);
+    double o0_53 = ((((x0_6 * x1_3) * x2_8) + ((x0_7 * x1_3) * x2_17) + ((x0_8 * x1_3) * x2_26)) + (((x0_6 * x1_4) * x2_35) + ((x0_7 * x1_4) * x2_44) + ((x0_8 * x1_4) * x2_53)) + (((x0_6 * x1_5) * x2_62) + ((x0_7 * x1_5) * x2_71) + ((x0_8 * x1_5) * x2_80)));
+    st(0, 53, o0_53);
+    double o0_54 = ((((x0_0 * x1_6) * x2_0) + ((x0_1 * x1_6) * x2_9) + ((x0_2 * x1_6) * x2_18)) + (((x0_0 * x1_7) * x2_27) + ((x0_1 * x1_7) * x2_36) + ((x0_2 * x1_7) * x2_45)) + (((x0_0 * x1_8) * x2_54) + ((x0_1 * x1_8) * x2_63) + ((x0_2 * x1_8) * x2_72)));
+    st(0, 54, o0_54);
+    double o0_55 = ((((x0_0 * x1_6) * x2_1) + ((x0_1 * x1_6) * x2_10) + ((x0_2 * x1_6) * x2_19)) + (((x0_0 * x1_7) * x2_28) + ((x0_1 * x1_7) * x2_37) + ((x0_2 * x1_7) * x2_46)) + (((x0_0 * x1_8) * x2_55) + ((x0_1 * x1_8) * x2_64) + ((x0_2 * x1_8) * x2_73)));
+    st(0, 55, o0_55);
+    double o0_56 = ((((x0_0 * x1_6) * x2_2) + ((x0_1 * x1_6) * x2_11) + ((x0_2 * x1_6) * x2_20)) + (((x0_0 * x1_7) * x2_29) + ((x0_1 * x1_7) * x2_38) + ((x0_2 * x1_7) * x2_47)) + (((x0_0 * x1_8) * x2_56) + ((x0_1 * x1_8) * x2_65) + ((x0_2 * x1_8) * x2_74)));
+    st(0, 56, o0_56);
+    double o0_57 = ((((x0_0 * x1_6) * x2_3) + ((x0_1 * x1_6) * x2_12) + ((x0_2 * x1_6) * x2_21)) + (((x0_0 * x1_7) * x2_30) + ((x0_1 * x1_7) * x2_39) + ((x0_2 * x1_7) * x2_48)) + (((x0_0 * x1_8) * x2_57) + ((x0_1 * x1_8) * x2_66) + ((x0_2 * x1_8) * x2_75)));
+    st(0, 57, o0_57);
+    double o0_58 = ((((x0_0 * x1_6) * x2_4) + ((x0_1 * x1_6) * x2_13) + ((x0_2 * x1_6) * x2_22)) + (((x0_0 * x1_7) * x2_31) + ((x0_1 * x1_7) * x2_40) + ((x0_2 * x1_7) * x2_49)) + (((x0_0 * x1_8) * x2_58) + ((x0_1 * x1_8) * x2_67) + ((x0_2 * x1_8) * x2_76)));
+    st(0, 58, o0_58);
+    double o0_59 = ((((x0_0 * x1_6) * x2_5) + ((x0_1 * x1_6) * x2_14) + ((x0_2 * x1_6) * x2_23)) + (((x0_0 * x1_7) * x2_32) + ((x0_1 * x1_7) * x2_41) + ((x0_2 * x1_7) * x2_50)) + (((x0_0 * x1_8) * x2_59) + ((x0_1 * x1_8) * x2_68) + ((x0_2 * x1_8) * x2_77)));
+    st(0, 59, o0_59);
+    double o0_60 = ((((x0_0 * x1_6) * x2_6) + ((x0_1 * x1_6) * x2_15) + ((x0_2 * x1_6) * x2_24)) + (((x0_0 * x1_7) * x2_33) + ((x0_1 * x1_7) * x2_42) + ((x0_2 * x1_7) * x2_51)) + (((x0_0 * x1_8) * x2_60) + ((x0_1 * x1_8) * x2_69) + ((x0_2 * x1_8) * x2_78)));
+    st(0, 60, o0_60);
+    double o0_61 = ((((x0_0 * x1_6) * x2_7) + ((x0_1 * x1_6) * x2_16) + ((x0_2 * x1_6) * x2_25)) + (((x0_0 * x1_7) * x2_34) + ((x0_1 * x1_7) * x2_43) + ((x0_2 * x1_7) * x2_52)) + (((x0_0 * x1_8) * x2_61) + ((x0_1 * x1_8) * x2_70) + ((x0_2 * x1_8) * x2_79)));
+    st(0, 61, o0_61);
+    double o0_62 = ((((x0_0 * x1_6) * x2_8) + ((x0_1 * x1_6) * x2_17) + ((x0_2 * x1_6) * x2_26)) + (((x0_0 * x1_7) * x2_35) + ((x0_1 * x1_7) * x2_44) + ((x0_2 * x1_7) * x2_53)) + (((x0_0 * x1_8) * x2_62) + ((x0_1 * x1_8) * x2_71) + ((x0_2 * x1_8) * x2_80)));
+    st(0, 62, o0_62);
+    double o0_63 = ((((x0_3 * x1_6) * x2_0) + ((x0_4 * x1_6) * x2_9) + ((x0_5 * x1_6) * x2_18)) + (((x0_3 * x1_7) * x2_27) + ((x0_4 * x1_7) * x2_36) + ((x0_5 * x1_7) * x2_45)) + (((x0_3 * x1_8) * x2_54) + ((x0_4 * x1_8) * x2_63) + ((x0_5 * x1_8) * x2_72)));
+    st(0, 63, o0_63);
+    double o0_64 = ((((x0_3 * x1_6) * x2_1) + ((x0_4 * x1_6) * x2_10) + ((x0_5 * x1_6) * x2_19)) + (((x0_3 * x1_7) * x2_28) + ((x0_4 * x1_7) * x2_37) + ((x0_5 * x1_7) * x2_46)) + (((x0_3 * x1_8) * x2_55) + ((x0_4 * x1_8) * x2_64) + ((x0_5 * x1_8) * x2_73)));
+    st(0, 64, o0_64);
+    double o0_65 = ((((x0_3 * x1_6) * x2_2) + ((x0_4 * x1_6) * x2_11) + ((x0_5 * x1_6) * x2_20)) + (((x0_3 * x1_7) * x2_29) + ((x0_4 * x1_7) * x2_38) + ((x0_5 * x1_7) * x2_47)) + (((x0_3 * x1_8) * x2_56) + ((x0_4 * x1_8) * x2_65) + ((x0_5 * x1_8) * x2_74)));
+    st(0, 65, o0_65);
+    double o0_66 = ((((x0_3 * x1_6) * x2_3) + ((x0_4 * x1_6) * x2_12) + ((x0_5 * x1_6) * x2_21)) + (((x0_3 * x1_7) * x2_30) + ((x0_4 * x1_7) * x2_39) + ((x0_5 * x1_7) * x2_48)) + (((x0_3 * x1_8) * x2_57) + ((x0_4 * x1_8) * x2_66) + ((x0_5 * x1_8) * x2_75)));
+    st(0, 66, o0_66);
+    double o0_67 = ((((x0_3 * x1_6) * x2_4) + ((x0_4 * x1_6) * x2_13) + ((x0_5 * x1_6) * x2_22)) + (((x0_3 * x1_7) * x2_31) + ((x0_4 * x1_7) * x2_40) + ((x0_5 * x1_7) * x2_49)) + (((x0_3 * x1_8) * x2_58) + ((x0_4 * x1_8) * x2_67) + ((x0_5 * x1_8) * x2_76)));
+    st(0, 67, o0_67);
+    double o0_68 = ((((x0_3 * x1_6) * x2_5) + ((x0_4 * x1_6) * x2_14) + ((x0_5 * x1_6) * x2_23)) + (((x0_3 * x1_7) * x2_32) + ((x0_4 * x1_7) * x2_41) + ((x0_5 * x1_7) * x2_50)) + (((x0_3 * x1_8) * x2_59) + ((x0_4 * x1_8) * x2_68) + ((x0_5 * x1_8) * x2_77)));
+    st(0, 68, o0_68);
+    double o0_69 = ((((x0_3 * x1_6) * x2_6) + ((x0_4 * x1_6) * x2_15) + ((x0_5 * x1_6) * x2_24)) + (((x0_3 * x1_7) * x2_33) + ((x0_4 * x1_7) * x2_42) + ((x0_5 * x1_7) * x2_51)) + (((x0_3 * x1_8) * x2_60) + ((x0_4 * x1_8) * x2_69) + ((x0_5 * x1_8) * x2_78)));
+    st(0, 69, o0_69);
+    double o0_70 = ((((x0_3 * x1_6) * x2_7) + ((x0_4 * x1_6) * x2_16) + ((x0_5 * x1_6) * x2_25)) + (((x0_3 * x1_7) * x2_34) + ((x0_4 * x1_7) * x2_43) + ((x0_5 * x1_7) * x2_52)) + (((x0_3 * x1_8) * x2_61) + ((x0_4 * x1_8) * x2_70) + ((x0_5 * x1_8) * x2_79)));
+    st(0, 70, o0_70);
+    double o0_71 = ((((x0_3 * x1_6) * x2_8) + ((x0_4 * x1_6) * x2_17) + ((x0_5 * x1_6) * x2_26)) + (((x0_3 * x1_7) * x2_35) + ((x0_4 * x1_7) * x2_44) + ((x0_5 * x1_7) * x2_53)) + (((x0_3 * x1_8) * x2_62) + ((x0_4 * x1_8) * x2_71) + ((x0_5 * x1_8) * x2_80)));
+    st(0, 71, o0_71);
+    double o0_72 = ((((x0_6 * x1_6) * x2_0) + ((x0_7 * x1_6) * x2_9) + ((x0_8 * x1_6) * x2_18)) + (((x0_6 * x1_7) * x2_27) + ((x0_7 * x1_7) * x2_36) + ((x0_8 * x1_7) * x2_45)) + (((x0_6 * x1_8) * x2_54) + ((x0_7 * x1_8) * x2_63) + ((x0_8 * x1_8) * x2_72)));
+    st(0, 72, o0_72);
+    double o0_73 = ((((x0_6 * x1_6) * x2_1) + ((x0_7 * x1_6) * x2_10) + ((x0_8 * x1_6) * x2_19)) + (((x0_6 * x1_7) * x2_28) + ((x0_7 * x1_7) * x2_37) + ((x0_8 * x1_7) * x2_46)) + (((x0_6 * x1_8) * x2_55) + ((x0_7 * x1_8) * x2_64) + ((x0_8 * x1_8) * x2_73)));
+    st(0, 73, o0_73);
+    double o0_74 = ((((x0_6 * x1_6) * x2_2) + ((x0_7 * x1_6) * x2_11) + ((x0_8 * x1_6) * x2_20)) + (((x0_6 * x1_7) * x2_29) + ((x0_7 * x1_7) * x2_38) + ((x0_8 * x1_7) * x2_47)) + (((x0_6 * x1_8) * x2_56) + ((x0_7 * x1_8) * x2_65) + ((x0_8 * x1_8) * x2_74)));
+    st(0, 74, o0_74);
+    double o0_75 = ((((x0_6 * x1_6) * x2_3) + ((x0_7 * x1_6) * x2_12) + ((x0_8 * x1_6) * x2_21)) + (((x0_6 * x1_7) * x2_30) + ((x0_7 * x1_7) * x2_39) + ((x0_8 * x1_7) * x2_48)) + (((x0_6 * x1_8) * x2_57) + ((x0_7 * x1_8) * x2_66) + ((x0_8 * x1_8) * x2_75)));
+    st(0, 75, o0_75);
+    double o0_76 = ((((x0_6 * x1_6) * x2_4) + ((x0_7 * x1_6) * x2_13) + ((x0_8 * x1_6) * x2_22)) + (((x0_6 * x1_7) * x2_31) + ((x0_7 * x1_7) * x2_40) + ((x0_8 * x1_7) * x2_49)) + (((x0_6 * x1_8) * x2_58) + ((x0_7 * x1_8) * x2_67) + ((x0_8 * x1_8) * x2_76)));
+    st(0, 76, o0_76);
+    double o0_77 = ((((x0_6 * x1_6) * x2_5) + ((x0_7 * x1_6) * x2_14) + ((x0_8 * x1_6) * x2_23)) + (((x0_6 * x1_7) * x2_32) + ((x0_7 * x1_7) * x2_41) + ((x0_8 * x1_7) * x2_50)) + (((x0_6 * x1_8) * x2_59) + ((x0_7 * x1_8) * x2_68) + ((x0_8 * x1_8) * x2_77)));
+    st(0, 77, o0_77);
+    double o0_78 = ((((x0_6 * x1_6) * x2_6) + ((x0_7 * x1_6) * x2_15) + ((x0_8 * x1_6) * x2_24)) + (((x0_6 * x1_7) * x2_33) + ((x0_7 * x1_7) * x2_42) + ((x0_8 * x1_7) * x2_51)) + (((x0_6 * x1_8) * x2_60) + ((x0_7 * x1_8) * x2_69) + ((x0_8 * x1_8) * x2_78)));
+    st(0, 78, o0_78);
+    double o0_79 = ((((x0_6 * x1_6) * x2_7) + ((x0_7 * x1_6) * x2_16) + ((x0_8 * x1_6) * x2_25)) + (((x0_6 * x1_7) * x2_34) + ((x0_7 * x1_7) * x2_43) + ((x0_8 * x1_7) * x2_52)) + (((x0_6 * x1_8) * x2_61) + ((x0_7 * x1_8) * x2_70) + ((x0_8 * x1_8) * x2_79)));
+    st(0, 79, o0_79);
+    double o0_80 = ((((x0_6 * x1_6) * x2_8) + ((x0_7 * x1_6) * x2_17) + ((x0_8 * x1_6) * x2_26)) + (((x0_6 * x1_7) * x2_35) + ((x0_7 * x1_7) * x2_44) + ((x0_8 * x1_7) * x2_53)) + (((x0_6 * x1_8) * x2_62) + ((x0_7 * x1_8) * x2_71) + ((x0_8 * x1_8) * x2_80)));
+    st(0, 80, o0_80);
+  }
+};
+
+// contract3: A_ijkl = D_k^o C_j^n B_i^m E_mnol (Sec. 5.1, eq:Contract3)
+struct Gen_contract3 {
+  static constexpr bool kStream = true;
+  static constexpr int kMaxBlock = 256;  // more than 100 inputs live
+  static constexpr int NF_IN = 4, NF_OUT = 1;
+  static constexpr int fin[NF_IN] = {9, 9, 9, 81};
+  static constexpr int fout[NF_OUT] = {81};
+  static constexpr int NIN = 108, NOUT = 81;
+  template <class L, class S>
+  __device__ static inline void stream(L&& ld, S&& st) {
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    const double x0_3 = ld(0, 3);
+    const double x0_4 = ld(0, 4);
+    const double x0_5 = ld(0, 5);
+    const double x0_6 = ld(0, 6);
+    const double x0_7 = ld(0, 7);
+    const double x0_8 = ld(0, 8);
+    const double x1_0 = ld(1, 0);
+    const double x1_1 = ld(1, 1);
+    const double x1_2 = ld(1, 2);
+    const double x1_3 = ld(1, 3);
+    const double x1_4 = ld(1, 4);
+    const double x1_5 = ld(1, 5);
+    const double x1_6 = ld(1, 6);
+    const double x1_7 = ld(1, 7);
+    const double x1_8 = ld(1, 8);
+    const double x2_0 = ld(2, 0);
+    const double x2_1 = ld(2, 1);
+    const double x2_2 = ld(2, 2);
+    const double x2_3 = ld(2, 3);
+    const double x2_4 = ld(2, 4);
+    const double x2_5 = ld(2, 5);
+    const double x2_6 = ld(2, 6);
+    const double x2_7 = ld(2, 7);
+    const double x2_8 = ld(2, 8);
+    const double x3_0 = ld(3, 0);
+    const double x3_1 = ld(3, 1);
+    const double x3_2 = ld(3, 2);
+    const double x3_3 = ld(3, 3);
+    const double x3_4 = ld(3, 4);
+    const double x3_5 = ld(3, 5);
+    const double x3_6 = ld(3, 6);
+    const double x3_7 = ld(3, 7);
+    const double x3_8 = ld(3, 8);
+    const double x3_9 = ld(3, 9);
+    const double x3_10 = ld(3, 10);
+    const double x3_11 = ld(3, 11);
+    const double x3_12 = ld(3, 12);
+    const double x3_13 = ld(3, 13);
+    const double x3_14 = ld(3, 14);
+    const double x3_15 = ld(3, 15);
+    const double x3_16 = ld(3, 16);
+    const double x3_17 = ld(3, 17);
+    const double x3_18 = ld(3, 18);
+    const double x3_19 = ld(3, 19);
+    const double x3_20 = ld(3, 20);
+    const double x3_21 = ld(3, 21);
+    const double x3_22 = ld(3, 22);
+    const double x3_23 = ld(3, 23);
+    const double x3_24 = ld(3, 24);
+    const double x3_25 = ld(3, 25);
+    const double x3_26 = ld(3, 26);
+    const double x3_27 = ld(3, 27);
+    const double x3_28 = ld(3, 28);
+    const double x3_29 = ld(3, 29);
+    const double x3_30 = ld(3, 30);
+    const double x3_31 = ld(3, 31);
+    const double x3_32 = ld(3, 32);
+    const double x3_33 = ld(3, 33);
+    const double x3_34 = ld(3, 34);
+    const double x3_35 = ld(3, 35);
+    const double x3_36 = ld(3, 36);
+    const double x3_37 = ld(3, 37);
+    const double x3_38 = ld(3, 38);
+    const double x3_39 = ld(3, 39);
+    const double x3_40 = ld(3, 40);
+    const double x3_41 = ld(3, 41);
+    const double x3_42 = ld(3, 42);
+    const double x3_43 = ld(3, 43);
+    const double x3_44 = ld(3, 44);
+    const double x3_45 = ld(3, 45);
+    const double x3_46 = ld(3, 46);
+    const double x3_47 = ld(3, 47);
+    const double x3_48 = ld(3, 48);
+    const double x3_49 = ld(3, 49);
+    const double x3_50 = ld(3, 50);
+    const double x3_51 = ld(3, 51);
+    const double x3_52 = ld(3, 52);
+    const double x3_53 = ld(3, 53);
+    const double x3_54 = ld(3, 54);
+    const double x3_55 = ld(3, 55);
+    const double x3_56 = ld(3, 56);
+    const double x3_57 = ld(3, 57);
+    const double x3_58 = ld(3, 58);
+    const double x3_59 = ld(3, 59);
+    const double x3_60 = ld(3, 60);
+    const double x3_61 = ld(3, 61);
+    const double x3_62 = ld(3, 62);
+    const double x3_63 = ld(3, 63);
+    const double x3_64 = ld(3, 64);
+    const double x3_65 = ld(3, 65);
+    const double x3_66 = ld(3, 66);
+    const double x3_67 = ld(3, 67);
+    const double x3_68 = ld(3, 68);
+    const double x3_69 = ld(3, 69);
+    const double x3_70 = ld(3, 70);
+    const double x3_71 = ld(3, 71);
+    const double x3_72 = ld(3, 72);
+    const double x3_73 = ld(3, 73);
+    const double x3_74 = ld(3, 74);
+    const double x3_75 = ld(3, 75);
+    const double x3_76 = ld(3, 76);
+    const double x3_77 = ld(3, 77);
+    const double x3_78 = ld(3, 78);
+    const double x3_79 = ld(3, 79);
+    const double x3_80 = ld(3, 80);
+    // A(i,j,k,l) = Sum(m, Sum(n, Sum(o, (((D(k,o) * C(j,n)) * B(i,m)) * E(m,n,o,l)))))
+    double o0_0 = ((((((x0_0 * x1_0) * x2_0) * x3_0) + (((x0_1 * x1_0) * x2_0) * x3_3) + (((x0_2 * x1_0) * x2_0) * x3_6)) + ((((x0_0 * x1_1) * x2_0) * x3_9) + (((x0_1 * x1_1) * x2_0) * x3_12) + (((x0_2 * x1_1) * x2_0) * x3_15)) + ((((x0_0 * x1_2) * x2_0) * x3_18) + (((x0_1 * x1_2) * x2_0) * x3_21) + (((x0_2 * x1_2) * x2_0) * x3_24))) + (((((x0_0 * x1_0) * x2_1) * x3_27) + (((x0_1 * x1_0) * x2_1) * x3_30) + (((x0_2 * x1_0) * x2_1) * x3_33)) + ((((x0_0 * x1_1) * x2_1) * x3_36) + (((x0_1 * x1_1) * x2_1) * x3_39) + (((x0_2 * x1_1) * x2_1) * x3_42)) + ((((x0_0 * x1_2) * x2_1) * x3_45) + (((x0_1 * x1_2) * x2_1) * x3_48) + (((x0_2 * x1_2) * x2_1) * x3_51))) + (((((x0_0 * x1_0) * x2_2) * x3_54) + (((x0_1 * x1_0) * x2_2) * x3_57) + (((x0_2 * x1_0) * x2_2) * x3_60)) + ((((x0_0 * x1_1) * x2_2) * x3_63) + (((x0_1 * x1_1) * x2_2) * x3_66) + (((x0_2 * x1_1) * x2_2) * x3_69)) + ((((x0_0 * x1_2) * x2_2) * x3_72) + (((x0_1 * x1_2) * x2_2) * x3_75) + (((x0_2 * x1_2) * x2_2) * x3_78))));
+    st(0, 0, o0_0);
+    double o0_1 = ((((((x0_0 * x1_0) * x2_0) * x3_1) + (((x0_1 * x1_0) * x2_0) * x3_4) + (((x0_2 * x1_0) * x2_0) * x3_7)) + ((((x0_0 * x1_1) * x2_0) * x3_10) + (((x0_1 * x1_1) * x2_0) * x3_13) + (((x0_2 * x1_1) * x2_0) * x3_16)) + ((((x0_0 * x1_2) * x2_0) * x3_19) + (((x0_1 * x1_2) * x2_0) * x3_22) + (((x0_2 * x1_2) * x2_0) * x3_25))) + (((((x0_0 * x1_0) * x2_1) * x3_28) + (((x0_1 * x1_0) * x2_1) * x3_31) + (((x0_2 * x1_0) * x2_1) * x3_34)) + ((((x0_0 * x1_1) * x2_1) * x3_37) + (((x0_1 * x1_1) * x2_1) * x3_40) + (((x0_2 * x1_1) * x2_1) * x3_43)) + ((((x0_0 * x1_2) * x2_1) * x3_46) + (((x0_1 * x1_2) * x2_1) * x3_49) + (((x0_2 * x1_2) * x2_1) * x3_52))) + (((((x0_0 * x1_0) * x2_2) * x3_55) + (((x0_1 * x1_0) * x2_2) * x3_58) + (((x0_2 * x1_0) * x2_2) * x3_61)) + ((((x0_0 * x1_1) * x2_2) * x3_64) + (((x0_1 * x1_1) * x2_2) * x3_67) + (((x0_2 * x1_1) * x2_2) * x3_70)) + ((((x0_0 * x1_2) * x2_2) * x3_73) + (((x0_1 * x1_2) * x2_2) * x3_76) + (((x0_2 * x1_2) * x2_2) * x3_79))));
+    st(0, 1, o0_1);
+    double o0_2 = ((((((x0_0 * x1_0) * x2_0) * x3_2) + (((x0_1 * x1_0) * x2_0) * x3_5) + (((x0_2 * x1_0) * x2_0) * x3_8)) + ((((x0_0 * x1_1) * x2_0) * x3_11) + (((x0_1 * x1_1) * x2_0) * x3_14) + (((x0_2 * x1_1) * x2_0) * x3_17)) + ((((x0_0 * x1_2) * x2_0) * x3_20) + (((x0_1 * x1_2) * x2_0) * x3_23) + (((x0_2 * x1_2) * x2_0) * x3_26))) + (((((x0_0 * x1_0) * x2_1) * x3_29) + (((x0_1 * x1_0) * x2_1) * x3_32) + (((x0_2 * x1_0) * x2_1) * x3_35)) + ((((x0_0 * x1_1) * x2_1) * x3_38) + (((x0_1 * x1_1) * x2_1) * x3_41) + (((x0_2 * x1_1) * x2_1) * x3_44)) + ((((x0_0 * x1_2) * x2_1) * x3_47) + (((x0_1 * x1_2) * x2_1) * x3_50) + (((x0_2 * x1_2) * x2_1) * x3_53))) + (((((x0_0 * x1_0) * x2_2) * x3_56) + (((x0_1 * x1_0) * x2_2) * x3_59) + (((x0_2 * x1_0) * x2_2) * x3_62)) + ((((x0_0 * x1_1) * x2_2) * x3_65) + (((x0_1 * x1_1) * x2_2) * x3_68) + (((x0_2 * x1_1) * x2_2) * x3_71)) + ((((x0_0 * x1_2) * x2_2) * x3_74) + (((x0_1 * x1_2) * x2_2) * x3_77) + (((x0_2 * x1_2) * x2_2) * x3_80))));
+    st(0, 2, o0_2);
+    double o0_3 = ((((((x0_3 * x1_0) * x2_0) * x3_0) + (((x0_4 * x1_0) * x2_0) * x3_3) + (((x0_5 * x1_0) * x2_0) * x3_6)) + ((((x0_3 * x1_1) * x2_0) * x3_9) + (((x0_4 * x1_1) * x2_0) * x3_12) + (((x0_5 * x1_1) * x2_0) * x3_15)) + ((((x0_3 * x1_2) * x2_0) * x3_18) + (((x0_4 * x1_2) * x2_0) * x3_21) + (((x0_5 * x1_2) * x2_0) * x3_24))) + (((((x0_3 * x1_0) * x2_1) * x3_27) + (((x0_4 * x1_0) * x2_1) * x3_30) + (((x0_5 * x1_0) * x2_1) * x3_33)) + ((((x0_3 * x1_1) * x2_1) * x3_36) + (((x0_4 * x1_1) * x2_1) * x3_39) + (((x0_5 * x1_1) * x2_1) * x3_42)) + ((((x0_3 * x1_2) * x2_1) * x3_45) + (((x0_4 * x1_2) * x2_1) * x3_48) + (((x0_5 * x1_2) * x2_1) * x3_51))) + (((((x0_3 * x1_0) * x2_2) * x3_54) + (((x0_4 * x1_0) * x2_2) * x3_57) + (((x0_5 * x1_0) * x2_2) * x3_60)) + ((((x0_3 * x1_1) * x2_2) * x3_63) + (((x0_4 * x1_1) * x2_2) * x3_66) + (((x0_5 * x1_1) * x2_2) * x3_69)) + ((((x0_3 * x1_2) * x2_2) * x3_72) + (((x0_4 * x1_2) * x2_2) * x3_75) + (((x0_5 * x1_2) * x2_2) * x3_78))));
+    st(0, 3, o0_3);
+    double o0_4 = ((((((x0_3 * x1_0) * x2_0) * x3_1) + (((x0_4 * x1_0) * x2_0) * x3_4) + (((x0_5 * x1_0) * x2_0) * x3_7)) + ((((x0_3 * x1_1) * x2_0) * x3_10) + (((x0_4 * x1_1) * x2_0) * x3_13) + (((x0_5 * x1_1) * x2_0) * x3_16)) + ((((x0_3 * x1_2) * x2_0) * x3_19) + (((x0_4 * x1_2) * x2_0) * x3_22) + (((x0_5 * x1_2) * x2_0) * x3_25))) + (((((x0_3 * x1_0) * x2_1) * x3_28) + (((x0_4 * x1_0) * x2_1) * x3_31) + (((x0_5 * x1_0) * x2_1) * x3_34)) + ((((x0_3 * x1_1) * x2_1) * x3_37) + (((x0_4 * x1_1) * x2_1) * x3_40) + (((x0_5 * x1_1) * x2_1) * x3_43)) + ((((x0_3 * x1_2) * x2_1) * x3_46) + (((x0_4 * x1_2) * x2_1) * x3_49) + (((x0_5 * x1_2) * x2_1) * x3_52))) + (((((x0_3 * x1_0) * x2_2) * x3_55) + (((x0_4 * x1_0) * x2_2) * x3_58) + (((x0_5 * x1_0) * x2_2) * x3_61)) + ((((x0_3 * x1_1) * x2_2) * x3_64) + (((x0_4 * x1_1) * x2_2) * x3_67) + (((x0_5 * x1_1) * x2_2) * x3_70)) + ((((x0_3 * x1_2) * x2_2) * x3_73) + (((x0_4 * x1_2) * x2_2) * x3_76) + (((x0_5 * x1_2) * x2_2) * x3_79))));
+    st(0, 4, o0_4);
+    double o0_5 = ((((((x0_3 * x1_0) * x2_0) * x3_2) + (((x0_4 * x1_0) * x2_0) * x3_5) + (((x0_5 * x1_0) * x2_0) * x3_8)) + ((((x0_3 * x1_1) * x2_0) * x3_11) + (((x0_4 * x1_1) * x2_0) * x3_14) + (((x0_5 * x1_1) * x2_0) * x3_17)) + ((((x0_3 * x1_2) * x2_0) * x3_20) + (((x0_4 * x1_2) * x2_0) * x3_23) + (((x0_5 * x1_2) * x2_0) * x3_26))) + (((((x0_3 * x1_0) * x2_1) * x3_29) + (((x0_4 * x1_0) * x2_1) * x3_32) + (((x0_5 * x1_0) * x2_1) * x3_35)) + ((((x0_3 * x1_1) * x2_1) * x3_38) + (((x0_4 * x1_1) * x2_1) * x3_41) + (((x0_5 * x1_1) * x2_1) * x3_44)) + ((((x0_3 * x1_2) * x2_1) * x3_47) + (((x0_4 * x1_2) * x2_1) * x3_50) + (((x0_5 * x1_2) * x2_1) * x3_53))) + (((((x0_3 * x1_0) * x2_2) * x3_56) + (((x0_4 * x1_0) * x2_2) * x3_59) + (((x0_5 * x1_0) * x2_2) * x3_62)) + ((((x0_3 * x1_1) * x2_2) * x3_65) + (((x0_4 * x1_1) * x2_2) * x3_68) + (((x0_5 * x1_1) * x2_2) * x3_71)) + ((((x0_3 * x1_2) * x2_2) * x3_74) + (((x0_4 * x1_2) * x2_2) * x3_77) + (((x0_5 * x1_2) * x2_2) * x3_80))));
+    st(0, 5, o0_5);
+    double o0_6 = ((((((x0_6 * x1_0) * x2_0) * x3_0) + (((x0_7 * x1_0) * x2_0) * x3_3) + (((x0_8 * x1_0) * x2_0) * x3_6)) + ((((x0_6 * x1_1) * x2_0) * x3_9) + (((x0_7 * x1_1) * x2_0) * x3_12) + (((x0_8 * x1_1) * x2_0) * x3_15)) + ((((x0_6 * x1_2) * x2_0) * x3_18) + (((x0_7 * x1_2) * x2_0) * x3_21) + (((x0_8 * x1_2) * x2_0) * x3_24))) + (((((x0_6 * x1_0) * x2_1) * x3_27) + (((x0_7 * x1_0) * x2_1) * x3_30) + (((x0_8 * x1_0) * x2_1) * x3_33)) + ((((x0_6 * x1_1) * x2_1) * x3_36) + (((x0_7 * x1_1) * x2_1) * x3_39) + (((x0_8 * x1_1) * x2_1) * x3_42)) + ((((x0_6 * x1_2) * x2_1) * x3_45) + (((x0_7 * x1_2) * x2_1) * x3_48) + (((x0_8 * x1_2) * x2_1) * x3_51))) + (((((x0_6 * x1_0) * x2_2) * x3_54) + (((x0_7 * x1_0) * x2_2) * x3_57) + (((x0_8 * x1_0) * x2_2) * x3_60)) + ((((x0_6 * x1_1) * x2_2) * x3_63) + (((x0_7 * x1_1) * x2_2) * x3_66) + (((x0_8 * x1_1) * x2_2) * x3_69)) + ((((x0_6 * x1_2) * x2_2) * x3_72) + (((x0_7 * x1_2) * x2_2) * x3_75) + (((x0_8 * x1_2) * x2_2) * x3_78))));
+    st(0, 6, o0_6);
+    double o0_7 = ((((((x0_6 * x1_0) * x2_0) * x3_1) + (((x0_7 * x1_0) * x2_0) * x3_4) + (((x0_8 * x1_0) * x2_0) * x3_7)) + ((((x0_6 * x1_1) * x2_0) * x3_10) + (((x0_7 * x1_1) * x2_0) * x3_13) + (((x0_8 * x1_1) * x2_0) * x3_16)) + ((((x0_6 * x1_2) * x2_0) * x3_19) + (((x0_7 * x1_2) * x2_0) * x3_22) + (((x0_8 * x1_2) * x2_0) * x3_25))) + (((((x0_6 * x1_0) * x2_1) * x3_28) + (((x0_7 * x1_0) * x2_1) * x3_31) + (((x0_8 * x1_0) * x2_1) * x3_34)) + ((((x0_6 * x1_1) * x2_1) * x3_37) + (((x0_7 * x1_1) * x2_1) * x3_40) + (((x0_8 * x1_1) * x2_1) * x3_43)) + ((((x0_6 * x1_2) * x2_1) * x3_46) + (((x0_7 * x1_2) * x2_1) * x3_49) + (((x0_8 * x1_2) * x2_1) * x3_52))) + (((((x0_6 * x1_0) * x2_2) * x3_55) + (((x0_7 * x1_0) * x2_2) * x3_58) + (((x0_8 * x1_0) * x2_2) * x3_61)) + ((((x0_6 * x1_1) * x2_2) * x3_64) + (((x0_7 * x1_1) * x2_2) * x3_67) + (((x0_8 * x1_1) * x2_2) * x3_70)) + ((((x0_6 * x1_2) * x2_2) * x3_73) + (((x0_7 * x1_2) * x2_2) * x3_76) + (((x0_8 * x1_2) * x2_2) * x3_79))));
+    st(0, 7, o0_7);
+    double o0_8 = ((((((x0_6 * x1_0) * x2_0) * x3_2) + (((x0_7 * x1_0) * x2_0) * x3_5) + (((x0_8 * x1_0) * x2_0) * x3_8)) + ((((x0_6 * x1_1) * x2_0) * x3_11) + (((x0_7 * x1_1) * x2_0) * x3_14) + (((x0_8 * x1_1) * x2_0) * x3_17)) + ((((x0_6 * x1_2) * x2_0) * x3_20) + (((x0_7 * x1_2) * x2_0) * x3_23) + (((x0_8 * x1_2) * x2_0) * x3_26))) + (((((x0_6 * x1_0) * x2_1) * x3_29) + (((x0_7 * x1_0) * x2_1) * x3_32) + (((x0_8 * x1_0) * x2_1) * x3_35)) + ((((x0_6 * x1_1) * x2_1) * x3_38) + (((x0_7 * x1_1) * x2_1) * x3_41) + (((x0_8 * x1_1) * x2_1) * x3_44)) + ((((x0_6 * x1_2) * x2_1) * x3_47) + (((x0_7 * x1_2) * x2_1) * x3_50) + (((x0_8 * x1_2) * x2_1) * x3_53))) + (((((x0_6 * x1_0) * x2_2) * x3_56) + (((x0_7 * x1_0) * x2_2) * x3_59) + (((x0_8 * x1_0) * x2_2) * x3_62)) + ((((x0_6 * x1_1) * x2_2) * x3_65) + (((x0_7 * x1_1) * x2_2) * x3_68) + (((x0_8 * x1_1) * x2_2) * x3_71)) + ((((x0_6 * x1_2) * x2_2) * x3_74) + (((x0_7 * x1_2) * x2_2) * x3_77) + (((x0_8 * x1_2) * x2_2) * x3_80))));
+    st(0, 8, o0_8);
+    double o0_9 = ((((((x0_0 * x1_3) * x2_0) * x3_0) + (((x0_1 * x1_3) * x2_0) * x3_3) + (((x0_2 * x1_3) * x2_0) * x3_6)) + ((((x0_0 * x1_4) * x2_0) * x3_9) + (((x0_1 * x1_4) * x2_0) * x3_12) + (((x0_2 * x1_4) * x2_0) * x3_15)) + ((((x0_0 * x1_5) * x2_0) * x3_18) + (((x0_1 * x1_5) * x2_0) * x3_21) + (((x0_2 * x1_5) * x2_0) * x3_24))) + (((((x0_0 * x1_3) * x2_1) * x3_27) + (((x0_1 * x1_3) * x2_1) * x3_30) + (((x0_2 * x1_3) * x2_1) * x3_33)) + ((((x0_0 * x1_4) * x2_1) * x3_36) + (((x0_1 * x1_4) * x2_1) * x3_39) + (((x0_2 * x1_4) * x2_1) * x3_42)) + ((((x0_0 * x1_5) * x2_1) * x3_45) + (((x0_1 * x1_5) * x2_1) * x3_48) + (((x0_2 * x1_5) * x2_1) * x3_51))) + (((((x0_0 * x1_3) * x2_2) * x3_54) + (((x0_1 * x1_3) * x2_2) * x3_57) + (((x0_2 * x1_3) * x2_2) * x3_60)) + ((((x0_0 * x1_4) * x2_2) * x3_63) + (((x0_1 * x1_4) * x2_2) * x3_66) + (((x0_2 * x1_4) * x2_2) * x3_69)) + ((((x0_0 * x1_5) * x2_2) * x3_72) + (((x0_1 * x1_5) * x2_2) * x3_75) + (((x0_2 * x1_5) * x2_2) * x3_78))));
+    st(0, 9, o0_9);
+    double o0_10 = ((((((x0_0 * x1_3) * x2_0) * x3_1) + (((x0_1 * x1_3) * x2_0) * x3_4) + (((x0_2 * x1_3) * x2_0) * x3_7)) + ((((x0_0 * x1_4) * x2_0) * x3_10) + (((x0_1 * x1_4) * x2_0) * x3_13) + (((x0_2 * x1_4) * x2_0) * x3_16)) + ((((x0_0 * x1_5) * x2_0) * x3_19) + (((x0_1 * x1_5) * x2_0) * x3_22) + (((x0_2 * x1_5) * x2_0) * x3_25))) + (((((x0_0 * x1_3) * x2_1) * x3_28) + (((x0_1 * x1_3) * x2_1) * x3_31) + (((x0_2 * x1_3) * x2_1) * x3_34)) + ((((x0_0 * x1_4) * x2_1) * x3_37) + (((x0_1 * x1_4) * x2_1) * x3_40) + (((x0_2 * x1_4) * x2_1) * x3_43)) + ((((x0_0 * x1_5) * x2_1) * x3_46) + (((x0_1 * x1_5) * x2_1) * x3_49) + (((x0_2 * x1_5) * x2_1) * x3_52))) + (((((x0_0 * x1_3) * x2_2) * x3_55) + (((x0_1 * x1_3) * x2_2) * x3_58) + (((x0_2 * x1_3) * x2_2) * x3_61)) + ((((x0_0 * x1_4) * x2_2) * x3_64) + (((x0_1 * x1_4) * x2_2) * x3_67) + (((x0_2 * x1_4) * x2_2) * x3_70)) + ((((x0_0 * x1_5) * x2_2) * x3_73) + (((x0_1 * x1_5) * x2_2) * x3_76) + (((x0_2 * x1_5) * x2_2) * x3_79))));
+    st(0, 10, o0_10);
+    double o0_11 = ((((((x0_0 * x1_3) * x2_0) * x3_2) + (((x0_1 * x1_3) * x2_0) * x3_5) + (((x0_2 * x1_3) * x2_0) * x3_8)) + ((((x0_0 * x1_4) * x2_0) * x3_11) + (((x0_1 * x1_4) * x2_0) * x3_14) + (((x0_2 * x1_4) * x2_0) * x3_17)) + ((((x0_0 * x1_5) * x2_0) * x3_20) + (((x0_1 * x1_5) * x2_0) * x3_23) + (((x0_2 * x1_5) * x2_0) * x3_26))) + (((((x0_0 * x1_3) * x2_1) * x3_29) + (((x0_1 * x1_3) * x2_1) * x3_32) + (((x0_2 * x1_3) * x2_1) * x3_35)) + ((((x0_0 * x1_4) * x2_1) * x3_38) + (((x0_1 * x1_4) * x2_1) * x3_41) + (((x0_2 * x1_4) * x2_1) * x3_44)) + ((((x0_0 * x1_5) * x2_1) * x3_47) + (((x0_1 * x1_5) * x2_1) * x3_50) + (((x0_2 * x1_5) * x2_1) * x3_53))) + (((((x0_0 * x1_3) * x2_2) * x3_56) + (((x0_1 * x1_3) * x2_2) * x3_59) + (((x0_2 * x1_3) * x2_2) * x3_62)) + ((((x0_0 * x1_4) * x2_2) * x3_65) + (((x0_1 * x1_4) * x2_2) * x3_68) + (((x0_2 * x1_4) * x2_2) * x3_71)) + ((((x0_0 * x1_5) * x2_2) * x3_74) + (((x0_1 * x1_5) * x2_2) * x3_77) + (((x0_2 * x1_5) * x2_2) * x3_80))));
+    st(0, 11, o0_11);
+    double o0_12 = ((((((x0_3 * x1_3) * x2_0) * x3_0) + (((x0_4 * x1_3) * x2_0) * x3_3) + (((x0_5 * x1_3) * x2_0) * x3_6)) + ((((x0_3 * x1_4) * x2_0) * x3_9) + (((x0_4 * x1_4) * x2_0) * x3_12) + (((x0_5 * x1_4) * x2_0) * x3_15)) + ((((x0_3 * x1_5) * x2_0) * x3_18) + (((x0_4 * x1_5) * x2_0) * x3_21) + (((x0_5 * x1_5) * x2_0) * x3_24))) + (((((x0_3 * x1_3) * x2_1) * x3_27) + (((x0_4 * x1_3) * x2_1) * x3_30) + (((x0_5 * x1_3) * x2_1) * x3_33)) + ((((x0_3 * x1_4) * x2_1) * x3_36) + (((x0_4 * x1_4) * x2_1) * x3_39) + (((x0_5 * x1_4) * x2_1) * x3_42)) + ((((x0_3 * x1_5) * x2_1) * x3_45) + (((x0_4 * x1_5) * x2_1) * x3_48) + (((x0_5 * x1_5) * x2_1) * x3_51))) + (((((x0_3 * x1_3) * x2_2) * x3_54) + (((x0_4 * x1_3) * x2_2) * x3_57) + (((x0_5 * x1_3) * x2_2) * x3_60)) + ((((x0_3 * x1_4) * x2_2) * x3_63) + (((x0_4 * x1_4) * x2_2) * x3_66) + (((x0_5 * x1_4) * x2_2) * x3_69)) + ((((x0_3 * x1_5) * x2_2) * x3_72) + (((x0_4 * x1_5) * x2_2) * x3_75) + (((x0_5 * x1_5) * x2_2) * x3_78))));
+    st(0, 12, o0_12);
+    double o0_13 = ((((((x0_3 * x1_3) * x2_0) * x3_1) + (((x0_4 * x1_3) * x2_0) * x3_4) + (((x0_5 * x1_3) * x2_0) * x3_7)) + ((((x0_3 * x1_4) * x2_0) * x3_10) + (((x0_4 * x1_4) * x2_0) * x3_13) + (((x0_5 * x1_4) * x2_0) * x3_16)) + ((((x0_3 * x1_5) * x2_0) * x3_19) + (((x0_4 * x1_5) * x2_0) * x3_22) + (((x0_5 * x1_5) * x2_0) * x3_25))) + (((((x0_3 * x1_3) * x2_1) * x3_28) + (((x0_4 * x1_3) * x2_1) * x3_31) + (((x0_5 * x1_3) * x2_1) * x3_34)) + ((((x0_3 * x1_4) * x2_1) * x3_37) + (((x0_4 * x1_4) * x2_1) * x3_40) + (((x0_5 * x1_4) * x2_1) * x3_43)) + ((((x0_3 * x1_5) * x2_1) * x3_46) + (((x0_4 * x1_5) * x2_1) * x3_49) + (((x0_5 * x1_5) * x2_1) * x3_52))) + (((((x0_3 * x1_3) * x2_2) * x3_55) + (((x0_4 * x1_3) * x2_2) * x3_58) + (((x0_5 * x1_3) * x2_2) * x3_61)) + ((((x0_3 * x1_4) * x2_2) * x3_64) + (((x0_4 * x1_4) * x2_2) * x3_67) + (((x0_5 * x1_4) * x2_2) * x3_70)) + ((((x0_3 * x1_5) * x2_2) * x3_73) + (((x0_4 * x1_5) * x2_2) * x3_76) + (((x0_5 * x1_5) * x2_2) * x3_79))));
+    st(0, 13, o0_13);
+    double o0_14 = ((((((x0_3 * x1_3) * x2_0) * x3_2) + (((x0_4 * x1_3) * x2_0) * x3_5) + (((x0_5 * x1_3) * x2_0) * x3_8)) + ((((x0_3 * x1_4) * x2_0) * x3_11) + (((x0_4 * x1_4) * x2_0) * x3_14) + (((x0_5 * x1_4) * x2_0) * x3_17)) + ((((x0_3 * x1_5) * x2_0) * x3_20) + (((x0_4 * x1_5) * x2_0) * x3_23) + (((x0_5 * x1_5) * x2_0) * x3_26))) + (((((x0_3 * x1_3) * x2_1) * x3_29) + (((x0_4 * x1_3) * x2_1) * x3_32) + (((x0_5 * x1_3) * x2_1) * x3_35)) + ((((x0_3 * x1_4) * x2_1) * x3_38) + (((x0_4 * x1_4) * x2_1) * x3_41) + (((x0_5 * x1_4) * x2_1) * x3_44)) + ((((x0_3 * x1_5) * x2_1) * x3_47) + (((x0_4 * x1_5) * x2_1) * x3_50) + (((x0_5 * x1_5) * x2_1) * x3_53))) + (((((x0_3 * x1_3) * x2_2) * x3_56) + (((x0_4 * x1_3) * x2_2) * x3_59) + (((x0_5 * x1_3) * x2_2) * x3_62)) + ((((x0_3 * x1_4) * x2_2) * x3_65) + (((x0_4 * x1_4) * x2_2) * x3_68) + (((x0_5 * x1_4) * x2_2) * x3_71)) + ((((x0_3 * x1_5) * x2_2) * x3_74) + (((x0_4 * x1_5) * x2_2) * x3_77) + (((x0_5 * x1_5) * x2_2) * x3_80))));
+    st(0, 14, o0_14);
+    double o0_15 = ((((((x0_6 * x1_3) * x2_0) * x3_0) + (((x0_7 * x1_3) * x2_0) * x3_3) + (((x0_8 * x1_3) * x2_0) * x3_6)) + ((((x0_6 * x1_4) * x2_0) * x3_9) + (((x0_7 * x1_4) * x2_0) * x3_12) + (((x0_8 * x1_4) * x2_0) * x3_15)) + ((((x0_6 * x1_5) * x2_0) * x3_18) + (((x0_7 * x1_5) * x2_0) * x3_21) + (((x0_8 * x1_5) * x2_0) * x3_24))) + (((((x0_6 * x1_3) * x2_1) * x3_27) + (((x0_7 * x1_3) * x2_1) * x3_30) + (((x0_8 * x1_3) * x2_1) * x3_33)) + ((((x0_6 * x1_4) * x2_1) * x3_36) + (((x0_7 * x1_4) * x2_1) * x3_39) + (((x0_8 * x1_4) * x2_1) * x3_42)) + ((((x0_6 * x1_5) * x2_1) * x3_45) + (((x0_7 * x1_5) * x2_1) * x3_48) + (((x0_8 * x1_5) * x2_1) * x3_51))) + (((((x0_6 * x1_3) * x2_2) * x3_54) + (((x0_7 * x1_3) * x2_2) * x3_57) + (((x0_8 * x1_3) * x2_2) * x3_60)) + ((((x0_6 * x1_4) * x2_2) * x3_63) + (((x0_7 * x1_4) * x2_2) * x3_66) + (((x0_8 * x1_4) * x2_2) * x3_69)) + ((((x0_6 * x1_5) * x2_2) * x3_72) + (((x0_7 * x1_5) * x2_2) * x3_75) + (((x0_8 * x1_5) * x2_2) * x3_78))));
+    st(0, 15, o0_15);
+    double o0_16 = ((((((x0_6 * x1_3) * x2_0) * x3_1) + (((x0_7 * x1_3) * x2_0) * x3_4) + (((x0_8 * x1_3) * x2_0) * x3_7)) + ((((x0_6 * x1_4) * x2_0) * x3_10) + (((x0_7 * x1_4) * x2_0) * x3_13) + (((x0_8 * x1_4) * x2_0) * x3_16)) + ((((x0_6 * x1_5) * x2_0) * x3_19) + (((x0_7 * x1_5) * x2_0) * x3_22) + (((x0_8 * x1_5) * x2_0) * x3_25))) + (((((x0_6 * x1_3) * x2_1) * x3_28) + (((x0_7 * x1_3) * x2_1) * x3_31) + (((x0_8 * x1_3) * x2_1) * x3_34)) + ((((x0_6 * x1_4) * x2_1) * x3_37) + (((x0_7 * x1_4) * x2_1) * x3_40) + (((x0_8 * x1_4) * x2_1) * x3_43)) + ((((x0_6 * x1_5) * x2_1) * x3_46) + (((x0_7 * x1_5) * x2_1) * x3_49) + (((x0_8 * x1_5) * x2_1) * x3_52))) + (((((x0_6 * x1_3) * x2_2) * x3_55) + (((x0_7 * x1_3) * x2_2) * x3_58) + (((x0_8 * x1_3) * x2_2) * x3_61)) + ((((x0_6 * x1_4) * x2_2) * x3_64) + (((x0_7 * x1_4) * x2_2) * x3_67) + (((x0_8 * x1_4) * x2_2) * x3_70)) + ((((x0_6 * x1_5) * x2_2) * x3_73) + (((x0_7 * x1_5) * x2_2) * x3_76) + (((x0_8 * x1_5) * x2_2) * x3_79))));
+    st(0, 16, o0_16);
+    double o0_17 = ((((((x0_6 * x1_3) * x2_0) * x3_2) + (((x0_7 * x1_3) * x2_0) * x3_5) + (((x0_8 * x1_3) * x2_0) * x3_8)) + ((((x0_6 * x1_4) * x2_0) * x3_11) + (((x0_7 * x1_4) * x2_0) * x3_14) + (((x0_8 * x1_4) * x2_0) * x3_17)) + ((((x0_6 * x1_5) * x2_0) * x3_20) + (((x0_7 * x1_5) * x2_0) * x3_23) + (((x0_8 * x1_5) * x2_0) * x3_26))) + (((((x0_6 * x1_3) * x2_1) * x3_29) + (((x0_7 * x1_3) * x2_1) * x3_32) + (((x0_8 * x1_3) * x2_1) * x3_35)) + ((((x0_6 * x1_4) * x2_1) * x3_38) + (((x0_7 * x1_4) * x2_1) * x3_41) + (((x0_8 * x1_4) * x2_1) * x3_44)) + ((((x0_6 * x1_5) * x2_1) * x3_47) + (((x0_7 * x1_5) * x2_1) * x3_50) + (((x0_8 * x1_5) * x2_1) * x3_53))) + (((((x0_6 * x1_3) * x2_2) * x3_56) + (((x0_7 * x1_3) * x2_2) * x3_59) + (((x0_8 * x1_3) * x2_2) * x3_62)) + ((((x0_6 * x1_4) * x2_2) * x3_65) + (((x0_7 * x1_4) * x2_2) * x3_68) + (((x0_8 * x1_4) * x2_2) * x3_71)) + ((((x0_6 * x1_5) * x2_2) * x3_74) + (((x0_7 * x1_5) * x2_2) * x3_77) + (((x0_8 * x1_5) * x2_2) * x3_80))));
+    st(0, 17, o0_17);
+    double o0_18 = ((((((x0_0 * x1_6) * x2_0) * x3_0) + (((x0_1 * x1_6) * x2_0) * x3_3) + (((x0_2 * x1_6) * x2_0) * x3_6)) + ((((x0_0 * x1_7) * x2_0) * x3_9) + (((x0_1 * x1_7) * x2_0) * x3_12) + (((x0_2 * x1_7) * x2_0) * x3_15)) + ((((x0_0 * x1_8) * x2_0) * x3_18) + (((x0_1 * x1_8) * x2_0) * x3_21) + (((x0_2 * x1_8) * x2_0) * x3_24))) + (((((x0_0 * x1_6) * x2_1) * x3_27) + (((x0_1 * x1_6) * x2_1) * x3_30) + (((x0_2 * x1_6) * x2_1) * x3_33)) + ((((x0_0 * x1_7) * x2_1) * x3_36) + (((x0_1 * x1_7) * x2_1) * x3_39) + (((x0_2 * x1_7) * x2_1) * x3_42)) + ((((x0_0 * x1_8) * x2_1) * x3_45) + (((x0_1 * x1_8) * x2_1) * x3_48) + (((x0_2 * x1_8) * x2_1) * x3_51))) + (((((x0_0 * x1_6) * x2_2) * x3_54) + (((x0_1 * x1_6) * x2_2) * x3_57) + (((x0_2 * x1_6) * x2_2) * x3_60)) + ((((x0_0 * x1_7) * x2_2) * x3_63) + (((x0_1 * x1_7) * x2_2) * x3_66) + (((x0_2 * x1_7) * x2_2) * x3_69)) + ((((x0_0 * x1_8) * x2_2) * x3_72) + (((x0_1 * x1_8) * x2_2) * x3_75) + (((x0_2 * x1_8) * x2_2) * x3_78))));
+    st(0, 18, o0_18);
+    double o0_19 = ((((((x0_0 * x1_6) * x2_0) * x3_1) + (((x0_1 * x1_6) * x2_0) * x3_4) + (((x0_2 * x1_6) * x2_0) * x3_7)) + ((((x0_0 * x1_7) * x2_0) * x3_10) + (((x0_1 * x1_7) * x2_0) * x3_13) + (((x0_2 * x1_7) * x2_0) * x3_16)) + ((((x0_0 * x1_8) * x2_0) * x3_19) + (((x0_1 * x1_8) * x2_0) * x3_22) + (((x0_2 * x1_8) * x2_0) * x3_25))) + (((((x0_0 * x1_6) * x2_1) * x3_28) + (((x0_1 * x1_6) * x2_1) * x3_31) + (((x0_2 * x1_6) * x2_1) * x3_34)) + ((((x0_0 * x1_7) * x2_1) * x3_37) + (((x0_1 * x1_7) * x2_1) * x3_40) + (((x0_2 * x1_7) * x2_1) * x3_43)) + ((((x0_0 * x1_8) * x2_1) * x3_46) + (((x0_1 * x1_8) * x2_1) * x3_49) + (((x0_2 * x1_8) * x2_1) * x3_52))) + (((((x0_0 * x1_6) * x2_2) * x3_55) + (((x0_1 * x1_6) * x2_2) * x3_58) + (((x0_2 * x1_6) * x2_2) * x3_61)) + ((((x0_0 * x1_7) * x2_2) * x3_64) + (((x0_1 * x1_7) * x2_2) * x3_67) + (((x0_2 * x1_7) * x2_2) * x3_70)) + ((((x0_0 * x1_8) * x2_2) * x3_73) + (((x0_1 * x1_8) * x2_2) * x3_76) + (((x0_2 * x1_8) * x2_2) * x3_79))));
+    st(0, 19, o0_19);
+    double o0_20 = ((((((x0_0 * x1_6) * x2_0) * x3_2) + (((x0_1 * x1_6) * x2_0) * x3_5) + (((x0_2 * x1_6) * x2_0) * x3_8)) + ((((x0_0 * x1_7) * x2_0) * x3_11) + (((x0_1 * x1_7) * x2_0) * x3_14) + (((x0_2 * x1_7) * x2_0) * x3_17)) + ((((x0_0 * x1_8) * x2_0) * x3_20) + (((x0_1 * x1_8) * x2_0) * x3_23) + (((x0_2 * x1_8) * x2_0) * x3_26))) + (((((x0_0 * x1_6) * x2_1) * x3_29) + (((x0_1 * x1_6) * x2_1) * x3_32) + (((x0_2 * x1_6) * x2_1) * x3_35)) + ((((x0_0 * x1_7) * x2_1) * x3_38) + (((x0_1 * x1_7) * x2_1) * x3_41) + (((x0_2 * x1_7) * x2_1) * x3_44)) + ((((x0_0 * x1_8) * x2_1) * x3_47) + (((x0_1 * x1_8) * x2_1) * x3_50) + (((x0_2 * x1_8) * x2_1) * x3_53))) + (((((x0_0 * x1_6) * x2_2) * x3_56) + (((x0_1 * x1_6) * x2_2) * x3_59) + (((x0_2 * x1_6) * x2_2) * x3_62)) + ((((x0_0 * x1_7) * x2_2) * x3_65) + (((x0_1 * x1_7) * x2_2) * x3_68) + (((x0_2 * x1_7) * x2_2) * x3_71)) + ((((x0_0 * x1_8) * x2_2) * x3_74) + (((x0_1 * x1_8) * x2_2) * x3_77) + (((x0_2 * x1_8) * x2_2) * x3_80))));
+    st(0, 20, o0_20);
+    double o0_21 = ((((((x0_3 * x1_6) * x2_0) * x3_0) + (((x0_4 * x1_6) * x2_0) * x3_3) + (((x0_5 * x1_6) * x2_0) * x3_6)) + ((((x0_3 * x1_7) * x2_0) * x3_9) + (((x0_4 * x1_7) * x2_0) * x3_12) + (((x0_5 * x1_7) * x2_0) * x3_15)) + ((((x0_3 * x1_8) * x2_0) * x3_18) + (((x0_4 * x1_8) * x2_0) * x3_21) + (((x0_5 * x1_8) * x2_0) * x3_24))) + (((((x0_3 * x1_6) * x2_1) * x3_27) + (((x0_4 * x1_6) * x2_1) * x3_30) + (((x0_5 * x1_6) * x2_1) * x3_33)) + ((((x0_3 * x1_7) * x2_1) * x3_36) + (((x0_4 * x1_7) * x2_1) * x3_39) + (((x0_5 * x1_7) * x2_1) * x3_42)) + ((((x0_3 * x1_8) * x2_1) * x3_45) + (((x0_4 * x1_8) * x2_1) * x3_48) + (((x0_5 * x1_8) * x2_1) * x3_51))) + (((((x0_3 * x1_6) * x2_2) * x3_54) + (((x0_4 * x1_6) * x2_2) * x3_57) + (((x0_5 * x1_6) * x2_2) * x3_60)) + ((((x0_3 * x1_7) * x2_2) * x3_63) + (((x0_4 * x1_7) * x2_2) * x3_66) + (((x0_5 * x1_7) * x2_2) * x3_69)) + ((((x0_3 * x1_8) * x2_2) * x3_72) + (((x0_4 * x1_8) * x2_2) * x3_75) + (((x0_5 * x1_8) * x2_2) * x3_78))));
+    st(0, 21, o0_21);
+    double o0_22 = ((((((x0_3 * x1_6) * x2_0) * x3_1) + (((x0_4 * x1_6) * x2_0) * x3_4) + (((x0_5 * x1_6) * x2_0) * x3_7)) + ((((x0_3 * x1_7) * x2_0) * x3_10) + (((x0_4 * x1_7) * x2_0) * x3_13) + (((x0_5 * x1_7) * x2_0) * x3_16)) + ((((x0_3 * x1_8) * x2_0) * x3_19) + (((x0_4 * x1_8) * x2_0) * x3_22) + (((x0_5 * x1_8) * x2_0) * x3_25))) + (((((x0_3 * x1_6) * x2_1) * x3_28) + (((x0_4 * x1_6) * x2_1) * x3_31) + (((x0_5 * x1_6) * x2_1) * x3_34)) + ((((x0_3 * x1_7) * x2_1) * x3_37) + (((x0_4 * x1_7) * x2_1) * x3_40) + (((x0_5 * x1_7) * x2_1) * x3_43)) + ((((x0_3 * x1_8) * x2_1) * x3_46) + (((x0_4 * x1_8) * x2_1) * x3_49) + (((x0_5 * x1_8) * x2_1) * x3_52))) + (((((x0_3 * x1_6) * x2_2) * x3_55) + (((x0_4 * x1_6) * x2_2) * x3_58) + (((x0_5 * x1_6) * x2_2) * x3_61)) + ((((x0_3 * x1_7) * x2_2) * x3_64) + (((x0_4 * x1_7) * x2_2) * x3_67) + (((x0_5 * x1_7) * x2_2) * x3_70)) + ((((x0_3 * x1_8) * x2_2) * x3_73) + (((x0_4 * x1_8) * x2_2) * x3_76) + (((x0_5 * x1_8) * x2_2) * x3_79))));
+    st(0, 22, o0_22);
+    double o0_23 = ((((((x0_3 * x1_6) * x2_0) * x3_2) + (((x0_4 * x1_6) * x2_0) * x3_5) + (((x0_5 * x1_6) * x2_0) * x3_8)) + ((((x0_3 * x1_7) * x2_0) * x3_11) + (((x0_4 * x1_7) * x2_0) * x3_14) + (((x0_5 * x1_7) * x2_0) * x3_17)) + ((((x0_3 * x1_8) * x2_0) * x3_20) + (((x0_4 * x1_8) * x2_0) * x3_23) + (((x0_5 * x1_8) * x2_0) * x3_26))) + (((((x0_3 * x1_6) * x2_1) * x3_29) + (((x0_4 * x1_6) * x2_1) * x3_32) + (((x0_5 * x1_6) * x2_1) * x3_35)) + ((((x0_3 * x1_7) * x2_1) * x3_38) + (((x0_4 * x1_7) * x2_1) * x3_41) + (((x0_5 * x1_7) * x2_1) * x3_44)) + ((((x0_3 * x1_8) * x2_1) * x3_47) + (((x0_4 * x1_8) * x2_1) * x3_50) + (((x0_5 * x1_8) * x2_1) * x3_53))) + (((((x0_3 * x1_6) * x2_2) * x3_56) + (((x0_4 * x1_6) * x2_2) * x3_59) + (((x0_5 * x1_6) * x2_2) * x3_62)) + ((((x0_3 * x1_7) * x2_2) * x3_65) + (((x0_4 * x1_7) * x2_2) * x3_68) + (((x0_5 * x1_7) * x2_2) * x3_71)) + ((((x0_3 * x1_8) * x2_2) * x3_74) + (((x0_4 * x1_8) * x2_2) * x3_77) + (((x0_5 * x1_8) * x2_2) * x3_80))));
+    st(0, 23, o0_23);
+    double o0_24 = ((((((x0_6 * x1_6) * x2_0) * x3_0) + (((x0_7 * x1_6) * x2_0) * x3_3) + (((x0_8 * x1_6) * x2_0) * x3_6)) + ((((x0_6 * x1_7) * x2_0) * x3_9) + (((x0_7 * x1_7) * x2_0) * x3_12) + (((x0_8 * x1_7) * x2_0) * x3_15)) + ((((x0_6 * x1_8) * x2_0) * x3_18) + (((x0_7 * x1_8) * x2_0) * x3_21) + (((x0_8 * x1_8) * x2_0) * x3_24))) + (((((x0_6 * x1_6) * x2_1) * x3_27) + (((x0_7 * x1_6) * x2_1) * x3_30) + (((x0_8 * x1_6) * x2_1) * x3_33)) + ((((x0_6 * x1_7) * x2_1) * x3_36) + (((x0_7 * x1_7) * x2_1) * x3_39) + (((x0_8 * x1_7) * x2_1) * x3_42)) + ((((x0_6 * x1_8) * x2_1) * x3_45) + (((x0_7 * x1_8) * x2_1) * x3_48) + (((x0_8 * x1_8) * x2_1) * x3_51))) + (((((x0_6 * x1_6) * x2_2) * x3_54) + (((x0_7 * x1_6) * x2_2) * x3_57) + (((x0_8 * x1_6) * x2_2) * x3_60)) + ((((x0_6 * x1_7) * x2_2) * x3_63) + (((x0_7 * x1_7) * x2_2) * x3_66) + (((x0_8 * x1_7) * x2_2) * x3_69)) + ((((x0_6 * x1_8) * x2_2) * x3_72) + (((x0_7 * x1_8) * x2_2) * x3_75) + (((x0_8 * x1_8) * x2_2) * x3_78))));
+    st(0, 24, o0_24);
+    double o0_25 = ((((((x0_6 * x1_6) * x2_0) * x3_1) + (((x0_7 * x1_6) * x2_0) * x3_4) + (((x0_8 * x1_6) * x2_0) * x3_7)) + ((((x0_6 * x1_7) * x2_0) * x3_10) + (((x0_7 * x1_7) * x2_0) * x3_13) + (((x0_8 * x1_7) * x2_0) * x3_16)) + ((((x0_6 * x1_8) * x2_0) * x3_19) + (((x0_7 * x1_8) * x2_0) * x3_22) + (((x0_8 * x1_8) * x2_0) * x3_25))) + (((((x0_6 * x1_6) * x2_1) * x3_28) + (((x0_7 * x1_6) * x2_1) * x3_31) + (((x0_8 * x1_6) * x2_1) * x3_34)) + ((((x0_6 * x1_7) * x2_1) * x3_37) + (((x0_7 * x1_7) * x2_1) * x3_40) + (((x0_8 * x1_7) * x2_1) * x3_43)) + ((((x0_6 * x1_8) * x2_1) * x3_46) + (((x0_7 * x1_8) * x2_1) * x3_49) + (((x0_8 * x1_8) * x2_1) * x3_52))) + (((((x0_6 * x1_6) * x2_2) * x3_55) + (((x0_7 * x1_6) * x2_2) * x3_58) + (((x0_8 * x1_6) * x2_2) * x3_61)) + ((((x0_6 * x1_7) * x2_2) * x3_64) + (((x0_7 * x1_7) * x2_2) * x3_67) + (((x0_8 * x1_7) * x2_2) * x3_70)) + ((((x0_6 * x1_8) * x2_2) * x3_73) + (((x0_7 * x1_8) * x2_2) * x3_76) + (((x0_8 * x1_8) * x2_2) * x3_79))));
+    st(0, 25, o0_25);
+    double o0_26 = ((((((x0_6 * x1_6) * x2_0) * x3_2) + (((x0_7 * x1_6) * x2_0) * x3_5) + (((x0_8 * x1_6) * x2_0) * x3_8)) + ((((x0_6 * x1_7) * x2_0) * x3_11) + (((x0_7 * x1_7) * x2_0) * x3_14) + (((x0_8 * x1_7) * x2_0) * x3_17)) + ((((x0_6 * x1_8) * x2_0) * x3_20) + (((x0_7 * x1_8) * x2_0) * x3_23) + (((x0_8 * x1_8) * x2_0) * x3_26))) + (((((x0_6 * x1_6) * x2_1) * x3_29) + (((x0_7 * x1_6) * x2_1) * x3_32) + (((x0_8 * x1_6) * x2_1) * x3_35)) + ((((x0_6 * x1_7) * x2_1) * x3_38) + (((x0_7 * x1_7) * x2_1) * x3_41) + (((x0_8 * x1_7) * x2_1) * x3_44)) + ((((x0_6 * x1_8) * x2_1) * x3_47) + (((x0_7 * x1_8) * x2_1) * x3_50) + (((x0_8 * x1_8) * x2_1) * x3_53))) + (((((x0_6 * x1_6) * x2_2) * x3_56) + (((x0_7 * x1_6) * x2_2) * x3_59) + (((x0_8 * x1_6) * x2_2) * x3_62)) + ((((x0_6 * x1_7) * x2_2) * x3_65) + (((x0_7 * x1_7) * x2_2) * x3_68) + (((x0_8 * x1_7) * x2_2) * x3_71)) + ((((x0_6 * x1_8) * x2_2) * x3_74) + (((x0_7 * x1_8) * x2_2) * x3_77) + (((x0_8 * x1_8) * x2_2) * x3_80))));
+    st(0, 26, o0_26);
+    double o0_27 = ((((((x0_0 * x1_0) * x2_3) * x3_0) + (((x0_1 * x1_0) * x2_3) * x3_3) + (((x0_2 * x1_0) * x2_3) * x3_6)) + ((((x0_0 * x1_1) * x2_3) * x3_9) + (((x0_1 * x1_1) * x2_3) * x3_12) + (((x0_2 * x1_1) * x2_3) * x3_15)) + ((((x0_0 * x1_2) * x2_3) * x3_18) + (((x0_1 * x1_2) * x2_3) * x3_21) + (((x0_2 * x1_2) * x2_3) * x3_24))) + (((((x0_0 * x1_0) * x2_4) * x3_27) + (((x0_1 * x1_0) * x2_4) * x3_30) + (((x0_2 * x1_0) * x2_4) * x3_33)) + ((((x0_0 * x1_1) * x2_4) * x3_36) + (((x0_1 * x1_1) * x2_4) * x3_39) + (((x0_2 * x1_1) * x2_4) * x3_42)) + ((((x0_0 * x1_2) * x2_4) * x3_45) + (((x0_1 * x1_2) * x2_4) * x3_48) + (((x0_2 * x1_2) * x2_4) * x3_51))) + (((((x0_0 * x1_0) * x2_5) * x3_54) + (((x0_1 * x1_0) * x2_5) * x3_57) + (((x0_2 * x1_0) * x2_5) * x3_60)) + ((((x0_0 * x1_1) * x2_5) * x3_63) + (((x0_1 * x1_1) * x2_5) * x3_66) + (((x0_2 * x1_1) * x2_5) * x3_69)) + ((((x0_0 * x1_2) * x2_5) * x3_72) + (((x0_1 * x1_2) * x2_5) * x3_75) + (((x0_2 * x1_2) * x2_5) * x3_78))));
+    st(0, 27, o0_27);
+    double o0_28 = ((((((x0_0 * x1_0) * x2_3) * x3_1) + (((x0_1 * x1_0) * x2_3) * x3_4) + (((x0_2 * x1_0) * x2_3) * x3_7)) + ((((x0_0 * x1_1) * x2_3) * x3_10) + (((x0_1 * x1_1) * x2_3) * x3_13) + (((x0_2 * x1_1) * x2_3) * x3_16)) + ((((x0_0 * x1_2) * x2_3) * x3_19) + (((x0_1 * x1_2) * x2_3) * x3_22) + (((x0_2 * x1_2) * x2_3) * x3_25))) + (((((x0_0 * x1_0) * x2_4) * x3_28) + (((x0_1 * x1_0) * x2_4) * x3_31) + (((x0_2 * x1_0) * x2_4) * x3_34)) + ((((x0_0 * x1_1) * x2_4) * x3_37) + (((x0_1 * x1_1) * x2_4) * x3_40) + (((x0_2 * x1_1) * x2_4) * x3_43)) + ((((x0_0 * x1_2) * x2_4) * x3_46) + (((x0_1 * x1_2) * x2_4) * x3_49) + (((x0_2 * x1_2) * x2_4) * x3_52))) + (((((x0_0 * x1_0) * x2_5) * x3_55) + (((x0_1 * x1_0) * x2_5) * x3_58) + (((x0_2 * x1_0) * x2_5) * x3_61)) + ((((x0_0 * x1_1) * x2_5) * x3_64) + (((x0_1 * x1_1) * x2_5) * x3_67) + (((x0_2 * x1_1) * x2_5) * x3_70)) + ((((x0_0 * x1_2) * x2_5) * x3_73) + (((x0_1 * x1_2) * x2_5) * x3_76) + (((x0_2 * x1_2) * x2_5) * x3_79))));
+    st(0, 28, o0_28);
+    double o0_29 = ((((((x0_0 * x1_0) * x2_3) * x3_2) + (((x0_1 * x1_0) * x2_3) * x3_5) + (((x0_2 * x1_0) * x2_3) * x3_8)) + ((((x0_0 * x1_1) * x2_3) * x3_11) + (((x0_1 * x1_1) * x2_3) * x3_14) + (((x0_2 * x1_1) * x2_3) * x3_17)) + ((((x0_0 * x1_2) * x2_3) * x3_20) + (((x0_1 * x1_2) * x2_3) * x3_23) + (((x0_2 * x1_2) * x2_3) * x3_26))) + (((((x0_0 * x1_0) * x2_4) * x3_29) + (((x0_1 * x1_0) * x2_4) * x3_32) + (((x0_2 * x1_0) * x2_4) * x3_35)) + ((((x0_0 * x1_1) * x2_4) * x3_38) + (((x0_1 * x1_1) * x2_4) * x3_41) + (((x0_2 * x1_1) * x2_4) * x3_44)) + ((((x0_0 * x1_2) * x2_4) * x3_47) + (((x0_1 * x1_2) * x2_4) * x3_50) + (((x0_2 * x1_2) * x2_4) * x3_53))) + (((((x0_0 * x1_0) * x2_5) * x3_56) + (((x0_1 * x1_0) * x2_5) * x3_59) + (((x0_2 * x1_0) * x2_5) * x3_62)) + ((((x0_0 * x1_1) * x2_5) * x3_65) + (((x0_1 * x1_1) * x2_5) * x3_68) + (((x0_2 * x1_1) * x2_5) * x3_71)) + ((((x0_0 * x1_2) * x2_5) * x3_74) + (((x0_1 * x1_2) * x2_5) * x3_77) + (((x0_2 * x1_2) * x2_5) * x3_80))));
+    st(0, 29, o0_29);
+    double o0_30 = ((((((x0_3 * x1_0) * x2_3) * x3_0) + (((x0_4 * x1_0) * x2_3) * x3_3) + (((x0_5 * x1_0) * x2_3) * x3_6)) + ((((x0_3 * x1_1) * x2_3) * x3_9) + (((x0_4 * x1_1) * x2_3) * x3_12) + (((x0_5 * x1_1) * x2_3) * x3_15)) + ((((x0_3 * x1_2) * x2_3) * x3_18) + (((x0_4 * x1_2) * x2_3) * x3_21) + (((x0_5 * x1_2) * x2_3) * x3_24))) + (((((x0_3 * x1_0) * x2_4) * x3_27) + (((x0_4 * x1_0) * x2_4) * x3_30) + (((x0_5 * x1_0) * x2_4) * x3_33)) + ((((x0_3 * x1_1) * x2_4) * x3_36) + (((x0_4 * x1_1) * x2_4) * x3_39) + (((x0_5 * x1_1) * x2_4) * x3_42)) + ((((x0_3 * x1_2) * x2_4) * x3_45) + (((x0_4 * x1_2) * x2_4) * x3_48) + (((x0_5 * x1_2) * x2_4) * x3_51))) + (((((x0_3 * x1_0) * x2_5) * x3_54) + (((x0_4 * x1_0) * x2_5) * x3_57) + (((x0_5 * x1_0) * x2_5) * x3_60)) + ((((x0_3 * x1_1) * x2_5) * x3_63) + (((x0_4 * x1_1) * x2_5) * x3_66) + (((x0_5 * x1_1) * x2_5) * x3_69)) + ((((x0_3 * x1_2) * x2_5) * x3_72) + (((x0_4 * x1_2) * x2_5) * x3_75) + (((x0_5 * x1_2) * x2_5) * x3_78))));
+    st(0, 30, o0_30);
+    double o0_31 = ((((((x0_3 * x1_0) * x2_3) * x3_1) + (((x0_4 * x1_0) * x2_3) * x3_4) + (((x0_5 * x1_0) * x2_3) * x3_7)) + ((((x0_3 * x1_1) * x2_3) * x3_10) + (((x0_4 * x1_1) * x2_3) * x3_13) + (((x0_5 * x1_1) * x2_3) * x3_16)) + ((((x0_3 * x1_2) * x2_3) * x3_19) + (((x0_4 * x1_2) * x2_3) * x3_22) + (((x0_5 * x1_2) * x2_3) * x3_25))) + (((((x0_3 * x1_0) * x2_4) * x3_28) + (((x0_4 * x1_0) * x2_4) * x3_31) + (((x0_5 * x1_0) * x2_4) * x3_34)) + ((((x0_3 * x1_1) * x2_4) * x3_37) + (((x0_4 * x1_1) * x2_4) * x3_40) + (((x0_5 * x1_1) * x2_4) * x3_43)) + ((((x0_3 * x1_2) * x2_4) * x3_46) + (((x0_4 * x1_2) * x2_4) * x3_49) + (((x0_5 * x1_2) * x2_4) * x3_52))) + (((((x0_3 * x1_0) * x2_5) * x3_55) + (((x0_4 * x1_0) * x2_5) * x3_58) + (((x0_5 * x1_0) * x2_5) * x3_61)) + ((((x0_3 * x1_1) * x2_5) * x3_64) + (((x0_4 * x1_1) * x2_5) * x3_67) + (((x0_5 * x1_1) * x2_5) * x3_70)) + ((((x0_3 * x1_2) * x2_5) * x3_73) + (((x0_4 * x1_2) * x2_5) * x3_76) + (((x0_5 * x1_2) * x2_5) * x3_79))));
+    st(0, 31, o0_31);
+    double o0_32 = ((((((x0_3 * x1_0) * x2_3) * x3_2) + (((x0_4 * x1_0) * x2_3) * x3_5) + (((x0_5 * x1_0) * x2_3) * x3_8)) + ((((x0_3 * x1_1) * x2_3) * x3_11) + (((x0_4 * x1_1) * x2_3) * x3_14) + (((x0_5 * x1_1) * x2_3) * x3_17)) + ((((x0_3 * x1_2) * x2_3) * x3_20) + (((x0_4 * x1_2) * x2_3) * x3_23) + (((x0_5 * x1_2) * x2_3) * x3_26))) + (((((x0_3 * x1_0) * x2_4) * x3_29) + (((x0_4 * x1_0) * x2_4) * x3_32) + (((x0_5 * x1_0) * x2_4) * x3_35)) + ((((x0_3 * x1_1) * x2_4) * x3_38) + (((x0_4 * x1_1) * x2_4) * x3_41) + (((x0_5 * x1_1) * x2_4) * x3_44)) + ((((x0_3 * x1_2) * x2_4) * x3_47) + (((x0_4 * x1_2) * x2_4) * x3_50) + (((x0_5 * x1_2) * x2_4) * x3_53))) + (((((x0_3 * x1_0) * x2_5) * x3_56) + (((x0_4 * x1_0) * x2_5) * x3_59) + (((x0_5 * x1_0) * x2_5) * x3_62)) + ((((x0_3 * x1_1) * x2_5) * x3_65) + (((x0_4 * x1_1) * x2_5) * x3_68) + (((x0_5 * x1_1) * x2_5) * x3_71)) + ((((x0_3 * x1_2) * x2_5) * x3_74) + (((x0_4 * x1_2) * x2_5) * x3_77) + (((x0_5 * x1_2) * x2_5) * x3_80))));
+    st(0, 32, o0_32);
+    double o0_33 = ((((((x0_6 * x1_0) * x2_3) * x3_0) + (((x0_7 * x1_0) * x2_3) * x3_3) + (((x0_8 * x1_0) * x2_3) * x3_6)) + ((((x0_6 * x1_1) * x2_3) * x3_9) + (((x0_7 * x1_1) * x2_3) * x3_12) + (((x0_8 * x1_1) * x2_3) * x3_15)) + ((((x0_6 * x1_2) * x2_3) * x3_18) + (((x0_7 * x1_2) * x2_3) * x3_21) + (((x0_8 * x1_2) * x2_3) * x3_24))) + (((((x0_6 * x1_0) * x2_4) * x3_27) + (((x0_7 * x1_0) * x2_4) * x3_30) + (((x0_8 * x1_0) * x2_4) * x3_33)) + ((((x0_6 * x1_1) * x2_4) * x3_36) + (((x0_7 * x1_1) * x2_4) * x3_39) + (((x0_8 * x1_1) * x2_4) * x3_42)) + ((((x0_6 * x1_2) * x2_4) * x3_45) + (((x0_7 * x1_2) * x2_4) * x3_48) + (((x0_8 * x1_2) * x2_4) * x3_51))) + (((((x0_6 * x1_0) * x2_5) * x3_54) + (((x0_7 * x1_0) * x2_5) * x3_57) + (((x0_8 * x1_0) * x2_5) * x3_60)) + ((((x0_6 * x1_1) * x2_5) * x3_63) + (((x0_7 * x1_1) * x2_5) * x3_66) + (((x0_8 * x1_1) * x2_5) * x3_69)) + ((((x0_6 * x1_2) * x2_5) * x3_72) + (((x0_7 * x1_2) * x2_5) * x3_75) + (((x0_8 * x1_2) * x2_5) * x3_78))));
+    st(0, 33, o0_33);
+    double o0_34 = ((((((x0_6 * x1_0) * x2_3) * x3_1) + (((x0_7 * x1_0) * x2_3) * x3_4) + (((x0_8 * x1_0) * x2_3) * x3_7)) + ((((x0_6 * x1_1) * x2_3) * x3_10) + (((x0_7 * x1_1) * x2_3) * x3_13) + (((x0_8 * x1_1) * x2_3) * x3_16)) + ((((x0_6 * x1_2) * x2_3) * x3_19) + (((x0_7 * x1_2) * x2_3) * x3_22) + (((x0_8 * x1_2) * x2_3) * x3_25))) + (((((x0_6 * x1_0) * x2_4) * x3_28) + (((x0_7 * x1_0) * x2_4) * x3_31) + (((x0_8 * x1_0) * x2_4) * x3_34)) + ((((x0_6 * x1_1) * x2_4) * x3_37) + (((x0_7 * x1_1) * x2_4) * x3_40) + (((x0_8 * x1_1) * x2_4) * x3_43)) + ((((x0_6 * x1_2) * x2_4) * x3_46) + (((x0_7 * x1_2) * x2_4) * x3_49) + (((x0_8 * x1_2) * x2_4) * x3_52))) + (((((x0_6 * x1_0) * x2_5) * x3_55) + (((x0_7 * x1_0) * x2_5) * x3_58) + (((x0_8 * x1_0) * x2_5) * x3_61)) + ((((x0_6 * x1_1) * x2_5) * x3_64) + (((x0_7 * x1_1) * x2_5) * x3_67) + (((x0_8 * x1_1) * x2_5) * x3_70)) + ((((x0_6 * x1_2) * x2_5) * x3_73) + (((x0_7 * x1_2) * x2_5) * x3_76) + (((x0_8 * x1_2) * x2_5) * x3_79))));
+    st(0, 34, o0_34);
+    double o0_35 = ((((((x0_6 * x1_0) * x2_3) * x3_2) + (((x0_7 * x1_0) * x2_3) * x3_5) + (((x0_8 * x1_0) * x2_3) * x3_8)) + ((((x0_6 * x1_1) * x2_3) * x3_11) + (((x0_7 * x1_1) * x2_3) * x3_14) + (((x0_8 * x1_1) * x2_3) * x3_17)) + ((((x0_6 * x1_2) * x2_3) * x3_20) + (((x0_7 * x1_2) * x2_3) * x3_23) + (((x0_8 * x1_2) * x2_3) * x3_26))) + (((((x0_6 * x1_0) * x2_4) * x3_29) + (((x0_7 * x1_0) * x2_4) * x3_32) + (((x0_8 * x1_0) * x2_4) * x3_35)) + ((((x0_6 * x1_1) * x2_4) * x3_38) + (((x0_7 * x1_1) * x2_4) * x3_41) + (((x0_8 * x1_1) * x2_4) * x3_44)) + ((((x0_6 * x1_2) * x2_4) * x3_47) + (((x0_7 * x1_2) * x2_4) * x3_50) + (((x0_8 * x1_2) * x2_4) * x3_53))) + (((((x0_6 * x1_0) * x2_5) * x3_56) + (((x0_7 * x1_0) * x2_5) * x3_59) + (((x0_8 * x1_0) * x2_5) * x3_62)) + ((((x0_6 * x1_1) * x2_5) * x3_65) + (((x0_7 * x1_1) * x2_5) * x3_68) + (((x0_8 * x1_1) * x2_5) * x3_71)) + ((((x0_6 * x1_2) * x2_5) * x3_74) + (((x0_7 * x1_2) * x2_5) * x3_77) + (((x0_8 * x1_2) * x2_5) * x3_80))));
+    st(0, 35, o0_35);
+    double o0_36 = ((((((x0_0 * x1_3) * x2_3) * x3_0) + (((x0_1 * x1_3) * x2_3) * x3_3) + (((x0_2 * x1_3) * x2_3) * x3_6)) + ((((x0_0 * x1_4) * x2_3) * x3_9) + (((x0_1 * x1_4) * x2_3) * x3_12) + (((x0_2 * x1_4) * x2_3) * x3_15)) + ((((x0_0 * x1_5) * x2_3) * x3_18) + (((x0_1 * x1_5) * x2_3) * x3_21) + (((x0_2 * x1_5) * x2_3) * x3_24))) + (((((x0_0 * x1_3) * x2_4) * x3_27) + (((x0_1 * x1_3) * x2_4) * x3_30) + (((x0_2 * x1_3) * x2_4) * x3_33)) + ((((x0_0 * x1_4) * x2_4) * x3_36) + (((x0_1 * x1_4) * x2_4) * x3_39) + (((x0_2 * x1_4) * x2_4) * x3_42)) + ((((x0_0 * x1_5) * x2_4) * x3_45) + (((x0_1 * x1_5) * x2_4) * x3_48) + (((x0_2 * x1_5) * x2_4) * x3_51))) + (((((x0_0 * x1_3) * x2_5) * x3_54) + (((x0_1 * x1_3) * x2_5) * x3_57) + (((x0_2 * x1_3) * x2_5) * x3_60)) + ((((x0_0 * x1_4) * x2_5) * x3_63) + (((x0_1 * x1_4) * x2_5) * x3_66) + (((x0_2 * x1_4) * x2_5) * x3_69)) + ((((x0_0 * x1_5) * x2_5) * x3_72) + (((x0_1 * x1_5) * x2_5) * x3_75) + (((x0_2 * x1_5) * x2_5) * x3_78))));
+    st(0, 36, o0_36);
+    double o0_37 = ((((((x0_0 * x1_3) * x2_3) * x3_1) + (((x0_1 * x1_3) * x2_3) * x3_4) + (((x0_2 * x1_3) * x2_3) * x3_7)) + ((((x0_0 * x1_4) * x2_3) * x3_10) + (((x0_1 * x1_4) * x2_3) * x3_13) + (((x0_2 * x1_4) * x2_3) * x3_16)) + ((((x0_0 * x1_5) * x2_3) * x3_19) + (((x0_1 * x1_5) * x2_3) * x3_22) + (((x0_2 * x1_5) * x2_3) * x3_25))) + (((((x0_0 * x1_3) * x2_4) * x3_28) + (((x0_1 * x1_3) * x2_4) * x3_31) + (((x0_2 * x1_3) * x2_4) * x3_34)) + ((((x0_0 * x1_4) * x2_4) * x3_37) + (((x0_1 * x1_4) * x2_4) * x3_40) + (((x0_2 * x1_4) * x2_4) * x3_43)) + ((((x0_0 * x1_5) * x2_4) * x3_46) + (((x0_1 * x1_5) * x2_4) * x3_49) + (((x0_2 * x1_5) * x2_4) * x3_52))) + (((((x0_0 * x1_3) * x2_5) * x3_55) + (((x0_1 * x1_3) * x2_5) * x3_58) + (((x0_2 * x1_3) * x2_5) * x3_61)) + ((((x0_0 * x1_4) * x2_5) * x3_64) + (((x0_1 * x1_4) * x2_5) * x3_67) + (((x0_2 * x1_4) * x2_5) * x3_70)) + ((((x0_0 * x1_5) * x2_5) * x3_73) + (((x0_1 * x1_5) * x2_5) * x3_76) + (((x0_2 * x1_5) * x2_5) * x3_79))));
+    st(0, 37, o0_37);
+    double o0_38 = ((((((x0_0 * x1_3) * x2_3) * x3_2) + (((x0_1 * x1_3) * x2_3) * x3_5) + (((x0_2 * x1_3) * x2_3) * x3_8)) + ((((x0_0 * x1_4) * x2_3) * x3_11) + (((x0_1 * x1_4) * x2_3) * x3_14) + (((x0_2 * x1_4) * x2_3) * x3_17)) + ((((x0_0 * x1_5) * x2_3) * x3_20) + (((x0_1 * x1_5) * x2_3) * x3_23) + (((x0_2 * x1_5) * x2_3) * x3_26))) + (((((x0_0 * x1_3) * x2_4) * x3_29) + (((x0_1 * x1_3) * x2_4) * x3_32) + (((x0_2 * x1_3) * x2_4) * x3_35)) + ((((x0_0 * x1_4) * x2_4) * x3_38) + (((x0_1 * x1_4) * x2_4) * x3_41) + (((x0_2 * x1_4) * x2_4) * x3_44)) + ((((x0_0 * x1_5) * x2_4) * x3_47) + (((x0_1 * x1_5) * x2_4) * x3_50) + (((x0_2 * x1_5) * x2_4) * x3_53))) + (((((x0_0 * x1_3) * x2_5) * x3_56) + (((x0_1 * x1_3) * x2_5) * x3_59) + (((x0_2 * x1_3) * x2_5) * x3_62)) + ((((x0_0 * x1_4) * x2_5) * x3_65) + (((x0_1 * x1_4) * x2_5) * x3_68) + (((x0_2 * x1_4) * x2_5) * x3_71)) + ((((x0_0 * x1_5) * x2_5) * x3_74) + (((x0_1 * x1_5) * x2_5) * x3_77) + (((x0_2 * x1_5) * x2_5) * x3_80))));
+    st(0, 38, o0_38);
+    double o0_39 = ((((((x0_3 * x1_3) * x2_3) * x3_0) + (((x0_4 * x1_3) * x2_3) * x3_3) + (((x0_5 * x1_3) * x2_3) * x3_6)) + ((((x0_3 * x1_4) * x2_3) * x3_9) + (((x0_4 * x1_4) * x2_3) * x3_12) + (((x0_5 * x1_4) * x2_3) * x3_15)) + ((((x0_3 * x1_5) * x2_3) * x3_18) + (((x0_4 * x1_5) * x2_3) * x3_21) + (((x0_5 * x1_5) * x2_3) * x3_24))) + (((((x0_3 * x1_3) * x2_4) * x3_27) + (((x0_4 * x1_3) * x2_4) * x3_30) + (((x0_5 * x1_3) * x2_4) * x3_33)) + ((((x0_3 * x1_4) * x2_4) * x3_36) + (((x0_4 * x1_4) * x2_4) * x3_39) + (((x0_5 * x1_4) * x2_4) * x3_42)) + ((((x0_3 * x1_5) * x2_4) * x3_45) + (((x0_4 * x1_5) * x2_4) * x3_48) + (((x0_5 * x1_5) * x2_4) * x3_51))) + (((((x0_3 * x1_3) * x2_5) * x3_54) + (((x0_4 * x1_3) * x2_5) * x3_57) + (((x0_5 * x1_3) * x2_5) * x3_60)) + ((((x0_3 * x1_4) * x2_5) * x3_63) + (((x0_4 * x1_4) * x2_5) * x3_66) + (((x0_5 * x1_4) * x2_5) * x3_69)) + ((((x0_3 * x1_5) * x2_5) * x3_72) + (((x0_4 * x1_5) * x2_5) * x3_75) + (((x0_5 * x1_5) * x2_5) * x3_78))));
+    st(0, 39, o0_39);
+    double o0_40 = ((((((x0_3 * x1_3) * x2_3) * x3_1) + (((x0_4 * x1_3) * x2_3) * x3_4) + (((x0_5 * x1_3) * x2_3) * x3_7)) + ((((x0_3 * x1_4) * x2_3) * x3_10) + (((x0_4 * x1_4) * x2_3) * x3_13) + (((x0_5 * x1_4) * x2_3) * x3_16)) + ((((x0_3 * x1_5) * x2_3) * x3_19) + (((x0_4 * x1_5) * x2_3) * x3_22) + (((x0_5 * x1_5) * x2_3) * x3_25))) + (((((x0_3 * x1_3) * x2_4) * x3_28) + (((x0_4 * x1_3) * x2_4) * x3_31) + (((x0_5 * x1_3) * x2_4) * x3_34)) + ((((x0_3 * x1_4) * x2_4) * x3_37) + (((x0_4 * x1_4) * x2_4) * x3_40) + (((x0_5 * x1_4) * x2_4) * x3_43)) + ((((x0_3 * x1_5) * x2_4) * x3_46) + (((x0_4 * x1_5) * x2_4) * x3_49) + (((x0_5 * x1_5) * x2_4) * x3_52))) + (((((x0_3 * x1_3) * x2_5) * x3_55) + (((x0_4 * x1_3) * x2_5) * x3_58) + (((x0_5 * x1_3) * x2_5) * x3_61)) + ((((x0_3 * x1_4) * x2_5) * x3_64) + (((x0_4 * x1_4) * x2_5) * x3_67) + (((x0_5 * x1_4) * x2_5) * x3_70)) + ((((x0_3 * x1_5) * x2_5) * x3_73) + (((x0_4 * x1_5) * x2_5) * x3_76) + (((x0_5 * x1_5) * x2_5) * x3_79))));
+    st(0, 40, o0_40);
+    double o0_41 = ((((((x0_3 * x1_3) * x2_3) * x3_2) + (((x0_4 * x1_3) * x2_3) * x3_5) + (((x0_5 * x1_3) * x2_3) * x3_8)) + ((((x0_3 * x1_4) * x2_3) * x3_11) + (((x0_4 * x1_4) * x2_3) * x3_14) + (((x0_5 * x1_4) * x2_3) * x3_17)) + ((((x0_3 * x1_5) * x2_3) * x3_20) + (((x0_4 * x1_5) * x2_3) * x3_23) + (((x0_5 * x1_5) * x2_3) * x3_26))) + (((((x0_3 * x1_3) * x2_4) * x3_29) + (((x0_4 * x1_3) * x2_4) * x3_32) + (((x0_5 * x1_3) * x2_4) * x3_35)) + ((((x0_3 * x1_4) * x2_4) * x3_38) + (((x0_4 * x1_4) * x2_4) * x3_41) + (((x0_5 * x1_4) * x2_4) * x3_44)) + ((((x0_3 * x1_5) * x2_4) * x3_47) + (((x0_4 * x1_5) * x2_4) * x3_50) + (((x0_5 * x1_5) * x2_4) * x3_53))) + (((((x0_3 * x1_3) * x2_5) * x3_56) + (((x0_4 * x1_3) * x2_5) * x3_59) + (((x0_5 * x1_3) * x2_5) * x3_62)) + ((((x0_3 * x1_4) * x2_5) * x3_65) + (((x0_4 * x1_4) * x2_5) * x3_68) + (((x0_5 * x1_4) * x2_5) * x3_71)) + ((((x0_3 * x1_5) * x2_5) * x3_74) + (((x0_4 * x1_5) * x2_5) * x3_77) + (((x0_5 * x1_5) * x2_5) * x3_80))));
+    st(0, 41, o0_41);
+    double o0_42 = ((((((x0_6 * x1_3) * x2_3) * x3_0) + (((x0_7 * x1_3) * x2_3) * x3_3) + (((x0_8 * x1_3) * x2_3) * x3_6)) + ((((x0_6 * x1_4) * x2_3) * x3_9) + (((x0_7 * x1_4) * x2_3) * x3_12) + (((x0_8 * x1_4) * x2_3) * x3_15)) + ((((x0_6 * x1_5) * x2_3) * x3_18) + (((x0_7 * x1_5) * x2_3) * x3_21) + (((x0_8 * x1_5) * x2_3) * x3_24))) + (((((x0_6 * x1_3) * x2_4) * x3_27) + (((x0_7 * x1_3) * x2_4) * x3_30) + (((x0_8 * x1_3) * x2_4) * x3_33)) + ((((x0_6 * x1_4) * x2_4) * x3_36) + (((x0_7 * x1_4) * x2_4) * x3_39) + (((x0_8 * x1_4) * x2_4) * x3_42)) + ((((x0_6 * x1_5) * x2_4) * x3_45) + (((x0_7 * x1_5) * x2_4) * x3_48) + (((x0_8 * x1_5) * x2_4) * x3_51))) + (((((x0_6 * x1_3) * x2_5) * x3_54) + (((x0_7 * x1_3) * x2_5) * x3_57) + (((x0_8 * x1_3) * x2_5) * x3_60)) + ((((x0_6 * x1_4) * x2_5) * x3_63) + (((x0_7 * x1_4) * x2_5) * x3_66) + (((x0_8 * x1_4) * x2_5) * x3_69)) + ((((x0_6 * x1_5) * x2_5) * x3_72) + (((x0_7 * x1_5) * x2_5) * x3_75) + (((x0_8 * x1_5) * x2_5) * x3_78))));
+    st(0, 42, o0_42);
+    double o0_43 = ((((((x0_6 * x1_3) * x2_3) * x3_1) + (((x0_7 * x1_3) * x2_3) * x3_4) + (((x0_8 * x1_3) * x2_3) * x3_7)) + ((((x0_6 * x1_4) * x2_3) * x3_10) + (((x0_7 * x1_4) * x2_3) * x3_13) + (((x0_8 * x1_4) * x2_3) * x3_16)) + ((((x0_6 * x1_5) * x2_3) * x3_19) + (((x0_7 * x1_5) * x2_3) * x3_22) + (((x0_8 * x1_5) * x2_3) * x3_25))) + (((((x0_6 * x1_3) * x2_4) * x3_28) + (((x0_7 * x1_3) * x2_4) * x3_31) + (((x0_8 * x1_3) * x2_4) * x3_34)) + ((((x0_6 * x1_4) * x2_4) * x3_37) + (((x0_7 * x1_4) * x2_4) * x3_40) + (((x0_8 * x1_4) * x2_4) * x3_43)) + ((((x0_6 * x1_5) * x2_4) * x3_46) + (((x0_7 * x1_5) * x2_4) * x3_49) + (((x0_8 * x1_5) * x2_4) * x3_52))) + (((((x0_6 * x1_3) * x2_5) * x3_55) + (((x0_7 * x1_3) * x2_5) * x3_58) + (((x0_8 * x1_3) * x2_5) * x3_61)) + ((((x0_6 * x1_4) * x2_5) * x3_64) + (((x0_7 * x1_4) * x2_5) * x3_67) + (((x0_8 * x1_4) * x2_5) * x3_70)) + ((((x0_6 * x1_5) * x2_5) * x3_73) + (((x0_7 * x1_5) * x2_5) * x3_76) + (((x0_8 * x1_5) * x2_5) * x3_79))));
+    st(0, 43, o0_43);
+    double o0_44 = ((((((x0_6 * x1_3) * x2_3) * x3_2) + (((x0_7 * x1_3) * x2_3) * x3_5) + (((x0_8 * x1_3) * x2_3) * x3_8)) + ((((x0_6 * x1_4) * x2_3) * x3_11) + (((x0_7 * x1_4) * x2_3) * x3_14) + (((x0_8 * x1_4) * x2_3) * x3_17)) + ((((x0_6 * x1_5) * x2_3) * x3_20) + (((x0_7 * x1_5) * x2_3) * x3_23) + (((x0_8 * x1_5) * x2_3) * x3_26))) + (((((x0_6 * x1_3) * x2_4) * x3_29) + (((x0_7 * x1_3) * x2_4) * x3_32) + (((x0_8 * x1_3) * x2_4) * x3_35)) + ((((x0_6 * x1_4) * x2_4) * x3_38) + (((x0_7 * x1_4) * x2_4) * x3_41) + (((x0_8 * x1_4) * x2_4) * x3_44)) + ((((x0_6 * x1_5) * x2_4) * x3_47) + (((x0_7 * x1_5) * x2_4) * x3_50) + (((x0_8 * x1_5) * x2_4) * x3_53))) + (((((x0_6 * x1_3) * x2_5) * x3_56) + (((x0_7 * x1_3) * x2_5) * x3_59) + (((x0_8 * x1_3) * x2_5) * x3_62)) + ((((x0_6 * x1_4) * x2_5) * x3_65) + (((x0_7 * x1_4) * x2_5) * x3_68) + (((x0_8 * x1_4) * x2_5) * x3_71)) + ((((x0_6 * x1_5) * x2_5) * x3_74) + (((x0_7 * x1_5) * x2_5) * x3_77) + (((x0_8 * x1_5) * x2_5) * x3_80))));
+    st(0, 44, o0_44);
+    double o0_45 = ((((((x0_0 * x1_6) * x2_3) * x3_0) + (((x0_1 * x1_6) * x2_3) * x3_3) + (((x0_2 * x1_6) * x2_3) * x3_6)) + ((((x0_0 * x1_7) * x2_3) * x3_9) + (((x0_1 * x1_7) * x2_3) * x3_12) + (((x0_2 * x1_7) * x2_3) * x3_15)) + ((((x0_0 * x1_8) * x2_3) * x3_18) + (((x0_1 * x1_8) * x2_3) * x3_21) + (((x0_2 * x1_8) * x2_3) * x3_24))) + (((((x0_0 * x1_6) * x2_4) * x3_27) + (((x0_1 * x1_6) * x2_4) * x3_30) + (((x0_2 * x1_6) * x2_4) * x3_33)) + ((((x0_0 * x1_7) * x2_4) * x3_36) + (((x0_1 * x1_7) * x2_4) * x3_39) + (((x0_2 * x1_7) * x2_4) * x3_42)) + ((((x0_0 * x1_8) * x2_4) * x3_45) + (((x0_1 * x1_8) * x2_4) * x3_48) + (((x0_2 * x1_8) * x2_4) * x3_51))) + (((((x0_0 * x1_6) * x2_5) * x3_54) + (((x0_1 * x1_6) * x2_5) * x3_57) + (((x0_2 * x1_6) * x2_5) * x3_60)) + ((((x0_0 * x1_7) * x2_5) * x3_63) + (((x0_1 * x1_7) * x2_5) * x3_66) + (((x0_2 * x1_7) * x2_5) * x3_69)) + ((((x0_0 * x1_8) * x2_5) * x3_72) + (((x0_1 * x1_8) * x2_5) * x3_75) + (((x0_2 * x1_8) * x2_5) * x3_78))));
+    st(0, 45, o0_45);
+    double o0_46 = ((((((x0_0 * x1_6) * x2_3) * x3_1) + (((x0_1 * x1_6) * x2_3) * x3_4) + (((x0_2 * x1_6) * x2_3) * x3_7)) + ((((x0_0 * x1_7) * x2_3) * x3_10) + (((x0_1 * x1_7) * x2_3) * x3_13) + (((x0_2 * x1_7) * x2_3) * x3_16)) + ((((x0_0 * x1_8) * x2_3) * x3_19) + (((x0_1 * x1_8) * x2_3) * x3_22) + (((x0_2 * x1_8) * x2_3) * x3_25))) + (((((x0_0 * x1_6) * x2_4) * x3_28) + (((x0_1 * x1_6) * x2_4) * x3_31) + (((x0_2 * x1_6) * x2_4) * x3_34)) + ((((x0_0 * x1_7) * x2_4) * x3_37) + (((x0_1 * x1_7) * x2_4) * x3_40) + (((x0_2 * x1_7) * x2_4) * x3_43)) + ((((x0_0 * x1_8) * x2_4) * x3_46) + (((x0_1 * x1_8) * x2_4) * x3_49) + (((x0_2 * x1_8) * x2_4) * x3_52))) + (((((x0_0 * x1_6) * x2_5) * x3_55) + (((x0_1 * x1_6) * x2_5) * x3_58) + (((x0_2 * x1_6) * x2_5) * x3_61)) + ((((x0_0 * x1_7) * x2_5) * x3_64) + (((x0_1 * x1_7) * x2_5) * x3_67) + (((x0_2 * x1_7) * x2_5) * x3_70)) + ((((x0_0 * x1_8) * x2_5) * x3_73) + (((x0_1 * x1_8) * x2_5) * x3_76) + (((x0_2 * x1_8) * x2_5) * x3_79))));
+    st(0, 46, o0_46);
+    double o0_47 = ((((((x0_0 * x1_6) * x2_3) * x3_2) + (((x0_1 * x1_6) * x2_3) * x3_5) + (((x0_2 * x1_6) * x2_3) * x3_8)) + ((((x0_0 * x1_7) * x2_3) * x3_11) + (((x0_1 * x1_7) * x2_3) * x3_14) + (((x0_2 * x1_7) * x2_3) * x3_17)) + ((((x0_0 * x1_8) * x2_3) * x3_20) + (((x0_1 * x1_8) * x2_3) * x3_23) + (((x0_2 * x1_8) * x2_3) * x3_26))) + (((((x0_0 * x1_6) * x2_4) * x3_29) + (((x0_1 * x1_6) * x2_4) * x3_32) + (((x0_2 * x1_6) * x2_4) * x3_35)) + ((((x0_0 * x1_7) * x2_4) * x3_38) + (((x0_1 * x1_7) * x2_4) * x3_41) + (((x0_2 * x1_7) * x2_4) * x3_44)) + ((((x0_0 * x1_8) * x2_4) * x3_47) + (((x0_1 * x1_8) * x2_4) * x3_50) + (((x0_2 * x1_8) * x2_4) * x3_53))) + (((((x0_0 * x1_6) * x2_5) * x3_56) + (((x0_1 * x1_6) * x2_5) * x3_59) + (((x0_2 * x1_6) * x2_5) * x3_62)) + ((((x0_0 * x1_7) * x2_5) * x3_65) + (((x0_1 * x1_7) * x2_5) * x3_68) + (((x0_2 * x1_7) * x2_5) * x3_71)) + ((((x0_0 * x1_8) * x2_5) * x3_74) + (((x0_1 * x1_8) * x2_5) * x3_77) + (((x0_2 * x1_8) * x2_5) * x3_80))));
+    st(0, 47, o0_47);
+    double o0_48 = ((((((x0_3 * x1_6) * x2_3) * x3_0) + (((x0_4 * x1_6) * x2_3) * x3_3) + (((x0_5 * x1_6) * x2_3) * x3_6)) + ((((x0_3 * x1_7) * x2_3) * x3_9) + (((x0_4 * x1_7) * x2_3) * x3_12) + (((x0_5 * x1_7) * x2_3) * x3_15)) + ((((x0_3 * x1_8) * x2_3) * x3_18) + (((x0_4 * x1_8) * x2_3) * x3_21) + (((x0_5 * x1_8) * x2_3) * x3_24))) + (((((x0_3 * x1_6) * x2_4) * x3_27) + (((x0_4 * x1_6) * x2_4) * x3_30) + (((x0_5 * x1_6) * x2_4) * x3_33)) + ((((x0_3 * x1_7) * x2_4) * x3_36) + (((x0_4 * x1_7) * x2_4) * x3_39) + (((x0_5 * x1_7) * x2_4) * x3_42)) + ((((x0_3 * x1_8) * x2_4) * x3_45) + (((x0_4 * x1_8) * x2_4) * x3_48) + (((x0_5 * x1_8) * x2_4) * x3_51))) + (((((x0_3 * x1_6) * x2_5) * x3_54) + (((x0_4 * x1_6) * x2_5) * x3_57) + (((x0_5 * x1_6) * x2_5) * x3_60)) + ((((x0_3 * x1_7) * x2_5) * x3_63) + (((x0_4 * x1_7) * x2_5) * x3_66) + (((x0_5 * x1_7) * x2_5) * x3_69)) + ((((x0_3 * x1_8) * x2_5) * x3_72) + (((x0_4 * x1_8) * x2_5) * x3_75) + (((x0_5 * x1_8) * x2_5) * x3_78))));
+    st(0, 48, o0_48);
+    double o0_49 = ((((((x0_3 * x1_6) * x2_3) * x3_1) + (((x0_4 * x1_6) * x2_3) * x3_4) + (((x0_5 * x1_6) * x2_3) * x3_7)) + ((((x0_3 * x1_7) * x2_3) * x3_10) + (((x0_4 * x1_7) * x2_3) * x3_13) + (((x0_5 * x1_7) * x2_3) * x3_16)) + ((((x0_3 * x1_8) * x2_3) * x3_19) + (((x0_4 * x1_8) * x2_3) * x3_22) + (((x0_5 * x1_8) * x2_3) * x3_25))) + (((((x0_3 * x1_6) * x2_4) * x3_28) + (((x0_4 * x1_6) * x2_4) * x3_31) + (((x0_5 * x1_6) * x2_4) * x3_34)) + ((((x0_3 * x1_7) * x2_4) * x3_37) + (((x0_4 * x1_7) * x2_4) * x3_40) + (((x0_5 * x1_7) * x2_4) * x3_43)) + ((((x0_3 * x1_8) * x2_4) * x3_46) + (((x0_4 * x1_8) * x2_4) * x3_49) + (((x0_5 * x1_8) * x2_4) * x3_52))) + (((((x0_3 * x1_6) * x2_5) * x3_55) + (((x0_4 * x1_6) * x2_5) * x3_58) + (((x0_5 * x1_6) * x2_5) * x3_61)) + ((((x0_3 * x1_7) * x2_5) * x3_64) + (((x0_4 * x1_7) * x2_5) * x3_67) + (((x0_5 * x1_7) * x2_5) * x3_70)) + ((((x0_3 * x1_8) * x2_5) * x3_73) + (((x0_4 * x1_8) * x2_5) * x3_76) + (((x0_5 * x1_8) * x2_5) * x3_79))));
+    st(0, 49, o0_49);
+    double o0_50 = ((((((x0_3 * x1_6) * x2_3) * x3_2) + (((x0_4 * x1_6) * x2_3) * x3_5) + (((x0_5 * x1_6) * x2_3) * x3_8)) + ((((x0_3 * x1_7) * x2_3) * x3_11) + (((x0_4 * x1_7) * x2_3) * x3_14) + (((x0_5 * x1_7) * x2_3) * x3_17)) + ((((x0_3 * x1_8) * x2_3) * x3_20) + (((x0_4 * x1_8) * x2_3) * x3_23) + (((x0_5 * x1_8) * x2_3) * x3_26))) + (((((x0_3 * x1_6) * x2_4) * x3_29) + (((x0_4 * x1_6) * x2_4) * x3_32) + (((x0_5 * x1_6) * x2_4) * x3_35)) + ((((x0_3 * x1_7) * x2_4) * x3_38) + (((x0_4 * x1_7) * x2_4) * x3_41) + (((x0_5 * x1_7) * x2_4) * x3_44)) + ((((x0_3 * x1_8) * x2_4) * x3_47) + (((x0_4 * x1_8) * x2_4) * x3_50) + (((x0_5 * x1_8) * x2_4) * x3_53))) + (((((x0_3 * x1_6) * x2_5) * x3_56) + (((x0_4 * x1_6) * x2_5) * x3_59) + (((x0_5 * x1_6) * x2_5) * x3_62)) + ((((x0_3 * x1_7) * x2_5) * x3_65) + (((x0_4 * x1_7) * x2_5) * x3_68) + (((x0_5 * x1_7) * x2_5) * x3_71)) + ((((x0_3 * x1_8) * x2_5) * x3_74) + (((x0_4 * x1_8) * x2_5) * x3_77) + (((x0_5 * x1_8) * x2_5) * x3_80))));
+    st(0, 50, o0_50);
+    double o0_51 = ((((((x0_6 * x1_6) * x2_3) * x3_0) + (((x0_7 * x1_6) * x2_3) * x3_3) + (((x0_8 * x1_6) * x2_3) * x3_6)) + ((((x0_6 * x1_7) * x2_3) * x3_9) + (((x0_7 * x1_7) * x2_3) * x3_12) + (((x0_8 * x1_7) * x2_3) * x3_15)) + ((((x0_6 * x1_8) * x2_3) * x3_18) + (((x0_7 * x1_8) * x2_3) * x3_21) + (((x0_8 * x1_8) * x2_3) * x3_24))) + (((((x0_6 * x1_6) * x2_4) * x3_27) + (((x0_7 * x1_6) * x2_4) * x3_30) + (((x0_8 * x1_6) * x2_4) * x3_33)) + ((((x0_6 * x1_7) * x2_4) * x3_36) + (((x0_7 * x1_7) * x2_4) * x3_39) + (((x0_8 * x1_7) * x2_4) * x3_42)) + ((((x0_6 * x1_8) * x2_4) * x3_45) + (((x0_7 * x1_8) * x2_4) * x3_48) + (((x0_8 * x1_8) * x2_4) * x3_51))) + (((((x0_6 * x1_6) * x2_5) * x3_54) + (((x0_7 * x1_6) * x2_5) * x3_57) + (((x0_8 * x1_6) * x2_5) * x3_60)) + ((((x0_6 * x1_7) * x2_5) * x3_63) + (((x0_7 * x1_7) * x2_5) * x3_66) + (((x0_8 * x1_7) * x2_5) * x3_69)) + ((((x0_6 * x1_8) * x2_5) * x3_72) + (((x0_7 * x1_8) * x2_5) * x3_75) + (((x0_8 * x1_8) * x2_5) * x3_78))));
+    st(0, 51, o0_51);
+    double o0_52 = ((((((x0_6 * x1_6) * x2_3) * x3_1) + (((x0_7 * x1_6) * x2_3) * x3_4) + (((x0_8 * x1_6) * x2_3) * x3_7)) + ((((x0_6 * x1_7) * x2_3) * x3_10) + (((x0_7 * x1_7) * x2_3) * x3_13) + (((x0_8 * x1_7) * x2_3) * x3_16)) + ((((x0_6 * x1_8) * x2_3) * x3_19) + (((x0_7 * x1_8) * x2_3) * x3_22) + (((x0_8 * x1_8) * x2_3) * x3_25))) + (((((x0_6 * x1_6) * x2_4) * x3_28) + (((x0_7 * x1_6) * x2_4) * x3_31) + (((x0_8 * x1_6) * x2_4) * x3_34)) + ((((x0_6 * x1_7) * x2_4) * x3_37) + (((x0_7 * x1_7) * x2_4) * x3_40) + (((x0_8 * x1_7) * x2_4) * x3_43)) + ((((x0_6 * x1_8) * x2_4) * x3_46) + (((x0_7 * x1_8) * x2_4) * x3_49) + (((x0_8 * x1_8) * x2_4) * x3_52))) + (((((x0_6 * x1_6) * x2_5) * x3_55) + (((x0_7 * x1_6) * x2_5) * x3_58) + (((x0_8 * x1_6) * x2_5) * x3_61)) + ((((x0_6 * x1_7) * x2_5) * x3_64) + (((x0_7 * x1_7) * x2_5) * x3_67) + (((x0_8 * x1_7) * x2_5) * x3_70)) + ((((x0_6 * x1_8) * x2_5) * x3_73) + (((x0_7 * x1_8) * x2_5) * x3_76) + (((x0_8 * x1_8) * x2_5) * x3_79))));
+    st(0, 52, o0_52);
+    double o0_53 = ((((((x0_6 * x1_6) * x2_3) * x3_2) + (((x0_7 * x1_6) * x2_3) * x3_5) + (((x0_8 * x1_6) * x2_3) * x3_8)) + ((((x0_6 * x1_7) * x2_3) * x3_11) + (((x0_7 * x1_7) * x2_3) * x3_14) + (((x0_8 * x1_7) * x2_3) * x3_17)) + ((((x0_6 * x1_8) * x2_3) * x3_20) + (((x0_7 * x1_8) * x2_3) * x3_23) + (((x0_8 * x1_8) * x2_3) * x3_26))) + (((((x0_6 * x1_6) * x2_4) * x3_29) + (((x0_7 * x1_6) * x2_4) * x3_32) + (((x0_8 * x1_6) * x2_4) * x3_35)) + ((((x0_6 * x1_7) * x2_4) * x3_38) + (((x0_7 * x1_7) * x2_4) * x3_41) + (((x0_8 * x1_7) * x2_4) * x3_44)) + ((((x0_6 * x1_8) * x2_4) * x3_47) + (((x0_7 * x1_8) * x2_4) * x3_50) + (((x0_8 * x1_8) * x2_4) * x3_53))) + (((((x0_6 * x1_6) * x2_5) * x3_56) + (((x0_7 * x1_6) * x2_5) * x3_59) + (((x0_8 * x1_6) * x2_5) * x3_62)) + ((((x0_6 * x1_7) * x2_5) * x3_65) + (((x0_7 * x1_7) * x2_5) * x3_68) + (((x0_8 * x1_7) * x2_5) * x3_71)) + ((((x0_6 * x1_8) * x2_5) * x3_74) + (((x0_7 * x1_8) * x2_5) * x3_77) + (((x0_8 * x1_8) * x2_5) * x3_80))));
+    st(0, 53, o0_53);
+    double o0_54 = ((((((x0_0 * x1_0) * x2_6) * x3_0) + (((x0_1 * x1_0) * x2_6) * x3_3) + (((x0_2 * x1_0) * x2_6) * x3_6)) + ((((x0_0 * x1_1) * x2_6) * x3_9) + (((x0_1 * x1_1) * x2_6) * x3_12) + (((x0_2 * x1_1) * x2_6) * x3_15)) + ((((x0_0 * x1_2) * x2_6) * x3_18) + (((x0_1 * x1_2) * x2_6) * x3_21) + (((x0_2 * x1_2) * x2_6) * x3_24))) + (((((x0_0 * x1_0) * x2_7) * x3_27) + (((x0_1 * x1_0) * x2_7) * x3_30) + (((x0_2 * x1_0) * x2_7) * x3_33)) + ((((x0_0 * x1_1) * x2_7) * x3_36) + (((x0_1 * x1_1) * x2_7) * x3_39) + (((x0_2 * x1_1) * x2_7) * x3_42)) + ((((x0_0 * x1_2) * x2_7) * x3_45) + (((x0_1 * x1_2) * x2_7) * x3_48) + (((x0_2 * x1_2) * x2_7) * x3_51))) + (((((x0_0 * x1_0) * x2_8) * x3_54) + (((x0_1 * x1_0) * x2_8) * x3_57) + (((x0_2 * x1_0) * x2_8) * x3_60)) + ((((x0_0 * x1_1) * x2_8) * x3_63) + (((x0_1 * x1_1) * x2_8) * x3_66) + (((x0_2 * x1_1) * x2_8) * x3_69)) + ((((x0_0 * x1_2) * x2_8) * x3_72) + (((x0_1 * x1_2) * x2_8) * x3_75) + (((x0_2 * x1_2) * x2_8) * x3_78))));
+    st(0, 54, o0_54);
+    double o0_55 = ((((((x0_0 * x1_0) * x2_6) * x3_1) + (((x0_1 * x1_0) * x2_6) * x3_4) + (((x0_2 * x1_0) * x2_6) * x3_7)) + ((((x0_0 * x1_1) * x2_6) * x3_10) + (((x0_1 * x1_1) * x2_6) * x3_13) + (((x0_2 * x1_1) * x2_6) * x3_16)) + ((((x0_0 * x1_2) * x2_6) * x3_19) + (((x0_1 * x1_2) * x2_6) * x3_22) + (((x0_2 * x1_2) * x2_6) * x3_25))) + (((((x0_0 * x1_0) * x2_7) * x3_28) + (((x0_1 * x1_0) * x2_7) * x3_31) + (((x0_2 * x1_0) * x2_7) * x3_34)) + ((((x0_0 * x1_1) * x2_7) * x3_37) + (((x0_1 * x1_1) * x2_7) * x3_40) + (((x0_2 * x1_1) * x2_7) * x3_43)) + ((((x0_0 * x1_2) * x2_7) * x3_46) + (((x0_1 * x1_2) * x2_7) * x3_49) + (((x0_2 * x1_2) * x2_7) * x3_52))) + (((((x0_0 * x1_0) * x2_8) * x3_55) + (((x0_1 * x1_0) * x2_8) * x3_58) + (((x0_2 * x1_0) * x2_8) * x3_61)) + ((((x0_0 * x1_1) * x2_8) * x3_64) + (((x0_1 * x1_1) * x2_8) * x3_67) + (((x0_2 * x1_1) * x2_8) * x3_70)) + ((((x0_0 * x1_2) * x2_8) * x3_73) + (((x0_1 * x1_2) * x2_8) * x3_76) + (((x0_2 * x1_2) * x2_8) * x3_79))));
+    st(0, 55, o0_55);
+    double o0_56 = ((((((x0_0 * x1_0) * x2_6) * x3_2) + (((x0_1 * x1_0) * x2_6) * x3_5) + (((x0_2 * x1_0) * x2_6) * x3_8)) + ((((x0_0 * x1_1) * x2_6) * x3_11) + (((x0_1 * x1_1) * x2_6) * x3_14) + (((x0_2 * x1_1) * x2_6) * x3_17)) + ((((x0_0 * x1_2) * x2_6) * x3_20) + (((x0_1 * x1_2) * x2_6) * x3_23) + (((x0_2 * x1_2) * x2_6) * x3_26))) + (((((x0_0 * x1_0) * x2_7) * x3_29) + (((x0_1 * x1_0) * x2_7) * x3_32) + (((x0_2 * x1_0) * x2_7) * x3_35)) + ((((x0_0 * x1_1) * x2_7) * x3_38) + (((x0_1 * x1_1) * x2_7) * x3_41) + (((x0_2 * x1_1) * x2_7) * x3_44)) + ((((x0_0 * x1_2) * x2_7) * x3_47) + (((x0_1 * x1_2) * x2_7) * x3_50) + (((x0_2 * x1_2) * x2_7) * x3_53))) + (((((x0_0 * x1_0) * x2_8) * x3_56) + (((x0_1 * x1_0) * x2_8) * x3_59) + (((x0_2 * x1_0) * x2_8) * x3_62)) + ((((x0_0 * x1_1) * x2_8) * x3_65) + (((x0_1 * x1_1) * x2_8) * x3_68) + (((x0_2 * x1_1) * x2_8) * x3_71)) + ((((x0_0 * x1_2) * x2_8) * x3_74) + (((x0_1 * x1_2) * x2_8) * x3_77) + (((x0_2 * x1_2) * x2_8) * x3_80))));
+    st(0, 56, o0_56);
+    double o0_57 = ((((((x0_3 * x1_0) * x2_6) * x3_0) + (((x0_4 * x1_0) * x2_6) * x3_3) + (((x0_5 * x1_0) * x2_6) * x3_6)) + ((((x0_3 * x1_1) * x2_6) * x3_9) + (((x0_4 * x1_1) * x2_6) * x3_12) + (((x0_5 * x1_1) * x2_6) * x3_15)) + ((((x0_3 * x1_2) * x2_6) * x3_18) + (((x0_4 * x1_2) * x2_6) * x3_21) + (((x0_5 * x1_2) * x2_6) * x3_24))) + (((((x0_3 * x1_0) * x2_7) * x3_27) + (((x0_4 * x1_0) * x2_7) * x3_30) + (((x0_5 * x1_0) * x2_7) * x3_33)) + ((((x0_3 * x1_1) * x2_7) * x3_36) + (((x0_4 * x1_1) * x2_7) * x3_39) + (((x0_5 * x1_1) * x2_7) * x3_42)) + ((((x0_3 * x1_2) * x2_7) * x3_45) + (((x0_4 * x1_2) * x2_7) * x3_48) + (((x0_5 * x1_2) * x2_7) * x3_51))) + (((((x0_3 * x1_0) * x2_8) * x3_54) + (((x0_4 * x1_0) * x2_8) * x3_57) + (((x0_5 * x1_0) * x2_8) * x3_60)) + ((((x0_3 * x1_1) * x2_8) * x3_63) + (((x0_4 * x1_1) * x2_8) * x3_66) + (((x0_5 * x1_1) * x2_8) * x3_69)) + ((((x0_3 * x1_2) * x2_8) * x3_72) + (((x0_4 * x1_2) * x2_8) * x3_75) + (((x0_5 * x1_2) * x2_8) * x3_78))));
+    st(0, 57, o0_57);
+    double o0_58 = ((((((x0_3 * x1_0) * x2_6) * x3_1) + (((x0_4 * x1_0) * x2_6) * x3_4) + (((x0_5 * x1_0) * x2_6) * x3_7)) + ((((x0_3 * x1_1) * x2_6) * x3_10) + (((x0_4 * x1_1) * x2_6) * x3_13) + (((x0_5 * x1_1) * x2_6) * x3_16)) + ((((x0_3 * x1_2) * x2_6) * x3_19) + (((x0_4 * x1_2) * x2_6) * x3_22) + (((x0_5 * x1_2) * x2_6) * x3_25))) + (((((x0_3 * x1_0) * x2_7) * x3_28) + (((x0_4 * x1_0) * x2_7) * x3_31) + (((x0_5 * x1_0) * x2_7) * x3_34)) + ((((x0_3 * x1_1) * x2_7) * x3_37) + (((x0_4 * x1_1) * x2_7) * x3_40) + (((x0_5 * x1_1) * x2_7) * x3_43)) + ((((x0_3 * x1_2) * x2_7) * x3_46) + (((x0_4 * x1_2) * x2_7) * x3_49) + (((x0_5 * x1_2) * x2_7) * x3_52))) + (((((x0_3 * x1_0) * x2_8) * x3_55) + (((x0_4 * x1_0) * x2_8) * x3_58) + (((x0_5 * x1_0) * x2_8) * x3_61)) + ((((x0_3 * x1_1) * x2_8) * x3_64) + (((x0_4 * x1_1) * x2_8) * x3_67) + (((x0_5 * x1_1) * x2_8) * x3_70)) + ((((x0_3 * x1_2) * x2_8) * x3_73) + (((x0_4 * x1_2) * x2_8) * x3_76) + (((x0_5 * x1_2) * x2_8) * x3_79))));
+    st(0, 58, o0_58);
+    double o0_59 = ((((((x0_3 * x1_0) * x2_6) * x3_2) + (((x0_4 * x1_0) * x2_6) * x3_5) + (((x0_5 * x1_0) * x2_6) * x3_8)) + ((((x0_3 * x1_1) * x2_6) * x3_11) + (((x0_4 * x1_1) * x2_6) * x3_14) + (((x0_5 * x1_1) * x2_6) * x3_17)) + ((((x0_3 * x1_2) * x2_6) * x3_20) + (((x0_4 * x1_2) * x2_6) * x3_23) + (((x0_5 * x1_2) * x2_6) * x3_26))) + (((((x0_3 * x1_0) * x2_7) * x3_29) + (((x0_4 * x1_0) * x2_7) * x3_32) + (((x0_5 * x1_0) * x2_7) * x3_35)) + ((((x0_3 * x1_1) * x2_7) * x3_38) + (((x0_4 * x1_1) * x2_7) * x3_41) + (((x0_5 * x1_1) * x2_7) * x3_44)) + ((((x0_3 * x1_2) * x2_7) * x3_47) + (((x0_4 * x1_2) * x2_7) * x3_50) + (((x0_5 * x1_2) * x2_7) * x3_53))) + (((((x0_3 * x1_0) * x2_8) * x3_56) + (((x0_4 * x1_0) * x2_8) * x3_59) + (((x0_5 * x1_0) * x2_8) * x3_62)) + ((((x0_3 * x1_1) * x2_8) * x3_65) + (((x0_4 * x1_1) * x2_8) * x3_68) + (((x0_5 * x1_1) * x2_8) * x3_71)) + ((((x0_3 * x1_2) * x2_8) * x3_74) + (((x0_4 * x1_2) * x2_8) * x3_77) + (((x0_5 * x1_2) * x2_8) * x3_80))));
+    st(0, 59, o0_59);
+    double o0_60 = ((((((x0_6 * x1_0) * x2_6) * x3_0) + (((x0_7 * x1_0) * x2_6) * x3_3) + (((x0_8 * x1_0) * x2_6) * x3_6)) + ((((x0_6 * x1_1) * x2_6) * x3_9) + (((x0_7 * x1_1) * x2_6) * x3_12) + (((x0_8 * x1_1) * x2_6) * x3_15)) + ((((x0_6 * x1_2) * x2_6) * x3_18) + (((x0_7 * x1_2) * x2_6) * x3_21) + (((x0_8 * x1_2) * x2_6) * x3_24))) + (((((x0_6 * x1_0) * x2_7) * x3_27) + (((x0_7 * x1_0) * x2_7) * x3_30) + (((x0_8 * x1_0) * x2_7) * x3_33)) + ((((x0_6 * x1_1) * x2_7) * x3_36) + (((x0_7 * x1_1) * x2_7) * x3_39) + (((x0_8 * x1_1) * x2_7) * x3_42)) + ((((x0_6 * x1_2) * x2_7) * x3_45) + (((x0_7 * x1_2) * x2_7) * x3_48) + (((x0_8 * x1_2) * x2_7) * x3_51))) + (((((x0_6 * x1_0) * x2_8) * x3_54) + (((x0_7 * x1_0) * x2_8) * x3_57) + (((x0_8 * x1_0) * x2_8) * x3_60)) + ((((x0_6 * x1_1) * x2_8) * x3_63) + (((x0_7 * x1_1) * x2_8) * x3_66) + (((x0_8 * x1_1) * x2_8) * x3_69)) + ((((x0_6 * x1_2) * x2_8) * x3_72) + (((x0_7 * x1_2) * x2_8) * x3_75) + (((x0_8 * x1_2) * x2_8) * x3_78))));
+    st(0, 60, o0_60);
+    double o0_61 = ((((((x0_6 * x1_0) * x2_6) * x3_1) + (((x0_7 * x1_0) * x2_6) * x3_4) + (((x0_8 * x1_0) * x2_6) * x3_7)) + ((((x0_6 * x1_1) * x2_6) * x3_10) + (((x0_7 * x1_1) * x2_6) * x3_13) + (((x0_8 * x1_1) * x2_6) * x3_16)) + ((((x0_6 * x1_2) * x2_6) * x3_19) + (((x0_7 * x1_2) * x2_6) * x3_22) + (((x0_8 * x1_2) * x2_6) * x3_25))) + (((((x0_6 * x1_0) * x2_7) * x3_28) + (((x0_7 * x1_0) * x2_7) * x3_31) + (((x0_8 * x1_0) * x2_7) * x3_34)) + ((((x0_6 * x1_1) * x2_7) * x3_37) + (((x0_7 * x1_1) * x2_7) * x3_40) + (((x0_8 * x1_1) * x2_7) * x3_43)) + ((((x0_6 * x1_2) * x2_7) * x3_46) + (((x0_7 * x1_2) * x2_7) * x3_49) + (((x0_8 * x1_2) * x2_7) * x3_52))) + (((((x0_6 * x1_0) * x2_8) * x3_55) + (((x0_7 * x1_0) * x2_8) * x3_58) + (((x0_8 * x1_0) * x2_8) * x3_61)) + ((((x0_6 * x1_1) * x2_8) * x3_64) + (((x0_7 * x1_1) * x2_8) * x3_67) + (((x0_8 * x1_1) * x2_8) * x3_70)) + ((((x0_6 * x1_2) * x2_8) * x3_73) + (((x0_7 * x1_2) * x2_8) * x3_76) + (((x0_8 * x1_2) * x2_8) * x3_79))));
+    st(0, 61, o0_61);
+    double o0_62 = ((((((x0_6 * x1_0) * x2_6) * x3_2) + (((x0_7 * x1_0) * x2_6) * x3_5) + (((x0_8 * x1_0) * x2_6) * x3_8)) + ((((x0_6 * x1_1) * x2_6) * x3_11) + (((x0_7 * x1_1) * x2_6) * x3_14) + (((x0_8 * x1_1) * x2_6) * x3_17)) + ((((x0_6 * x1_2) * x2_6) * x3_20) + (((x0_7 * x1_2) * x2_6) * x3_23) + (((x0_8 * x1_2) * x2_6) * x3_26))) + (((((x0_6 * x1_0) * x2_7) * x3_29) + (((x0_7 * x1_0) * x2_7) * x3_32) + (((x0_8 * x1_0) * x2_7) * x3_35)) + ((((x0_6 * x1_1) * x2_7) * x3_38) + (((x0_7 * x1_1) * x2_7) * x3_41) + (((x0_8 * x1_1) * x2_7) * x3_44)) + ((((x0_6 * x1_2) * x2_7) * x3_47) + (((x0_7 * x1_2) * x2_7) * x3_50) + (((x0_8 * x1_2) * x2_7) * x3_53))) + (((((x0_6 * x1_0) * x2_8) * x3_56) + (((x0_7 * x1_0) * x2_8) * x3_59) + (((x0_8 * x1_0) * x2_8) * x3_62)) + ((((x0_6 * x1_1) * x2_8) * x3_65) + (((x0_7 * x1_1) * x2_8) * x3_68) + (((x0_8 * x1_1) * x2_8) * x3_71)) + ((((x0_6 * x1_2) * x2_8) * x3_74) + (((x0_7 * x1_2) * x2_8) * x3_77) + (((x0_8 * x1_2) * x2_8) * x3_80))));
+    st(0, 62, o0_62);
+    double o0_63 = ((((((x0_0 * x1_3) * x2_6) * x3_0) + (((x0_1 * x1_3) * x2_6) * x3_3) + (((x0_2 * x1_3) * x2_6) * x3_6)) + ((((x0_0 * x1_4) * x2_6) * x3_9) + (((x0_1 * x1_4) * x2_6) * x3_12) + (((x0_2 * x1_4) * x2_6) * x3_15)) + ((((x0_0 * x1_5) * x2_6) * x3_18) + (((x0_1 * x1_5) * x2_6) * x3_21) + (((x0_2 * x1_5) * x2_6) * x3_24))) + (((((x0_0 * x1_3) * x2_7) * x3_27) + (((x0_1 * x1_3) * x2_7) * x3_30) + (((x0_2 * x1_3) * x2_7) * x3_33)) + ((((x0_0 * x1_4) * x2_7) * x3_36) + (((x0_1 * x1_4) * x2_7) * x3_39) + (((x0_2 * x1_4) * x2_7) * x3_42)) + ((((x0_0 * x1_5) * x2_7) * x3_45) + (((x0_1 * x1_5) * x2_7) * x3_48) + (((x0_2 * x1_5) * x2_7) * x3_51))) + (((((x0_0 * x1_3) * x2_8) * x3_54) + (((x0_1 * x1_3) * x2_8) * x3_57) + (((x0_2 * x1_3) * x2_8) * x3_60)) + ((((x0_0 * x1_4) * x2_8) * x3_63) + (((x0_1 * x1_4) * x2_8) * x3_66) + (((x0_2 * x1_4) * x2_8) * x3_69)) + ((((x0_0 * x1_5) * x2_8) * x3_72) + (((x0_1 * x1_5) * x2_8) * x3_75) + (((x0_2 * x1_5) * x2_8) * x3_78))));
+    st(0, 63, o0_63);
+    double o0_64 = ((((((x0_0 * x1_3) * x2_6) * x3_1) + (((x0_1 * x1_3) * x2_6) * x3_4) + (((x0_2 * x1_3) * x2_6) * x3_7)) + ((((x0_0 * x1_4) * x2_6) * x3_10) + (((x0_1 * x1_4) * x2_6) * x3_13) + (((x0_2 * x1_4) * x2_6) * x3_16)) + ((((x0_0 * x1_5) * x2_6) * x3_19) + (((x0_1 * x1_5) * x2_6) * x3_22) + (((x0_2 * x1_5) * x2_6) * x3_25))) + (((((x0_0 * x1_3) * x2_7) * x3_28) + (((x0_1 * x1_3) * x2_7) * x3_31) + (((x0_2 * x1_3) * x2_7) * x3_34)) + ((((x0_0 * x1_4) * x2_7) * x3_37) + (((x0_1 * x1_4) * x2_7) * x3_40) + (((x0_2 * x1_4) * x2_7) * x3_43)) + ((((x0_0 * x1_5) * x2_7) * x3_46) + (((x0_1 * x1_5) * x2_7) * x3_49) + (((x0_2 * x1_5) * x2_7) * x3_52))) + (((((x0_0 * x1_3) * x2_8) * x3_55) + (((x0_1 * x1_3) * x2_8) * x3_58) + (((x0_2 * x1_3) * x2_8) * x3_61)) + ((((x0_0 * x1_4) * x2_8) * x3_64) + (((x0_1 * x1_4) * x2_8) * x3_67) + (((x0_2 * x1_4) * x2_8) * x3_70)) + ((((x0_0 * x1_5) * x2_8) * x3_73) + (((x0_1 * x1_5) * x2_8) * x3_76) + (((x0_2 * x1_5) * x2_8) * x3_79))));
+    st(0, 64, o0_64);
+    double o0_65 = ((((((x0_0 * x1_3) * x2_6) * x3_2) + (((x0_1 * x1_3) * x2_6) * x3_5) + (((x0_2 * x1_3) * x2_6) * x3_8)) + ((((x0_0 * x1_4) * x2_6) * x3_11) + (((x0_1 * x1_4) * x2_6) * x3_14) + (((x0_2 * x1_4) * x2_6) * x3_17)) + ((((x0_0 * x1_5) * x2_6) * x3_20) + (((x0_1 * x1_5) * x2_6) * x3_23) + (((x0_2 * x1_5) * x2_6) * x3_26))) + (((((x0_0 * x1_3) * x2_7) * x3_29) + (((x0_1 * x1_3) * x2_7) * x3_32) + (((x0_2 * x1_3) * x2_7) * x3_35)) + ((((x0_0 * x1_4) * x2_7) * x3_38) + (((x0_1 * x1_4) * x2_7) * x3_41) + (((x0_2 * x1_4) * x2_7) * x3_44)) + ((((x0_0 * x1_5) * x2_7) * x3_47) + (((x0_1 * x1_5) * x2_7) * x3_50) + (((x0_2 * x1_5) * x2_7) * x3_53))) + (((((x0_0 * x1_3) * x2_8) * x3_56) + (((x0_1 * x1_3) * x2_8) * x3_59) + (((x0_2 * x1_3) * x2_8) * x3_62)) + ((((x0_0 * x1_4) * x2_8) * x3_65) + (((x0_1 * x1_4) * x2_8) * x3_68) + (((x0_2 * x1_4) * x2_8) * x3_71)) + ((((x0_0 * x1_5) * x2_8) * x3_74) + (((x0_1 * x1_5) * x2_8) * x3_77) + (((x0_2 * x1_5) * x2_8) * x3_80))));
+    st(0, 65, o0_65);
+    double o0_66 = ((((((x0_3 * x1_3) * x2_6) * x3_0) + (((x0_4 * x1_3) * x2_6) * x3_3) + (((x0_5 * x1_3) * x2_6) * x3_6)) + ((((x0_3 * x1_4) * x2_6) * x3_9) + (((x0_4 * x1_4) * x2_6) * x3_12) + (((x0_5 * x1_4) * x2_6) * x3_15)) + ((((x0_3 * x1_5) * x2_6) * x3_18) + (((x0_4 * x1_5) * x2_6) * x3_21) + (((x0_5 * x1_5) * x2_6) * x3_24))) + (((((x0_3 * x1_3) * x2_7) * x3_27) + (((x0_4 * x1_3) * x2_7) * x3_30) + (((x0_5 * x1_3) * x2_7) * x3_33)) + ((((x0_3 * x1_4) * x2_7) * x3_36) + (((x0_4 * x1_4) * x2_7) * x3_39) + (((x0_5 * x1_4) * x2_7) * x3_42)) + ((((x0_3 * x1_5) * x2_7) * x3_45) + (((x0_4 * x1_5) * x2_7) * x3_48) + (((x0_5 * x1_5) * x2_7) * x3_51))) + (((((x0_3 * x1_3) * x2_8) * x3_54) + (((x0_4 * x1_3) * x2_8) * x3_57) + (((x0_5 * x1_3) * x2_8) * x3_60)) + ((((x0_3 * x1_4) * x2_8) * x3_63) + (((x0_4 * x1_4) * x2_8) * x3_66) + (((x0_5 * x1_4) * x2_8) * x3_69)) + ((((x0_3 * x1_5) * x2_8) * x3_72) + (((x0_4 * x1_5) * x2_8) * x3_75) + (((x0_5 * x1_5) * x2_8) * x3_78))));
+    st(0, 66, o0_66);
+    double o0_67 = ((((((x0_3 * x1_3) * x2_6) * x3_1) + (((x0_4 * x1_3) * x2_6) * x3_4) + (((x0_5 * x1_3) * x2_6) * x3_7)) + ((((x0_3 * x1_4) * x2_6) * x3_10) + (((x0_4 * x1_4) * x2_6) * x3_13) + (((x0_5 * x1_4) * x2_6) * x3_16)) + ((((x0_3 * x1_5) * x2_6) * x3_19) + (((x0_4 * x1_5) * x2_6) * x3_22) + (((x0_5 * x1_5) * x2_6) * x3_25))) + (((((x0_3 * x1_3) * x2_7) * x3_28) + (((x0_4 * x1_3) * x2_7) * x3_31) + (((x0_5 * x1_3) * x2_7) * x3_34)) + ((((x0_3 * x1_4) * x2_7) * x3_37) + (((x0_4 * x1_4) * x2_7) * x3_40) + (((x0_5 * x1_4) * x2_7) * x3_43)) + ((((x0_3 * x1_5) * x2_7) * x3_46) + (((x0_4 * x1_5) * x2_7) * x3_49) + (((x0_5 * x1_5) * x2_7) * x3_52))) + (((((x0_3 * x1_3) * x2_8) * x3_55) + (((x0_4 * x1_3) * x2_8) * x3_58) + (((x0_5 * x1_3) * x2_8) * x3_61)) + ((((x0_3 * x1_4) * x2_8) * x3_64) + (((x0_4 * x1_4) * x2_8) * x3_67) + (((x0_5 * x1_4) * x2_8) * x3_70)) + ((((x0_3 * x1_5) * x2_8) * x3_73) + (((x0_4 * x1_5) * x2_8) * x3_76) + (((x0_5 * x1_5) * x2_8) * x3_79))));
+    st(0, 67, o0_67);
+    double o0_68 = ((((((x0_3 * x1_3) * x2_6) * x3_2) + (((x0_4 * x1_3) * x2_6) * x3_5) + (((x0_5 * x1_3) * x2_6) * x3_8)) + ((((x0_3 * x1_4) * x2_6) * x3_11) + (((x0_4 * x1_4) * x2_6) * x3_14) + (((x0_5 * x1_4) * x2_6) * x3_17)) + ((((x0_3 * x1_5) * x2_6) * x3_20) + (((x0_4 * x1_5) * x2_6) * x3_23) + (((x0_5 * x1_5) * x2_6) * x3_26))) + (((((x0_3 * x1_3) * x2_7) * x3_29) + (((x0_4 * x1_3) * x2_7) * x3_32) + (((x0_5 * x1_3) * x2_7) * x3_35)) + ((((x0_3 * x1_4) * x2_7) * x3_38) + (((x0_4 * x1_4) * x2_7) * x3_41) + (((x0_5 * x1_4) * x2_7) * x3_44)) + ((((x0_3 * x1_5) * x2_7) * x3_47) + (((x0_4 * x1_5) * x2_7) * x3_50) + (((x0_5 * x1_5) * x2_7) * x3_53))) + (((((x0_3 * x1_3) * x2_8) * x3_56) + (((x0_4 * x1_3) * x2_8) * x3_59) + (((x0_5 * x1_3) * x2_8) * x3_62)) + ((((x0_3 * x1_4) * x2_8) * x3_65) + (((x0_4 * x1_4) * x2_8) * x3_68) + (((x0_5 * x1_4) * x2_8) * x3_71)) + ((((x0_3 * x1_5) * x2_8) * x3_74) + (((x0_4 * x1_5) * x2_8) * x3_77) + (((x0_5 * x1_5) * x2_8) * x3_80))));
+    st(0, 68, o0_68);
+    double o0_69 = ((((((x0_6 * x1_3) * x2_6) * x3_0) + (((x0_7 * x1_3) * x2_6) * x3_3) + (((x0_8 * x1_3) * x2_6) * x3_6)) + ((((x0_6 * x1_4) * x2_6) * x3_9) + (((x0_7 * x1_4) * x2_6) * x3_12) + (((x0_8 * x1_4) * x2_6) * x3_15)) + ((((x0_6 * x1_5) * x2_6) * x3_18) + (((x0_7 * x1_5) * x2_6) * x3_21) + (((x0_8 * x1_5) * x2_6) * x3_24))) + (((((x0_6 * x1_3) * x2_7) * x3_27) + (((x0_7 * x1_3) * x2_7) * x3_30) + (((x0_8 * x1_3) * x2_7) * x3_33)) + ((((x0_6 * x1_4) * x2_7) * x3_36) + (((x0_7 * x1_4) * x2_7) * x3_39) + (((x0_8 * x1_4) * x2_7) * x3_42)) + ((((x0_6 * x1_5) * x2_7) * x3_45) + (((x0_7 * x1_5) * x2_7) * x3_48) + (((x0_8 * x1_5) * x2_7) * x3_51))) + (((((x0_6 * x1_3) * x2_8) * x3_54) + (((x0_7 * x1_3) * x2_8) * x3_57) + (((x0_8 * x1_3) * x2_8) * x3_60)) + ((((x0_6 * x1_4) * x2_8) * x3_63) + (((x0_7 * x1_4) * x2_8) * x3_66) + (((x0_8 * x1_4) * x2_8) * x3_69)) + ((((x0_6 * x1_5) * x2_8) * x3_72) + (((x0_7 * x1_5) * x2_8) * x3_75) + (((x0_8 * x1_5) * x2_8) * x3_78))));
+    st(0, 69, o0_69);
+    double o0_70 = ((((((x0_6 * x1_3) * x2_6) * x3_1) + (((x0_7 * x1_3) * x2_6) * x3_4) + (((x0_8 * x1_3) * x2_6) * x3_7)) + ((((x0_6 * x1_4) * x2_6) * x3_10) + (((x0_7 * x1_4) * x2_6) * x3_13) + (((x0_8 * x1_4) * x2_6) * x3_16)) + ((((x0_6 * x1_5) * x2_6) * x3_19) + (((x0_7 * x1_5) * x2_6) * x3_22) + (((x0_8 * x1_5) * x2_6) * x3_25))) + (((((x0_6 * x1_3) * x2_7) * x3_28) + (((x0_7 * x1_3) * x2_7) * x3_31) + (((x0_8 * x1_3) * x2_7) * x3_34)) + ((((x0_6 * x1_4) * x2_7) * x3_37) + (((x0_7 * x1_4) * x2_7) * x3_40) + (((x0_8 * x1_4) * x2_7) * x3_43)) + ((((x0_6 * x1_5) * x2_7) * x3_46) + (((x0_7 * x1_5) * x2_7) * x3_49) + (((x0_8 * x1_5) * x2_7) * x3_52))) + (((((x0_6 * x1_3) * x2_8) * x3_55) + (((x0_7 * x1_3) * x2_8) * x3_58) + (((x0_8 * x1_3) * x2_8) * x3_61)) + ((((x0_6 * x1_4) * x2_8) * x3_64) + (((x0_7 * x1_4) * x2_8) * x3_67) + (((x0_8 * x1_4) * x2_8) * x3_70)) + ((((x0_6 * x1_5) * x2_8) * x3_73) + (((x0_7 * x1_5) * x2_8) * x3_76) + (((x0_8 * x1_5) * x2_8) * x3_79))));
+    st(0, 70, o0_70);
+    double o0_71 = ((((((x0_6 * x1_3) * x2_6) * x3_2) + (((x0_7 * x1_3) * x2_6) * x3_5) + (((x0_8 * x1_3) * x2_6) * x3_8)) + ((((x0_6 * x1_4) * x2_6) * x3_11) + (((x0_7 * x1_4) * x2_6) * x3_14) + (((x0_8 * x1_4) * x2_6) * x3_17)) + ((((x0_6 * x1_5) * x2_6) * x3_20) + (((x0_7 * x1_5) * x2_6) * x3_23) + (((x0_8 * x1_5) * x2_6) * x3_26))) + (((((x0_6 * x1_3) * x2_7) * x3_29) + (((x0_7 * x1_3) * x2_7) * x3_32) + (((x0_8 * x1_3) * x2_7) * x3_35)) + ((((x0_6 * x1_4) * x2_7) * x3_38) + (((x0_7 * x1_4) * x2_7) * x3_41) + (((x0_8 * x1_4) * x2_7) * x3_44)) + ((((x0_6 * x1_5) * x2_7) * x3_47) + (((x0_7 * x1_5) * x2_7) * x3_50) + (((x0_8 * x1_5) * x2_7) * x3_53))) + (((((x0_6 * x1_3) * x2_8) * x3_56) + (((x0_7 * x1_3) * x2_8) * x3_59) + (((x0_8 * x1_3) * x2_8) * x3_62)) + ((((x0_6 * x1_4) * x2_8) * x3_65) + (((x0_7 * x1_4) * x2_8) * x3_68) + (((x0_8 * x1_4) * x2_8) * x3_71)) + ((((x0_6 * x1_5) * x2_8) * x3_74) + (((x0_7 * x1_5) * x2_8) * x3_77) + (((x0_8 * x1_5) * x2_8) * x3_80))));
+    st(0, 71, o0_71);
+    double o0_72 = ((((((x0_0 * x1_6) * x2_6) * x3_0) + (((x0_1 * x1_6) * x2_6) * x3_3) + (((x0_2 * x1_6) * x2_6) * x3_6)) + ((((x0_0 * x1_7) * x2_6) * x3_9) + (((x0_1 * x1_7) * x2_6) * x3_12) + (((x0_2 * x1_7) * x2_6) * x3_15)) + ((((x0_0 * x1_8) * x2_6) * x3_18) + (((x0_1 * x1_8) * x2_6) * x3_21) + (((x0_2 * x1_8) * x2_6) * x3_24))) + (((((x0_0 * x1_6) * x2_7) * x3_27) + (((x0_1 * x1_6) * x2_7) * x3_30) + (((x0_2 * x1_6) * x2_7) * x3_33)) + ((((x0_0 * x1_7) * x2_7) * x3_36) + (((x0_1 * x1_7) * x2_7) * x3_39) + (((x0_2 * x1_7) * x2_7) * x3_42)) + ((((x0_0 * x1_8) * x2_7) * x3_45) + (((x0_1 * x1_8) * x2_7) * x3_48) + (((x0_2 * x1_8) * x2_7) * x3_51))) + (((((x0_0 * x1_6) * x2_8) * x3_54) + (((x0_1 * x1_6) * x2_8) * x3_57) + (((x0_2 * x1_6) * x2_8) * x3_60)) + ((((x0_0 * x1_7) * x2_8) * x3_63) + (((x0_1 * x1_7) * x2_8) * x3_66) + (((x0_2 * x1_7) * x2_8) * x3_69)) + ((((x0_0 * x1_8) * x2_8) * x3_72) + (((x0_1 * x1_8) * x2_8) * x3_75) + (((x0_2 * x1_8) * x2_8) * x3_78))));
+    st(0, 72, o0_72);
+    double o0_73 = ((((((x0_0 * x1_6) * x2_6) * x3_1) + (((x0_1 * x1_6) * x2_6) * x3_4) + (((x0_2 * x1_6) * x2_6) * x3_7)) + ((((x0_0 * x1_7) * x2_6) * x3_10) + (((x0_1 * x1_7) * x2_6) * x3_13) + (((x0_2 * x1_7) * x2_6) * x3_16)) + ((((x0_0 * x1_8) * x2_6) * x3_19) + (((x0_1 * x1_8) * x2_6) * x3_22) + (((x0_2 * x1_8) * x2_6) * x3_25))) + (((((x0_0 * x1_6) * x2_7) * x3_28) + (((x0_1 * x1_6) * x2_7) * x3_31) + (((x0_2 * x1_6) * x2_7) * x3_34)) + ((((x0_0 * x1_7) * x2_7) * x3_37) + (((x0_1 * x1_7) * x2_7) * x3_40) + (((x0_2 * x1_7) * x2_7) * x3_43)) + ((((x0_0 * x1_8) * x2_7) * x3_46) + (((x0_1 * x1_8) * x2_7) * x3_49) + (((x0_2 * x1_8) * x2_7) * x3_52))) + (((((x0_0 * x1_6) * x2_8) * x3_55) + (((x0_1 * x1_6) * x2_8) * x3_58) + (((x0_2 * x1_6) * x2_8) * x3_61)) + ((((x0_0 * x1_7) * x2_8) * x3_64) + (((x0_1 * x1_7) * x2_8) * x3_67) + (((x0_2 * x1_7) * x2_8) * x3_70)) + ((((x0_0 * x1_8) * x2_8) * x3_73) + (((x0_1 * x1_8) * x2_8) * x3_76) + (((x0_2 * x1_8) * x2_8) * x3_79))));
+    st(0, 73, o0_73);
+    double o0_74 = ((((((x0_0 * x1_6) * x2_6) * x3_2) + (((x0_1 * x1_6) * x2_6) * x3_5) + (((x0_2 * x1_6) * x2_6) * x3_8)) + ((((x0_0 * x1_7) * x2_6) * x3_11) + (((x0_1 * x1_7) * x2_6) * x3_14) + (((x0_2 * x1_7) * x2_6) * x3_17)) + ((((x0_0 * x1_8) * x2_6) * x3_20) + (((x0_1 * x1_8) * x2_6) * x3_23) + (((x0_2 * x1_8) * x2_6) * x3_26))) + (((((x0_0 * x1_6) * x2_7) * x3_29) + (((x0_1 * x1_6) * x2_7) * x3_32) + (((x0_2 * x1_6) * x2_7) * x3_35)) + ((((x0_0 * x1_7) * x2_7) * x3_38) + (((x0_1 * x1_7) * x2_7) * x3_41) + (((x0_2 * x1_7) * x2_7) * x3_44)) + ((((x0_0 * x1_8) * x2_7) * x3_47) + (((x0_1 * x1_8) * x2_7) * x3_50) + (((x0_2 * x1_8) * x2_7) * x3_53))) + (((((x0_0 * x1_6) * x2_8) * x3_56) + (((x0_1 * x1_6) * x2_8) * x3_59) + (((x0_2 * x1_6) * x2_8) * x3_62)) + ((((x0_0 * x1_7) * x2_8) * x3_65) + (((x0_1 * x1_7) * x2_8) * x3_68) + (((x0_2 * x1_7) * x2_8) * x3_71)) + ((((x0_0 * x1_8) * x2_8) * x3_74) + (((x0_1 * x1_8) * x2_8) * x3_77) + (((x0_2 * x1_8) * x2_8) * x3_80))));
+    st(0, 74, o0_74);
+    double o0_75 = ((((((x0_3 * x1_6) * x2_6) * x3_0) + (((x0_4 * x1_6) * x2_6) * x3_3) + (((x0_5 * x1_6) * x2_6) * x3_6)) + ((((x0_3 * x1_7) * x2_6) * x3_9) + (((x0_4 * x1_7) * x2_6) * x3_12) + (((x0_5 * x1_7) * x2_6) * x3_15)) + ((((x0_3 * x1_8) * x2_6) * x3_18) + (((x0_4 * x1_8) * x2_6) * x3_21) + (((x0_5 * x1_8) * x2_6) * x3_24))) + (((((x0_3 * x1_6) * x2_7) * x3_27) + (((x0_4 * x1_6) * x2_7) * x3_30) + (((x0_5 * x1_6) * x2_7) * x3_33)) + ((((x0_3 * x1_7) * x2_7) * x3_36) + (((x0_4 * x1_7) * x2_7) * x3_39) + (((x0_5 * x1_7) * x2_7) * x3_42)) + ((((x0_3 * x1_8) * x2_7) * x3_45) + (((x0_4 * x1_8) * x2_7) * x3_48) + (((x0_5 * x1_8) * x2_7) * x3_51))) + (((((x0_3 * x1_6) * x2_8) * x3_54) + (((x0_4 * x1_6) * x2_8) * x3_57) + (((x0_5 * x1_6) * x2_8) * x3_60)) + ((((x0_3 * x1_7) * x2_8) * x3_63) + (((x0_4 * x1_7) * x2_8) * x3_66) + (((x0_5 * x1_7) * x2_8) * x3_69)) + ((((x0_3 * x1_8) * x2_8) * x3_72) + (((x0_4 * x1_8) * x2_8) * x3_75) + (((x0_5 * x1_8) * x2_8) * x3_78))));
+    st(0, 75, o0_75);
+    double o0_76 = ((((((x0_3 * x1_6) * x2_6) * x3_1) + (((x0_4 * x1_6) * x2_6) * x3_4) + (((x0_5 * x1_6) * x2_6) * x3_7)) + ((((x0_3 * x1_7) * x2_6) * x3_10) + (((x0_4 * x1_7) * x2_6) * x3_13) + (((x0_5 * x1_7) * x2_6) * x3_16)) + ((((x0_3 * x1_8) * x2_6) * x3_19) + (((x0_4 * x1_8) * x2_6) * x3_22) + (((x0_5 * x1_8) * x2_6) * x3_25))) + (((((x0_3 * x1_6) * x2_7) * x3_28) + (((x0_4 * x1_6) * x2_7) * x3_31) + (((x0_5 * x1_6) * x2_7) * x3_34)) + ((((x0_3 * x1_7) * x2_7) * x3_37) + (((x0_4 * x1_7) * x2_7) * x3_40) + (((x0_5 * x1_7) * x2_7) * x3_43)) + ((((x0_3 * x1_8) * x2_7) * x3_46) + (((x0_4 * x1_8) * x2_7) * x3_49) + (((x0_5 * x1_8) * x2_7) * x3_52))) + (((((x0_3 * x1_6) * x2_8) * x3_55) + (((x0_4 * x1_6) * x2_8) * x3_58) + (((x0_5 * x1_6) * x2_8) * x3_61)) + ((((x0_3 * x1_7) * x2_8) * x3_64) + (((x0_4 * x1_7) * x2_8) * x3_67) + (((x0_5 * x1_7) * x2_8) * x3_70)) + ((((x0_3 * x1_8) * x2_8) * x3_73) + (((x0_4 * x1_8) * x2_8) * x3_76) + (((x0_5 * x1_8) * x2_8) * x3_79))));
+    st(0, 76, o0_76);
+    double o0_77 = ((((((x0_3 * x1_6) * x2_6) * x3_2) + (((x0_4 * x1_6) * x2_6) * x3_5) + (((x0_5 * x1_6) * x2_6) * x3_8)) + ((((x0_3 * x1_7) * x2_6) * x3_11) + (((x0_4 * x1_7) * x2_6) * x3_14) + (((x0_5 * x1_7) * x2_6) * x3_17)) + ((((x0_3 * x1_8) * x2_6) * x3_20) + (((x0_4 * x1_8) * x2_6) * x3_23) + (((x0_5 * x1_8) * x2_6) * x3_26))) + (((((x0_3 * x1_6) * x2_7) * x3_29) + (((x0_4 * x1_6) * x2_7) * x3_32) + (((x0_5 * x1_6) * x2_7) * x3_35)) + ((((x0_3 * x1_7) * x2_7) * x3_38) + (((x0_4 * x1_7) * x2_7) * x3_41) + (((x0_5 * x1_7) * x2_7) * x3_44)) + ((((x0_3 * x1_8) * x2_7) * x3_47) + (((x0_4 * x1_8) * x2_7) * x3_50) + (((x0_5 * x1_8) * x2_7) * x3_53))) + (((((x0_3 * x1_6) * x2_8) * x3_56) + (((x0_4 * x1_6) * x2_8) * x3_59) + (((x0_5 * x1_6) * x2_8) * x3_62)) + ((((x0_3 * x1_7) * x2_8) * x3_65) + (((x0_4 * x1_7) * x2_8) * x3_68) + (((x0_5 * x1_7) * x2_8) * x3_71)) + ((((x0_3 * x1_8) * x2_8) * x3_74) + (((x0_4 * x1_8) * x2_8) * x3_77) + (((x0_5 * x1_8) * x2_8) * x3_80))));
+    st(0, 77, o0_77);
+    double o0_78 = ((((((x0_6 * x1_6) * x2_6) * x3_0) + (((x0_7 * x1_6) * x2_6) * x3_3) + (((x0_8 * x1_6) * x2_6) * x3_6)) + ((((x0_6 * x1_7) * x2_6) * x3_9) + (((x0_7 * x1_7) * x2_6) * x3_12) + (((x0_8 * x1_7) * x2_6) * x3_15)) + ((((x0_6 * x1_8) * x2_6) * x3_18) + (((x0_7 * x1_8) * x2_6) * x3_21) + (((x0_8 * x1_8) * x2_6) * x3_24))) + (((((x0_6 * x1_6) * x2_7) * x3_27) + (((x0_7 * x1_6) * x2_7) * x3_30) + (((x0_8 * x1_6) * x2_7) * x3_33)) + ((((x0_6 * x1_7) * x2_7) * x3_36) + (((x0_7 * x1_7) * x2_7) * x3_39) + (((x0_8 * x1_7) * x2_7) * x3_42)) + ((((x0_6 * x1_8) * x2_7) * x3_45) + (((x0_7 * x1_8) * x2_7) * x3_48) + (((x0_8 * x1_8) * x2_7) * x3_51))) + (((((x0_6 * x1_6) * x2_8) * x3_54) + (((x0_7 * x1_6) * x2_8) * x3_57) + (((x0_8 * x1_6) * x2_8) * x3_60)) + ((((x0_6 * x1_7) * x2_8) * x3_63) + (((x0_7 * x1_7) * x2_8) * x3_66) + (((x0_8 * x1_7) * x2_8) * x3_69)) + ((((x0_6 * x1_8) * x2_8) * x3_72) + (((x0_7 * x1_8) * x2_8) * x3_75) + (((x0_8 * x1_8) * x2_8) * x3_78))));
+    st(0, 78, o0_78);
+    double o0_79 = ((((((x0_6 * x1_6) * x2_6) * x3_1) + (((x0_7 * x1_6) * x2_6) * x3_4) + (((x0_8 * x1_6) * x2_6) * x3_7)) + ((((x0_6 * x1_7) * x2_6) * x3_10) + (((x0_7 * x1_7) * x2_6) * x3_13) + (((x0_8 * x1_7) * x2_6) * x3_16)) + ((((x0_6 * x1_8) * x2_6) * x3_19) + (((x0_7 * x1_8) * x2_6) * x3_22) + (((x0_8 * x1_8) * x2_6) * x3_25))) + (((((x0_6 * x1_6) * x2_7) * x3_28) + (((x0_7 * x1_6) * x2_7) * x3_31) + (((x0_8 * x1_6) * x2_7) * x3_34)) + ((((x0_6 * x1_7) * x2_7) * x3_37) + (((x0_7 * x1_7) * x2_7) * x3_40) + (((x0_8 * x1_7) * x2_7) * x3_43)) + ((((x0_6 * x1_8) * x2_7) * x3_46) + (((x0_7 * x1_8) * x2_7) * x3_49) + (((x0_8 * x1_8) * x2_7) * x3_52))) + (((((x0_6 * x1_6) * x2_8) * x3_55) + (((x0_7 * x1_6) * x2_8) * x3_58) + (((x0_8 * x1_6) * x2_8) * x3_61)) + ((((x0_6 * x1_7) * x2_8) * x3_64) + (((x0_7 * x1_7) * x2_8) * x3_67) + (((x0_8 * x1_7) * x2_8) * x3_70)) + ((((x0_6 * x1_8) * x2_8) * x3_73) + (((x0_7 * x1_8) * x2_8) * x3_76) + (((x0_8 * x1_8) * x2_8) * x3_79))));
+    st(0, 79, o0_79);
+    double o0_80 = ((((((x0_6 * x1_6) * x2_6) * x3_2) + (((x0_7 * x1_6) * x2_6) * x3_5) + (((x0_8 * x1_6) * x2_6) * x3_8)) + ((((x0_6 * x1_7) * x2_6) * x3_11) + (((x0_7 * x1_7) * x2_6) * x3_14) + (((x0_8 * x1_7) * x2_6) * x3_17)) + ((((x0_6 * x1_8) * x2_6) * x3_20) + (((x0_7 * x1_8) * x2_6) * x3_23) + (((x0_8 * x1_8) * x2_6) * x3_26))) + (((((x0_6 * x1_6) * x2_7) * x3_29) + (((x0_7 * x1_6) * x2_7) * x3_32) + (((x0_8 * x1_6) * x2_7) * x3_35)) + ((((x0_6 * x1_7) * x2_7) * x3_38) + (((x0_7 * x1_7) * x2_7) * x3_41) + (((x0_8 * x1_7) * x2_7) * x3_44)) + ((((x0_6 * x1_8) * x2_7) * x3_47) + (((x0_7 * x1_8) * x2_7) * x3_50) + (((x0_8 * x1_8) * x2_7) * x3_53))) + (((((x0_6 * x1_6) * x2_8) * x3_56) + (((x0_7 * x1_6) * x2_8) * x3_59) + (((x0_8 * x1_6) * x2_8) * x3_62)) + ((((x0_6 * x1_7) * x2_8) * x3_65) + (((x0_7 * x1_7) * x2_8) * x3_68) + (((x0_8 * x1_7) * x2_8) * x3_71)) + ((((x0_6 * x1_8) * x2_8) * x3_74) + (((x0_7 * x1_8) * x2_8) * x3_77) + (((x0_8 * x1_8) * x2_8) * x3_80))));
+    st(0, 80, o0_80);
+  }
+};
+
 // lst_sym_contract: C_(ab) = sum_c A_ac B_cb, symmetric left-hand side (Sec. 4, rank 2 contraction example)
 struct Gen_lst_sym_contract {
   static constexpr bool kStream = true;
@@ -764,11 +1862,88 @@ tl_status tlg_kij(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* o
                            1, stream, tune, &tl::launch_op<tl::Gen_kij>);
 }
 
+tl_status tlg_assign1(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {3};
+  static const int32_t kOut[] = {3};
+  return tl::run_generated("assign1", n, in, nin, kIn, 1, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_assign1>);
+}
+
+tl_status tlg_assign2(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {9};
+  static const int32_t kOut[] = {9};
+  return tl::run_generated("assign2", n, in, nin, kIn, 1, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_assign2>);
+}
+
+tl_status tlg_assign3(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {27};
+  static const int32_t kOut[] = {27};
+  return tl::run_generated("assign3", n, in, nin, kIn, 1, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_assign3>);
+}
+
+tl_status tlg_add1(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {3, 3};
+  static const int32_t kOut[] = {3};
+  return tl::run_generated("add1", n, in, nin, kIn, 2, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_add1>);
+}
+
+tl_status tlg_add2(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {3, 3, 3};
+  static const int32_t kOut[] = {3};
+  return tl::run_generated("add2", n, in, nin, kIn, 3, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_add2>);
+}
+
+tl_status tlg_add3(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {3, 3, 3, 3};
+  static const int32_t kOut[] = {3};
+  return tl::run_generated("add3", n, in, nin, kIn, 4, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_add3>);
+}
+
+tl_status tlg_mult1(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {3, 3};
+  static const int32_t kOut[] = {9};
+  return tl::run_generated("mult1", n, in, nin, kIn, 2, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_mult1>);
+}
+
+tl_status tlg_mult2(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {3, 3, 3};
+  static const int32_t kOut[] = {27};
+  return tl::run_generated("mult2", n, in, nin, kIn, 3, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_mult2>);
+}
+
+tl_status tlg_mult3(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {3, 3, 3, 3};
+  static const int32_t kOut[] = {81};
+  return tl::run_generated("mult3", n, in, nin, kIn, 4, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_mult3>);
+}
+
 tl_status tlg_contract1(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
   static const int32_t kIn[] = {9, 81};
   static const int32_t kOut[] = {81};
   return tl::run_generated("contract1", n, in, nin, kIn, 2, out, nout, kOut,
                            1, stream, tune, &tl::launch_op<tl::Gen_contract1>);
+}
+
+tl_status tlg_contract2(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {9, 9, 81};
+  static const int32_t kOut[] = {81};
+  return tl::run_generated("contract2", n, in, nin, kIn, 3, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_contract2>);
+}
+
+tl_status tlg_contract3(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {
+  static const int32_t kIn[] = {9, 9, 9, 81};
+  static const int32_t kOut[] = {81};
+  return tl::run_generated("contract3", n, in, nin, kIn, 4, out, nout, kOut,
+                           1, stream, tune, &tl::launch_op<tl::Gen_contract3>);
 }
 
 tl_status tlg_lst_sym_contract(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune) {

@@ -114,6 +114,14 @@ constexpr Offsets<Op::NF_OUT> out_offsets() {
   return o;
 }
 
+// Largest block an Op may run in (Op::kMaxBlock, default 1024): bodies that
+// keep many values live would spill to scratch in larger blocks.
+template <class Op, class = void>
+struct max_block : std::integral_constant<int, 1024> {};
+template <class Op>
+struct max_block<Op, std::void_t<decltype(Op::kMaxBlock)>>
+    : std::integral_constant<int, Op::kMaxBlock> {};
+
 // Streaming bodies (Op::kStream) run one point per lane through ld/st.
 template <class Op, class = void>
 struct is_stream : std::false_type {};
@@ -356,16 +364,29 @@ static hipError_t launch_b(const Resolved& r, const KArgs& a, int64_t n, int64_t
 }
 
 template <class Op>
-static hipError_t launch_op(const Resolved& r, const KArgs& a, int64_t n, hipStream_t s) {
+static Resolved clamp_block(const Resolved& r0) {
+  Resolved r = r0;
+  if (r.block > max_block<Op>::value) r.block = max_block<Op>::value;
+  return r;
+}
+
+template <class Op>
+static hipError_t launch_op(const Resolved& r0, const KArgs& a, int64_t n, hipStream_t s) {
+  const Resolved r = clamp_block<Op>(r0);
   const int64_t per = static_cast<int64_t>(r.block) * (is_stream<Op>::value ? 1 : r.ppt);
   const int64_t ntiles = (n + per - 1) / per;
   const int64_t grid = grid_size(r, ntiles);
+  constexpr int cap = max_block<Op>::value;
   switch (r.block) {
     case 64: return launch_b<Op, 64>(r, a, n, ntiles, grid, s);
     case 128: return launch_b<Op, 128>(r, a, n, ntiles, grid, s);
     case 256: return launch_b<Op, 256>(r, a, n, ntiles, grid, s);
-    case 512: return launch_b<Op, 512>(r, a, n, ntiles, grid, s);
-    case 1024: return launch_b<Op, 1024>(r, a, n, ntiles, grid, s);
+    case 512:
+      if constexpr (cap >= 512) return launch_b<Op, 512>(r, a, n, ntiles, grid, s);
+      return hipErrorInvalidValue;
+    case 1024:
+      if constexpr (cap >= 1024) return launch_b<Op, 1024>(r, a, n, ntiles, grid, s);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
@@ -377,11 +398,14 @@ static const void* ptr_p(const Resolved& r) {
 }
 
 template <class Op>
-static const void* ptr_op(const Resolved& r) {
+static const void* ptr_op(const Resolved& r0) {
+  const Resolved r = clamp_block<Op>(r0);
   constexpr int P2 = is_stream<Op>::value ? 1 : 2;
-#define TL_PTR(B) \
-  case B:         \
-    return r.ppt == 2 ? ptr_p<Op, B, P2>(r) : ptr_p<Op, B, 1>(r);
+  constexpr int cap = max_block<Op>::value;
+#define TL_PTR(B)                                                                  \
+  case B:                                                                          \
+    if constexpr (cap >= B) return r.ppt == 2 ? ptr_p<Op, B, P2>(r) : ptr_p<Op, B, 1>(r); \
+    return nullptr;
   switch (r.block) {
     TL_PTR(64)
     TL_PTR(128)

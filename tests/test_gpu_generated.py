@@ -65,7 +65,11 @@ def test_generated_fused_chain(n, tune):
     assert_close(dtg, hand.cpu().numpy(), what="generated vs hand-written chain")
 
 
-@pytest.mark.parametrize("name", ["kij", "contract1"])
+FAMILY = ("assign1", "assign2", "assign3", "add1", "add2", "add3", "mult1", "mult2", "mult3",
+          "contract1", "contract2", "contract3", "kij")
+
+
+@pytest.mark.parametrize("name", FAMILY)
 @pytest.mark.parametrize("n", SIZES)
 def test_against_the_expression_kernels(name, n):
     xs = make_expr_inputs(name, n, seed=n)
@@ -93,6 +97,17 @@ def test_listing_examples_and_spacetime_split(n):
 
 
 def test_every_generated_program_is_exercised():
-    tested = {"christoffel", "cov_deriv", "dtg", "dtg_chain_invg", "kij", "contract1",
-              "lst_sym_contract", "lst_fixed_offset", "spacetime_split"}
+    tested = {"christoffel", "cov_deriv", "dtg", "dtg_chain_invg", "lst_sym_contract",
+              "lst_fixed_offset", "spacetime_split"} | set(FAMILY)
     assert set(programs()) == tested
+
+
+@pytest.mark.parametrize("name", ["contract3", "mult3"])
+@pytest.mark.parametrize("block", [512, 1024])
+def test_wide_programs_in_large_blocks(name, block):
+    """A wide program asked for more threads per block than its cap runs in
+    the capped block size, with the same results."""
+    n = 3001
+    xs = make_expr_inputs(name, n, seed=9)
+    (out,) = call(name, *[dev(x) for x in xs], tune=dict(block=block, nt=True))
+    assert_close(out, oracle.expr(name, *xs), what=f"generated {name} block={block}")
