@@ -19,6 +19,7 @@ import argparse
 import csv
 import glob
 import hashlib
+import json
 import os
 from collections import defaultdict
 
@@ -74,8 +75,21 @@ def launch_shapes(folder):
         agg[key].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
         vgpr[key] = int(r["VGPR_Count"]) + int(r.get("Accum_VGPR_Count", 0) or 0)
     out = [{"name": k[0], "grid": k[1], "calls": len(v), "avg_ns": sum(v) / len(v),
-            "total_ns": sum(v), "vgpr": vgpr[k]} for k, v in agg.items()]
+            "min_ns": min(v), "max_ns": max(v), "total_ns": sum(v), "vgpr": vgpr[k]}
+           for k, v in agg.items()]
     return sorted(out, key=lambda r: -r["total_ns"])
+
+
+def bench_lines(specs):
+    """[(label, JSON record)] of the benchmark lines in the files ``LABEL=PATH``."""
+    out = []
+    for spec in specs:
+        label, _, fn = spec.rpartition("=")
+        with open(fn) as f:
+            for line in f:
+                if line.startswith('{"metric"'):
+                    out.append((label or os.path.basename(fn), json.loads(line)))
+    return out
 
 
 def counters(folder, counter):
@@ -109,6 +123,9 @@ def main():
     ap.add_argument("--points", type=int, required=True, help="grid points per launch")
     ap.add_argument("--copy-doubles", type=int, default=64 * 1024 * 1024)
     ap.add_argument("--workload", required=True)
+    ap.add_argument("--bench", nargs="*", default=[],
+                    help="LABEL=FILE of bench.py's JSON line (the profiled run's output, and "
+                         "the same workload's unprofiled run)")
     ap.add_argument("--out", default="profiles")
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
@@ -130,6 +147,28 @@ def main():
         for r in launch_shapes(a.trace)[:10]:
             f.write(f"| `{short(r['name'])}` | {r['grid']} | {r['calls']} | "
                     f"{r['avg_ns'] / 1e3:.2f} | {r['vgpr']} |\n")
+        shapes = launch_shapes(a.trace)
+        f.write(f"\nThe kernels of the benchmark step (one launch each over {a.points} points; "
+                "every dispatch of that kernel at that size in the run, the step's and the "
+                "other rows' alike):\n\n"
+                "| kernel | grid (work-items) | calls | average (us) | min (us) | max (us) |\n"
+                "|---|---|---|---|---|---|\n")
+        for kernel, needle in OPS.items():
+            for r in shapes:
+                if r["name"].startswith("void tl::k_points<" + needle) and r["grid"] == a.points:
+                    f.write(f"| `{short(r['name'])}` ({kernel}) | {r['grid']} | {r['calls']} | "
+                            f"{r['avg_ns'] / 1e3:.2f} | {r['min_ns'] / 1e3:.2f} | "
+                            f"{r['max_ns'] / 1e3:.2f} |\n")
+        lines = bench_lines(a.bench)
+        if lines:
+            f.write("\nbench.py's own timing of its dominant kernel (HIP events on the kernel's "
+                    "stream, averaged over the timed region):\n\n"
+                    "| run | kernel | average (us) | achieved (GB/s) | fraction of peak |\n"
+                    "|---|---|---|---|---|\n")
+            for label, d in lines:
+                r = d["roofline"]
+                f.write(f"| {label} | {r['kernel']} | {r['duration_us']:.2f} | "
+                        f"{r['achieved']:.1f} | {r['frac']:.4f} |\n")
     print("wrote", path)
 
     if not (a.fetch and a.write):
