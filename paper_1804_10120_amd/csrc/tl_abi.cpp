@@ -86,8 +86,6 @@ struct Checker {
 
   tl_status overlaps() {
     if (st != TL_OK) return st;
-    const Span* a = nullptr;
-    const Span* b = nullptr;
     const char* x = nullptr;
     const char* y = nullptr;
     if (overlapping(spans, &x, &y)) return st = fail(TL_ERR_ALIAS, "%s overlaps %s", x, y);
@@ -398,9 +396,8 @@ tl_status tl_dtg(int64_t n, tl_cfield alpha, tl_cfield K, tl_cfield nabla_beta, 
   return run(tl::KernelId::Dtg, c, tune, a, stream);
 }
 
-static void chain_fields(Checker& c, const char* prefix, tl_cfield g, tl_cfield dg, tl_cfield beta,
-                         tl_cfield dbeta, tl_cfield K, tl_cfield alpha, tl_field dtg) {
-  (void)prefix;
+static void chain_fields(Checker& c, tl_cfield g, tl_cfield dg, tl_cfield beta, tl_cfield dbeta,
+                         tl_cfield K, tl_cfield alpha, tl_field dtg) {
   c.field("g", g.ptr, g.ld, 6, false);
   c.field("dg", dg.ptr, dg.ld, 18, false);
   c.field("beta", beta.ptr, beta.ld, 3, false);
@@ -430,7 +427,7 @@ tl_status tl_dtg_chain(int64_t n, tl_cfield g, tl_cfield dg, tl_cfield beta, tl_
   if (n < 0) return fail(TL_ERR_SIZE, "n=%lld < 0", (long long)n);
   if (n == 0) return TL_OK;
   Checker c(n);
-  chain_fields(c, "", g, dg, beta, dbeta, K, alpha, dtg);
+  chain_fields(c, g, dg, beta, dbeta, K, alpha, dtg);
   if (c.overlaps() != TL_OK) return c.st;
   return run(tl::KernelId::Chain, c, tune, chain_args(g, dg, beta, dbeta, K, alpha, dtg), stream);
 }
@@ -788,7 +785,7 @@ tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tun
     if (x.n < 0) return fail(TL_ERR_SIZE, "domain %d: n=%lld < 0", d, (long long)x.n);
     Checker c(x.n);
     if (x.n > 0) {
-      chain_fields(c, "", x.g, x.dg, x.beta, x.dbeta, x.K, x.alpha, x.dtg);
+      chain_fields(c, x.g, x.dg, x.beta, x.dbeta, x.K, x.alpha, x.dtg);
       if (c.overlaps() != TL_OK) return fail(c.st, "domain %d: %s", d, g_last_error.c_str());
     }
     in.add(x.n, x.n > 0 ? chain_args(x.g, x.dg, x.beta, x.dbeta, x.K, x.alpha, x.dtg)
