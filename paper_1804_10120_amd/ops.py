@@ -282,6 +282,8 @@ def tl_dtg_chain_bwd(g, dg, beta, K, alpha, w, g_bar=None, dg_bar=None, beta_bar
     for t, name in ((g, "g"), (dg, "dg"), (beta, "beta"), (K, "K"), (alpha, "alpha"), (w, "w")):
         c.add(t, name)
     want = (True,) * 6 if want is None else tuple(bool(x) for x in want)
+    if len(want) != 6:
+        raise ValueError("tl_dtg_chain_bwd: want has 6 entries")
     outs = [g_bar, dg_bar, beta_bar, dbeta_bar, K_bar, alpha_bar]
     ncomp = (6, 18, 3, 9, 6, 1)
     likes = (g, dg, beta, dg, K, alpha)
@@ -338,7 +340,8 @@ def tl_bw_copy(src, dst=None, *, stream=None):
         raise ValueError("tl_bw_copy: src must be a contiguous float64 device tensor")
     if dst is None:
         dst = torch.empty_like(src)
-    if dst.shape != src.shape or not dst.is_contiguous() or dst.dtype != torch.float64:
+    if dst.shape != src.shape or not dst.is_contiguous() or dst.dtype != torch.float64 \
+            or dst.device != src.device:
         raise ValueError("tl_bw_copy: dst must match src")
     with torch.cuda.device(src.device):
         args = (src.numel(), ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
@@ -550,6 +553,7 @@ class BatchPlan:
             pass
 
 
-__all__ = ["record", "Prepared", "tl_sym_inverse", "tl_christoffel", "tl_cov_deriv", "tl_dtg", "tl_dtg_chain",
-           "tl_dtg_chain_bwd", "tl_bw_copy", "tl_bw_twin", "tl_expr", "tl_expr_shape",
-           "tl_kernel_info", "BatchPlan", "TLError"]
+__all__ = ["record", "Prepared", "tl_sym_inverse", "tl_christoffel", "tl_cov_deriv", "tl_dtg",
+           "tl_dtg_chain", "tl_dtg_chain_bwd", "tl_dtg_chain_fwd_bwd", "tl_bw_copy", "tl_bw_read",
+           "tl_bw_write", "tl_bw_twin", "tl_expr", "tl_expr_shape", "tl_kernel_info", "BatchPlan",
+           "TLError", "empty_field", "to_field", "padded_ld", "LD_ALIGN"]
