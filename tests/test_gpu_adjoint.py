@@ -80,6 +80,21 @@ def test_bwd_full_size_128_sampled():
         assert_close(x[:, ti], ref[k], what=f"{k}_bar 128^3")
 
 
+@pytest.mark.parametrize("tune", [dict(block=1024, ppt=2, nt=True, xcd=True),
+                                  dict(block=512, ppt=2, nt=True)], ids=_tid)
+def test_bwd_two_point_shapes_full_size(tune):
+    """Two points per lane (16-byte loads and stores) at 128^3 points against
+    one point per lane, element by element: the 16-byte stores are written with
+    explicit wait states, and a missing one shows only at this size, as a
+    fraction of a percent of wrong points."""
+    n = 128 ** 3
+    f = make_fields(n, seed=config_seed(3) + 1)
+    ref = _bwd(f)
+    got = _bwd(f, tune)
+    for k, x, r in zip(KEYS, got, ref):
+        assert_close(x, r, what=f"{k}_bar 128^3 {_tid(tune)}")
+
+
 @pytest.mark.parametrize("want", [(1, 0, 0, 0, 0, 0), (0, 1, 0, 0, 0, 0), (0, 0, 1, 0, 1, 0),
                                   (0, 0, 0, 1, 0, 1), (1, 1, 1, 1, 1, 1)])
 @pytest.mark.parametrize("tune", [None, dict(block=128, ppt=2, nt=True, xcd=True)], ids=_tid)

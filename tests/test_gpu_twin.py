@@ -33,6 +33,23 @@ def test_twin(nin, nout, n, tune):
     assert dst.canaries_intact()
 
 
+@pytest.mark.parametrize("nin,nout", [(40, 43), (24, 18)])
+@pytest.mark.parametrize("tune", [dict(block=1024, ppt=2, nt=True, xcd=True),
+                                  dict(block=512, ppt=2, nt=True)], ids=["b1024ppt2", "b512ppt2"])
+def test_twin_two_point_stores_full_size(nin, nout, tune):
+    """Two points per lane (16-byte stores with explicit wait states) over 2^21
+    points and a ragged tail, every element exact."""
+    n = (1 << 21) + 6
+    gen = torch.Generator(device="cuda").manual_seed(nin * 7 + nout)
+    src = torch.randn(nin, n, dtype=torch.float64, device="cuda", generator=gen)
+    dst = tl_bw_twin(src, nout, tune=tune)
+    s = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for i in range(nin):          # the kernel's summation order
+        s = s + src[i]
+    for c in range(nout):
+        assert torch.equal(dst[c], s + c), f"component {c}"
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 1001, 1 << 20])
 def test_copy(n):
     src = torch.randn(n, dtype=torch.float64, device="cuda")
