@@ -50,6 +50,21 @@ def test_twin_two_point_stores_full_size(nin, nout, tune):
         assert torch.equal(dst[c], s + c), f"component {c}"
 
 
+def test_more_than_2_31_points():
+    """The streaming template's index arithmetic beyond 2^31 points (one
+    component in and out, 17 GB each, 64-bit addressing), every element, in
+    the default shape and with two points per lane."""
+    n = (1 << 31) + 1029
+    src = torch.arange(n, dtype=torch.float64, device="cuda").view(1, n)
+    dst = torch.empty(1, n, dtype=torch.float64, device="cuda")
+    for tune in (None, dict(block=512, ppt=2, nt=True)):
+        dst.fill_(-1.0)
+        tl_bw_twin(src, 1, dst, tune=tune)
+        assert torch.equal(dst, src), tune
+    del src, dst
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 1001, 1 << 20])
 def test_copy(n):
     src = torch.randn(n, dtype=torch.float64, device="cuda")
