@@ -249,3 +249,48 @@ def test_bwd_plan_full_multidomain_workload():
             for k, o in zip(GRADS, outs):
                 assert_close(o, ref[k], what=f"subgrid {i} {k}_bar vs oracle")
     plan.close()
+
+
+def test_blocked_layout_through_plans():
+    """A grid cut into blocks of T points whose fields lie next to each other
+    in one allocation per block ([blocks][components][T]), run as one plan
+    per direction: equal to the plain kernels on the same values stored
+    component-major, and to the oracle."""
+    T, nb = 4096, 6
+    ncin = {"g": 6, "dg": 18, "beta": 3, "dbeta": 9, "K": 6, "alpha": 1, "W": 6}
+    f = make_fields(T * nb, seed=31)
+    blk = torch.empty(nb, sum(ncin.values()) * T, dtype=torch.float64, device="cuda")
+    fwd_out = torch.empty(nb, 6 * T, dtype=torch.float64, device="cuda")
+    bwd_out = torch.empty(nb, 43 * T, dtype=torch.float64, device="cuda")
+    fdoms, bdoms = [], []
+    for b in range(nb):
+        views, o = {}, 0
+        for k, c in ncin.items():
+            views[k] = blk[b, o * T:(o + c) * T].view(c, T)
+            views[k].copy_(torch.from_numpy(np.ascontiguousarray(f[k][:, b * T:(b + 1) * T])))
+            o += c
+        fdoms.append(dict({k: views[k] for k in KEYS}, dtg=fwd_out[b].view(6, T)))
+        grads, o = {}, 0
+        for k, c in zip(GRADS, (6, 18, 3, 9, 6, 1)):
+            grads[k + "_bar"] = bwd_out[b, o * T:(o + c) * T].view(c, T)
+            o += c
+        bdoms.append(dict({k: views[k] for k in ("g", "dg", "beta", "K", "alpha", "W")}, **grads))
+    pf, pb = BatchPlan(fdoms), BatchPlan(bdoms, kind="bwd")
+    pf.run()
+    pb.run()
+    torch.cuda.synchronize()
+    flat = {k: dev(f[k]) for k in ncin}
+    dtg = tl_dtg_chain(*[flat[k] for k in KEYS])
+    grads = tl_dtg_chain_bwd(flat["g"], flat["dg"], flat["beta"], flat["K"], flat["alpha"],
+                             flat["W"])
+    ref_fwd = oracle.dtg_chain(*[f[k] for k in KEYS])
+    ref_bwd = oracle.dtg_chain_vjp(tuple(f[k] for k in KEYS), f["W"])
+    got_fwd = torch.cat(pf.outputs, dim=1)
+    assert_close(got_fwd, dtg.cpu().numpy(), what="blocked d_t g vs plain")
+    assert_close(got_fwd, ref_fwd, what="blocked d_t g vs oracle")
+    for i, k in enumerate(GRADS):
+        got = torch.cat([outs[i] for outs in pb.outputs], dim=1)
+        assert_close(got, grads[i].cpu().numpy(), what=f"blocked {k}_bar vs plain")
+        assert_close(got, ref_bwd[k], what=f"blocked {k}_bar vs oracle")
+    pf.close()
+    pb.close()
