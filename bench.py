@@ -105,6 +105,61 @@ def rate(nbytes, ms):
     return nbytes / (ms * 1e-3) / 1e9
 
 
+def blocked_layout(d, n, T=4096):
+    """The benchmark grid cut into blocks of T points, each block holding all
+    its components together ([n/T][C][T], the way a multi-domain code stores
+    each element's fields), run as one forward and one adjoint batch plan with
+    one subgrid per block.  Returns the timings and the largest relative
+    difference from the outputs of the non-batched kernels on the
+    component-major fields (d["dtg"], d["grads"])."""
+    import torch
+    from paper_1804_10120_amd import BatchPlan
+    from paper_1804_10120_amd.ops import GRAD_NAMES
+    if n % T:
+        return None
+    nb = n // T
+    fields = (("g", 6), ("dg", 18), ("beta", 3), ("dbeta", 9), ("K", 6), ("alpha", 1), ("W", 6))
+    dev = d["g"].device
+    blk = torch.empty(nb, sum(c for _, c in fields) * T, dtype=torch.float64, device=dev)
+    views, o = [{} for _ in range(nb)], 0
+    for k, c in fields:
+        blk[:, o * T:(o + c) * T].view(nb, c, T).copy_(d[k].reshape(c, nb, T).permute(1, 0, 2))
+        for b in range(nb):
+            views[b][k] = blk[b, o * T:(o + c) * T].view(c, T)
+        o += c
+    ncg = (6, 18, 3, 9, 6, 1)
+    fout = torch.empty(nb, 6 * T, dtype=torch.float64, device=dev)
+    bout = torch.empty(nb, sum(ncg) * T, dtype=torch.float64, device=dev)
+    fdoms, bdoms = [], []
+    for b, v in enumerate(views):
+        fdoms.append(dict({k: v[k] for k in KEYS}, dtg=fout[b].view(6, T)))
+        grads, o = {}, 0
+        for k, c in zip(GRAD_NAMES, ncg):
+            grads[k + "_bar"] = bout[b, o * T:(o + c) * T].view(c, T)
+            o += c
+        bdoms.append(dict({k: v[k] for k in ("g", "dg", "beta", "K", "alpha", "W")}, **grads))
+    pf, pb = BatchPlan(fdoms), BatchPlan(bdoms, kind="bwd")
+    _, (ms_f, ms_b) = time_calls([[pf.run, pb.run]], 20, 3)
+
+    def unblock(x, c):
+        return x.view(nb, c, T).permute(1, 0, 2).reshape(c, n)
+
+    diffs = [unblock(fout, 6) - d["dtg"].reshape(6, n)]
+    scale = [d["dtg"].abs().max()]
+    o = 0
+    for c, ref in zip(ncg, d["grads"]):
+        diffs.append(unblock(bout[:, o * T:(o + c) * T], c) - ref.reshape(c, n))
+        scale.append(ref.abs().max())
+        o += c
+    rel = max(float(x.abs().max() / s) for x, s in zip(diffs, scale))
+    pf.close()
+    pb.close()
+    return {"block_points": T, "blocks": nb,
+            "fwd_us": ms_f * 1e3, "fwd_GB_s": rate(BYTES["dtg_chain"] * n, ms_f),
+            "bwd_us": ms_b * 1e3, "bwd_GB_s": rate(BYTES["dtg_chain_bwd"] * n, ms_b),
+            "max_rel_diff_vs_component_major": rel}
+
+
 def copy_ceiling(device, reps=20):
     """GB/s of the library's streaming copy over 2 x 512 MiB."""
     import torch
@@ -567,6 +622,8 @@ def main():
                                    "graph_points_per_s": n64 / (ms_g64 * 1e-3 / 8)}
         del s64, lists, outs64, g64
 
+        log("[bench] blocked field layout, batch plans over blocks of 4096 points")
+        rows["blocked_layout"] = blocked_layout(d, n)
         log("[bench] 256 subgrids")
         edges = domain_edges(256, seed=config_seed(4))
         hosts = [make_fields(int(e) ** 3, seed=config_seed(4) * 1000 + i, fields=KEYS)
