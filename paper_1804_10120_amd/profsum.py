@@ -134,7 +134,8 @@ def main():
     path = os.path.join(a.out, f"kernel_stats_{a.workload}.md")
     with open(path, "w") as f:
         f.write(f"# rocprofv3 kernel statistics: {a.workload}\n\n")
-        f.write(f"Command ($REPO is the repository root; run from /tmp with TMPDIR=/tmp):\n\n"
+        f.write(f"Command ($REPO is the repository root, $OUT the directory the results went to; "
+                f"run from /tmp with TMPDIR=/tmp):\n\n"
                 f"    {a.cmd}\n\n")
         f.write("| kernel | calls | average (us) | total (us) | % |\n|---|---|---|---|---|\n")
         for r in st[:20]:
@@ -195,7 +196,8 @@ def main():
         path = os.path.join(a.out, f"pmc_{kernel}.md")
         with open(path, "w") as f:
             f.write(f"# HBM traffic of {kernel}: {a.workload}\n\n"
-                    f"Two counter runs, one counter each ($REPO is the repository root; run "
+                    f"Two counter runs, one counter each ($REPO is the repository root, $OUT the "
+                    f"directory the results went to; run "
                     f"from /tmp with TMPDIR=/tmp):\n\n"
                     f"    {a.pmc_cmd.replace('COUNTER', 'FETCH_SIZE')}\n"
                     f"    {a.pmc_cmd.replace('COUNTER', 'WRITE_SIZE')}\n\n"
