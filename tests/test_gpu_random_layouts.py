@@ -30,16 +30,10 @@ SETTINGS = settings(max_examples=40, deadline=None, derandomize=True,
                     suppress_health_check=list(HealthCheck))
 
 
-def _skip_spilling(tune):
-    return tune is not None and tune["block"] == 1024 and tune["ppt"] == 2
-
-
 @SETTINGS
 @given(n=st.integers(1, 5000), tune=tunes, lay=layouts, seed=st.integers(0, 10 ** 6))
 def test_chain_random(n, tune, lay, seed):
     need_gpu()
-    if _skip_spilling(tune):
-        return
     f = make_fields(n, seed=seed)
     ins = [DevField(f[k], pad=lay[0], offset=lay[1]) for k in KEYS]
     out = DevField.empty(6, n, pad=lay[0] + 1, offset=lay[1])
@@ -54,8 +48,6 @@ def test_chain_random(n, tune, lay, seed):
        one_pass=st.booleans())
 def test_adjoint_random(n, tune, lay, seed, one_pass):
     need_gpu()
-    if _skip_spilling(tune):
-        return
     f = make_fields(n, seed=seed)
     ref = oracle.dtg_chain_vjp(tuple(f[k] for k in KEYS), f["W"])
     dev = {k: DevField(f[k], pad=lay[0], offset=lay[1]).view for k in KEYS + ("W",)}
