@@ -342,3 +342,12 @@ def test_bwd_plan_validation(L):
     arr[1].g_bar = Field(BASE + 1 * MB + 8, n)
     assert L.tl_batch_plan_bwd_create(arr, 2, bad, ctypes.byref(plan)) == _abi.TL_ERR_ALIAS
     assert not plan.value
+
+
+def test_missing_library_raises(monkeypatch, tmp_path):
+    """Without libtl.so every entry point fails loudly: there is no fallback."""
+    from paper_1804_10120_amd import _abi
+    monkeypatch.setattr(_abi, "LIB_PATH", str(tmp_path / "libtl.so"))
+    monkeypatch.setattr(_abi, "_lib", None)
+    with pytest.raises(RuntimeError, match="no fallback"):
+        _abi.lib()
