@@ -1,9 +1,9 @@
 // Per-grid-point bodies of the tensor expressions (device code, gfx950).
 //
 // Every body maps the components of one grid point, gathered into registers,
-// to the output components of that point.  The kernels in tl_kernels.hip load
-// and store the components (component-major fields, one coalesced stream per
-// component) and call these bodies; all index arithmetic below is on
+// to the output components of that point.  The kernel templates (tl_stream.hpp)
+// load and store the components (component-major fields, one coalesced stream
+// per component) and call these bodies; all index arithmetic below is on
 // compile-time constants, so after unrolling every tensor lives in registers.
 //
 // Component orders are those of include/tl.h: symmetric pair s(i,j) in the
@@ -33,8 +33,9 @@ __device__ inline void cofactors(const double* g, double* cof, double& det) {
 }
 
 // ---------------------------------------------------------------- inverse
-// g^ij of the symmetric 3x3 g_ij: adjugate times one IEEE reciprocal of the
-// determinant.
+// g^ij of the symmetric 3x3 g_ij (the inverse metric of the Christoffel
+// definition, Sec. 1, eq:SpatialChristoffel): adjugate times one IEEE
+// reciprocal of the determinant.
 struct OpSymInverse {
   static constexpr int NF_IN = 1, NF_OUT = 1;
   static constexpr int fin[NF_IN] = {6};
@@ -50,7 +51,8 @@ struct OpSymInverse {
 };
 
 // ---------------------------------------------------------------- Christoffel
-// Gamma^i_jk = sum_l g^il Gamma_ljk with the first-kind symbols
+// Gamma^i_jk (Sec. 1, eq:SpatialChristoffel) = sum_l g^il Gamma_ljk with the
+// first-kind symbols
 // Gamma_ljk = 1/2 (d_k g_jl + d_j g_lk - d_l g_jk) (each needed once per l and
 // pair jk, so 18 of them, then 54 multiply-adds to raise the index).
 struct OpChristoffel {
@@ -80,7 +82,8 @@ struct OpChristoffel {
 };
 
 // ---------------------------------------------------------------- nabla beta
-// nabla_j beta_i = d_j beta_i - Gamma^k_ij beta_k.
+// nabla_j beta_i = d_j beta_i - Gamma^k_ij beta_k (Sec. 1, the footnote to the
+// schematic listing of eq:dtg_ij).
 struct OpCovDeriv {
   static constexpr int NF_IN = 3, NF_OUT = 1;
   static constexpr int fin[NF_IN] = {18, 3, 9};
@@ -101,7 +104,7 @@ struct OpCovDeriv {
 };
 
 // ---------------------------------------------------------------- d_t g
-// d_t g_ij = -2 alpha K_ij + nabla_i beta_j + nabla_j beta_i.
+// d_t g_ij = -2 alpha K_ij + nabla_i beta_j + nabla_j beta_i (Sec. 1, eq:dtg_ij).
 struct OpDtg {
   static constexpr int NF_IN = 3, NF_OUT = 1;
   static constexpr int fin[NF_IN] = {1, 6, 9};
@@ -119,7 +122,8 @@ struct OpDtg {
 };
 
 // ---------------------------------------------------------------- fused chain
-// Reduced form of the chain.  With b^l = g^lk beta_k,
+// Reduced form of the chain (eq:dtg_ij with eq:SpatialChristoffel substituted,
+// Sec. 1).  With b^l = g^lk beta_k,
 //   Gamma^k_ij beta_k = 1/2 b^l (d_j g_il + d_i g_lj - d_l g_ij),
 // so with A[k][i] = sum_l b^l d_k g_il and B_ij = sum_l b^l d_l g_ij
 //   d_t g_ij = -2 alpha K_ij + d_i beta_j + d_j beta_i - (A[j][i] + A[i][j] - B_ij).
