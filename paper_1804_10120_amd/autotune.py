@@ -14,6 +14,7 @@ import itertools
 import json
 import math
 import os
+import threading
 
 import torch
 
@@ -50,18 +51,33 @@ def cache_key(kernel, n):
     return f"{kernel}|{_arch()}|log2n={int(math.log2(max(n, 1)))}"
 
 
+_loaded = {}     # cache path -> (modification time, contents): tune="auto" looks up per call
+
+
 def load_cache():
+    p = cache_path()
     try:
-        with open(cache_path()) as f:
-            return json.load(f)
+        mtime = os.stat(p).st_mtime_ns
+    except OSError:
+        return {}
+    hit = _loaded.get(p)
+    if hit is not None and hit[0] == mtime:
+        return dict(hit[1])
+    try:
+        with open(p) as f:
+            c = json.load(f)
     except (OSError, ValueError):
         return {}
+    _loaded[p] = (mtime, c)
+    return dict(c)
 
 
 def save_cache(c):
+    """Writes the cache atomically (a private temporary file, then a rename), so
+    concurrent tuners never leave a partial file."""
     p = cache_path()
     os.makedirs(os.path.dirname(p), exist_ok=True)
-    tmp = p + ".tmp"
+    tmp = f"{p}.{os.getpid()}.{threading.get_ident()}.tmp"
     with open(tmp, "w") as f:
         json.dump(c, f, indent=1, sort_keys=True)
     os.replace(tmp, p)

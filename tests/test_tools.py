@@ -96,3 +96,20 @@ def test_record_is_per_thread():
         assert ops._recording() is calls
     assert seen["other"] is None
     assert ops._recording() is None
+
+
+def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
+    """The tuning cache: atomic writes leave no temporary file, and a read after
+    a new write sees the new contents (reads are memoised per file version)."""
+    from paper_1804_10120_amd import autotune
+    path = tmp_path / "sub" / "tune.json"
+    monkeypatch.setenv("TLMI_TUNE_CACHE", str(path))
+    assert autotune.load_cache() == {}
+    autotune.save_cache({"k|gfx950|log2n=21": {"tune": {"block": 256}}})
+    assert autotune.load_cache()["k|gfx950|log2n=21"]["tune"] == {"block": 256}
+    c = autotune.load_cache()
+    c["other"] = {"tune": {"block": 64}}
+    assert "other" not in autotune.load_cache()      # callers get a copy
+    autotune.save_cache(c)
+    assert autotune.load_cache()["other"]["tune"] == {"block": 64}
+    assert sorted(p.name for p in path.parent.iterdir()) == ["tune.json"]
