@@ -1,13 +1,20 @@
 """HIP emitter: a Program becomes a streaming per-point body for gfx950, a
 C-ABI entry point ``tlg_<name>``, a header declaration and a manifest entry.
 
-The body loads every referenced input component once (all loads first, so
-they are in flight together), evaluates the statements with every index
-substituted and every sum unrolled (straight-line FP64 code; the compiler
-shares common subexpressions), keeps temporaries in registers and stores each
-output component as soon as it is computed.  It runs through the library's
-streaming template, so it gets the same launch shapes, non-temporal accesses
-and XCD order as the hand-written kernels.
+The body evaluates the statements with every index substituted and every sum
+unrolled (straight-line FP64 code; the compiler shares common
+subexpressions), keeps temporaries in registers and stores each output
+component as soon as it is computed.  Before unrolling, factors that do not
+depend on a sum's index are moved out of the sum, so a chain of contractions
+is evaluated one index at a time (the partial sums are shared between the
+output components that need them); the output components are then visited
+with the indices of the innermost factors outermost, so that the partial sums
+of one slice are used up before the next slice's are formed.  A body with few
+inputs loads them all first (so they are in flight together); one with many
+loads each input at its first use and keeps the compiler from moving work
+between slices, so only one slice's inputs are live at a time.  The body runs
+through the library's streaming template, so it gets the same launch shapes,
+non-temporal accesses and XCD order as the hand-written kernels.
 """
 from __future__ import annotations
 
@@ -39,10 +46,73 @@ def tensor_text(t) -> str:
     return f"{t.name} [{t.ncomp}] ({dims}{sym})"
 
 
-# Programs with more input components than WIDE_INPUTS keep them all live and
-# run in blocks of at most WIDE_MAX_BLOCK threads, which their registers fit.
+# Programs with more input components than WIDE_INPUTS run in blocks of at
+# most WIDE_MAX_BLOCK threads.  Programs with more than LAZY_INPUTS load each
+# input at its first use, slice by slice, instead of all inputs first.
 WIDE_INPUTS = 100
 WIDE_MAX_BLOCK = 256
+LAZY_INPUTS = 64
+
+
+def _factors(e):
+    if isinstance(e, Bin) and e.op == "*":
+        return _factors(e.a) + _factors(e.b)
+    return [e]
+
+
+def _product(fs):
+    out = fs[0]
+    for f in fs[1:]:
+        out = Bin("*", out, f)
+    return out
+
+
+def _depends(e, index) -> bool:
+    return any(x is index for x in e.free())
+
+
+def factor_sums(e):
+    """The expression with every factor that does not depend on a sum's index
+    moved out of that sum (innermost sums first): Sum(m, Sum(n, B(i,m) C(j,n)
+    E(m,n,k))) becomes Sum(m, B(i,m) Sum(n, C(j,n) E(m,n,k))).  Exact algebra;
+    only the rounding order changes."""
+    if isinstance(e, SumExpr):
+        fs = _factors(factor_sums(e.body))
+        indep = [f for f in fs if not _depends(f, e.index)]
+        dep = [f for f in fs if _depends(f, e.index)]
+        inner = SumExpr(e.index, _product(dep))
+        return _product(indep + [inner]) if indep else inner
+    if isinstance(e, Bin):
+        return Bin(e.op, factor_sums(e.a), factor_sums(e.b))
+    if isinstance(e, Neg):
+        return Neg(factor_sums(e.a))
+    return e
+
+
+def index_order(lhs_free, rhs):
+    """The left-hand indices, outermost first: those met deepest inside the
+    sums of the (factored) right-hand side first, among equals those of the
+    larger tensor, then in written order."""
+    depth, size = {}, {}
+
+    def walk(e, d):
+        if isinstance(e, Ref):
+            for a in e.free():
+                if depth.get(id(a), -1) < d or (depth[id(a)] == d and
+                                                size[id(a)] < e.tensor.ncomp):
+                    depth[id(a)], size[id(a)] = d, e.tensor.ncomp
+        elif isinstance(e, Bin):
+            walk(e.a, d)
+            walk(e.b, d)
+        elif isinstance(e, Neg):
+            walk(e.a, d)
+        elif isinstance(e, SumExpr):
+            walk(e.body, d + 1)
+
+    walk(rhs, 0)
+    pos = {id(x): k for k, x in enumerate(lhs_free)}
+    return sorted(lhs_free, key=lambda x: (-depth.get(id(x), 0), -size.get(id(x), 0),
+                                           pos[id(x)]))
 
 
 class _Emitter:
@@ -54,7 +124,9 @@ class _Emitter:
         self.fin = {t: f for f, t in enumerate(self.ins)}
         self.fout = {t: f for f, t in enumerate(self.outs)}
         self.loaded = {}         # (field, comp) -> variable
+        self.pending = []        # loads referenced since the last statement was emitted
         self.written = set()     # (field, comp) of outputs with a value
+        self.lazy = sum(t.ncomp for t in self.ins) > LAZY_INPUTS
 
     def ref(self, e: Ref, env) -> str:
         t = e.tensor
@@ -65,6 +137,7 @@ class _Emitter:
             key = (self.fin[t], c)
             if key not in self.loaded:
                 self.loaded[key] = f"x{key[0]}_{c}"
+                self.pending.append(key)
             return self.loaded[key]
         f = self.fout[t]
         if (f, c) not in self.written:
@@ -85,6 +158,11 @@ class _Emitter:
                                     for v in range(e.index.dim)) + ")"
         raise CodegenError(repr(e))
 
+    def _flush_loads(self, out):
+        for f, c in self.pending:
+            out.append(f"    const double {self.loaded[(f, c)]} = ld({f}, {c});")
+        self.pending = []
+
     def body(self) -> str:
         lines = []
         for t in self.p.temps:
@@ -94,8 +172,19 @@ class _Emitter:
         for st in self.p.statements:
             stmts.append(f"    // {statement_text(st)}")
             t = st.lhs.tensor
-            for c, env in st.assignments():
-                rhs = self.expr(st.rhs, env)
+            rhs_f = factor_sums(st.rhs)
+            order = index_order(st.lhs.free(), rhs_f)
+            todo = sorted(st.assignments(), key=lambda ce: tuple(ce[1][x] for x in order))
+            outer = None
+            for c, env in todo:
+                if self.lazy and order:
+                    if outer is not None and env[order[0]] != outer:
+                        # the next slice: nothing moves across this point
+                        stmts.append("    __builtin_amdgcn_sched_barrier(0);")
+                    outer = env[order[0]]
+                rhs = self.expr(rhs_f, env)
+                if self.lazy:
+                    self._flush_loads(stmts)
                 if t in self.p.temps:
                     stmts.append(f"    t_{t.name}[{c}] = {rhs};")
                 else:
@@ -106,6 +195,8 @@ class _Emitter:
                     self.written.add((f, c))
                     stmts.append(f"    {decl}{var} = {rhs};")
                     stmts.append(f"    st({f}, {c}, {var});")
+        if self.lazy:
+            return "\n".join(lines + stmts)
         loads = [f"    const double {v} = ld({f}, {c});"
                  for (f, c), v in sorted(self.loaded.items())]
         return "\n".join(lines + loads + stmts)
@@ -117,7 +208,7 @@ class _Emitter:
         fout = ", ".join(str(t.ncomp) for t in self.outs)
         nin = sum(t.ncomp for t in self.ins)
         cap = (f"\n  static constexpr int kMaxBlock = {WIDE_MAX_BLOCK};  // more than "
-               f"{WIDE_INPUTS} inputs live" if nin > WIDE_INPUTS else "")
+               f"{WIDE_INPUTS} inputs" if nin > WIDE_INPUTS else "")
         return f"""// {p.name}: {p.doc}
 struct Gen_{p.name} {{
   static constexpr bool kStream = true;{cap}

@@ -108,3 +108,51 @@ def test_generated_entry_points_are_exported_and_validate():
     assert fn(8, cin, 1, cout, 1, None, None) == _abi.TL_ERR_INVALID     # nin must be 2
     man = json.load(open(FILES["manifest"]))
     assert [p["name"] for p in man["programs"]] == [p.name for p in registry.programs()]
+
+
+def _evaluate(e, env, vals):
+    """Plain recursive evaluation of an index-notation expression (component
+    values from ``vals``), for checking rewrites of the expression tree."""
+    from paper_1804_10120_amd.codegen.dsl import Bin, Const, Neg, Ref, SumExpr
+    if isinstance(e, Const):
+        return e.value
+    if isinstance(e, Ref):
+        return vals[e.tensor.name][e.tensor.comp(e.resolve(env))]
+    if isinstance(e, Neg):
+        return -_evaluate(e.a, env, vals)
+    if isinstance(e, Bin):
+        a, b = _evaluate(e.a, env, vals), _evaluate(e.b, env, vals)
+        return a + b if e.op == "+" else (a - b if e.op == "-" else a * b)
+    if isinstance(e, SumExpr):
+        return sum(_evaluate(e.body, {**env, e.index: v}, vals) for v in range(e.index.dim))
+    raise TypeError(e)
+
+
+def test_sum_factoring_and_slice_order():
+    """Factors free of a sum's index move out of it (the triple contraction
+    becomes one index at a time), the value is unchanged up to rounding, and
+    the left-hand indices of the innermost factors come outermost."""
+    import numpy as np
+    from paper_1804_10120_amd.codegen.dsl import Bin, SumExpr
+    from paper_1804_10120_amd.codegen.emit import factor_sums, index_order
+    i, j, k, l, m, n, o = indices("i j k l m n o")
+    A, B, C, D = (Tensor(x, (3, 3)) for x in "ABCD")
+    E = Tensor("E", (3, 3, 3, 3))
+    R = Tensor("R", (3, 3, 3, 3))
+    rhs = Sum(m, Sum(n, Sum(o, D[k, o] * C[j, n] * B[i, m] * E[m, n, o, l])))
+    f = factor_sums(rhs)
+    # Sum(m, B(i,m) * Sum(n, C(j,n) * Sum(o, D(k,o) * E(m,n,o,l))))
+    assert isinstance(f, SumExpr) and f.index is m
+    assert isinstance(f.body, Bin) and f.body.a.tensor is B
+    inner = f.body.b
+    assert isinstance(inner, SumExpr) and inner.index is n and inner.body.a.tensor is C
+    assert isinstance(inner.body.b, SumExpr) and inner.body.b.index is o
+    rng = np.random.default_rng(3)
+    vals = {t.name: rng.uniform(-1, 1, t.ncomp) for t in (A, B, C, D, E)}
+    for vi, vj, vk, vl in [(0, 0, 0, 0), (2, 1, 0, 2), (1, 2, 2, 1)]:
+        env = {i: vi, j: vj, k: vk, l: vl}
+        assert abs(_evaluate(f, env, vals) - _evaluate(rhs, env, vals)) <= 1e-14
+    assert [x.name for x in index_order(R[i, j, k, l].free(), f)] == ["l", "k", "j", "i"]
+    # a sum whose factors all depend on its index is left as written
+    g = Sum(m, A[i, m] * (E[m, j, k, l] + E[j, m, k, l]))
+    assert factor_sums(g).body.op == "*"
