@@ -69,6 +69,22 @@ FAMILY = ("assign1", "assign2", "assign3", "add1", "add2", "add3", "mult1", "mul
           "contract1", "contract2", "contract3", "kij")
 
 
+@pytest.mark.parametrize("name", ["contract1", "contract2", "contract3"])
+def test_wide_programs_full_size(name):
+    """The programs whose inputs are loaded slice by slice, at 2^21 points and
+    a ragged tail in the default launch shape: every element against the
+    hand-written kernel, sampled points against the oracle."""
+    n = (1 << 21) + 5
+    ins = [torch.rand(c, n, dtype=torch.float64, device="cuda") * 2 - 1
+           for c in (t["ncomp"] for t in programs()[name]["inputs"])]
+    (out,) = call(name, *ins)
+    hand = tl_expr(name, *ins)
+    assert_close(out, hand, what=f"generated {name} vs hand-written, 2^21 + 5 points")
+    idx = torch.tensor([0, 1, 4095, 1 << 20, n - 2, n - 1], device="cuda")
+    sub = [np.ascontiguousarray(x[:, idx].cpu().numpy()) for x in ins]
+    assert_close(out[:, idx], oracle.expr(name, *sub), what=f"generated {name} vs oracle")
+
+
 @pytest.mark.parametrize("name", FAMILY)
 @pytest.mark.parametrize("n", SIZES)
 def test_against_the_expression_kernels(name, n):
