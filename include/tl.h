@@ -126,8 +126,10 @@ tl_status tl_dtg(int64_t n, tl_cfield alpha, tl_cfield K, tl_cfield nabla_beta, 
 
 /* ---- Fused chain ---------------------------------------------------------- */
 
-/* d_t g_ij from g, d g, beta, d beta, K and alpha in one pass: the four steps
- * above with g^ij and Gamma kept in registers (never written to memory),
+/* d_t g_ij from g, d g, beta, d beta, K and alpha in one pass (Sec. 1,
+ * eq:dtg_ij with the covariant derivative of its footnote and
+ * eq:SpatialChristoffel substituted): the four steps above with g^ij and
+ * Gamma kept in registers (never written to memory),
  * evaluated in the equivalent reduced form
  *   b^l = g^lk beta_k,  F_lij = d_j g_il + d_i g_lj - d_l g_ij,
  *   d_t g_ij = -2 alpha K_ij + d_i beta_j + d_j beta_i - b^l F_lij,
@@ -137,7 +139,8 @@ tl_status tl_dtg_chain(int64_t n, tl_cfield g, tl_cfield dg, tl_cfield beta, tl_
                        tl_cfield K, tl_cfield alpha, tl_field dtg, void* stream,
                        const tl_tune* tune);
 
-/* Adjoint of tl_dtg_chain: given w = dL/d(dtg) (6 comps), writes the gradient
+/* Adjoint of tl_dtg_chain (not in the paper: the reverse-mode derivative of the
+ * same definitions): given w = dL/d(dtg) (6 comps), writes the gradient
  * of L with respect to every stored input component (an off-diagonal stored
  * slot of g, dg or K receives the sum of its (i,j) and (j,i) partials).
  * g^ij and b^l are recomputed, not stored.  d beta is not an input: d_t g is
