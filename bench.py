@@ -559,11 +559,20 @@ def main():
                 tl_sym_inverse(e16["g"], gi_g)
                 tl_christoffel(gi_g, e16["dg"], ga_g)
         _, (ms_g,) = time_calls([[graph.replay]], 20, 3)
+        # the Christoffel kernel with the components of a point spread over lanes
+        lanes_us = {}
+        for la in (2, 3, 6, 9, 18):
+            with record() as cl:
+                tl_christoffel(gi16, e16["dg"], tune=dict(block=64, nt=True, lanes=la))
+            _, (ms_l,) = time_calls([cl], 200, 20)
+            lanes_us[str(la)] = ms_l * 1e3
         rows["christoffel_16cubed"] = {
             "points": n16, "sym_inverse_us": ms_i * 1e3, "christoffel_us": ms_c * 1e3,
+            "christoffel_lanes_us": lanes_us,
             "graph_us_per_pair": ms_g * 1e3 / 10,
             "points_per_s": n16 / (ms_g * 1e-3 / 10),
-            "note": "latency-bound: 1.6 MB per pair; graph = 10 pairs per replay"}
+            "note": "latency-bound: 1.6 MB per pair; graph = 10 pairs per replay; "
+                    "christoffel_lanes_us: one point's 18 components over 2..18 lanes"}
         graph.replay()
         torch.cuda.synchronize()
         assert torch.equal(gi_g, gi16)
