@@ -166,11 +166,13 @@ void cov_deriv_point(const T gam27[27], const T beta[3], const T dbeta[9], T nb[
 }
 
 // Metric evolution (Sec. 1, eq:dtg_ij and the schematic/TLoops listings):
-//   d_t g_ij = -2 alpha K_ij + nabla_i beta_j + nabla_j beta_i,  i <= j.
+//   d_t g_ij = -2 alpha K_ij + nabla_i beta_j + nabla_j beta_i,
+// evaluated for i >= j, the member the paper's loops for the Sym<0,1>
+// left-hand side visit (Sec. 2.4: the first index starts at the second).
 template <class T>
 void dtg_point(const T& alpha, const T K[6], const T nb[9], T dtg[6]) {
-  for (int i = 0; i < 3; ++i)
-    for (int j = i; j < 3; ++j)
+  for (int j = 0; j < 3; ++j)
+    for (int i = j; i < 3; ++i)
       dtg[sym(i, j)] = T(-2.0) * alpha * K[sym(i, j)] + nb[i * 3 + j] + nb[j * 3 + i];
 }
 
@@ -366,8 +368,12 @@ void tlo_dtg_chain_vjp(int64_t n, const double* g, const double* dg, const doubl
 //   14  D_(i0) = sum_c E_(i+1)c F_c0, i = 0..2       16 16     10 (3 written)
 //   15  g_ij = psi_(i+1)(j+1)                         10        6
 //   16  beta_i = psi_(i+1)0                           10        3
-// For a symmetric left-hand side with both slots free, the components with
-// a <= b are evaluated (ascending pairs, like the storage order).
+// For a symmetric left-hand side with both slots free, each stored pair is
+// evaluated at the member whose first index is >= the second: the paper's
+// loops for a Sym<0,1> left-hand side start the first index at the value of
+// the second (the tensor-index loop of Sec. 2.4, and the generated C loop and
+// CUDA kernel of the rank-2 contraction example in Sec. 4).  For a right-hand
+// side that is not symmetric this decides which of C_ab and C_ba is stored.
 namespace {
 
 inline int sym4(int a, int b) {
@@ -455,14 +461,14 @@ void expr_point(int id, const std::vector<const double*>& in, double* out) {
     }
     case 12: {  // alpha = in[0], g = in[1], beta = in[2]
       const double alpha = in[0][0];
-      for (int i = 0; i < 3; ++i)
-        for (int j = i; j < 3; ++j)
+      for (int j = 0; j < 3; ++j)
+        for (int i = j; i < 3; ++i)
           out[sym(i, j)] = 2.0 * alpha * in[1][sym(i, j)] + in[2][i] * in[2][j];
       break;
     }
-    case 13: {  // A = in[0], B = in[1], both 4x4 row-major
-      for (int a = 0; a < 4; ++a)
-        for (int b = a; b < 4; ++b) {
+    case 13: {  // A = in[0], B = in[1], both 4x4 row-major; evaluated for a >= b
+      for (int b = 0; b < 4; ++b)
+        for (int a = b; a < 4; ++a) {
           double sum = 0.0;
           for (int c = 0; c < 4; ++c) sum += in[0][a * 4 + c] * in[1][c * 4 + b];
           out[sym4(a, b)] = sum;
@@ -478,8 +484,8 @@ void expr_point(int id, const std::vector<const double*>& in, double* out) {
       break;
     }
     case 15:
-      for (int i = 0; i < 3; ++i)
-        for (int j = i; j < 3; ++j) out[sym(i, j)] = in[0][sym4(i + 1, j + 1)];
+      for (int j = 0; j < 3; ++j)
+        for (int i = j; i < 3; ++i) out[sym(i, j)] = in[0][sym4(i + 1, j + 1)];
       break;
     case 16:
       for (int i = 0; i < 3; ++i) out[i] = in[0][sym4(i + 1, 0)];

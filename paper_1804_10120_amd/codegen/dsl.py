@@ -259,19 +259,29 @@ class Statement:
 
     def assignments(self):
         """(LHS storage component, index environment) for every component the
-        statement writes: free LHS indices run lexicographically, and a
-        component reached again (both slots of a symmetric pair free) is
-        written once, at its first (ascending) tuple."""
+        statement writes, in the order the components are first reached with
+        the free LHS indices running lexicographically.  A component reached
+        by several index tuples (both slots of a symmetric pair free) is
+        written once, evaluated at the tuple whose first slot of each
+        symmetric pair is >= the second: the paper's loops for a symmetric
+        left-hand side start the first index of the pair at the value of the
+        second (the tensor-index loop of Sec. 2.4; the generated C loop and
+        CUDA kernel of the rank-2 contraction example, Sec. 4).  When the
+        right-hand side is not symmetric this decides which of C_ab and C_ba
+        is stored."""
         lf = self.lhs.free()
-        seen = set()
+        sym = self.lhs.tensor.sym
+        where = {}
         out = []
         for vals in itertools.product(*[range(x.dim) for x in lf]):
             env = dict(zip(lf, vals))
-            c = self.lhs.tensor.comp(self.lhs.resolve(env))
-            if c in seen:
-                continue
-            seen.add(c)
-            out.append((c, env))
+            t = self.lhs.resolve(env)
+            c = self.lhs.tensor.comp(t)
+            if c not in where:
+                where[c] = len(out)
+                out.append((c, env))
+            elif all(t[p] >= t[q] for p, q in sym):
+                out[where[c]] = (c, env)
         return out
 
 

@@ -279,6 +279,9 @@ HEADER_TOP = """/*
  *   nin, nout must equal the counts listed; components of a tensor are its
  *   index tuples in lexicographic order, keeping only first <= second within
  *   each symmetric slot pair (so s(i,j) = 00 01 02 11 12 22 for 3x3);
+ *   a component of a symmetric left-hand side is evaluated with the first
+ *   index of the pair >= the second, the member the paper's loops for a
+ *   symmetric left-hand side visit (Sec. 2.4, Sec. 4), and stored in its slot;
  *   an output component that no statement writes is left untouched.
  * Ownership, execution (asynchronous on `stream`), tuning and errors are as
  * for the entry points of tl.h (TL_ERR_INVALID for a wrong nin or nout).

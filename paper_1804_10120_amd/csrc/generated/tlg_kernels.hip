@@ -50,29 +50,29 @@ struct Gen_christoffel {
     st(0, 6, o0_6);
     double o0_12 = (0.5 * ((x0_2 * ((x1_0 + x1_0) - x1_0)) + (x0_4 * ((x1_1 + x1_1) - x1_6)) + (x0_5 * ((x1_2 + x1_2) - x1_12))));
     st(0, 12, o0_12);
-    double o0_1 = (0.5 * ((x0_0 * ((x1_6 + x1_1) - x1_1)) + (x0_1 * ((x1_7 + x1_3) - x1_7)) + (x0_2 * ((x1_8 + x1_4) - x1_13))));
+    double o0_1 = (0.5 * ((x0_0 * ((x1_1 + x1_6) - x1_1)) + (x0_1 * ((x1_3 + x1_7) - x1_7)) + (x0_2 * ((x1_4 + x1_8) - x1_13))));
     st(0, 1, o0_1);
-    double o0_7 = (0.5 * ((x0_1 * ((x1_6 + x1_1) - x1_1)) + (x0_3 * ((x1_7 + x1_3) - x1_7)) + (x0_4 * ((x1_8 + x1_4) - x1_13))));
+    double o0_7 = (0.5 * ((x0_1 * ((x1_1 + x1_6) - x1_1)) + (x0_3 * ((x1_3 + x1_7) - x1_7)) + (x0_4 * ((x1_4 + x1_8) - x1_13))));
     st(0, 7, o0_7);
-    double o0_13 = (0.5 * ((x0_2 * ((x1_6 + x1_1) - x1_1)) + (x0_4 * ((x1_7 + x1_3) - x1_7)) + (x0_5 * ((x1_8 + x1_4) - x1_13))));
+    double o0_13 = (0.5 * ((x0_2 * ((x1_1 + x1_6) - x1_1)) + (x0_4 * ((x1_3 + x1_7) - x1_7)) + (x0_5 * ((x1_4 + x1_8) - x1_13))));
     st(0, 13, o0_13);
-    double o0_2 = (0.5 * ((x0_0 * ((x1_12 + x1_2) - x1_2)) + (x0_1 * ((x1_13 + x1_4) - x1_8)) + (x0_2 * ((x1_14 + x1_5) - x1_14))));
-    st(0, 2, o0_2);
-    double o0_8 = (0.5 * ((x0_1 * ((x1_12 + x1_2) - x1_2)) + (x0_3 * ((x1_13 + x1_4) - x1_8)) + (x0_4 * ((x1_14 + x1_5) - x1_14))));
-    st(0, 8, o0_8);
-    double o0_14 = (0.5 * ((x0_2 * ((x1_12 + x1_2) - x1_2)) + (x0_4 * ((x1_13 + x1_4) - x1_8)) + (x0_5 * ((x1_14 + x1_5) - x1_14))));
-    st(0, 14, o0_14);
     double o0_3 = (0.5 * ((x0_0 * ((x1_7 + x1_7) - x1_3)) + (x0_1 * ((x1_9 + x1_9) - x1_9)) + (x0_2 * ((x1_10 + x1_10) - x1_15))));
     st(0, 3, o0_3);
     double o0_9 = (0.5 * ((x0_1 * ((x1_7 + x1_7) - x1_3)) + (x0_3 * ((x1_9 + x1_9) - x1_9)) + (x0_4 * ((x1_10 + x1_10) - x1_15))));
     st(0, 9, o0_9);
     double o0_15 = (0.5 * ((x0_2 * ((x1_7 + x1_7) - x1_3)) + (x0_4 * ((x1_9 + x1_9) - x1_9)) + (x0_5 * ((x1_10 + x1_10) - x1_15))));
     st(0, 15, o0_15);
-    double o0_4 = (0.5 * ((x0_0 * ((x1_13 + x1_8) - x1_4)) + (x0_1 * ((x1_15 + x1_10) - x1_10)) + (x0_2 * ((x1_16 + x1_11) - x1_16))));
+    double o0_2 = (0.5 * ((x0_0 * ((x1_2 + x1_12) - x1_2)) + (x0_1 * ((x1_4 + x1_13) - x1_8)) + (x0_2 * ((x1_5 + x1_14) - x1_14))));
+    st(0, 2, o0_2);
+    double o0_8 = (0.5 * ((x0_1 * ((x1_2 + x1_12) - x1_2)) + (x0_3 * ((x1_4 + x1_13) - x1_8)) + (x0_4 * ((x1_5 + x1_14) - x1_14))));
+    st(0, 8, o0_8);
+    double o0_14 = (0.5 * ((x0_2 * ((x1_2 + x1_12) - x1_2)) + (x0_4 * ((x1_4 + x1_13) - x1_8)) + (x0_5 * ((x1_5 + x1_14) - x1_14))));
+    st(0, 14, o0_14);
+    double o0_4 = (0.5 * ((x0_0 * ((x1_8 + x1_13) - x1_4)) + (x0_1 * ((x1_10 + x1_15) - x1_10)) + (x0_2 * ((x1_11 + x1_16) - x1_16))));
     st(0, 4, o0_4);
-    double o0_10 = (0.5 * ((x0_1 * ((x1_13 + x1_8) - x1_4)) + (x0_3 * ((x1_15 + x1_10) - x1_10)) + (x0_4 * ((x1_16 + x1_11) - x1_16))));
+    double o0_10 = (0.5 * ((x0_1 * ((x1_8 + x1_13) - x1_4)) + (x0_3 * ((x1_10 + x1_15) - x1_10)) + (x0_4 * ((x1_11 + x1_16) - x1_16))));
     st(0, 10, o0_10);
-    double o0_16 = (0.5 * ((x0_2 * ((x1_13 + x1_8) - x1_4)) + (x0_4 * ((x1_15 + x1_10) - x1_10)) + (x0_5 * ((x1_16 + x1_11) - x1_16))));
+    double o0_16 = (0.5 * ((x0_2 * ((x1_8 + x1_13) - x1_4)) + (x0_4 * ((x1_10 + x1_15) - x1_10)) + (x0_5 * ((x1_11 + x1_16) - x1_16))));
     st(0, 16, o0_16);
     double o0_5 = (0.5 * ((x0_0 * ((x1_14 + x1_14) - x1_5)) + (x0_1 * ((x1_16 + x1_16) - x1_11)) + (x0_2 * ((x1_17 + x1_17) - x1_17))));
     st(0, 5, o0_5);
@@ -172,13 +172,13 @@ struct Gen_dtg {
     // dtg(i,j) = ((((-2.0 * alpha()) * K(i,j)) + nabla(i,j)) + nabla(j,i))
     double o0_0 = ((((-2.0 * x0_0) * x1_0) + x2_0) + x2_0);
     st(0, 0, o0_0);
-    double o0_1 = ((((-2.0 * x0_0) * x1_1) + x2_1) + x2_3);
+    double o0_1 = ((((-2.0 * x0_0) * x1_1) + x2_3) + x2_1);
     st(0, 1, o0_1);
-    double o0_2 = ((((-2.0 * x0_0) * x1_2) + x2_2) + x2_6);
-    st(0, 2, o0_2);
     double o0_3 = ((((-2.0 * x0_0) * x1_3) + x2_4) + x2_4);
     st(0, 3, o0_3);
-    double o0_4 = ((((-2.0 * x0_0) * x1_4) + x2_5) + x2_7);
+    double o0_2 = ((((-2.0 * x0_0) * x1_2) + x2_6) + x2_2);
+    st(0, 2, o0_2);
+    double o0_4 = ((((-2.0 * x0_0) * x1_4) + x2_7) + x2_5);
     st(0, 4, o0_4);
     double o0_5 = ((((-2.0 * x0_0) * x1_5) + x2_8) + x2_8);
     st(0, 5, o0_5);
@@ -243,18 +243,18 @@ struct Gen_dtg_chain_invg {
     t_Gamma[0] = (0.5 * ((x0_0 * ((x1_0 + x1_0) - x1_0)) + (x0_1 * ((x1_1 + x1_1) - x1_6)) + (x0_2 * ((x1_2 + x1_2) - x1_12))));
     t_Gamma[6] = (0.5 * ((x0_1 * ((x1_0 + x1_0) - x1_0)) + (x0_3 * ((x1_1 + x1_1) - x1_6)) + (x0_4 * ((x1_2 + x1_2) - x1_12))));
     t_Gamma[12] = (0.5 * ((x0_2 * ((x1_0 + x1_0) - x1_0)) + (x0_4 * ((x1_1 + x1_1) - x1_6)) + (x0_5 * ((x1_2 + x1_2) - x1_12))));
-    t_Gamma[1] = (0.5 * ((x0_0 * ((x1_6 + x1_1) - x1_1)) + (x0_1 * ((x1_7 + x1_3) - x1_7)) + (x0_2 * ((x1_8 + x1_4) - x1_13))));
-    t_Gamma[7] = (0.5 * ((x0_1 * ((x1_6 + x1_1) - x1_1)) + (x0_3 * ((x1_7 + x1_3) - x1_7)) + (x0_4 * ((x1_8 + x1_4) - x1_13))));
-    t_Gamma[13] = (0.5 * ((x0_2 * ((x1_6 + x1_1) - x1_1)) + (x0_4 * ((x1_7 + x1_3) - x1_7)) + (x0_5 * ((x1_8 + x1_4) - x1_13))));
-    t_Gamma[2] = (0.5 * ((x0_0 * ((x1_12 + x1_2) - x1_2)) + (x0_1 * ((x1_13 + x1_4) - x1_8)) + (x0_2 * ((x1_14 + x1_5) - x1_14))));
-    t_Gamma[8] = (0.5 * ((x0_1 * ((x1_12 + x1_2) - x1_2)) + (x0_3 * ((x1_13 + x1_4) - x1_8)) + (x0_4 * ((x1_14 + x1_5) - x1_14))));
-    t_Gamma[14] = (0.5 * ((x0_2 * ((x1_12 + x1_2) - x1_2)) + (x0_4 * ((x1_13 + x1_4) - x1_8)) + (x0_5 * ((x1_14 + x1_5) - x1_14))));
+    t_Gamma[1] = (0.5 * ((x0_0 * ((x1_1 + x1_6) - x1_1)) + (x0_1 * ((x1_3 + x1_7) - x1_7)) + (x0_2 * ((x1_4 + x1_8) - x1_13))));
+    t_Gamma[7] = (0.5 * ((x0_1 * ((x1_1 + x1_6) - x1_1)) + (x0_3 * ((x1_3 + x1_7) - x1_7)) + (x0_4 * ((x1_4 + x1_8) - x1_13))));
+    t_Gamma[13] = (0.5 * ((x0_2 * ((x1_1 + x1_6) - x1_1)) + (x0_4 * ((x1_3 + x1_7) - x1_7)) + (x0_5 * ((x1_4 + x1_8) - x1_13))));
     t_Gamma[3] = (0.5 * ((x0_0 * ((x1_7 + x1_7) - x1_3)) + (x0_1 * ((x1_9 + x1_9) - x1_9)) + (x0_2 * ((x1_10 + x1_10) - x1_15))));
     t_Gamma[9] = (0.5 * ((x0_1 * ((x1_7 + x1_7) - x1_3)) + (x0_3 * ((x1_9 + x1_9) - x1_9)) + (x0_4 * ((x1_10 + x1_10) - x1_15))));
     t_Gamma[15] = (0.5 * ((x0_2 * ((x1_7 + x1_7) - x1_3)) + (x0_4 * ((x1_9 + x1_9) - x1_9)) + (x0_5 * ((x1_10 + x1_10) - x1_15))));
-    t_Gamma[4] = (0.5 * ((x0_0 * ((x1_13 + x1_8) - x1_4)) + (x0_1 * ((x1_15 + x1_10) - x1_10)) + (x0_2 * ((x1_16 + x1_11) - x1_16))));
-    t_Gamma[10] = (0.5 * ((x0_1 * ((x1_13 + x1_8) - x1_4)) + (x0_3 * ((x1_15 + x1_10) - x1_10)) + (x0_4 * ((x1_16 + x1_11) - x1_16))));
-    t_Gamma[16] = (0.5 * ((x0_2 * ((x1_13 + x1_8) - x1_4)) + (x0_4 * ((x1_15 + x1_10) - x1_10)) + (x0_5 * ((x1_16 + x1_11) - x1_16))));
+    t_Gamma[2] = (0.5 * ((x0_0 * ((x1_2 + x1_12) - x1_2)) + (x0_1 * ((x1_4 + x1_13) - x1_8)) + (x0_2 * ((x1_5 + x1_14) - x1_14))));
+    t_Gamma[8] = (0.5 * ((x0_1 * ((x1_2 + x1_12) - x1_2)) + (x0_3 * ((x1_4 + x1_13) - x1_8)) + (x0_4 * ((x1_5 + x1_14) - x1_14))));
+    t_Gamma[14] = (0.5 * ((x0_2 * ((x1_2 + x1_12) - x1_2)) + (x0_4 * ((x1_4 + x1_13) - x1_8)) + (x0_5 * ((x1_5 + x1_14) - x1_14))));
+    t_Gamma[4] = (0.5 * ((x0_0 * ((x1_8 + x1_13) - x1_4)) + (x0_1 * ((x1_10 + x1_15) - x1_10)) + (x0_2 * ((x1_11 + x1_16) - x1_16))));
+    t_Gamma[10] = (0.5 * ((x0_1 * ((x1_8 + x1_13) - x1_4)) + (x0_3 * ((x1_10 + x1_15) - x1_10)) + (x0_4 * ((x1_11 + x1_16) - x1_16))));
+    t_Gamma[16] = (0.5 * ((x0_2 * ((x1_8 + x1_13) - x1_4)) + (x0_4 * ((x1_10 + x1_15) - x1_10)) + (x0_5 * ((x1_11 + x1_16) - x1_16))));
     t_Gamma[5] = (0.5 * ((x0_0 * ((x1_14 + x1_14) - x1_5)) + (x0_1 * ((x1_16 + x1_16) - x1_11)) + (x0_2 * ((x1_17 + x1_17) - x1_17))));
     t_Gamma[11] = (0.5 * ((x0_1 * ((x1_14 + x1_14) - x1_5)) + (x0_3 * ((x1_16 + x1_16) - x1_11)) + (x0_4 * ((x1_17 + x1_17) - x1_17))));
     t_Gamma[17] = (0.5 * ((x0_2 * ((x1_14 + x1_14) - x1_5)) + (x0_4 * ((x1_16 + x1_16) - x1_11)) + (x0_5 * ((x1_17 + x1_17) - x1_17))));
@@ -271,13 +271,13 @@ struct Gen_dtg_chain_invg {
     // dtg(i,j) = ((((-2.0 * alpha()) * K(i,j)) + nabla(i,j)) + nabla(j,i))
     double o0_0 = ((((-2.0 * x4_0) * x5_0) + t_nabla[0]) + t_nabla[0]);
     st(0, 0, o0_0);
-    double o0_1 = ((((-2.0 * x4_0) * x5_1) + t_nabla[1]) + t_nabla[3]);
+    double o0_1 = ((((-2.0 * x4_0) * x5_1) + t_nabla[3]) + t_nabla[1]);
     st(0, 1, o0_1);
-    double o0_2 = ((((-2.0 * x4_0) * x5_2) + t_nabla[2]) + t_nabla[6]);
-    st(0, 2, o0_2);
     double o0_3 = ((((-2.0 * x4_0) * x5_3) + t_nabla[4]) + t_nabla[4]);
     st(0, 3, o0_3);
-    double o0_4 = ((((-2.0 * x4_0) * x5_4) + t_nabla[5]) + t_nabla[7]);
+    double o0_2 = ((((-2.0 * x4_0) * x5_2) + t_nabla[6]) + t_nabla[2]);
+    st(0, 2, o0_2);
+    double o0_4 = ((((-2.0 * x4_0) * x5_4) + t_nabla[7]) + t_nabla[5]);
     st(0, 4, o0_4);
     double o0_5 = ((((-2.0 * x4_0) * x5_5) + t_nabla[8]) + t_nabla[8]);
     st(0, 5, o0_5);
@@ -306,13 +306,13 @@ struct Gen_kij {
     // K(i,j) = (((2.0 * alpha()) * g(i,j)) + (beta(i) * beta(j)))
     double o0_0 = (((2.0 * x0_0) * x1_0) + (x2_0 * x2_0));
     st(0, 0, o0_0);
-    double o0_1 = (((2.0 * x0_0) * x1_1) + (x2_0 * x2_1));
+    double o0_1 = (((2.0 * x0_0) * x1_1) + (x2_1 * x2_0));
     st(0, 1, o0_1);
-    double o0_2 = (((2.0 * x0_0) * x1_2) + (x2_0 * x2_2));
-    st(0, 2, o0_2);
     double o0_3 = (((2.0 * x0_0) * x1_3) + (x2_1 * x2_1));
     st(0, 3, o0_3);
-    double o0_4 = (((2.0 * x0_0) * x1_4) + (x2_1 * x2_2));
+    double o0_2 = (((2.0 * x0_0) * x1_2) + (x2_2 * x2_0));
+    st(0, 2, o0_2);
+    double o0_4 = (((2.0 * x0_0) * x1_4) + (x2_2 * x2_1));
     st(0, 4, o0_4);
     double o0_5 = (((2.0 * x0_0) * x1_5) + (x2_2 * x2_2));
     st(0, 5, o0_5);
@@ -1732,21 +1732,21 @@ struct Gen_lst_sym_contract {
     // C(a,b) = Sum(c, (A(a,c) * B(c,b)))
     double o0_0 = ((x0_0 * x1_0) + (x0_1 * x1_4) + (x0_2 * x1_8) + (x0_3 * x1_12));
     st(0, 0, o0_0);
-    double o0_1 = ((x0_0 * x1_1) + (x0_1 * x1_5) + (x0_2 * x1_9) + (x0_3 * x1_13));
+    double o0_1 = ((x0_4 * x1_0) + (x0_5 * x1_4) + (x0_6 * x1_8) + (x0_7 * x1_12));
     st(0, 1, o0_1);
-    double o0_2 = ((x0_0 * x1_2) + (x0_1 * x1_6) + (x0_2 * x1_10) + (x0_3 * x1_14));
-    st(0, 2, o0_2);
-    double o0_3 = ((x0_0 * x1_3) + (x0_1 * x1_7) + (x0_2 * x1_11) + (x0_3 * x1_15));
-    st(0, 3, o0_3);
     double o0_4 = ((x0_4 * x1_1) + (x0_5 * x1_5) + (x0_6 * x1_9) + (x0_7 * x1_13));
     st(0, 4, o0_4);
-    double o0_5 = ((x0_4 * x1_2) + (x0_5 * x1_6) + (x0_6 * x1_10) + (x0_7 * x1_14));
+    double o0_2 = ((x0_8 * x1_0) + (x0_9 * x1_4) + (x0_10 * x1_8) + (x0_11 * x1_12));
+    st(0, 2, o0_2);
+    double o0_5 = ((x0_8 * x1_1) + (x0_9 * x1_5) + (x0_10 * x1_9) + (x0_11 * x1_13));
     st(0, 5, o0_5);
-    double o0_6 = ((x0_4 * x1_3) + (x0_5 * x1_7) + (x0_6 * x1_11) + (x0_7 * x1_15));
-    st(0, 6, o0_6);
     double o0_7 = ((x0_8 * x1_2) + (x0_9 * x1_6) + (x0_10 * x1_10) + (x0_11 * x1_14));
     st(0, 7, o0_7);
-    double o0_8 = ((x0_8 * x1_3) + (x0_9 * x1_7) + (x0_10 * x1_11) + (x0_11 * x1_15));
+    double o0_3 = ((x0_12 * x1_0) + (x0_13 * x1_4) + (x0_14 * x1_8) + (x0_15 * x1_12));
+    st(0, 3, o0_3);
+    double o0_6 = ((x0_12 * x1_1) + (x0_13 * x1_5) + (x0_14 * x1_9) + (x0_15 * x1_13));
+    st(0, 6, o0_6);
+    double o0_8 = ((x0_12 * x1_2) + (x0_13 * x1_6) + (x0_14 * x1_10) + (x0_15 * x1_14));
     st(0, 8, o0_8);
     double o0_9 = ((x0_12 * x1_3) + (x0_13 * x1_7) + (x0_14 * x1_11) + (x0_15 * x1_15));
     st(0, 9, o0_9);
@@ -1811,10 +1811,10 @@ struct Gen_spacetime_split {
     st(0, 0, o0_0);
     double o0_1 = x0_5;
     st(0, 1, o0_1);
-    double o0_2 = x0_6;
-    st(0, 2, o0_2);
     double o0_3 = x0_7;
     st(0, 3, o0_3);
+    double o0_2 = x0_6;
+    st(0, 2, o0_2);
     double o0_4 = x0_8;
     st(0, 4, o0_4);
     double o0_5 = x0_9;

@@ -510,12 +510,18 @@ PAIRS4 = [(a, b) for a in range(4) for b in range(a, 4)]
 
 
 def pin_listing_examples(orc):
-    """C_(ab) = A_ac B_cb on ascending pairs, and D_(i0) = E_(i+1)c F_c0 with the
-    other seven components of D left alone (einsum on small integers)."""
+    """C_(ab) = A_ac B_cb with a symmetric left-hand side, and D_(i0) =
+    E_(i+1)c F_c0 with the other seven components of D left alone (einsum on
+    small integers).  A B is not symmetric here, so the pin fixes which member
+    of each pair is stored: the one with a >= b, which the paper's generated C
+    loop and CUDA kernel for this example evaluate (Sec. 4, and the
+    tensor-index loop of Sec. 2.4), in slot s(b, a)."""
     n = 30
     A, B = _ints((4, 4, n), 101, -5, 5), _ints((4, 4, n), 102, -5, 5)
     full = np.einsum("acp,cbp->abp", A, B)
-    exp = np.stack([full[a, b] for a, b in PAIRS4])
+    exp = np.stack([full[b, a] for a, b in PAIRS4])         # slot s(a, b), a <= b: C_ba
+    _assert(not np.array_equal(exp, np.stack([full[a, b] for a, b in PAIRS4])),
+            "the inputs tell the two members apart")
     _assert(np.array_equal(orc.expr("lst_sym_contract", A.reshape(16, n), B.reshape(16, n)), exp),
             "symmetric contraction")
     At = A.transpose(1, 0, 2).reshape(16, n)       # B = A^T: a symmetric product

@@ -80,11 +80,24 @@ def test_index_rules():
 
 
 def test_symmetric_lhs_written_once_per_component():
-    i, j = indices("i j")
+    """Each stored component of a symmetric left-hand side is written once,
+    evaluated with the first index of the pair >= the second (the paper's
+    loops for a symmetric left-hand side); with a fixed index in one slot of
+    the pair, each component is reached once and evaluated there."""
+    i, j, k = indices("i j k")
     S, M = Tensor("S", (3, 3), sym=[(0, 1)]), Tensor("M", (3, 3))
     st = Program("p").let(S[i, j], M[i, j]).statements[0]
+    assert [c for c, _ in st.assignments()] == [0, 1, 2, 3, 4, 5]
     tuples = [tuple(env[x] for x in (i, j)) for _, env in st.assignments()]
-    assert tuples == [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    assert tuples == [(0, 0), (1, 0), (2, 0), (1, 1), (2, 1), (2, 2)]
+    G, D = Tensor("G", (3, 3, 3), sym=[(1, 2)]), Tensor("D", (3, 3, 3))
+    st = Program("p").let(G[i, j, k], D[i, j, k]).statements[0]
+    envs = [(env[i], env[j], env[k]) for _, env in st.assignments()]
+    assert len(envs) == 18 and all(b >= c for _, b, c in envs)
+    a, = indices("a", 4)
+    P, Q = Tensor("P", (4, 4), sym=[(0, 1)]), Tensor("Q", (4, 4))
+    st = Program("p").let(P[0, a], Q[0, a]).statements[0]
+    assert [env[a] for _, env in st.assignments()] == [0, 1, 2, 3]
 
 
 def test_committed_generated_files_are_fresh():
@@ -156,3 +169,55 @@ def test_sum_factoring_and_slice_order():
     # a sum whose factors all depend on its index is left as written
     g = Sum(m, A[i, m] * (E[m, j, k, l] + E[j, m, k, l]))
     assert factor_sums(g).body.op == "*"
+
+
+def test_evaluation_member_of_symmetric_left_hand_sides():
+    """The member of a symmetric left-hand-side pair that the generator
+    evaluates (first >= second) gives bitwise the same value as the other
+    member wherever the right-hand side is symmetric up to the order of the
+    operands of one addition or product (Gamma, K_ij, the spacetime split),
+    within rounding where the order of two additions changes (d_t g), and a
+    different value for the rank-2 contraction of Sec. 4, whose right-hand
+    side is not symmetric."""
+    import numpy as np
+    from paper_1804_10120_amd.codegen.dsl import Index
+    rng = np.random.default_rng(11)
+    checked = {}
+    for p in registry.programs():
+        tensors = {}
+        for st in p.statements:
+            _collect(st.rhs, tensors)
+            tensors[st.lhs.tensor.name] = st.lhs.tensor
+        vals = {name: rng.uniform(-1, 1, t.ncomp) for name, t in tensors.items()}
+        for st in p.statements:
+            t = st.lhs.tensor
+            pairs = [(st.lhs.args[a], st.lhs.args[b]) for a, b in t.sym
+                     if isinstance(st.lhs.args[a], Index) and isinstance(st.lhs.args[b], Index)]
+            if not pairs:
+                continue
+            worst = 0.0
+            for c, env in st.assignments():
+                other = dict(env)
+                for x, y in pairs:
+                    assert env[x] >= env[y]
+                    other[x], other[y] = env[y], env[x]
+                v, w = _evaluate(st.rhs, env, vals), _evaluate(st.rhs, other, vals)
+                worst = max(worst, abs(v - w) / max(abs(v), 1e-300))
+            checked[(p.name, t.name)] = worst
+    for key in [("christoffel", "Gamma"), ("dtg_chain_invg", "Gamma"), ("kij", "K"),
+                ("spacetime_split", "g")]:
+        assert checked[key] == 0.0, key
+    for key in [("dtg", "dtg"), ("dtg_chain_invg", "dtg")]:
+        assert 0.0 <= checked[key] <= 4e-16 * 8, key
+    assert checked[("lst_sym_contract", "C")] > 0.1
+
+
+def _collect(e, out):
+    from paper_1804_10120_amd.codegen.dsl import Bin, Neg, Ref, SumExpr
+    if isinstance(e, Ref):
+        out[e.tensor.name] = e.tensor
+    elif isinstance(e, Bin):
+        _collect(e.a, out)
+        _collect(e.b, out)
+    elif isinstance(e, (Neg, SumExpr)):
+        _collect(e.a if isinstance(e, Neg) else e.body, out)

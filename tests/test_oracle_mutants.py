@@ -62,6 +62,8 @@ MUTANTS = [
     ("sym4_table", "{1, 4, 5, 6}, {2, 5, 7, 8}", "{1, 4, 5, 6}, {2, 5, 8, 7}"),
     ("lst_contract_order", "sum += in[0][a * 4 + c] * in[1][c * 4 + b]",
      "sum += in[0][c * 4 + a] * in[1][c * 4 + b]"),
+    ("lst_ascending_member", "for (int b = 0; b < 4; ++b)\n        for (int a = b; a < 4; ++a) {",
+     "for (int a = 0; a < 4; ++a)\n        for (int b = a; b < 4; ++b) {"),
     ("lst_offset", "in[0][(i + 1) * 4 + c]", "in[0][i * 4 + c]"),
     ("lst_fixed", "in[1][c * 4 + 0]", "in[1][0 * 4 + c]"),
     ("spacetime_offset", "out[sym(i, j)] = in[0][sym4(i + 1, j + 1)]",
