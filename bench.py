@@ -47,11 +47,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def traffic_record(kernel, n):
+def traffic_record(kernel, n, root=ROOT):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
-    ``kernel``, if it was taken at this size from the current kernel sources."""
+    ``kernel``, if it was taken at this size from the current library sources,
+    headers and build flags."""
     from paper_1804_10120_amd.profsum import sources_sha256
-    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}.md")
+    path = os.path.join(root, "profiles", f"pmc_{kernel}.md")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -59,7 +60,7 @@ def traffic_record(kernel, n):
         if ":" in line and not line.startswith(("#", "|", " ")):
             k, v = line.split(":", 1)
             rec[k.strip()] = v.strip()
-    if rec.get("sources_sha256") != sources_sha256() or rec.get("points") != str(n):
+    if rec.get("sources_sha256") != sources_sha256(root) or rec.get("points") != str(n):
         return None
     try:
         return float(rec["traffic_bytes_per_launch"])

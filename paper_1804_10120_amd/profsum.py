@@ -30,13 +30,26 @@ DOUBLES_READ = {"dtg_chain": 43, "dtg_chain_bwd": 40}
 DOUBLES_WRITTEN = {"dtg_chain": 6, "dtg_chain_bwd": 43}
 
 
-def sources_sha256():
-    """Hash of every source file of the library (kernels, bodies, ABI)."""
+def sources_sha256(root=None):
+    """Hash of everything the library's machine code is built from: every
+    file under the package's ``csrc/`` (kernels, device bodies, the ABI and
+    the generated kernels), the public headers ``include/*.h`` and the
+    compiler flags of the build (with the repository path taken out).  A
+    counter figure taken from other code than this hash describes is stale."""
+    from . import build as tlbuild
+    root = os.path.dirname(PKG) if root is None else root
+    csrc = os.path.join(root, os.path.basename(PKG), "csrc")
+    inc = os.path.join(root, "include")
+    files = []
+    for d, _, names in os.walk(csrc):
+        files += [os.path.join(d, x) for x in names if not x.endswith((".pyc", ".o", ".so"))]
+    files += [os.path.join(inc, x) for x in os.listdir(inc) if x.endswith(".h")]
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for fn in sorted(files, key=lambda x: os.path.relpath(x, root)):
+        with open(fn, "rb") as f:
+            h.update(os.path.relpath(fn, root).encode() + b"\0" + f.read())
+    flags = [x.replace(tlbuild.ROOT, "$ROOT") for x in tlbuild.COMMON]
+    h.update(b"\0flags\0" + " ".join(flags).encode())
     return h.hexdigest()
 
 

@@ -113,3 +113,35 @@ def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
     autotune.save_cache(c)
     assert autotune.load_cache()["other"]["tune"] == {"block": 64}
     assert sorted(p.name for p in path.parent.iterdir()) == ["tune.json"]
+
+
+def test_traffic_record_goes_stale_when_the_build_inputs_change(tmp_path):
+    """The committed counter figure is reported only while every input of the
+    library's machine code is unchanged: a kernel source, a generated kernel,
+    a public header (the hash also covers the compiler flags)."""
+    import shutil
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1804_10120_amd import profsum
+    pkg = os.path.basename(os.path.dirname(profsum.__file__))
+    root = tmp_path / "repo"
+    shutil.copytree(os.path.join(ROOT, pkg, "csrc"), root / pkg / "csrc")
+    shutil.copytree(os.path.join(ROOT, "include"), root / "include")
+    (root / "profiles").mkdir()
+    n = 4096
+
+    def write_record():
+        (root / "profiles" / "pmc_dtg_chain_bwd.md").write_text(
+            f"# x\n\nkernel: dtg_chain_bwd\npoints: {n}\n"
+            f"sources_sha256: {profsum.sources_sha256(str(root))}\n"
+            f"traffic_bytes_per_launch: 1234\n")
+
+    write_record()
+    assert bench.traffic_record("dtg_chain_bwd", n, root=str(root)) == 1234.0
+    assert bench.traffic_record("dtg_chain_bwd", n + 1, root=str(root)) is None
+    for rel in ("include/tl.h", f"{pkg}/csrc/generated/tlg_kernels.hip",
+                f"{pkg}/csrc/tl_stream.hpp"):
+        write_record()
+        with open(root / rel, "a") as f:
+            f.write("\n// edited\n")
+        assert bench.traffic_record("dtg_chain_bwd", n, root=str(root)) is None, rel
