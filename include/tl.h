@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define TL_ABI_VERSION 2
+#define TL_ABI_VERSION 3
 
 typedef enum {
   TL_OK = 0,
@@ -279,17 +279,32 @@ tl_status tl_bw_twin(int64_t n, int32_t nin, tl_cfield in, int32_t nout, tl_fiel
 
 /* ---- Introspection -------------------------------------------------------------- */
 
+/* Registers and occupancy of one compiled kernel: the counterpart of the
+ * paper's table of registers per thread and theoretical occupancy of its
+ * generated kernels (Sec. 5.3, tab:registertable). */
 typedef struct {
   int32_t block, ppt, flags;   /* the instantiation the tuning resolves to */
-  int32_t num_regs;            /* registers per thread reported by the runtime */
-  int32_t local_bytes;         /* private (scratch) bytes per thread */
+  int32_t vgprs;               /* architected vector registers per lane (runtime) */
+  int32_t agprs;               /* accumulation vector registers per lane */
+  int32_t sgprs;               /* scalar registers per wave, VCC and the other
+                                  reserved ones included */
+  int32_t scratch_bytes;       /* private (scratch) bytes per lane (runtime) */
+  int32_t waves_per_simd;      /* waves of this kernel resident per SIMD when it
+                                  is launched with `block` threads per block
+                                  (the runtime's occupancy calculator) */
+  int32_t max_waves_per_simd;  /* the compiler's bound from registers alone */
   int32_t max_threads;         /* max threads per block for the kernel */
 } tl_kernel_attr;
 
 /* Attributes of the kernel that `kernel` ("sym_inverse", "christoffel",
- * "cov_deriv", "dtg", "dtg_chain", "dtg_chain_bwd", "dtg_chain_batched", or an
- * expression name "assign1" ... "contract3", "kij") would run with `tune`
- * on a large grid (ppt assumes aligned fields). */
+ * "cov_deriv", "dtg", "dtg_chain", "dtg_chain_bwd", "dtg_chain_fwd_bwd",
+ * "dtg_chain_batched", "dtg_chain_bwd_batched", or an expression name
+ * "assign1" ... "contract3", "kij") would run with `tune` on a large grid
+ * (ppt assumes aligned fields).  VGPRs and scratch come from the HIP runtime,
+ * SGPRs, AGPRs and the register-bound occupancy from the compiler's resource
+ * report, compiled into the library when it was built, waves_per_simd from
+ * the runtime's occupancy calculator; a value that cannot be obtained is -1.
+ * Needs a HIP device (TL_ERR_HIP otherwise). */
 tl_status tl_kernel_info(const char* kernel, const tl_tune* tune, tl_kernel_attr* out);
 
 const char* tl_status_string(tl_status s);

@@ -21,7 +21,7 @@ TL_BW_READ_BLOCKS = 2048
 EXPRS = ("assign1", "assign2", "assign3", "add1", "add2", "add3", "mult1", "mult2", "mult3",
          "contract1", "contract2", "contract3", "kij")
 TWIN_SHAPES = ((1, 1), (6, 6), (24, 18), (30, 9), (16, 6), (43, 6), (40, 43))
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 class CField(ctypes.Structure):
@@ -51,8 +51,9 @@ class DomainBwd(ctypes.Structure):
 
 class KernelAttr(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("ppt", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("num_regs", ctypes.c_int32), ("local_bytes", ctypes.c_int32),
-                ("max_threads", ctypes.c_int32)]
+                ("vgprs", ctypes.c_int32), ("agprs", ctypes.c_int32), ("sgprs", ctypes.c_int32),
+                ("scratch_bytes", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
+                ("max_waves_per_simd", ctypes.c_int32), ("max_threads", ctypes.c_int32)]
 
 
 class TLError(RuntimeError):

@@ -680,53 +680,72 @@ struct PlanInput {
   }
 };
 
-// Checks the outputs of all domains against every field of every domain,
-// builds the tile tables, copies them to the device and captures the launch.
-tl_status build_plan(tl::KernelId kid, PlanInput& in, const tl_tune* tune, tl_batch_plan** out) {
+// The host side of a batched launch: the resolved shape, the device-layout
+// domain table, the tile prefix sums and the tile -> subgrid map, and the
+// grid (one block per tile, or a persistent grid of grid_mult blocks per
+// compute unit, each block walking one contiguous chunk of tiles).
+struct PlanTables {
+  tl::Resolved r;
+  std::vector<tl::BatchDomain> doms;
+  std::vector<int64_t> start;
+  std::vector<int32_t> tile_dom;
+  int64_t points = 0, ntiles = 0, grid = 0, chunk = 1;
+};
+
+// Checks the outputs of all domains against every field of every domain and
+// builds the tables.
+tl_status plan_tables(tl::KernelId kid, PlanInput& in, const tl_tune* tune, PlanTables* t) {
   {
     const char* a = nullptr;
     const char* b = nullptr;
     if (Checker::overlapping(in.spans, &a, &b))
       return fail(TL_ERR_ALIAS, "%s of one domain overlaps %s of another", a, b);
   }
-  tl::Resolved r;
-  tl_status s = resolve(kid, tune, in.vec_ok, in.buf_ok, in.points, &r);
+  tl_status s = resolve(kid, tune, in.vec_ok, in.buf_ok, in.points, &t->r);
   if (s != TL_OK) return s;
-
+  const tl::Resolved& r = t->r;
   const int32_t ndom = static_cast<int32_t>(in.n.size());
-  std::vector<tl::BatchDomain> h(ndom);
-  std::vector<int64_t> start(ndom + 1);
-  std::vector<int32_t> tile_dom;
+  t->doms.assign(ndom, tl::BatchDomain{});
+  t->start.assign(ndom + 1, 0);
+  t->tile_dom.clear();
   const int64_t per = static_cast<int64_t>(r.block) * r.ppt;
-  start[0] = 0;
   for (int32_t d = 0; d < ndom; ++d) {
-    std::memset(&h[d], 0, sizeof(tl::BatchDomain));
-    h[d].n = in.n[d];
-    if (in.n[d] > 0) h[d].args = in.args[d];
-    start[d + 1] = start[d] + (in.n[d] + per - 1) / per;
-    tile_dom.insert(tile_dom.end(), static_cast<size_t>(start[d + 1] - start[d]), d);
+    std::memset(&t->doms[d], 0, sizeof(tl::BatchDomain));
+    t->doms[d].n = in.n[d];
+    if (in.n[d] > 0) t->doms[d].args = in.args[d];
+    t->start[d + 1] = t->start[d] + (in.n[d] + per - 1) / per;
+    t->tile_dom.insert(t->tile_dom.end(), static_cast<size_t>(t->start[d + 1] - t->start[d]), d);
   }
-
-  tl_batch_plan* p = new (std::nothrow) tl_batch_plan;
-  if (p == nullptr) return fail(TL_ERR_INVALID, "out of host memory");
-  p->kid = kid;
-  p->r = r;
-  p->ndom = ndom;
-  p->points = in.points;
-  p->ntiles = start[ndom];
-  hipError_t e = hipGetDevice(&p->device);
-  // Grid: one block per tile (grid_mult 0, the default), or a persistent grid
-  // of grid_mult blocks per compute unit, each block walking one contiguous
-  // chunk of tiles.
-  int64_t blocks = p->ntiles;
+  t->points = in.points;
+  t->ntiles = t->start[ndom];
+  int64_t blocks = t->ntiles;
   if (r.grid_mult > 0) blocks = static_cast<int64_t>(r.grid_mult) * r.num_cu;
   if (r.xcd) blocks = (blocks + 7) & ~static_cast<int64_t>(7);
   if (blocks < 1) blocks = 1;
-  p->chunk = (p->ntiles + blocks - 1) / blocks;
-  if (p->chunk < 1) p->chunk = 1;
-  p->grid = (p->ntiles + p->chunk - 1) / p->chunk;
-  if (r.xcd) p->grid = (p->grid + 7) & ~static_cast<int64_t>(7);
-  if (p->grid < 1) p->grid = 1;
+  t->chunk = (t->ntiles + blocks - 1) / blocks;
+  if (t->chunk < 1) t->chunk = 1;
+  t->grid = (t->ntiles + t->chunk - 1) / t->chunk;
+  if (r.xcd) t->grid = (t->grid + 7) & ~static_cast<int64_t>(7);
+  if (t->grid < 1) t->grid = 1;
+  return TL_OK;
+}
+
+// Builds the tables, copies them to the device and captures the launch.
+tl_status build_plan(tl::KernelId kid, PlanInput& in, const tl_tune* tune, tl_batch_plan** out) {
+  PlanTables t;
+  tl_status s = plan_tables(kid, in, tune, &t);
+  if (s != TL_OK) return s;
+  const int32_t ndom = static_cast<int32_t>(t.doms.size());
+  tl_batch_plan* p = new (std::nothrow) tl_batch_plan;
+  if (p == nullptr) return fail(TL_ERR_INVALID, "out of host memory");
+  p->kid = kid;
+  p->r = t.r;
+  p->ndom = ndom;
+  p->points = t.points;
+  p->ntiles = t.ntiles;
+  p->grid = t.grid;
+  p->chunk = t.chunk;
+  hipError_t e = hipGetDevice(&p->device);
   auto cleanup = [&](hipError_t err, const char* what) {
     tl_status st = hip_fail(err, what);
     tl_batch_plan_destroy(p);
@@ -737,14 +756,14 @@ tl_status build_plan(tl::KernelId kid, PlanInput& in, const tl_tune* tune, tl_ba
   if (e != hipSuccess) return cleanup(e, "hipMalloc(domains)");
   e = hipMalloc(reinterpret_cast<void**>(&p->d_start), sizeof(int64_t) * (ndom + 1));
   if (e != hipSuccess) return cleanup(e, "hipMalloc(tile starts)");
-  e = hipMemcpy(p->d_doms, h.data(), sizeof(tl::BatchDomain) * ndom, hipMemcpyHostToDevice);
+  e = hipMemcpy(p->d_doms, t.doms.data(), sizeof(tl::BatchDomain) * ndom, hipMemcpyHostToDevice);
   if (e != hipSuccess) return cleanup(e, "hipMemcpy(domains)");
-  e = hipMemcpy(p->d_start, start.data(), sizeof(int64_t) * (ndom + 1), hipMemcpyHostToDevice);
+  e = hipMemcpy(p->d_start, t.start.data(), sizeof(int64_t) * (ndom + 1), hipMemcpyHostToDevice);
   if (e != hipSuccess) return cleanup(e, "hipMemcpy(tile starts)");
   if (p->ntiles > 0) {
     e = hipMalloc(reinterpret_cast<void**>(&p->d_tile_dom), sizeof(int32_t) * p->ntiles);
     if (e != hipSuccess) return cleanup(e, "hipMalloc(tile table)");
-    e = hipMemcpy(p->d_tile_dom, tile_dom.data(), sizeof(int32_t) * p->ntiles,
+    e = hipMemcpy(p->d_tile_dom, t.tile_dom.data(), sizeof(int32_t) * p->ntiles,
                   hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(e, "hipMemcpy(tile table)");
   }
@@ -775,11 +794,9 @@ tl_status plan_preamble(const void* doms, int32_t ndom, tl_batch_plan** out) {
 
 }  // namespace
 
-tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tune* tune,
-                               tl_batch_plan** out) {
-  const tl_status s0 = plan_preamble(doms, ndom, out);
-  if (s0 != TL_OK) return s0;
-  PlanInput in;
+// Validates every domain of a forward batch (as tl_dtg_chain would) and
+// collects their arguments and field spans.
+static tl_status chain_domains(const tl_domain* doms, int32_t ndom, PlanInput* in) {
   for (int32_t d = 0; d < ndom; ++d) {
     const tl_domain& x = doms[d];
     if (x.n < 0) return fail(TL_ERR_SIZE, "domain %d: n=%lld < 0", d, (long long)x.n);
@@ -788,9 +805,19 @@ tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tun
       chain_fields(c, x.g, x.dg, x.beta, x.dbeta, x.K, x.alpha, x.dtg);
       if (c.overlaps() != TL_OK) return fail(c.st, "domain %d: %s", d, g_last_error.c_str());
     }
-    in.add(x.n, x.n > 0 ? chain_args(x.g, x.dg, x.beta, x.dbeta, x.K, x.alpha, x.dtg)
-                        : zero_args(), c);
+    in->add(x.n, x.n > 0 ? chain_args(x.g, x.dg, x.beta, x.dbeta, x.K, x.alpha, x.dtg)
+                         : zero_args(), c);
   }
+  return TL_OK;
+}
+
+tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tune* tune,
+                               tl_batch_plan** out) {
+  const tl_status s0 = plan_preamble(doms, ndom, out);
+  if (s0 != TL_OK) return s0;
+  PlanInput in;
+  const tl_status s1 = chain_domains(doms, ndom, &in);
+  if (s1 != TL_OK) return s1;
   return build_plan(tl::KernelId::ChainBatched, in, tune, out);
 }
 
@@ -907,11 +934,23 @@ tl_status tl_kernel_info(const char* kernel, const tl_tune* tune, tl_kernel_attr
   hipFuncAttributes attr;
   hipError_t e = hipFuncGetAttributes(&attr, fn);
   if (e != hipSuccess) return hip_fail(e, "hipFuncGetAttributes");
-  out->block = r.block;
+  // The block size the kernel actually runs with (a wide body caps it).
+  const int block = std::min(r.block, attr.maxThreadsPerBlock);
+  int blocks_per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, fn, block, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+  tl::KernelResources res{-1, -1, -1, -1, -1};
+  tl::kernel_resources(hipKernelNameRefByPtr(fn, nullptr), &res);
+  out->block = block;
   out->ppt = r.ppt;
   out->flags = (r.nt ? TL_TUNE_NT : 0) | (r.xcd ? TL_TUNE_XCD : 0);
-  out->num_regs = attr.numRegs;
-  out->local_bytes = static_cast<int32_t>(attr.localSizeBytes);
+  out->vgprs = attr.numRegs;
+  out->agprs = res.agprs;
+  out->sgprs = res.sgprs;
+  out->scratch_bytes = static_cast<int32_t>(attr.localSizeBytes);
+  // four SIMDs per compute unit, 64-wide waves
+  out->waves_per_simd = blocks_per_cu * ((block + 63) / 64) / 4;
+  out->max_waves_per_simd = res.waves_per_simd;
   out->max_threads = attr.maxThreadsPerBlock;
   return TL_OK;
 }

@@ -81,4 +81,16 @@ hipError_t launch_read(const double* src, double* partial, int64_t n, int64_t gr
 hipError_t launch_write(double* dst, int64_t n, int64_t grid, bool vec, hipStream_t s);
 hipError_t launch_christoffel_lanes(const Resolved& r, const KArgs& a, int64_t n, hipStream_t s);
 
+// Registers, scratch and occupancy of one compiled kernel, as the compiler
+// reported them when the library was built (the build writes the table).
+struct KernelResources {
+  int sgprs;           // scalar registers per wave, VCC and other reserved ones included
+  int vgprs;           // architected vector registers per lane
+  int agprs;           // accumulation registers per lane
+  int scratch;         // private (scratch) bytes per lane
+  int waves_per_simd;  // occupancy bound from the resources alone
+};
+// Looks a kernel up by its mangled (or demangled) name; false if unknown.
+bool kernel_resources(const char* name, KernelResources* out);
+
 }  // namespace tl

@@ -446,6 +446,15 @@ def tl_kernel_info(kernel, tune=None):
     return {k: getattr(a, k) for k, _ in KernelAttr._fields_}
 
 
+def _fwd_domain(c, d):
+    """The tl_domain of one forward subgrid (its inputs already added to the
+    call ``c``), allocating d_t g with empty_field when it is not given."""
+    out = d.get("dtg")
+    out = c.out(empty_field(6, c.n, device=c.device) if out is None else out, "dtg", d["K"])
+    return (Domain(c.n, _cf(d["g"], 6), _cf(d["dg"], 18), _cf(d["beta"], 3), _cf(d["dbeta"], 9),
+                   _cf(d["K"], 6), _cf(d["alpha"], 1), _f(out, 6)), dict(d, dtg=out))
+
+
 class BatchPlan:
     """tl_batch_plan_*: d_t g (kind="fwd") or its adjoint (kind="bwd") over
     many subgrids in one graph-captured launch.
@@ -491,13 +500,8 @@ class BatchPlan:
             elif c.device != device:
                 raise ValueError("all subgrids must be on one device")
             if kind == "fwd":
-                out = d.get("dtg")
-                out = c.out(empty_field(6, c.n, device=c.device) if out is None else out, "dtg",
-                            d["K"])
-                self.domains.append(dict(d, dtg=out))
-                arr[i] = Domain(c.n, _cf(d["g"], 6), _cf(d["dg"], 18), _cf(d["beta"], 3),
-                                _cf(d["dbeta"], 9), _cf(d["K"], 6), _cf(d["alpha"], 1),
-                                _f(out, 6))
+                arr[i], dd = _fwd_domain(c, d)
+                self.domains.append(dd)
             else:
                 grads = []
                 for k, nc, w in zip(GRAD_NAMES, (6, 18, 3, 9, 6, 1), want):

@@ -351,3 +351,4 @@ def test_missing_library_raises(monkeypatch, tmp_path):
     monkeypatch.setattr(_abi, "_lib", None)
     with pytest.raises(RuntimeError, match="no fallback"):
         _abi.lib()
+

@@ -179,15 +179,36 @@ def test_singular_metric_propagates_nonfinite():
                                     "dtg_chain_bwd", "dtg_chain_batched", "dtg_chain_fwd_bwd",
                                     "dtg_chain_bwd_batched", "assign1", "contract3", "kij"])
 def test_kernel_info(kernel):
+    """Registers and occupancy of the default large-grid instantiation: the
+    runtime's VGPR count equals the compiler's report compiled into the
+    library, nothing spills, and the runtime's occupancy at the launch block
+    size is the compiler's register-bound occupancy (blocks of 256 threads
+    fill whole SIMD slots)."""
     a = tl_kernel_info(kernel)
-    assert a["num_regs"] > 0 and a["max_threads"] >= a["block"]
-    assert a["local_bytes"] == 0, f"{kernel} spills to scratch"
+    assert a["vgprs"] > 0 and a["max_threads"] >= a["block"]
+    assert a["scratch_bytes"] == 0, f"{kernel} spills to scratch"
+    assert 0 < a["sgprs"] <= 128 and a["agprs"] == 0, a
+    assert 1 <= a["waves_per_simd"] <= a["max_waves_per_simd"] <= 8, a
+    if a["block"] % 256 == 0:
+        assert a["waves_per_simd"] == a["max_waves_per_simd"], a
+
+
+def test_kernel_info_headline_kernels():
+    """The benchmark step's kernels (one point per lane, 256 threads, buffer
+    addressing): the forward fits 8 waves per SIMD, the adjoint 5, from their
+    62 and 84 VGPRs (512 per SIMD lane, allocated in granules of 8)."""
+    f = tl_kernel_info("dtg_chain")
+    b = tl_kernel_info("dtg_chain_bwd")
+    assert (f["block"], f["ppt"]) == (256, 1) and (b["block"], b["ppt"]) == (256, 1)
+    assert f["vgprs"] <= 64 and f["waves_per_simd"] == 8, f
+    assert 80 < b["vgprs"] <= 88 and b["waves_per_simd"] == 5, b
 
 
 @pytest.mark.parametrize("lanes", [2, 3, 6, 9, 18])
 def test_kernel_info_lanes(lanes):
     a = tl_kernel_info("christoffel", tune=dict(block=64, lanes=lanes))
-    assert a["num_regs"] > 0 and a["block"] == 64 and a["local_bytes"] == 0
+    assert a["vgprs"] > 0 and a["block"] == 64 and a["scratch_bytes"] == 0
+    assert a["sgprs"] > 0 and a["waves_per_simd"] >= 1
 
 
 def test_graph_capture_replays():
