@@ -78,10 +78,77 @@ def device_sets(n, nsets, device, seed0):
     return sets
 
 
-def time_calls(lists, reps, warmup):
-    """Runs the call lists round-robin.  Returns (wall ms per list, HIP-event
-    ms per call position averaged over reps)."""
+class KernelLabels:
+    """roctx ranges around timed calls (``--label-kernels``): a profiler run
+    with kernel renaming (rocprofv3 --marker-trace --kernel-rename) then names
+    every dispatch after the configuration and call that launched it, e.g.
+    ``c2 dtg_chain n=262144``, so the kernel trace splits by configuration."""
+
+    def __init__(self):
+        self.push = self.pop = None
+
+    def enable(self):
+        import ctypes
+        lib = ctypes.CDLL(os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib",
+                                       "librocprofiler-sdk-roctx.so"))
+        lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+        lib.roctxRangePushA.restype = ctypes.c_int
+        lib.roctxRangePop.restype = ctypes.c_int
+        self.push, self.pop = lib.roctxRangePushA, lib.roctxRangePop
+
+    def wrap(self, label, call):
+        if self.push is None or label is None:
+            return call
+        name, push, pop = label.encode(), self.push, self.pop
+
+        def labelled():
+            push(name)
+            call()
+            pop()
+        return labelled
+
+
+LABELS = KernelLabels()
+
+
+def label(cfg, kernel, n, extra=""):
+    return f"c{cfg} {kernel} n={n}" + (f" {extra}" if extra else "")
+
+
+def _labelled(lists, labels):
+    if labels is None:
+        return lists
+    if isinstance(labels, str):
+        labels = [labels] * len(lists[0])
+    return [[LABELS.wrap(lab, c) for lab, c in zip(labels, calls)] for calls in lists]
+
+
+def back_to_back(lists, reps, warmup=3, labels=None):
+    """Mean ms per call list with HIP events around all ``reps`` lists only:
+    the launches queue back to back, so this is the kernels' own time plus
+    the gaps between consecutive dispatches, without per-call event cost."""
     import torch
+    lists = _labelled(lists, labels)
+    for i in range(warmup):
+        for c in lists[i % len(lists)]:
+            c()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for i in range(reps):
+        for c in lists[i % len(lists)]:
+            c()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def time_calls(lists, reps, warmup, labels=None):
+    """Runs the call lists round-robin.  Returns (wall ms per list, HIP-event
+    ms per call position averaged over reps).  ``labels``: a roctx range name
+    per call position (or one for all) when kernel labelling is on."""
+    import torch
+    lists = _labelled(lists, labels)
     nl, nc = len(lists), len(lists[0])
     for i in range(warmup):
         for c in lists[i % nl]:
@@ -198,6 +265,52 @@ def rw_model(read_doubles, write_doubles, read_gbs, write_gbs):
     its reads ran at the read-only rate and its writes at the write-only rate,
     one after the other (the streaming copy matches this model)."""
     return (read_doubles + write_doubles) / (read_doubles / read_gbs + write_doubles / write_gbs)
+
+
+MID_SHAPES = {"ppt1_b256": dict(block=256, ppt=1, nt=True),
+              "ppt2_b512": dict(block=512, ppt=2, nt=True)}
+
+
+def mid_size_shapes(sets, n):
+    """At 64^3 points (all blocks resident at once), one point per lane in
+    blocks of 256 against two points per lane (16-byte accesses) in blocks of
+    512, for the adjoint and the four unfused kernels: HIP-event time per call
+    and time per call queued back to back, over rotating buffer sets."""
+    import torch
+    from paper_1804_10120_amd import (tl_christoffel, tl_cov_deriv, tl_dtg, tl_dtg_chain_bwd,
+                                      tl_sym_inverse)
+    from paper_1804_10120_amd.ops import record
+    mids = []
+    for _, e in sets:
+        gi = tl_sym_inverse(e["g"])
+        ga = tl_christoffel(gi, e["dg"])
+        mids.append((e, gi, ga, tl_cov_deriv(ga, e["beta"], e["dbeta"])))
+    calls = {
+        "dtg_chain_bwd": lambda e, gi, ga, nb, t: tl_dtg_chain_bwd(
+            e["g"], e["dg"], e["beta"], e["K"], e["alpha"], e["W"], tune=t),
+        "sym_inverse": lambda e, gi, ga, nb, t: tl_sym_inverse(e["g"], tune=t),
+        "christoffel": lambda e, gi, ga, nb, t: tl_christoffel(gi, e["dg"], tune=t),
+        "cov_deriv": lambda e, gi, ga, nb, t: tl_cov_deriv(ga, e["beta"], e["dbeta"], tune=t),
+        "dtg": lambda e, gi, ga, nb, t: tl_dtg(e["alpha"], e["K"], nb, tune=t),
+    }
+    out = {}
+    for kname, fn in calls.items():
+        out[kname] = {}
+        for sname, tune in MID_SHAPES.items():
+            lists = []
+            for m in mids:
+                with record() as c:
+                    fn(*m, tune)
+                lists.append(c)
+            lab = label(5 if kname == "dtg_chain_bwd" else 2, kname, n, sname)
+            _, (ms,) = time_calls(lists, 100, 10, labels=lab)
+            ms_q = back_to_back(lists, 100, labels=lab + " queued")
+            out[kname][sname] = {"us": ms * 1e3, "GB_s": rate(BYTES[kname] * n, ms),
+                                 "queued_us": ms_q * 1e3,
+                                 "queued_GB_s": rate(BYTES[kname] * n, ms_q)}
+    del mids
+    torch.cuda.empty_cache()
+    return out
 
 
 def host_cpu():
@@ -359,6 +472,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-rows", action="store_true", help="time only the fwd+bwd step")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--label-kernels", action="store_true",
+                    help="name the timed calls with roctx ranges (for a profiler run with "
+                         "--marker-trace --kernel-rename)")
     ap.add_argument("--sweep", metavar="FILE",
                     help="also write the full grid-size sweep (GB/s) as a Markdown table")
     args = ap.parse_args()
@@ -371,6 +487,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.label_kernels:
+        LABELS.enable()
     import torch
     from paper_1804_10120_amd import (BatchPlan, tl_christoffel, tl_cov_deriv, tl_dtg,
                                       tl_dtg_chain, tl_dtg_chain_bwd, tl_dtg_chain_fwd_bwd,
@@ -392,7 +510,9 @@ def main():
         d["dtg"] = tl_dtg_chain(*[d[k] for k in KEYS])
         d["grads"] = tl_dtg_chain_bwd(d["g"], d["dg"], d["beta"], d["K"], d["alpha"], d["W"])
     log(f"[bench] {args.steps} steps after {args.warmup} warm-up steps")
-    ms_step, (ms_fwd, ms_bwd) = time_calls([step], args.steps, args.warmup)
+    ms_step, (ms_fwd, ms_bwd) = time_calls([step], args.steps, args.warmup,
+                                           labels=[label(3, "dtg_chain", n),
+                                                   label(3, "dtg_chain_bwd", n)])
     assert torch.isfinite(d["dtg"]).all() and torch.isfinite(d["grads"][0]).all()
 
     res = {
@@ -443,7 +563,8 @@ def main():
         ref = [d["dtg"].clone()] + [x.clone() for x in d["grads"]]
         with record() as fb:
             tl_dtg_chain_fwd_bwd(*[d[k] for k in KEYS], d["W"], d["dtg"], d["grads"])
-        _, (ms_fb,) = time_calls([fb], args.steps, args.warmup)
+        _, (ms_fb,) = time_calls([fb], args.steps, args.warmup,
+                                 labels=label(3, "dtg_chain_fwd_bwd", n))
         diff = max(float(((a - b).abs().max() / b.abs().max().clamp_min(1e-300)).item())
                    for a, b in zip([d["dtg"], *d["grads"]], ref))
         rows["fwd_bwd_one_kernel"] = {"us": ms_fb * 1e3, "points_per_s": n / (ms_fb * 1e-3),
@@ -485,8 +606,9 @@ def main():
             gam = tl_christoffel(ginv, d["dg"])
             nb = tl_cov_deriv(gam, d["beta"], d["dbeta"])
             tl_dtg(d["alpha"], d["K"], nb)
-        _, per = time_calls([unf], 20, 3)
-        for name, ms in zip(("sym_inverse", "christoffel", "cov_deriv", "dtg"), per):
+        unf_names = ("sym_inverse", "christoffel", "cov_deriv", "dtg")
+        _, per = time_calls([unf], 20, 3, labels=[label(3, k, n) for k in unf_names])
+        for name, ms in zip(unf_names, per):
             rows[name] = {"us": ms * 1e3, "GB_s": rate(BYTES[name] * n, ms)}
         rows["unfused_chain"] = {"us": sum(per) * 1e3, "points_per_s": n / (sum(per) * 1e-3),
                                  "GB_s": rate(BYTES["unfused_chain"] * n, sum(per)),
@@ -551,7 +673,8 @@ def main():
         with record() as cs:
             gi16 = tl_sym_inverse(e16["g"])
             tl_christoffel(gi16, e16["dg"])
-        _, (ms_i, ms_c) = time_calls([cs], 200, 20)
+        _, (ms_i, ms_c) = time_calls([cs], 200, 20, labels=[label(1, "sym_inverse", n16),
+                                                             label(1, "christoffel", n16)])
         graph = torch.cuda.CUDAGraph()
         gi_g = torch.empty_like(gi16)
         ga_g = torch.empty(18, n16, dtype=torch.float64, device=device)
@@ -565,7 +688,8 @@ def main():
         for la in (2, 3, 6, 9, 18):
             with record() as cl:
                 tl_christoffel(gi16, e16["dg"], tune=dict(block=64, nt=True, lanes=la))
-            _, (ms_l,) = time_calls([cl], 200, 20)
+            _, (ms_l,) = time_calls([cl], 200, 20,
+                                    labels=label(1, "christoffel", n16, f"lanes={la}"))
             lanes_us[str(la)] = ms_l * 1e3
         rows["christoffel_16cubed"] = {
             "points": n16, "sym_inverse_us": ms_i * 1e3, "christoffel_us": ms_c * 1e3,
@@ -608,8 +732,13 @@ def main():
                 tl_dtg_chain(*[e[k] for k in KEYS])
                 tl_dtg_chain_bwd(e["g"], e["dg"], e["beta"], e["K"], e["alpha"], e["W"])
             lists.append(c)
-        ms64, (f64, b64) = time_calls(lists, 100, 10)
-        _, (wf64, wb64) = time_calls(lists[:1], 100, 10)     # one set: cache-resident
+        lab64 = [label(2, "dtg_chain", n64), label(5, "dtg_chain_bwd", n64)]
+        ms64, (f64, b64) = time_calls(lists, 100, 10, labels=lab64)
+        _, (wf64, wb64) = time_calls(lists[:1], 100, 10,     # one set: cache-resident
+                                     labels=[x + " warm" for x in lab64])
+        # the same launches queued back to back (no event between calls)
+        bb_f64 = back_to_back([c[:1] for c in lists], 100, labels=lab64[0] + " queued")
+        bb_b64 = back_to_back([c[1:] for c in lists], 100, labels=lab64[1] + " queued")
         # the same forward + adjoint pairs over the 4 sets, twice, replayed from one graph
         outs64 = [(torch.empty(6, n64, dtype=torch.float64, device=device),
                    [torch.empty(c, n64, dtype=torch.float64, device=device)
@@ -628,8 +757,13 @@ def main():
                                    "bwd_us": b64 * 1e3,
                                    "bwd_GB_s": rate(BYTES["dtg_chain_bwd"] * n64, b64),
                                    "warm_fwd_us": wf64 * 1e3, "warm_bwd_us": wb64 * 1e3,
+                                   "queued_fwd_us": bb_f64 * 1e3,
+                                   "queued_fwd_GB_s": rate(BYTES["dtg_chain"] * n64, bb_f64),
+                                   "queued_bwd_us": bb_b64 * 1e3,
+                                   "queued_bwd_GB_s": rate(BYTES["dtg_chain_bwd"] * n64, bb_b64),
                                    "graph_us_per_pair": ms_g64 * 1e3 / 8,
                                    "graph_points_per_s": n64 / (ms_g64 * 1e-3 / 8)}
+        rows["shapes_64cubed"] = mid_size_shapes(s64, n64)
         del s64, lists, outs64, g64
 
         log("[bench] blocked field layout, batch plans over blocks of 4096 points")
@@ -642,24 +776,28 @@ def main():
         # the same subgrids with ld = n (contiguous [C, n] tensors)
         flat = [{k: torch.from_numpy(v).to(device) for k, v in fe.items()} for fe in hosts]
         plan = BatchPlan(flat)
-        _, (ms_flat,) = time_calls([[plan.run]], 20, 3)
+        _, (ms_flat,) = time_calls([[plan.run]], 20, 3,
+                                   labels=label(4, "dtg_chain_batched", npts, "ld=n"))
         plan.close()
         del flat, plan
         # each subgrid's fields with ld padded to a multiple of 16 doubles
         doms = [{k: to_field(v, device=device) for k, v in fe.items()} for fe in hosts]
         del hosts
         plan = BatchPlan(doms)
-        _, (ms_default,) = time_calls([[plan.run]], 20, 3)
+        _, (ms_default,) = time_calls([[plan.run]], 20, 3,
+                                      labels=label(4, "dtg_chain_batched", npts, "default"))
         plan.close()
         from paper_1804_10120_amd import autotune
         tuned = autotune.tune_plan(doms, save=False)
         plan = BatchPlan(doms, tune=tuned["tune"])
-        _, (ms_graph,) = time_calls([[plan.run]], 20, 3)
+        _, (ms_graph,) = time_calls([[plan.run]], 20, 3,
+                                    labels=label(4, "dtg_chain_batched", npts, "tuned"))
         outs = [empty_field(6, e["K"].shape[1], device=device) for e in doms]
         with record() as many:
             for e, o in zip(doms, outs):
                 tl_dtg_chain(*[e[k] for k in KEYS], o)
-        ms_many, _ = time_calls([many], 10, 2)
+        ms_many, _ = time_calls([many], 10, 2,
+                                labels=label(4, "dtg_chain", npts, "256 launches"))
         graph256 = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph256):    # the 256 plain launches, captured
             for e, o in zip(doms, outs):
@@ -688,11 +826,13 @@ def main():
         bdoms = [{k: d[k] for k in ("g", "dg", "beta", "K", "alpha", "W")} for d in doms]
         tuned_b = autotune.tune_plan(bdoms, kind="bwd", save=False)
         bplan = BatchPlan(bdoms, tune=tuned_b["tune"], kind="bwd")
-        _, (ms_bplan,) = time_calls([[bplan.run]], 20, 3)
+        _, (ms_bplan,) = time_calls([[bplan.run]], 20, 3,
+                                    labels=label(4, "dtg_chain_bwd_batched", npts, "tuned"))
         with record() as bmany:
             for d, gr in zip(bdoms, bplan.outputs):
                 tl_dtg_chain_bwd(d["g"], d["dg"], d["beta"], d["K"], d["alpha"], d["W"], *gr)
-        ms_bmany, _ = time_calls([bmany], 10, 2)
+        ms_bmany, _ = time_calls([bmany], 10, 2,
+                                 labels=label(4, "dtg_chain_bwd", npts, "256 launches"))
         rows["dtg_chain_bwd_batched"] = {
             "subgrids": 256, "points": npts, "us": ms_bplan * 1e3, "tune": tuned_b["tune"],
             "points_per_s": npts / (ms_bplan * 1e-3),

@@ -21,6 +21,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 from collections import defaultdict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -91,6 +92,40 @@ def launch_shapes(folder):
             "min_ns": min(v), "max_ns": max(v), "total_ns": sum(v), "vgpr": vgpr[k]}
            for k, v in agg.items()]
     return sorted(out, key=lambda r: -r["total_ns"])
+
+
+# Algorithmic bytes per grid point of each kernel named in a dispatch label
+# (8 B per stored element read or written).
+LABEL_BYTES = {"sym_inverse": 96, "christoffel": 336, "cov_deriv": 312, "dtg": 176,
+               "dtg_chain": 392, "dtg_chain_bwd": 664, "dtg_chain_fwd_bwd": 784,
+               "dtg_chain_batched": 392, "dtg_chain_bwd_batched": 664}
+LABEL = re.compile(r"^c(\d+) (\w+) n=(\d+)(?: (.*))?$")
+HBM_PEAK_GBS = 8000.0
+
+
+def labelled_dispatches(folder):
+    """Per dispatch label ``c<config> <kernel> n=<points> [variant]`` (the names
+    bench.py --label-kernels gives its calls, which the profiler's kernel
+    renaming puts in place of the kernel name): calls, average, min and max
+    duration (ns), and the algorithmic GB/s and fraction of the HBM peak of
+    the average."""
+    rows = _csv(folder, "kernel_trace.csv")
+    agg = defaultdict(list)
+    for r in rows:
+        if LABEL.match(r["Kernel_Name"].strip()):
+            agg[r["Kernel_Name"].strip()].append(
+                int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    out = []
+    for name, v in agg.items():
+        m = LABEL.match(name)
+        cfg, kernel, n, variant = int(m.group(1)), m.group(2), int(m.group(3)), m.group(4) or ""
+        avg = sum(v) / len(v)
+        gbs = LABEL_BYTES[kernel] * n / avg if kernel in LABEL_BYTES else None
+        out.append({"label": name, "config": cfg, "kernel": kernel, "points": n,
+                    "variant": variant, "calls": len(v), "avg_ns": avg, "min_ns": min(v),
+                    "max_ns": max(v), "GB_s": gbs,
+                    "frac": gbs / HBM_PEAK_GBS if gbs is not None else None})
+    return sorted(out, key=lambda r: (r["config"], r["points"], r["kernel"], r["variant"]))
 
 
 def bench_lines(specs):
@@ -173,6 +208,20 @@ def main():
                     f.write(f"| `{short(r['name'])}` ({kernel}) | {r['grid']} | {r['calls']} | "
                             f"{r['avg_ns'] / 1e3:.2f} | {r['min_ns'] / 1e3:.2f} | "
                             f"{r['max_ns'] / 1e3:.2f} |\n")
+        lab = labelled_dispatches(a.trace)
+        if lab:
+            f.write("\nEvery labelled dispatch of the run by configuration (bench.py "
+                    "--label-kernels; kernel durations from the trace; GB/s = algorithmic "
+                    "bytes of the launch / average duration):\n\n"
+                    "| configuration | kernel | points | variant | calls | average (us) | "
+                    "min (us) | max (us) | GB/s | of 8 TB/s |\n"
+                    "|---|---|---|---|---|---|---|---|---|---|\n")
+            for r in lab:
+                g = "" if r["GB_s"] is None else f"{r['GB_s']:.0f}"
+                fr = "" if r["frac"] is None else f"{100 * r['frac']:.1f} %"
+                f.write(f"| {r['config']} | {r['kernel']} | {r['points']} | {r['variant']} | "
+                        f"{r['calls']} | {r['avg_ns'] / 1e3:.2f} | {r['min_ns'] / 1e3:.2f} | "
+                        f"{r['max_ns'] / 1e3:.2f} | {g} | {fr} |\n")
         lines = bench_lines(a.bench)
         if lines:
             f.write("\nbench.py's own timing of its dominant kernel (HIP events on the kernel's "

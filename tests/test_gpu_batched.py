@@ -5,6 +5,7 @@ import pytest
 import torch
 
 import oracle
+import oracle_par
 from gpu_util import assert_close, dev, need_gpu
 from paper_1804_10120_amd import BatchPlan, tl_dtg_chain, tl_dtg_chain_bwd
 from paper_1804_10120_amd.synth import config_seed, domain_edges, make_fields
@@ -105,19 +106,35 @@ def test_new_plan_after_pointer_change():
     _check(plan2, hosts2, devs2)
 
 
+def _oracle_per_domain(hosts, fn):
+    """The oracle (on host threads) over all subgrids at once, split back per
+    subgrid."""
+    sizes = [f["g"].shape[1] for f in hosts]
+    cut = np.cumsum(sizes)[:-1]
+    res = fn({k: np.concatenate([f[k] for f in hosts], axis=1) for k in hosts[0]})
+    if isinstance(res, dict):
+        parts = {k: np.split(v, cut, axis=1) for k, v in res.items()}
+        return [{k: parts[k][d] for k in res} for d in range(len(sizes))]
+    return np.split(res, cut, axis=1)
+
+
 def test_full_multidomain_workload():
-    """256 subgrids with edges uniform on 8..48 (the benchmark's batch)."""
+    """256 subgrids with edges uniform on 8..48 (the benchmark's batch, its
+    fields with the leading dimension padded to 16 doubles as the benchmark
+    stores them): every subgrid against the oracle element by element, and
+    against the plain kernel."""
+    from paper_1804_10120_amd import to_field
     edges = domain_edges(256, seed=config_seed(4))
     sizes = [int(e) ** 3 for e in edges]
-    hosts, devs = _domains(sizes, seed=config_seed(4))
+    hosts = [make_fields(n, seed=config_seed(4) * 1000 + d, fields=KEYS)
+             for d, n in enumerate(sizes)]
+    devs = [{k: to_field(f[k], device="cuda") for k in KEYS} for f in hosts]
     plan = BatchPlan(devs)
     plan.run()
     torch.cuda.synchronize()
-    idx = np.random.default_rng(0).choice(256, 24, replace=False)
-    for d in idx:                      # oracle on a sample of whole subgrids
-        ref = oracle.dtg_chain(*[hosts[d][k] for k in KEYS])
-        assert_close(plan.outputs[d], ref, what=f"subgrid {d}")
-    for d in range(256):               # every subgrid against the plain kernel
+    refs = _oracle_per_domain(hosts, oracle_par.dtg_chain)
+    for d in range(256):
+        assert_close(plan.outputs[d], refs[d], what=f"subgrid {d} vs oracle")
         plain = tl_dtg_chain(*[devs[d][k] for k in KEYS])
         if not torch.equal(plain, plan.outputs[d]):
             assert_close(plan.outputs[d], plain.cpu().numpy(), what=f"subgrid {d} vs plain")
@@ -231,23 +248,21 @@ def test_bwd_plan_wanted_subset_and_graph_replay():
 
 
 def test_bwd_plan_full_multidomain_workload():
-    """256 subgrids with edges uniform on 8..48: every subgrid against the plain
-    adjoint kernel, 16 of them against the oracle."""
+    """256 subgrids with edges uniform on 8..48: every gradient component of
+    every subgrid against the oracle element by element, and against the plain
+    adjoint kernel."""
     edges = domain_edges(256, seed=config_seed(4))
     sizes = [int(e) ** 3 for e in edges]
     hosts, devs = _bwd_domains(sizes, seed=23)
     plan = BatchPlan(devs, kind="bwd")
     plan.run()
     torch.cuda.synchronize()
-    check = set(np.random.default_rng(1).choice(256, 16, replace=False).tolist())
-    for i, (f, d, outs) in enumerate(zip(hosts, devs, plan.outputs)):
+    refs = _oracle_per_domain(hosts, oracle_par.dtg_chain_vjp)
+    for i, (d, outs, ref) in enumerate(zip(devs, plan.outputs, refs)):
         plain = tl_dtg_chain_bwd(d["g"], d["dg"], d["beta"], d["K"], d["alpha"], d["W"])
         for k, o, p in zip(GRADS, outs, plain):
+            assert_close(o, ref[k], what=f"subgrid {i} {k}_bar vs oracle")
             assert_close(o, p, what=f"subgrid {i} {k}_bar vs plain")
-        if i in check:
-            ref = oracle.dtg_chain_vjp(tuple(f[k] for k in KEYS), f["W"])
-            for k, o in zip(GRADS, outs):
-                assert_close(o, ref[k], what=f"subgrid {i} {k}_bar vs oracle")
     plan.close()
 
 

@@ -145,3 +145,47 @@ def test_traffic_record_goes_stale_when_the_build_inputs_change(tmp_path):
         with open(root / rel, "a") as f:
             f.write("\n// edited\n")
         assert bench.traffic_record("dtg_chain_bwd", n, root=str(root)) is None, rel
+
+
+def test_threaded_oracle_equals_the_serial_oracle():
+    """The tests' threaded runner of the oracle (point ranges on host threads,
+    joined in point order) gives bitwise the serial oracle's results."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import oracle
+    import oracle_par
+    from paper_1804_10120_amd.synth import make_expr_inputs, make_fields
+    n = 1000
+    f = make_fields(n, seed=77)
+    keys = oracle_par.KEYS
+    assert np.array_equal(oracle_par.over_points(oracle.dtg_chain, *[f[k] for k in keys],
+                                                 chunk=97),
+                          oracle.dtg_chain(*[f[k] for k in keys]))
+    par = oracle_par.over_points(lambda *x: oracle.dtg_chain_vjp(tuple(x[:6]), x[6]),
+                                 *[f[k] for k in keys], f["W"], chunk=131)
+    ser = oracle.dtg_chain_vjp(tuple(f[k] for k in keys), f["W"])
+    assert set(par) == set(ser) and all(np.array_equal(par[k], ser[k]) for k in ser)
+    xs = make_expr_inputs("contract2", n, seed=5)
+    assert np.array_equal(oracle_par.expr("contract2", *xs), oracle.expr("contract2", *xs))
+
+
+def test_profsum_labelled_dispatches(tmp_path):
+    """Dispatches renamed after bench.py's labels are grouped per label, with
+    the algorithmic GB/s of the average duration."""
+    from paper_1804_10120_amd import profsum
+    trace = tmp_path / "trace"
+    trace.mkdir()
+    hdr = ["Kernel_Name", "Grid_Size_X", "Start_Timestamp", "End_Timestamp", "VGPR_Count",
+           "Accum_VGPR_Count"]
+    n = 262144
+    _write(trace / "t_kernel_trace.csv", hdr,
+           [["c2 dtg_chain n=262144", n, 0, 20000, 62, 0],
+            ["c2 dtg_chain n=262144", n, 30000, 40000, 62, 0],
+            ["c5 dtg_chain_bwd n=262144 ppt2_b512", n // 4, 0, 30000, 166, 0],
+            ["void tl::k_copy(double const*, double*, long)", 1024, 0, 5, 12, 0]])
+    rows = profsum.labelled_dispatches(str(trace))
+    assert [r["label"] for r in rows] == ["c2 dtg_chain n=262144",
+                                          "c5 dtg_chain_bwd n=262144 ppt2_b512"]
+    a, b = rows
+    assert a["calls"] == 2 and a["avg_ns"] == 15000 and a["min_ns"] == 10000
+    assert abs(a["GB_s"] - 392 * n / 15000) < 1e-9 and b["variant"] == "ppt2_b512"
+    assert abs(b["frac"] - 664 * n / 30000 / 8000) < 1e-12
