@@ -88,30 +88,18 @@ __device__ inline void bstore1(rsrc_t r, uint32_t voff, uint32_t soff, double v)
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff,
                                         NT ? kCpolNT : 0);
 }
-// A store of more than 64 bits reads its data registers after it issues; an
-// instruction that rewrites them must come two wait states later.  The
-// compiler pads this only when the component offset is a constant, and
-// measured on gfx950 a store with the offset in a scalar register that was
-// followed at once by such a write stored the new value now and then.  So the
-// 16-byte store is written out by hand, with wait states on both sides: two
-// after it for its data, and five before it, because a scalar operand (offset
-// or descriptor) may have just been written by a vector instruction (a scalar
-// register restored from a vector lane), which a memory instruction may read
-// only five wait states later.  The compiler cannot see into the statement,
-// so it inserts neither.
+// A store of more than 64 bits reads its data registers after it has issued,
+// so an instruction that rewrites them must come two wait states later.  The
+// compiler inserts that gap only for a store whose scalar offset operand is
+// not a register; with the component offset in a scalar register (as for the
+// 8-byte stores) it inserts none, and on gfx950 such a store followed at once
+// by a rewrite of its data stored the new value now and then.  So the 16-byte
+// store adds the component offset to the lane's vector offset and leaves the
+// scalar offset zero: one vector add per store, and a store the compiler pads.
 template <bool NT>
 __device__ inline void bstore2(rsrc_t r, uint32_t voff, uint32_t soff, dbl2 v) {
-  const u32x4 d = __builtin_bit_cast(u32x4, v);
-  if constexpr (NT)
-    asm volatile("s_nop 4\n\tbuffer_store_dwordx4 %0, %1, %2, %3 offen nt\n\ts_nop 1"
-                 :
-                 : "v"(d), "v"(voff), "s"(r), "s"(soff)
-                 : "memory");
-  else
-    asm volatile("s_nop 4\n\tbuffer_store_dwordx4 %0, %1, %2, %3 offen\n\ts_nop 1"
-                 :
-                 : "v"(d), "v"(voff), "s"(r), "s"(soff)
-                 : "memory");
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff + soff, 0,
+                                         NT ? kCpolNT : 0);
 }
 
 // Offsets of each field's first component in the gathered per-point vector.

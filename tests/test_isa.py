@@ -2,17 +2,15 @@
 
 A vector-memory store of more than 64 bits reads its data registers after it
 has issued, so an ALU instruction that rewrites them must come at least two
-wait states later.  The compiler inserts that gap for stores with a constant
-offset and for flat/global stores, but not for buffer stores whose offset is
-in a scalar register, which is how every component store of the library is
-addressed; measured on gfx950, such a store followed at once by a rewrite of
-its data stored the new value now and then.  The library therefore issues its
-16-byte buffer stores by hand with their own wait states, and this test checks
-the disassembly of every kernel for a rewrite that comes too early.  Because
-the compiler does not see into a hand-written instruction, the test also
-checks the other hazard such a store can meet: a scalar register written by a
-vector instruction must not be read by a memory instruction within five wait
-states.
+wait states later.  The compiler inserts that gap for stores whose scalar
+offset operand is not a register, but not for buffer stores with the offset in
+a scalar register; measured on gfx950, such a store followed at once by a
+rewrite of its data stored the new value now and then.  The library's 16-byte
+stores therefore carry the component offset in the vector offset and a zero
+scalar offset, and this test checks the disassembly of every kernel for a
+rewrite that comes too early.  It also checks the other hazard a buffer access
+can meet: a scalar register written by a vector instruction must not be read
+by a memory instruction within five wait states.
 """
 import os
 import re
