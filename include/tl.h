@@ -72,9 +72,14 @@ typedef struct { double* ptr; int64_t ld; } tl_field;
  * grid_mult selects the default value of that member; flags are taken as
  * given.
  *   block      threads per block: 64, 128, 256, 512 or 1024
- *   ppt        consecutive grid points per thread: 1 or 2 (2 uses 16-byte
- *              loads and needs every field 16-byte aligned with an even ld;
- *              otherwise the call silently uses 1)
+ *   ppt        consecutive grid points per thread: 1, 2 or 4 (2 and 4 use
+ *              16-byte loads and stores and need every field 16-byte aligned
+ *              with an even ld; otherwise the call silently uses 1).  4 is
+ *              taken by bodies with at most 24 component streams read and
+ *              written per point (tl_sym_inverse, tl_dtg, the expressions
+ *              assign1, assign2, add1-add3, mult1 and kij, and generated
+ *              kernels of that size); the others silently use 2.
+ *              tl_christoffel with lanes > 1 ignores ppt.
  *   flags      TL_TUNE_NT: non-temporal (streaming) loads and stores;
  *              TL_TUNE_XCD: the blocks resident on one XCD (workgroups go to
  *              the 8 XCDs round-robin) take consecutive tiles, so each XCD

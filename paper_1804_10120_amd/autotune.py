@@ -26,6 +26,8 @@ KERNELS = ("sym_inverse", "christoffel", "cov_deriv", "dtg", "dtg_chain", "dtg_c
            "dtg_chain_fwd_bwd")
 BLOCKS = (64, 128, 256, 512, 1024)
 PPTS = (1, 2)
+# kernels whose bodies also run four points per lane (few component streams)
+PPT4_KERNELS = ("sym_inverse", "dtg")
 NTS = (False, True)
 XCDS = (False, True)
 GRID_MULTS = (0, 1, 2, 4, 8)
@@ -91,7 +93,7 @@ def lookup(kernel, n):
 
 def candidates(blocks=BLOCKS, ppts=PPTS, nts=NTS, xcds=XCDS, grid_mults=GRID_MULTS):
     for b, p, nt, x, gm in itertools.product(blocks, ppts, nts, xcds, grid_mults):
-        if b == 1024 and p == 2:
+        if b == 1024 and p >= 2:
             continue    # this shape exceeds the register budget and spills
         yield {"block": b, "ppt": p, "nt": nt, "xcd": x, "grid_mult": gm}
 
@@ -162,7 +164,7 @@ def tune(kernel, n, tunes=None, reps=20, save=True, device="cuda"):
     """Times every candidate shape of ``kernel`` at ``n`` points; returns
     {"tune": best, "us": time, "GB_s": algorithmic bandwidth, "table": [...]}."""
     if tunes is None:
-        tunes = list(candidates())
+        tunes = list(candidates(ppts=PPTS + ((4,) if kernel in PPT4_KERNELS else ())))
         if kernel == "christoffel":     # components of a point spread over lanes
             tunes += [{"block": b, "nt": True, "lanes": la}
                       for b in (64, 256) for la in (2, 3, 6, 9, 18)]

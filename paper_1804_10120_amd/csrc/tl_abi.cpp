@@ -185,7 +185,7 @@ tl::Resolved defaults(tl::KernelId k, int64_t n) {
     r.block = 64;
     r.ppt = 1;
     r.xcd = false;
-  } else if (k == tl::KernelId::Chain) {
+  } else if (k == tl::KernelId::Chain || k == tl::KernelId::Generic) {
     r.block = 256;
     r.ppt = 1;
     r.xcd = false;
@@ -214,7 +214,8 @@ tl_status resolve(tl::KernelId k, const tl_tune* t, bool vec_ok, bool buf_ok, in
       r.block = t->block;
     }
     if (t->ppt != 0) {
-      if (t->ppt != 1 && t->ppt != 2) return fail(TL_ERR_INVALID, "tune.ppt=%d not in {1,2}", t->ppt);
+      if (t->ppt != 1 && t->ppt != 2 && t->ppt != 4)
+        return fail(TL_ERR_INVALID, "tune.ppt=%d not in {1,2,4}", t->ppt);
       r.ppt = t->ppt;
     }
     if (t->flags & ~(TL_TUNE_NT | TL_TUNE_XCD | TL_TUNE_PTR64))
@@ -226,6 +227,12 @@ tl_status resolve(tl::KernelId k, const tl_tune* t, bool vec_ok, bool buf_ok, in
       return fail(TL_ERR_INVALID, "tune.grid_mult=%d not in [0,1024]", t->grid_mult);
     r.grid_mult = t->grid_mult;
   }
+  // Four points per lane only where the body's values fit the registers
+  // (the inverse and d_t g from nabla beta; a generic body decides on the
+  // device), else two.
+  if (r.ppt == 4 && k != tl::KernelId::SymInverse && k != tl::KernelId::Dtg &&
+      k != tl::KernelId::Generic)
+    r.ppt = 2;
   if (!vec_ok) r.ppt = 1;
   r.buf = buf_ok;
   r.num_cu = num_cus();
@@ -303,7 +310,7 @@ tl_status run_generated(const char* name, int64_t n, const tl_cfield* in, int32_
   for (int f = 0; f < nin; ++f) set_in(a, f, in[f]);
   for (int f = 0; f < nout; ++f) set_out(a, f, out[f]);
   Resolved r;
-  tl_status s = resolve(KernelId::Chain, tune, c.vec_ok, c.buf_ok, n, &r);
+  tl_status s = resolve(KernelId::Generic, tune, c.vec_ok, c.buf_ok, n, &r);
   if (s != TL_OK) return s;
   hipError_t e = launch(r, a, n, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "generated kernel launch");
@@ -581,7 +588,7 @@ tl_status tl_expr(int32_t expr, int64_t n, const tl_cfield* in, int32_t nin, tl_
   for (int f = 0; f < k; ++f) set_in(a, f, in[f]);
   set_out(a, 0, out);
   tl::Resolved r;
-  tl_status s = resolve(tl::KernelId::Chain, tune, c.vec_ok, c.buf_ok, n, &r);
+  tl_status s = resolve(tl::KernelId::Generic, tune, c.vec_ok, c.buf_ok, n, &r);
   if (s != TL_OK) return s;
   hipError_t e = tl::launch_expr(expr, r, a, n, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "expression launch");
@@ -605,7 +612,7 @@ tl_status tl_bw_twin(int64_t n, int32_t nin, tl_cfield in, int32_t nout, tl_fiel
   set_in(a, 0, in);
   set_out(a, 0, out);
   tl::Resolved r;
-  tl_status s = resolve(tl::KernelId::Chain, tune, c.vec_ok, c.buf_ok, n, &r);
+  tl_status s = resolve(tl::KernelId::Generic, tune, c.vec_ok, c.buf_ok, n, &r);
   if (s != TL_OK) return s;
   hipError_t e = tl::launch_twin(nin, nout, r, a, n, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "twin launch");
@@ -927,7 +934,7 @@ tl_status tl_kernel_info(const char* kernel, const tl_tune* tune, tl_kernel_attr
     if (std::strcmp(kExprName[e], kernel) == 0) expr = e;
   if (id == nullptr && expr < 0) return fail(TL_ERR_INVALID, "unknown kernel '%s'", kernel);
   tl::Resolved r;
-  tl_status s = resolve(id ? *id : tl::KernelId::Chain, tune, true, true, int64_t(1) << 24, &r);
+  tl_status s = resolve(id ? *id : tl::KernelId::Generic, tune, true, true, int64_t(1) << 24, &r);
   if (s != TL_OK) return s;
   const void* fn = id ? tl::kernel_address(*id, r) : tl::expr_address(expr, r);
   if (fn == nullptr) return fail(TL_ERR_INVALID, "no instantiation for this tuning");
@@ -942,7 +949,7 @@ tl_status tl_kernel_info(const char* kernel, const tl_tune* tune, tl_kernel_attr
   tl::KernelResources res{-1, -1, -1, -1, -1};
   tl::kernel_resources(hipKernelNameRefByPtr(fn, nullptr), &res);
   out->block = block;
-  out->ppt = r.ppt;
+  out->ppt = id ? r.ppt : tl::expr_ppt(expr, r.ppt);
   out->flags = (r.nt ? TL_TUNE_NT : 0) | (r.xcd ? TL_TUNE_XCD : 0);
   out->vgprs = attr.numRegs;
   out->agprs = res.agprs;

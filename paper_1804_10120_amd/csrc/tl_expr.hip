@@ -35,4 +35,14 @@ const void* expr_address(int id, const Resolved& r) {
   }
 }
 
+int expr_ppt(int id, int ppt) {
+  switch (id) {
+#define TL_EXPR(I, OP) \
+  case I: return op_ppt<OP>(ppt);
+    TL_EXPR_OPS(TL_EXPR)
+#undef TL_EXPR
+    default: return ppt;
+  }
+}
+
 }  // namespace tl

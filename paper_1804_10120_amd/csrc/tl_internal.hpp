@@ -27,13 +27,16 @@ struct alignas(64) BatchDomain {
   int64_t n;
 };
 
+// Generic: a body chosen by the caller (the benchmark expressions, the
+// bandwidth twins, generated kernels): the fused chain's default shapes, and
+// the points per lane settled by the body's stream count (op_ppt).
 enum class KernelId { SymInverse, Christoffel, CovDeriv, Dtg, Chain, ChainBwd, ChainBatched,
-                      ChainFwdBwd, ChainBwdBatched };
+                      ChainFwdBwd, ChainBwdBatched, Generic };
 
 // A tuning request resolved to one compiled instantiation.
 struct Resolved {
   int block = 256;
-  int ppt = 1;
+  int ppt = 1;       // 1, 2 or 4 (4 only for bodies with few component streams)
   bool nt = false;
   bool xcd = false;  // XCD-contiguous tile order (grid is then a multiple of 8)
   int grid_mult = 0;
@@ -64,6 +67,8 @@ const void* kernel_address(KernelId k, const Resolved& r);
 // The benchmark expressions (ids as in tl_expr_id of tl.h).
 hipError_t launch_expr(int id, const Resolved& r, const KArgs& a, int64_t n, hipStream_t s);
 const void* expr_address(int id, const Resolved& r);
+// Points per lane expression `id` runs with when `ppt` is requested.
+int expr_ppt(int id, int ppt);
 // Validation, tuning and launch for a generated entry point: nin/nout and
 // the fields' component counts are checked against the expected ones.
 typedef hipError_t (*LaunchFn)(const Resolved&, const KArgs&, int64_t, hipStream_t);

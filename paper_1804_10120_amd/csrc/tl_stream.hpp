@@ -3,7 +3,7 @@
 //
 // One lane owns PPT consecutive grid points.  It issues every load of its
 // points up front -- one coalesced stream per tensor component, 16-byte
-// vector loads when PPT == 2 -- runs the per-point body (tl_device.hpp,
+// vector loads when PPT is 2 or 4 -- runs the per-point body (tl_device.hpp,
 // tl_expr_ops.hpp) in registers and streams the results out.  No LDS and no
 // MFMA: every point is independent and the contractions are 3 long, so the
 // kernels are bound by HBM bandwidth, and the levers are the bytes in flight
@@ -136,6 +136,16 @@ struct is_stream : std::false_type {};
 template <class Op>
 struct is_stream<Op, std::void_t<decltype(Op::kStream)>> : std::bool_constant<Op::kStream> {};
 
+// Points per lane a body actually runs with for a requested ppt: streaming
+// bodies take one; four only for bodies with at most kMaxStreams4 component
+// streams (their four points' values then fit the registers), else two.
+constexpr int kMaxStreams4 = 24;
+template <class Op>
+constexpr int op_ppt(int ppt) {
+  if constexpr (is_stream<Op>::value) return 1;
+  else return ppt == 4 && Op::NIN + Op::NOUT > kMaxStreams4 ? 2 : ppt;
+}
+
 template <class Op, bool NT>
 __device__ inline void point_stream(const KArgs& a, int64_t p) {
   Op::stream([&](int f, int c) { return load1<NT>(a.in[f] + c * a.ldin[f] + p); },
@@ -161,29 +171,38 @@ __device__ inline void points_full(const KArgs& a, int64_t p) {
       for (int c = 0; c < Op::fout[f]; ++c) store1<NT>(a.out[f] + c * a.ldout[f] + p, y[oo.v[f] + c]);
     }
   } else {
-    static_assert(PPT == 2, "PPT is 1 or 2");
-    dbl2 x2[Op::NIN];
+    static_assert(PPT == 2 || PPT == 4, "PPT is 1, 2 or 4");
+    constexpr int H = PPT / 2;  // 16-byte accesses per component
+    dbl2 x2[H][Op::NIN];
 #pragma unroll
     for (int f = 0; f < Op::NF_IN; ++f)
 #pragma unroll
-      for (int c = 0; c < Op::fin[f]; ++c) x2[io.v[f] + c] = load2<NT>(a.in[f] + c * a.ldin[f] + p);
-    double x[Op::NIN], y0[Op::NOUT], y1[Op::NOUT];
+      for (int c = 0; c < Op::fin[f]; ++c)
 #pragma unroll
-    for (int q = 0; q < Op::NIN; ++q) x[q] = x2[q].x;
-    Op::apply(x, y0);
+        for (int h = 0; h < H; ++h)
+          x2[h][io.v[f] + c] = load2<NT>(a.in[f] + c * a.ldin[f] + p + 2 * h);
+    double x[Op::NIN], y[PPT][Op::NOUT];
 #pragma unroll
-    for (int q = 0; q < Op::NIN; ++q) x[q] = x2[q].y;
-    Op::apply(x, y1);
+    for (int h = 0; h < H; ++h) {
+#pragma unroll
+      for (int q = 0; q < Op::NIN; ++q) x[q] = x2[h][q].x;
+      Op::apply(x, y[2 * h]);
+#pragma unroll
+      for (int q = 0; q < Op::NIN; ++q) x[q] = x2[h][q].y;
+      Op::apply(x, y[2 * h + 1]);
+    }
 #pragma unroll
     for (int f = 0; f < Op::NF_OUT; ++f) {
       if (a.out[f] == nullptr) continue;
 #pragma unroll
-      for (int c = 0; c < Op::fout[f]; ++c) {
-        dbl2 v;
-        v.x = y0[oo.v[f] + c];
-        v.y = y1[oo.v[f] + c];
-        store2<NT>(a.out[f] + c * a.ldout[f] + p, v);
-      }
+      for (int c = 0; c < Op::fout[f]; ++c)
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+          dbl2 v;
+          v.x = y[2 * h][oo.v[f] + c];
+          v.y = y[2 * h + 1][oo.v[f] + c];
+          store2<NT>(a.out[f] + c * a.ldout[f] + p + 2 * h, v);
+        }
     }
   }
 }
@@ -259,29 +278,38 @@ __device__ inline void points_full_buf(const KArgs& a, const Bufs<Op>& b, uint32
         bstore1<NT>(b.out[f], p8, c * b.ldout8[f], y[oo.v[f] + c]);
     }
   } else {
-    static_assert(PPT == 2, "PPT is 1 or 2");
-    dbl2 x2[Op::NIN];
+    static_assert(PPT == 2 || PPT == 4, "PPT is 1, 2 or 4");
+    constexpr int H = PPT / 2;  // 16-byte accesses per component
+    dbl2 x2[H][Op::NIN];
 #pragma unroll
     for (int f = 0; f < Op::NF_IN; ++f)
 #pragma unroll
-      for (int c = 0; c < Op::fin[f]; ++c) x2[io.v[f] + c] = bload2<NT>(b.in[f], p8, c * b.ldin8[f]);
-    double x[Op::NIN], y0[Op::NOUT], y1[Op::NOUT];
+      for (int c = 0; c < Op::fin[f]; ++c)
 #pragma unroll
-    for (int q = 0; q < Op::NIN; ++q) x[q] = x2[q].x;
-    Op::apply(x, y0);
+        for (int h = 0; h < H; ++h)
+          x2[h][io.v[f] + c] = bload2<NT>(b.in[f], p8 + 16 * h, c * b.ldin8[f]);
+    double x[Op::NIN], y[PPT][Op::NOUT];
 #pragma unroll
-    for (int q = 0; q < Op::NIN; ++q) x[q] = x2[q].y;
-    Op::apply(x, y1);
+    for (int h = 0; h < H; ++h) {
+#pragma unroll
+      for (int q = 0; q < Op::NIN; ++q) x[q] = x2[h][q].x;
+      Op::apply(x, y[2 * h]);
+#pragma unroll
+      for (int q = 0; q < Op::NIN; ++q) x[q] = x2[h][q].y;
+      Op::apply(x, y[2 * h + 1]);
+    }
 #pragma unroll
     for (int f = 0; f < Op::NF_OUT; ++f) {
       if (a.out[f] == nullptr) continue;
 #pragma unroll
-      for (int c = 0; c < Op::fout[f]; ++c) {
-        dbl2 v;
-        v.x = y0[oo.v[f] + c];
-        v.y = y1[oo.v[f] + c];
-        bstore2<NT>(b.out[f], p8, c * b.ldout8[f], v);
-      }
+      for (int c = 0; c < Op::fout[f]; ++c)
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+          dbl2 v;
+          v.x = y[2 * h][oo.v[f] + c];
+          v.y = y[2 * h + 1][oo.v[f] + c];
+          bstore2<NT>(b.out[f], p8 + 16 * h, c * b.ldout8[f], v);
+        }
     }
   }
 }
@@ -366,7 +394,10 @@ static hipError_t launch_b(const Resolved& r, const KArgs& a, int64_t n, int64_t
   if constexpr (is_stream<Op>::value) {
     return launch_p<Op, BLOCK, 1>(r, a, n, ntiles, grid, x, s);
   } else {
-    if (r.ppt == 2) return launch_p<Op, BLOCK, 2>(r, a, n, ntiles, grid, x, s);
+    const int ppt = op_ppt<Op>(r.ppt);
+    if constexpr (Op::NIN + Op::NOUT <= kMaxStreams4)
+      if (ppt == 4) return launch_p<Op, BLOCK, 4>(r, a, n, ntiles, grid, x, s);
+    if (ppt == 2) return launch_p<Op, BLOCK, 2>(r, a, n, ntiles, grid, x, s);
     return launch_p<Op, BLOCK, 1>(r, a, n, ntiles, grid, x, s);
   }
 }
@@ -381,7 +412,7 @@ static Resolved clamp_block(const Resolved& r0) {
 template <class Op>
 static hipError_t launch_op(const Resolved& r0, const KArgs& a, int64_t n, hipStream_t s) {
   const Resolved r = clamp_block<Op>(r0);
-  const int64_t per = static_cast<int64_t>(r.block) * (is_stream<Op>::value ? 1 : r.ppt);
+  const int64_t per = static_cast<int64_t>(r.block) * op_ppt<Op>(r.ppt);
   const int64_t ntiles = (n + per - 1) / per;
   const int64_t grid = grid_size(r, ntiles);
   constexpr int cap = max_block<Op>::value;
@@ -405,14 +436,25 @@ static const void* ptr_p(const Resolved& r) {
   return r.buf ? kernel_ptr<Op, BLOCK, PPT, true, true>() : kernel_ptr<Op, BLOCK, PPT, true, false>();
 }
 
+template <class Op, int BLOCK>
+static const void* ptr_b(const Resolved& r) {
+  if constexpr (is_stream<Op>::value) {
+    return ptr_p<Op, BLOCK, 1>(r);
+  } else {
+    const int ppt = op_ppt<Op>(r.ppt);
+    if constexpr (Op::NIN + Op::NOUT <= kMaxStreams4)
+      if (ppt == 4) return ptr_p<Op, BLOCK, 4>(r);
+    return ppt == 2 ? ptr_p<Op, BLOCK, 2>(r) : ptr_p<Op, BLOCK, 1>(r);
+  }
+}
+
 template <class Op>
 static const void* ptr_op(const Resolved& r0) {
   const Resolved r = clamp_block<Op>(r0);
-  constexpr int P2 = is_stream<Op>::value ? 1 : 2;
   constexpr int cap = max_block<Op>::value;
-#define TL_PTR(B)                                                                  \
-  case B:                                                                          \
-    if constexpr (cap >= B) return r.ppt == 2 ? ptr_p<Op, B, P2>(r) : ptr_p<Op, B, 1>(r); \
+#define TL_PTR(B)                                 \
+  case B:                                         \
+    if constexpr (cap >= B) return ptr_b<Op, B>(r); \
     return nullptr;
   switch (r.block) {
     TL_PTR(64)

@@ -133,7 +133,7 @@ def test_inputs_may_alias_each_other(L):
     assert call_chain(L, n, a, out, bad) == _abi.TL_ERR_INVALID
 
 
-@pytest.mark.parametrize("tune", [(96, 0, 0, 0), (256, 3, 0, 0), (256, 1, 8, 0), (256, 1, 0, -1),
+@pytest.mark.parametrize("tune", [(96, 0, 0, 0), (256, 3, 0, 0), (256, 8, 0, 0), (256, 1, 8, 0), (256, 1, 0, -1),
                                   (256, 1, 0, 0, 4), (256, 1, 0, 0, 3)])
 def test_invalid_tuning(L, tune):
     a, out = chain_args(64)

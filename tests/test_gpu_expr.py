@@ -14,7 +14,8 @@ pytestmark = pytest.mark.gpu
 EXPRS = tuple(EXPR_INPUTS)
 TUNES = [None, dict(block=64, ppt=1), dict(block=256, ppt=2, nt=True, xcd=True),
          dict(block=128, ppt=1, nt=True, grid_mult=1), dict(block=512, ppt=2),
-         dict(block=256, ppt=1, nt=True, xcd=True, ptr64=True)]
+         dict(block=256, ppt=1, nt=True, xcd=True, ptr64=True), dict(block=256, ppt=4, nt=True),
+         dict(block=64, ppt=4, xcd=True, grid_mult=1)]
 
 
 @pytest.fixture(scope="module", autouse=True)

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 SIZES = [1, 65, 1000, 4097]
 TUNES = [None, dict(block=64, nt=True), dict(block=512, nt=True, xcd=True, grid_mult=1),
-         dict(block=256, nt=True, xcd=True, ptr64=True)]
+         dict(block=256, nt=True, xcd=True, ptr64=True), dict(block=128, ppt=4, nt=True)]
 
 
 @pytest.fixture(scope="module", autouse=True)

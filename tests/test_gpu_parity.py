@@ -17,7 +17,10 @@ SIZES = [1, 2, 63, 64, 65, 127, 129, 512, 1553, 4096, 4097, 10007]
 TUNES = [None, dict(block=64, ppt=1), dict(block=128, ppt=2), dict(block=256, ppt=2, nt=True),
          dict(block=512, ppt=1, nt=True), dict(block=1024, ppt=1), dict(block=256, ppt=1, grid_mult=1),
          dict(block=256, ppt=1, nt=True, xcd=True), dict(block=64, ppt=2, xcd=True, grid_mult=1),
-         dict(block=256, ppt=1, nt=True, xcd=True, ptr64=True), dict(block=512, ppt=2, nt=True, ptr64=True)]
+         dict(block=256, ppt=1, nt=True, xcd=True, ptr64=True), dict(block=512, ppt=2, nt=True, ptr64=True),
+         # four points per lane (the kernels with more streams run two)
+         dict(block=256, ppt=4, nt=True), dict(block=128, ppt=4),
+         dict(block=64, ppt=4, nt=True, xcd=True, grid_mult=1), dict(block=512, ppt=4, nt=True, ptr64=True)]
 
 
 @pytest.fixture(scope="module", autouse=True)

@@ -22,7 +22,7 @@ GRADS = (6, 18, 3, 9, 6, 1)
 tunes = st.one_of(
     st.none(),
     st.fixed_dictionaries({"block": st.sampled_from([64, 128, 256, 512, 1024]),
-                           "ppt": st.sampled_from([1, 2]), "nt": st.booleans(),
+                           "ppt": st.sampled_from([1, 2, 4]), "nt": st.booleans(),
                            "xcd": st.booleans(), "ptr64": st.booleans(),
                            "grid_mult": st.sampled_from([0, 0, 1, 3])}))
 layouts = st.tuples(st.integers(0, 37), st.integers(0, 5))     # (pad, offset) in doubles

@@ -17,8 +17,9 @@ def _gpu():
 
 @pytest.mark.parametrize("nin,nout", TWIN_SHAPES)
 @pytest.mark.parametrize("n", [1, 129, 4097])
-@pytest.mark.parametrize("tune", [None, dict(block=64, ppt=2, nt=True, xcd=True)],
-                         ids=["default", "b64ppt2"])
+@pytest.mark.parametrize("tune", [None, dict(block=64, ppt=2, nt=True, xcd=True),
+                                  dict(block=256, ppt=4, nt=True)],
+                         ids=["default", "b64ppt2", "b256ppt4"])
 def test_twin(nin, nout, n, tune):
     x = np.random.default_rng(nin * 1000 + n).standard_normal((nin, n))
     src = DevField(x, pad=2)
