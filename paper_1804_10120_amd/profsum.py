@@ -164,6 +164,9 @@ def _largest(agg, needle):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
+    ap.add_argument("--labels", help="kernel trace of a run with labelled dispatches "
+                    "(bench.py --label-kernels under --kernel-rename); default: --trace")
+    ap.add_argument("--labels-cmd", default="", help="the labelled run's command")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--cmd", required=True, help="the profiled command, for the record")
@@ -208,12 +211,13 @@ def main():
                     f.write(f"| `{short(r['name'])}` ({kernel}) | {r['grid']} | {r['calls']} | "
                             f"{r['avg_ns'] / 1e3:.2f} | {r['min_ns'] / 1e3:.2f} | "
                             f"{r['max_ns'] / 1e3:.2f} |\n")
-        lab = labelled_dispatches(a.trace)
+        lab = labelled_dispatches(a.labels or a.trace)
         if lab:
             f.write("\nEvery labelled dispatch of the run by configuration (bench.py "
                     "--label-kernels; kernel durations from the trace; GB/s = algorithmic "
-                    "bytes of the launch / average duration):\n\n"
-                    "| configuration | kernel | points | variant | calls | average (us) | "
+                    "bytes of the launch / average duration)"
+                    + (f", from\n\n    {a.labels_cmd}\n\n" if a.labels_cmd else ":\n\n")
+                    + "| configuration | kernel | points | variant | calls | average (us) | "
                     "min (us) | max (us) | GB/s | of 8 TB/s |\n"
                     "|---|---|---|---|---|---|---|---|---|---|\n")
             for r in lab:
