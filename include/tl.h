@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define TL_ABI_VERSION 3
+#define TL_ABI_VERSION 4
 
 typedef enum {
   TL_OK = 0,
@@ -219,6 +219,36 @@ tl_status tl_batch_plan_info(const tl_batch_plan* plan, int64_t* points, int64_t
 /* Waits for all work on the plan's device, then frees the plan (from any
  * current device; the current device is restored); NULL is a no-op. */
 tl_status tl_batch_plan_destroy(tl_batch_plan* plan);
+
+/* ---- Many subgrids without allocating ------------------------------------ */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): evaluates
+ * tl_dtg_chain on every domain with the batched kernel of tl_batch_plan_create
+ * -- the same launch, tile order and results as creating a plan with the same
+ * doms and tune, calling tl_batch_plan_launch_direct and destroying the plan --
+ * but with the plan's tables (domain descriptors, first tile of each domain,
+ * tile -> domain map) in a fixed array of device memory that the library
+ * holds on each device it runs on, from the first call there until the
+ * process ends (about 1.4 MB).  Kernels launched on `stream` write the tables
+ * from their kernel arguments, then the batched kernel runs; the call makes no
+ * device allocation, no host-to-device copy and no memset, and returns once
+ * the launches are queued (asynchronous).  The caller passes every input and
+ * output, as for a plan; the domains' buffers must stay valid until the work
+ * on `stream` has finished.
+ * Every call on a device shares that device's array and leaves its tables in
+ * it: calls that overlap on one device (on different streams, or from several
+ * host threads without ordering between them) race and may read each other's
+ * tables; order them on one stream.
+ * Limits: 1 <= ndom <= TL_NOALLOC_MAX_DOMAINS, and at most TL_NOALLOC_MAX_TILES
+ * tiles in all, a domain of n points taking ceil(n / (block * ppt)) tiles of
+ * the resolved launch shape (the default, one block of 128 threads per tile,
+ * allows 33.5 M points); beyond either limit TL_ERR_SIZE, before anything is
+ * launched.  Validation otherwise as for tl_batch_plan_create. */
+#define TL_NOALLOC_MAX_DOMAINS 1024
+#define TL_NOALLOC_MAX_TILES 262144
+tl_status tl_batch_run_noalloc(const tl_domain* doms, int32_t ndom, const tl_tune* tune,
+                               void* stream);
 
 /* ---- The paper's benchmark expressions (Sec. 5.1) ------------------------- */
 

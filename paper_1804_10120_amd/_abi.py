@@ -21,7 +21,9 @@ TL_BW_READ_BLOCKS = 2048
 EXPRS = ("assign1", "assign2", "assign3", "add1", "add2", "add3", "mult1", "mult2", "mult3",
          "contract1", "contract2", "contract3", "kij")
 TWIN_SHAPES = ((1, 1), (6, 6), (24, 18), (30, 9), (16, 6), (43, 6), (40, 43))
-ABI_VERSION = 3
+ABI_VERSION = 4
+TL_NOALLOC_MAX_DOMAINS = 1024
+TL_NOALLOC_MAX_TILES = 262144
 
 
 class CField(ctypes.Structure):
@@ -78,6 +80,7 @@ SIGNATURES = {
     "tl_batch_plan_create": [ctypes.POINTER(Domain), ctypes.c_int32, _T, ctypes.POINTER(ctypes.c_void_p)],
     "tl_batch_plan_bwd_create": [ctypes.POINTER(DomainBwd), ctypes.c_int32, _T,
                                  ctypes.POINTER(ctypes.c_void_p)],
+    "tl_batch_run_noalloc": [ctypes.POINTER(Domain), ctypes.c_int32, _T, _S],
     "tl_batch_plan_launch": [ctypes.c_void_p, _S],
     "tl_batch_plan_launch_direct": [ctypes.c_void_p, _S],
     "tl_batch_plan_info": [ctypes.c_void_p, ctypes.POINTER(_I64), ctypes.POINTER(_I64),

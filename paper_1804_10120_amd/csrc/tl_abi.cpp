@@ -700,8 +700,9 @@ struct PlanTables {
 };
 
 // Checks the outputs of all domains against every field of every domain and
-// builds the tables.
-tl_status plan_tables(tl::KernelId kid, PlanInput& in, const tl_tune* tune, PlanTables* t) {
+// builds the tables (the tile -> domain map only if tile_map).
+tl_status plan_tables(tl::KernelId kid, PlanInput& in, const tl_tune* tune, PlanTables* t,
+                      bool tile_map = true) {
   {
     const char* a = nullptr;
     const char* b = nullptr;
@@ -721,7 +722,8 @@ tl_status plan_tables(tl::KernelId kid, PlanInput& in, const tl_tune* tune, Plan
     t->doms[d].n = in.n[d];
     if (in.n[d] > 0) t->doms[d].args = in.args[d];
     t->start[d + 1] = t->start[d] + (in.n[d] + per - 1) / per;
-    t->tile_dom.insert(t->tile_dom.end(), static_cast<size_t>(t->start[d + 1] - t->start[d]), d);
+    if (tile_map)
+      t->tile_dom.insert(t->tile_dom.end(), static_cast<size_t>(t->start[d + 1] - t->start[d]), d);
   }
   t->points = in.points;
   t->ntiles = t->start[ndom];
@@ -826,6 +828,29 @@ tl_status tl_batch_plan_create(const tl_domain* doms, int32_t ndom, const tl_tun
   const tl_status s1 = chain_domains(doms, ndom, &in);
   if (s1 != TL_OK) return s1;
   return build_plan(tl::KernelId::ChainBatched, in, tune, out);
+}
+
+tl_status tl_batch_run_noalloc(const tl_domain* doms, int32_t ndom, const tl_tune* tune,
+                               void* stream) {
+  if (doms == nullptr) return fail(TL_ERR_NULL, "doms is NULL");
+  if (ndom < 1 || ndom > TL_NOALLOC_MAX_DOMAINS)
+    return fail(TL_ERR_SIZE, "ndom=%d not in [1, %d] (TL_NOALLOC_MAX_DOMAINS)", ndom,
+                TL_NOALLOC_MAX_DOMAINS);
+  PlanInput in;
+  const tl_status s1 = chain_domains(doms, ndom, &in);
+  if (s1 != TL_OK) return s1;
+  PlanTables t;
+  const tl_status s2 = plan_tables(tl::KernelId::ChainBatched, in, tune, &t, false);
+  if (s2 != TL_OK) return s2;
+  if (t.ntiles > TL_NOALLOC_MAX_TILES)
+    return fail(TL_ERR_SIZE,
+                "%lld tiles of %d points exceed TL_NOALLOC_MAX_TILES=%d (a larger block or ppt "
+                "takes fewer tiles; a batch plan has no such limit)",
+                (long long)t.ntiles, t.r.block * t.r.ppt, TL_NOALLOC_MAX_TILES);
+  hipError_t e = tl::launch_batched_noalloc(t.r, t.doms.data(), t.start.data(), ndom, t.ntiles,
+                                            t.grid, t.chunk, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "no-allocation batched launch");
+  return TL_OK;
 }
 
 tl_status tl_batch_plan_bwd_create(const tl_domain_bwd* doms, int32_t ndom, const tl_tune* tune,

@@ -80,6 +80,12 @@ tl_status run_generated(const char* name, int64_t n, const tl_cfield* in, int32_
 hipError_t launch_batched(KernelId k, const Resolved& r, const BatchDomain* doms, const int64_t* start,
                           const int32_t* tile_dom, int64_t ntiles, int64_t grid, int64_t chunk,
                           hipStream_t s);
+// The forward batched kernel with its tables written into the library's
+// fixed per-device array (tl_noalloc.hip); doms and start are host arrays of
+// the plan tables (ndom descriptors, ndom + 1 tile starts).
+hipError_t launch_batched_noalloc(const Resolved& r, const BatchDomain* doms, const int64_t* start,
+                                  int32_t ndom, int64_t ntiles, int64_t grid, int64_t chunk,
+                                  hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, int64_t n, int64_t grid, hipStream_t s);
 hipError_t launch_read(const double* src, double* partial, int64_t n, int64_t grid, bool vec,
                        hipStream_t s);

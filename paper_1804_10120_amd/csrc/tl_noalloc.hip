@@ -1,0 +1,143 @@
+// The batched forward chain with its tables in a fixed device array, for
+// callers that cannot allocate device memory (tl_batch_run_noalloc).
+//
+// A batch plan keeps three tables in device memory it allocates: the domain
+// descriptors, the first tile of every domain, and the tile -> domain map.
+// Here they live in `scratch`, one file-scope array per device, and are
+// written by small kernels that receive the descriptors as kernel arguments
+// (so nothing is copied from host memory and nothing is allocated); the
+// batched kernel of the plans then reads them from there.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+
+#include "tl_internal.hpp"
+
+namespace tl {
+namespace {
+
+// Layout of the array: [domains][tile starts][tile -> domain map].
+constexpr int64_t kDomBytes = static_cast<int64_t>(sizeof(BatchDomain)) * TL_NOALLOC_MAX_DOMAINS;
+constexpr int64_t kStartOff = kDomBytes;
+constexpr int64_t kStartBytes = (8 * (TL_NOALLOC_MAX_DOMAINS + 1) + 255) / 256 * 256;
+constexpr int64_t kTileOff = kStartOff + kStartBytes;
+constexpr int64_t kScratchBytes = kTileOff + 4 * static_cast<int64_t>(TL_NOALLOC_MAX_TILES);
+static_assert(kDomBytes % 256 == 0, "tile starts must stay 256-byte aligned");
+
+// Each device holds its own copy until the process ends.  Host code never
+// uses this name as an address: it asks the runtime for the device's copy
+// (scratch_base) and passes that pointer on.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_mu;
+void* g_base[kMaxDevices] = {};
+
+// Address of the current device's copy of `scratch`, looked up once per
+// device with that device current.
+hipError_t scratch_base(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (g_base[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    g_base[dev] = p;
+  }
+  *out = g_base[dev];
+  return hipSuccess;
+}
+
+// Descriptors of up to kFillCap consecutive domains of the forward chain (six
+// inputs, one output), passed by value as a kernel argument (under 3 KB).
+constexpr int kFillCap = 22;
+struct FillChunk {
+  int32_t d0, nd;               // domains d0 .. d0 + nd - 1
+  int64_t start[kFillCap + 1];  // their first tiles, then the tile after the last
+  int64_t n[kFillCap];
+  const double* in[kFillCap][6];
+  int64_t ldin[kFillCap][6];
+  double* out[kFillCap];
+  int64_t ldout[kFillCap];
+};
+static_assert(sizeof(FillChunk) <= 3072, "kernel argument too large");
+
+// Writes the chunk's domain descriptors and tile starts (lane 0 of block 0),
+// and the domain of every tile of the chunk (one lane per tile: the last
+// domain whose first tile is not after it; domains without tiles are passed
+// over because the next one starts at the same tile).  Every index is
+// uniform except the tile's, so the chunk is read with scalar loads.
+__global__ __launch_bounds__(256) void k_fill_tables(FillChunk c, BatchDomain* __restrict__ doms,
+                                                     int64_t* __restrict__ start,
+                                                     int32_t* __restrict__ tile_dom) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int i = 0; i < c.nd; ++i) {
+      BatchDomain d = {};
+      for (int f = 0; f < 6; ++f) {
+        d.args.in[f] = c.in[i][f];
+        d.args.ldin[f] = c.ldin[i][f];
+      }
+      d.args.out[0] = c.out[i];
+      d.args.ldout[0] = c.ldout[i];
+      d.n = c.n[i];
+      doms[c.d0 + i] = d;
+      start[c.d0 + i] = c.start[i];
+    }
+    start[c.d0 + c.nd] = c.start[c.nd];
+  }
+  const int64_t t = c.start[0] + static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (t < c.start[c.nd]) {
+    int32_t i = 0;
+    for (int j = 1; j < c.nd; ++j) i += c.start[j] <= t ? 1 : 0;
+    tile_dom[t] = c.d0 + i;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_batched_noalloc(const Resolved& r, const BatchDomain* doms,
+                                  const int64_t* start, int32_t ndom, int64_t ntiles,
+                                  int64_t grid, int64_t chunk, hipStream_t s) {
+  if (ndom < 1 || ndom > TL_NOALLOC_MAX_DOMAINS || ntiles < 0 || ntiles > TL_NOALLOC_MAX_TILES ||
+      start[ndom] != ntiles)
+    return hipErrorInvalidValue;
+  void* base = nullptr;
+  hipError_t e = scratch_base(&base);
+  if (e != hipSuccess) return e;
+  unsigned char* b = static_cast<unsigned char*>(base);
+  BatchDomain* d_doms = reinterpret_cast<BatchDomain*>(b);
+  int64_t* d_start = reinterpret_cast<int64_t*>(b + kStartOff);
+  int32_t* d_tile_dom = reinterpret_cast<int32_t*>(b + kTileOff);
+  for (int32_t d0 = 0; d0 < ndom; d0 += kFillCap) {
+    FillChunk c = {};
+    c.d0 = d0;
+    c.nd = ndom - d0 < kFillCap ? ndom - d0 : kFillCap;
+    for (int i = 0; i < c.nd; ++i) {
+      const BatchDomain& x = doms[d0 + i];
+      c.start[i] = start[d0 + i];
+      c.n[i] = x.n;
+      for (int f = 0; f < 6; ++f) {
+        c.in[i][f] = x.args.in[f];
+        c.ldin[i][f] = x.args.ldin[f];
+      }
+      c.out[i] = x.args.out[0];
+      c.ldout[i] = x.args.ldout[0];
+    }
+    c.start[c.nd] = start[d0 + c.nd];
+    const int64_t tiles = c.start[c.nd] - c.start[0];
+    const int64_t blocks = tiles > 0 ? (tiles + 255) / 256 : 1;
+    hipLaunchKernelGGL(k_fill_tables, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, c,
+                       d_doms, d_start, d_tile_dom);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (ntiles == 0) return hipSuccess;
+  return launch_batched(KernelId::ChainBatched, r, d_doms, d_start, d_tile_dom, ntiles, grid,
+                        chunk, s);
+}
+
+}  // namespace tl

@@ -455,6 +455,36 @@ def _fwd_domain(c, d):
                    _cf(d["K"], 6), _cf(d["alpha"], 1), _f(out, 6)), dict(d, dtg=out))
 
 
+def tl_batch_run_noalloc(domains, *, stream=None, tune=None):
+    """tl_batch_run_noalloc: d_t g over many subgrids with the batched kernel,
+    its tables in the library's fixed device array (no device allocation).
+
+    ``domains``: dicts with the tensors g, dg, beta, dbeta, K, alpha and dtg
+    (the output, which must be given: nothing is allocated here).  Calls that
+    overlap on one device race (they share the array); order them on one
+    stream.
+    """
+    arr = (Domain * len(domains))()
+    device = None
+    for i, d in enumerate(domains):
+        if d.get("dtg") is None:
+            raise ValueError(f"domain {i}: dtg (the output) must be given")
+        c = _Call()
+        for name in ("g", "dg", "beta", "dbeta", "K", "alpha"):
+            c.add(d[name], name)
+        if device is None:
+            device = c.device
+        elif c.device != device:
+            raise ValueError("all subgrids must be on one device")
+        arr[i], _ = _fwd_domain(c, d)
+    if device is None:
+        raise ValueError("tl_batch_run_noalloc needs at least one subgrid")
+    with torch.cuda.device(device):
+        check(lib().tl_batch_run_noalloc(arr, len(domains), make_tune(tune),
+                                         _stream(device, stream)))
+    return [d["dtg"] for d in domains]
+
+
 class BatchPlan:
     """tl_batch_plan_*: d_t g (kind="fwd") or its adjoint (kind="bwd") over
     many subgrids in one graph-captured launch.
@@ -560,4 +590,5 @@ class BatchPlan:
 __all__ = ["record", "Prepared", "tl_sym_inverse", "tl_christoffel", "tl_cov_deriv", "tl_dtg",
            "tl_dtg_chain", "tl_dtg_chain_bwd", "tl_dtg_chain_fwd_bwd", "tl_bw_copy", "tl_bw_read",
            "tl_bw_write", "tl_bw_twin", "tl_expr", "tl_expr_shape", "tl_kernel_info", "BatchPlan",
+           "tl_batch_run_noalloc",
            "TLError", "empty_field", "to_field", "padded_ld", "LD_ALIGN"]

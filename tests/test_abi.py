@@ -2,7 +2,7 @@
 include/tl.h declares, and rejects bad arguments before touching the device.
 
 Fake (never dereferenced) host addresses are used: every call here returns an
-argument error before any HIP runtime call or launch.
+argument error before anything is launched.
 """
 import ctypes
 import os
@@ -199,6 +199,27 @@ def test_batch_plan_validation(L):
     doms[1].n = -5
     assert L.tl_batch_plan_create(doms, 2, None, ctypes.byref(plan)) == _abi.TL_ERR_SIZE
     assert L.tl_batch_plan_destroy(None) == _abi.TL_OK
+
+
+def test_noalloc_batch_limits(L):
+    """tl_batch_run_noalloc rejects a batch beyond its fixed tables (too many
+    subgrids, too many tiles) and bad domains before launching anything."""
+    assert L.tl_batch_run_noalloc(None, 1, None, None) == _abi.TL_ERR_NULL
+    doms = (Domain * (_abi.TL_NOALLOC_MAX_DOMAINS + 1))()
+    assert L.tl_batch_run_noalloc(doms, 0, None, None) == _abi.TL_ERR_SIZE
+    assert L.tl_batch_run_noalloc(doms, _abi.TL_NOALLOC_MAX_DOMAINS + 1, None, None) == \
+        _abi.TL_ERR_SIZE
+    assert b"TL_NOALLOC_MAX_DOMAINS" in L.tl_last_error()
+    # one subgrid of more tiles than the table holds (blocks of 64 points)
+    n = 64 * _abi.TL_NOALLOC_MAX_TILES + 1
+    gib = 1 << 30
+    one = (Domain * 1)()
+    one[0] = Domain(n, *[cf(BASE + i * 8 * gib, n) for i in range(6)], f(BASE + 6 * 8 * gib, n))
+    tune = Tune(64, 1, _abi.TL_TUNE_NT, 0, 0)
+    assert L.tl_batch_run_noalloc(one, 1, ctypes.byref(tune), None) == _abi.TL_ERR_SIZE
+    assert b"TL_NOALLOC_MAX_TILES" in L.tl_last_error()
+    one[0].dtg = Field(one[0].K.ptr, n)      # output over an input
+    assert L.tl_batch_run_noalloc(one, 1, ctypes.byref(tune), None) == _abi.TL_ERR_ALIAS
 
 
 def test_kernel_info_unknown(L):

@@ -1,0 +1,104 @@
+"""tl_batch_run_noalloc (the batched forward chain with its tables in the
+library's fixed per-device array) against the batch plan it varies: the same
+launch on the same subgrids must give bitwise the same d_t g, and both must
+match the oracle.  Two calls in a row, the second with fewer and smaller
+subgrids, so the second call runs over tables the first one left behind."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_close, dev, need_gpu
+from paper_1804_10120_amd import BatchPlan, TLError, empty_field, tl_batch_run_noalloc
+from paper_1804_10120_amd import _abi
+from paper_1804_10120_amd.synth import make_fields
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("g", "dg", "beta", "dbeta", "K", "alpha")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _domains(sizes, seed):
+    hosts, devs = [], []
+    for d, n in enumerate(sizes):
+        f = make_fields(int(n), seed=seed * 1000 + d)
+        hosts.append(f)
+        devs.append({k: dev(f[k]) for k in KEYS})
+    return hosts, devs
+
+
+def _run_both(hosts, devs, tune):
+    """d_t g of every subgrid from a batch plan (direct launch) and from the
+    no-allocation entry point, each into its own output fields."""
+    plan = BatchPlan(devs, tune=tune)
+    plan.run_direct()
+    torch.cuda.synchronize()
+    ref = [o.clone() for o in plan.outputs]
+    plan.close()
+    outs = [dict(d, dtg=empty_field(6, h["g"].shape[1], device="cuda")) for h, d in zip(hosts, devs)]
+    for o in outs:
+        o["dtg"].fill_(np.nan)
+    got = tl_batch_run_noalloc(outs, tune=tune)
+    torch.cuda.synchronize()
+    return ref, got
+
+
+def _check(hosts, ref, got, what):
+    assert len(ref) == len(got)
+    for i, (f, a, b) in enumerate(zip(hosts, ref, got)):
+        assert torch.equal(a, b), f"{what}: subgrid {i} (n={a.shape[1]}) differs from the plan"
+        assert_close(b, oracle.dtg_chain(*[f[k] for k in KEYS]),
+                     what=f"{what}: subgrid {i} vs oracle")
+
+
+@pytest.mark.parametrize("tune", [None, dict(block=64, ppt=2, nt=True, xcd=True, grid_mult=1),
+                                  dict(block=256, ppt=1, nt=True, ptr64=True)],
+                         ids=["default", "b64ppt2xcd_persistent", "b256ptr64"])
+def test_noalloc_matches_plan_two_calls(tune):
+    rng = np.random.default_rng(11)
+    # first call: 70 subgrids (more than three table-writing launches of
+    # descriptors), empty and one-point ones among them, about 1.2 M points
+    big = [int(x) ** 3 for x in rng.integers(8, 40, size=60)]
+    sizes1 = big + [0, 1, 0, 17, 63, 64, 65, 1000, 4097, 3]
+    hosts1, devs1 = _domains(sizes1, seed=21)
+    ref1, got1 = _run_both(hosts1, devs1, tune)
+    _check(hosts1, ref1, got1, "first call")
+    # second call: fewer, smaller subgrids, over the tables of the first
+    sizes2 = [5, 0, 700, 8 ** 3, 2]
+    hosts2, devs2 = _domains(sizes2, seed=22)
+    ref2, got2 = _run_both(hosts2, devs2, tune)
+    _check(hosts2, ref2, got2, "second call")
+
+
+def test_noalloc_on_a_side_stream_and_repeated():
+    """On a stream of its own, called again on the same fields: the results do
+    not change."""
+    sizes = [9 ** 3, 0, 30 ** 3, 1]
+    hosts, devs = _domains(sizes, seed=23)
+    outs = [dict(d, dtg=empty_field(6, h["g"].shape[1], device="cuda")) for h, d in zip(hosts, devs)]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        first = [o.clone() for o in tl_batch_run_noalloc(outs, stream=s)]
+        for o in outs:
+            o["dtg"].zero_()
+        again = tl_batch_run_noalloc(outs, stream=s)
+    s.synchronize()
+    for f, a, b in zip(hosts, first, again):
+        assert torch.equal(a, b)
+        assert_close(b, oracle.dtg_chain(*[f[k] for k in KEYS]), what="side stream")
+
+
+def test_noalloc_rejects_beyond_its_limits():
+    sizes = [10] * 3
+    hosts, devs = _domains(sizes, seed=24)
+    outs = [dict(d, dtg=empty_field(6, 10, device="cuda")) for d in devs]
+    with pytest.raises(TLError) as e:
+        tl_batch_run_noalloc(outs * 342)      # 1026 subgrids
+    assert e.value.status == _abi.TL_ERR_SIZE
+    with pytest.raises(ValueError):
+        tl_batch_run_noalloc([dict(devs[0])])  # no output given
