@@ -154,7 +154,7 @@ __device__ inline void point_stream(const KArgs& a, int64_t p) {
 
 // Points p .. p+PPT-1 of one tile, all in range.
 template <class Op, int PPT, bool NT>
-__device__ inline void points_full(const KArgs& a, int64_t p) {
+__device__ inline void points_full(const KArgs& a, int64_t p, int64_t hs = 0) {
   constexpr auto io = in_offsets<Op>();
   constexpr auto oo = out_offsets<Op>();
   if constexpr (PPT == 1) {
@@ -172,7 +172,7 @@ __device__ inline void points_full(const KArgs& a, int64_t p) {
     }
   } else {
     static_assert(PPT == 2 || PPT == 4, "PPT is 1, 2 or 4");
-    constexpr int H = PPT / 2;  // 16-byte accesses per component
+    constexpr int H = PPT / 2;  // point pairs, hs points apart: 16-byte accesses per component
     dbl2 x2[H][Op::NIN];
 #pragma unroll
     for (int f = 0; f < Op::NF_IN; ++f)
@@ -180,7 +180,7 @@ __device__ inline void points_full(const KArgs& a, int64_t p) {
       for (int c = 0; c < Op::fin[f]; ++c)
 #pragma unroll
         for (int h = 0; h < H; ++h)
-          x2[h][io.v[f] + c] = load2<NT>(a.in[f] + c * a.ldin[f] + p + 2 * h);
+          x2[h][io.v[f] + c] = load2<NT>(a.in[f] + c * a.ldin[f] + p + h * hs);
     double x[Op::NIN], y[PPT][Op::NOUT];
 #pragma unroll
     for (int h = 0; h < H; ++h) {
@@ -201,7 +201,7 @@ __device__ inline void points_full(const KArgs& a, int64_t p) {
           dbl2 v;
           v.x = y[2 * h][oo.v[f] + c];
           v.y = y[2 * h + 1][oo.v[f] + c];
-          store2<NT>(a.out[f] + c * a.ldout[f] + p + 2 * h, v);
+          store2<NT>(a.out[f] + c * a.ldout[f] + p + h * hs, v);
         }
     }
   }
@@ -260,7 +260,8 @@ __device__ inline void point_stream_buf(const Bufs<Op>& b, uint32_t p8) {
 }
 
 template <class Op, int PPT, bool NT>
-__device__ inline void points_full_buf(const KArgs& a, const Bufs<Op>& b, uint32_t p8) {
+__device__ inline void points_full_buf(const KArgs& a, const Bufs<Op>& b, uint32_t p8,
+                                       uint32_t hs8 = 0) {
   constexpr auto io = in_offsets<Op>();
   constexpr auto oo = out_offsets<Op>();
   if constexpr (PPT == 1) {
@@ -279,7 +280,7 @@ __device__ inline void points_full_buf(const KArgs& a, const Bufs<Op>& b, uint32
     }
   } else {
     static_assert(PPT == 2 || PPT == 4, "PPT is 1, 2 or 4");
-    constexpr int H = PPT / 2;  // 16-byte accesses per component
+    constexpr int H = PPT / 2;  // point pairs, hs points apart: 16-byte accesses per component
     dbl2 x2[H][Op::NIN];
 #pragma unroll
     for (int f = 0; f < Op::NF_IN; ++f)
@@ -287,7 +288,7 @@ __device__ inline void points_full_buf(const KArgs& a, const Bufs<Op>& b, uint32
       for (int c = 0; c < Op::fin[f]; ++c)
 #pragma unroll
         for (int h = 0; h < H; ++h)
-          x2[h][io.v[f] + c] = bload2<NT>(b.in[f], p8 + 16 * h, c * b.ldin8[f]);
+          x2[h][io.v[f] + c] = bload2<NT>(b.in[f], p8 + h * hs8, c * b.ldin8[f]);
     double x[Op::NIN], y[PPT][Op::NOUT];
 #pragma unroll
     for (int h = 0; h < H; ++h) {
@@ -308,19 +309,34 @@ __device__ inline void points_full_buf(const KArgs& a, const Bufs<Op>& b, uint32
           dbl2 v;
           v.x = y[2 * h][oo.v[f] + c];
           v.y = y[2 * h + 1][oo.v[f] + c];
-          bstore2<NT>(b.out[f], p8 + 16 * h, c * b.ldout8[f], v);
+          bstore2<NT>(b.out[f], p8 + h * hs8, c * b.ldout8[f], v);
         }
     }
   }
 }
 
+// A tile is BLOCK*PPT consecutive points.  With PPT of 1 or 2 a lane owns PPT
+// consecutive points of it; with PPT = 4 a lane owns two pairs of points, one
+// in each half of the tile (2*BLOCK points apart), so every 16-byte access of a
+// wave still covers a contiguous kilobyte.
 template <class Op, int BLOCK, int PPT, bool NT>
 __device__ inline void tile_buf(const KArgs& a, const Bufs<Op>& b, int64_t n, int64_t t) {
-  const int64_t p = (t * BLOCK + threadIdx.x) * PPT;
   if constexpr (is_stream<Op>::value) {
     static_assert(PPT == 1, "streaming bodies take one point per lane");
+    const int64_t p = t * BLOCK + threadIdx.x;
     if (p < n) point_stream_buf<Op, NT>(b, static_cast<uint32_t>(p * 8));
+  } else if constexpr (PPT == 4) {
+    const int64_t p = t * BLOCK * 4 + 2 * threadIdx.x;
+    const int64_t q = p + 2 * BLOCK;
+    if (q + 2 <= n) {
+      points_full_buf<Op, 4, NT>(a, b, static_cast<uint32_t>(p * 8), 16u * BLOCK);
+    } else {
+      if (p + 2 <= n) points_full_buf<Op, 2, NT>(a, b, static_cast<uint32_t>(p * 8));
+      else if (p < n) points_tail<Op, 2>(a, p, n);
+      if (q < n) points_tail<Op, 2>(a, q, n);
+    }
   } else {
+    const int64_t p = (t * BLOCK + threadIdx.x) * PPT;
     if (p + PPT <= n) points_full_buf<Op, PPT, NT>(a, b, static_cast<uint32_t>(p * 8));
     else if (p < n) points_tail<Op, PPT>(a, p, n);
   }
@@ -328,11 +344,22 @@ __device__ inline void tile_buf(const KArgs& a, const Bufs<Op>& b, int64_t n, in
 
 template <class Op, int BLOCK, int PPT, bool NT>
 __device__ inline void tile(const KArgs& a, int64_t n, int64_t t) {
-  const int64_t p = (t * BLOCK + threadIdx.x) * PPT;
   if constexpr (is_stream<Op>::value) {
     static_assert(PPT == 1, "streaming bodies take one point per lane");
+    const int64_t p = t * BLOCK + threadIdx.x;
     if (p < n) point_stream<Op, NT>(a, p);
+  } else if constexpr (PPT == 4) {
+    const int64_t p = t * BLOCK * 4 + 2 * threadIdx.x;
+    const int64_t q = p + 2 * BLOCK;
+    if (q + 2 <= n) {
+      points_full<Op, 4, NT>(a, p, 2 * BLOCK);
+    } else {
+      if (p + 2 <= n) points_full<Op, 2, NT>(a, p);
+      else if (p < n) points_tail<Op, 2>(a, p, n);
+      if (q < n) points_tail<Op, 2>(a, q, n);
+    }
   } else {
+    const int64_t p = (t * BLOCK + threadIdx.x) * PPT;
     if (p + PPT <= n) points_full<Op, PPT, NT>(a, p);
     else if (p < n) points_tail<Op, PPT>(a, p, n);
   }

@@ -103,12 +103,16 @@ LABEL = re.compile(r"^c(\d+) (\w+) n=(\d+)(?: (.*))?$")
 HBM_PEAK_GBS = 8000.0
 
 
+SPLIT = re.compile(r"\b(\d+) launches\b")
+
+
 def labelled_dispatches(folder):
     """Per dispatch label ``c<config> <kernel> n=<points> [variant]`` (the names
     bench.py --label-kernels gives its calls, which the profiler's kernel
     renaming puts in place of the kernel name): calls, average, min and max
     duration (ns), and the algorithmic GB/s and fraction of the HBM peak of
-    the average."""
+    the average.  A variant "<K> launches" marks n points split over K
+    launches, whose rate is taken over K average durations."""
     rows = _csv(folder, "kernel_trace.csv")
     agg = defaultdict(list)
     for r in rows:
@@ -120,7 +124,9 @@ def labelled_dispatches(folder):
         m = LABEL.match(name)
         cfg, kernel, n, variant = int(m.group(1)), m.group(2), int(m.group(3)), m.group(4) or ""
         avg = sum(v) / len(v)
-        gbs = LABEL_BYTES[kernel] * n / avg if kernel in LABEL_BYTES else None
+        k = SPLIT.search(variant)
+        per = avg * (int(k.group(1)) if k else 1)
+        gbs = LABEL_BYTES[kernel] * n / per if kernel in LABEL_BYTES else None
         out.append({"label": name, "config": cfg, "kernel": kernel, "points": n,
                     "variant": variant, "calls": len(v), "avg_ns": avg, "min_ns": min(v),
                     "max_ns": max(v), "GB_s": gbs,

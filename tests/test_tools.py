@@ -181,11 +181,16 @@ def test_profsum_labelled_dispatches(tmp_path):
            [["c2 dtg_chain n=262144", n, 0, 20000, 62, 0],
             ["c2 dtg_chain n=262144", n, 30000, 40000, 62, 0],
             ["c5 dtg_chain_bwd n=262144 ppt2_b512", n // 4, 0, 30000, 166, 0],
+            ["c4 dtg_chain n=262144 4 launches", n // 4, 0, 5000, 62, 0],
+            ["c4 dtg_chain n=262144 4 launches", n // 4, 9000, 16000, 62, 0],
             ["void tl::k_copy(double const*, double*, long)", 1024, 0, 5, 12, 0]])
     rows = profsum.labelled_dispatches(str(trace))
     assert [r["label"] for r in rows] == ["c2 dtg_chain n=262144",
+                                          "c4 dtg_chain n=262144 4 launches",
                                           "c5 dtg_chain_bwd n=262144 ppt2_b512"]
-    a, b = rows
+    a, s, b = rows
+    # n points over 4 launches of 6 us on average: 24 us per pass
+    assert s["calls"] == 2 and abs(s["GB_s"] - 392 * n / 24000) < 1e-9
     assert a["calls"] == 2 and a["avg_ns"] == 15000 and a["min_ns"] == 10000
     assert abs(a["GB_s"] - 392 * n / 15000) < 1e-9 and b["variant"] == "ppt2_b512"
     assert abs(b["frac"] - 664 * n / 30000 / 8000) < 1e-12
