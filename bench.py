@@ -490,9 +490,9 @@ def main():
     if args.label_kernels:
         LABELS.enable()
     import torch
-    from paper_1804_10120_amd import (BatchPlan, tl_christoffel, tl_cov_deriv, tl_dtg,
-                                      tl_dtg_chain, tl_dtg_chain_bwd, tl_dtg_chain_fwd_bwd,
-                                      tl_sym_inverse, empty_field, to_field)
+    from paper_1804_10120_amd import (BatchPlan, tl_batch_run_noalloc, tl_christoffel,
+                                      tl_cov_deriv, tl_dtg, tl_dtg_chain, tl_dtg_chain_bwd,
+                                      tl_dtg_chain_fwd_bwd, tl_sym_inverse, empty_field, to_field)
     from paper_1804_10120_amd.ops import record
     from paper_1804_10120_amd.synth import config_seed, domain_edges, make_fields
 
@@ -723,9 +723,9 @@ def main():
         rows["tiny_grid_floor"] = tiny
         del e32, fl
 
-        log("[bench] 64^3 with 4 rotating buffer sets")
+        log("[bench] 64^3 with 6 rotating buffer sets")
         n64 = 64 ** 3
-        s64 = device_sets(n64, 4, device, config_seed(2))
+        s64 = device_sets(n64, 6, device, config_seed(2))
         lists = []
         for _, e in s64:
             with record() as c:
@@ -761,8 +761,8 @@ def main():
                                    "queued_fwd_GB_s": rate(BYTES["dtg_chain"] * n64, bb_f64),
                                    "queued_bwd_us": bb_b64 * 1e3,
                                    "queued_bwd_GB_s": rate(BYTES["dtg_chain_bwd"] * n64, bb_b64),
-                                   "graph_us_per_pair": ms_g64 * 1e3 / 8,
-                                   "graph_points_per_s": n64 / (ms_g64 * 1e-3 / 8)}
+                                   "graph_us_per_pair": ms_g64 * 1e3 / (2 * len(s64)),
+                                   "graph_points_per_s": n64 / (ms_g64 * 1e-3 / (2 * len(s64)))}
         rows["shapes_64cubed"] = mid_size_shapes(s64, n64)
         del s64, lists, outs64, g64
 
@@ -786,7 +786,17 @@ def main():
         plan = BatchPlan(doms)
         _, (ms_default,) = time_calls([[plan.run]], 20, 3,
                                       labels=label(4, "dtg_chain_batched", npts, "default"))
+        _, (ms_direct,) = time_calls([[plan.run_direct]], 20, 3,
+                                     labels=label(4, "dtg_chain_batched", npts, "direct"))
+        # the same launch with its tables in the library's fixed array (no allocation)
+        na_doms = [dict(e, dtg=empty_field(6, e["K"].shape[1], device=device)) for e in doms]
+        with record() as na:
+            tl_batch_run_noalloc(na_doms)
+        _, (ms_na,) = time_calls([na], 20, 3,
+                                 labels=label(4, "dtg_chain_batched", npts, "no allocation"))
+        na_same = all(torch.equal(a["dtg"], b) for a, b in zip(na_doms, plan.outputs))
         plan.close()
+        del na, na_doms
         from paper_1804_10120_amd import autotune
         tuned = autotune.tune_plan(doms, save=False)
         plan = BatchPlan(doms, tune=tuned["tune"])
@@ -814,6 +824,9 @@ def main():
             "separate_launches_graph_us": ms_g256 * 1e3,
             "separate_launches_graph_points_per_s": npts / (ms_g256 * 1e-3),
             "separate_launches_match_batched": same,
+            "direct_launch_us": ms_direct * 1e3,
+            "no_allocation_us": ms_na * 1e3,
+            "no_allocation_matches_plan": na_same,
             "ld_unpadded_us": ms_flat * 1e3,
             "ld_unpadded_GB_s": rate(BYTES["dtg_chain_batched"] * npts, ms_flat)}
         plan.close()

@@ -233,7 +233,9 @@ tl_status tl_batch_plan_destroy(tl_batch_plan* plan);
  * process ends (about 1.4 MB).  Kernels launched on `stream` write the tables
  * from their kernel arguments, then the batched kernel runs; the call makes no
  * device allocation, no host-to-device copy and no memset, and returns once
- * the launches are queued (asynchronous).  The caller passes every input and
+ * the launches are queued (asynchronous).  Being kernel launches only, the
+ * call may be captured into a HIP graph: each replay writes the tables again
+ * before the batched kernel reads them.  The caller passes every input and
  * output, as for a plan; the domains' buffers must stay valid until the work
  * on `stream` has finished.
  * Every call on a device shares that device's array and leaves its tables in

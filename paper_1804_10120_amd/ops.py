@@ -480,8 +480,14 @@ def tl_batch_run_noalloc(domains, *, stream=None, tune=None):
     if device is None:
         raise ValueError("tl_batch_run_noalloc needs at least one subgrid")
     with torch.cuda.device(device):
-        check(lib().tl_batch_run_noalloc(arr, len(domains), make_tune(tune),
-                                         _stream(device, stream)))
+        full = (arr, len(domains), make_tune(tune), _stream(device, stream))
+        if _recording() is not None:
+            _recording().append(Prepared(lib().tl_batch_run_noalloc, full,
+                                         [arr] + [d[k] for d in domains for k in
+                                                  ("g", "dg", "beta", "dbeta", "K", "alpha",
+                                                   "dtg")], device))
+        else:
+            check(lib().tl_batch_run_noalloc(*full))
     return [d["dtg"] for d in domains]
 
 

@@ -102,3 +102,31 @@ def test_noalloc_rejects_beyond_its_limits():
     assert e.value.status == _abi.TL_ERR_SIZE
     with pytest.raises(ValueError):
         tl_batch_run_noalloc([dict(devs[0])])  # no output given
+
+
+def test_noalloc_captured_in_a_graph():
+    """Captured into a HIP graph (it launches kernels only: no allocation, copy
+    or memset) and replayed several times, with eager work and
+    synchronisation between the replays: every replay equals the eager call."""
+    sizes = [20 ** 3, 7, 0, 33 ** 3]
+    hosts, devs = _domains(sizes, seed=25)
+    outs = [dict(d, dtg=empty_field(6, h["g"].shape[1], device="cuda")) for h, d in zip(hosts, devs)]
+    eager = [o.clone() for o in tl_batch_run_noalloc(outs)]
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        tl_batch_run_noalloc(outs)
+    for rep in range(3):
+        for o in outs:
+            o["dtg"].fill_(np.nan)
+        # other eager work on the same device between the replays
+        other = [dict(d, dtg=empty_field(6, h["g"].shape[1], device="cuda"))
+                 for h, d in zip(hosts[:2], devs[:2])]
+        tl_batch_run_noalloc(other)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for i, (a, o) in enumerate(zip(eager, outs)):
+            assert torch.equal(a, o["dtg"]), f"replay {rep}: subgrid {i} differs from the eager call"
+    for f, o in zip(hosts, outs):
+        assert_close(o["dtg"], oracle.dtg_chain(*[f[k] for k in KEYS]), what="graph replay")
