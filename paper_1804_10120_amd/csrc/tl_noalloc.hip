@@ -9,6 +9,7 @@
 // batched kernel of the plans then reads them from there.
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <mutex>
 
 #include "tl_internal.hpp"
@@ -52,44 +53,51 @@ hipError_t scratch_base(void** out) {
   return hipSuccess;
 }
 
-// Descriptors of up to kFillCap consecutive domains of the forward chain (six
-// inputs, one output), passed by value as a kernel argument (under 3 KB).
+// The 64-bit words of a BatchDomain that a forward-chain domain sets (its six
+// input fields, one output field and n); every other word is zero.
+constexpr int kDomWords = static_cast<int>(sizeof(BatchDomain) / 8);
+constexpr int kSetWords = 15;
+constexpr int word_of(int k) {  // word of the BatchDomain that packed word k fills
+  return k < 6 ? k                                  // args.in[0..5]
+       : k < 12 ? kMaxFields + (k - 6)               // args.ldin[0..5]
+       : k == 12 ? 2 * kMaxFields                    // args.out[0]
+       : k == 13 ? 3 * kMaxFields                    // args.ldout[0]
+       : 4 * kMaxFields;                             // n
+}
+static_assert(word_of(14) * 8 == offsetof(BatchDomain, n), "BatchDomain layout");
+static_assert(kDomWords <= 64, "one wave writes a descriptor");
+
+// Packed descriptors of up to kFillCap consecutive domains, passed by value as
+// a kernel argument (under 3 KB).
 constexpr int kFillCap = 22;
 struct FillChunk {
-  int32_t d0, nd;               // domains d0 .. d0 + nd - 1
-  int64_t start[kFillCap + 1];  // their first tiles, then the tile after the last
-  int64_t n[kFillCap];
-  const double* in[kFillCap][6];
-  int64_t ldin[kFillCap][6];
-  double* out[kFillCap];
-  int64_t ldout[kFillCap];
+  int32_t d0, nd;                   // domains d0 .. d0 + nd - 1
+  int64_t start[kFillCap + 1];      // their first tiles, then the tile after the last
+  int64_t w[kFillCap][kSetWords];   // word k of domain i: see word_of(k)
 };
 static_assert(sizeof(FillChunk) <= 3072, "kernel argument too large");
 
-// Writes the chunk's domain descriptors and tile starts (lane 0 of block 0),
-// and the domain of every tile of the chunk (one lane per tile: the last
-// domain whose first tile is not after it; domains without tiles are passed
-// over because the next one starts at the same tile).  Every index is
-// uniform except the tile's, so the chunk is read with scalar loads.
+// Block 0 writes the chunk's descriptors (lane l of the first wave writes word
+// l of each, so a descriptor is one store) and tile starts; every lane of the
+// grid then writes the domain of one tile of the chunk: the last domain whose
+// first tile is not after it (domains without tiles are passed over because
+// the next one starts at the same tile).
 __global__ __launch_bounds__(256) void k_fill_tables(FillChunk c, BatchDomain* __restrict__ doms,
                                                      int64_t* __restrict__ start,
                                                      int32_t* __restrict__ tile_dom) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    for (int i = 0; i < c.nd; ++i) {
-      BatchDomain d = {};
-      for (int f = 0; f < 6; ++f) {
-        d.args.in[f] = c.in[i][f];
-        d.args.ldin[f] = c.ldin[i][f];
-      }
-      d.args.out[0] = c.out[i];
-      d.args.ldout[0] = c.ldout[i];
-      d.n = c.n[i];
-      doms[c.d0 + i] = d;
-      start[c.d0 + i] = c.start[i];
+  const int l = threadIdx.x;
+  if (blockIdx.x == 0) {
+    int k = -1;  // the packed word this lane writes, if any
+#pragma unroll
+    for (int q = 0; q < kSetWords; ++q)
+      if (word_of(q) == l) k = q;
+    if (l < kDomWords) {
+      int64_t* out = reinterpret_cast<int64_t*>(doms + c.d0);
+      for (int i = 0; i < c.nd; ++i) out[i * kDomWords + l] = k >= 0 ? c.w[i][k] : 0;
     }
-    start[c.d0 + c.nd] = c.start[c.nd];
+    if (l <= c.nd) start[c.d0 + l] = c.start[l];
   }
-  const int64_t t = c.start[0] + static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t t = c.start[0] + static_cast<int64_t>(blockIdx.x) * 256 + l;
   if (t < c.start[c.nd]) {
     int32_t i = 0;
     for (int j = 1; j < c.nd; ++j) i += c.start[j] <= t ? 1 : 0;
@@ -119,13 +127,13 @@ hipError_t launch_batched_noalloc(const Resolved& r, const BatchDomain* doms,
     for (int i = 0; i < c.nd; ++i) {
       const BatchDomain& x = doms[d0 + i];
       c.start[i] = start[d0 + i];
-      c.n[i] = x.n;
       for (int f = 0; f < 6; ++f) {
-        c.in[i][f] = x.args.in[f];
-        c.ldin[i][f] = x.args.ldin[f];
+        c.w[i][f] = reinterpret_cast<intptr_t>(x.args.in[f]);
+        c.w[i][6 + f] = x.args.ldin[f];
       }
-      c.out[i] = x.args.out[0];
-      c.ldout[i] = x.args.ldout[0];
+      c.w[i][12] = reinterpret_cast<intptr_t>(x.args.out[0]);
+      c.w[i][13] = x.args.ldout[0];
+      c.w[i][14] = x.n;
     }
     c.start[c.nd] = start[d0 + c.nd];
     const int64_t tiles = c.start[c.nd] - c.start[0];

@@ -207,6 +207,17 @@ def test_kernel_info_headline_kernels():
     assert 80 < b["vgprs"] <= 88 and b["waves_per_simd"] == 5, b
 
 
+@pytest.mark.parametrize("kernel,ppt", [("sym_inverse", 4), ("dtg", 4), ("assign1", 4),
+                                        ("kij", 4), ("assign3", 2), ("christoffel", 2),
+                                        ("dtg_chain", 2), ("dtg_chain_bwd", 2),
+                                        ("dtg_chain_batched", 2)])
+def test_kernel_info_four_points(kernel, ppt):
+    """A request of four points per lane runs with four only for bodies of at
+    most 24 component streams, otherwise with two, and kernel_info says so."""
+    a = tl_kernel_info(kernel, tune=dict(block=256, ppt=4, nt=True))
+    assert a["ppt"] == ppt and a["block"] == 256 and a["scratch_bytes"] == 0, a
+
+
 @pytest.mark.parametrize("lanes", [2, 3, 6, 9, 18])
 def test_kernel_info_lanes(lanes):
     a = tl_kernel_info("christoffel", tune=dict(block=64, lanes=lanes))
