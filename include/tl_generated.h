@@ -147,7 +147,10 @@ tl_status tlg_contract1(int64_t n, const tl_cfield* in, int32_t nin, const tl_fi
 tl_status tlg_contract2(int64_t n, const tl_cfield* in, int32_t nin, const tl_field* out, int32_t nout, void* stream, const tl_tune* tune);
 
 /* contract3: A_ijkl = D_k^o C_j^n B_i^m E_mnol (Sec. 5.1, eq:Contract3)
- *   A(i,j,k,l) = Sum(m, Sum(n, Sum(o, (((D(k,o) * C(j,n)) * B(i,m)) * E(m,n,o,l)))))
+ *   T(i,n,o,l) = Sum(m, (B(i,m) * E(m,n,o,l)))
+ *   M(i,j,o,l) = Sum(n, (C(j,n) * T(i,n,o,l)))
+ *   A(i,j,k,l) = Sum(o, (D(k,o) * M(i,j,o,l)))
+ * in registers only: M, T
  * in:  D [9] (3x3); C [9] (3x3); B [9] (3x3); E [81] (3x3x3x3)
  * out: A [81] (3x3x3x3)
  * stored elements read + written per point (BW_eff N_e): 189 */

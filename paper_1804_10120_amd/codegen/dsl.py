@@ -294,6 +294,27 @@ class Program:
         self.name, self.doc = name, doc
         self.statements = []
         self.temps = []
+        self.fused = None
+        self.arg_order = None
+
+    def input_order(self, *tensors):
+        """Pass the inputs in this order (default: order of first appearance),
+        e.g. to keep an expression's written order once it is split into
+        several statements."""
+        self.arg_order = list(tensors)
+        return self
+
+    def fuse(self, index: Index):
+        """Evaluate the statements slice by slice in ``index`` (a free index
+        of every left-hand side): all statements at index value 0, then at 1,
+        ...  A statement may then read a temporary only at the slice being
+        evaluated, so each slice's temporaries are used up before the next
+        slice's are formed (the generator rejects a read of a temporary
+        component not yet written)."""
+        if not isinstance(index, Index):
+            raise CodegenError("fuse() takes an index")
+        self.fused = index
+        return self
 
     def temp(self, *tensors):
         """Declare tensors that stay in registers (never read or written in memory)."""
@@ -340,9 +361,20 @@ class Program:
     @property
     def inputs(self):
         written = {st.lhs.tensor for st in self.statements}
-        return [t for t in self._order() if t not in written]
+        found = [t for t in self._order() if t not in written]
+        if self.arg_order is None:
+            return found
+        if set(self.arg_order) != set(found) or len(self.arg_order) != len(found):
+            raise CodegenError(f"{self.name}: input_order {self.arg_order} does not name the "
+                               f"inputs {found}")
+        return list(self.arg_order)
 
     def check(self):
+        if self.fused is not None:
+            for st in self.statements:
+                if not any(x is self.fused for x in st.lhs.free()):
+                    raise CodegenError(f"{self.name}: fused index {self.fused} is not free on "
+                                       f"the left-hand side of {st.lhs.tensor}")
         written = set()
         for st in self.statements:
             for t in _reads(st.rhs):

@@ -126,12 +126,15 @@ class _Emitter:
         self.loaded = {}         # (field, comp) -> variable
         self.pending = []        # loads referenced since the last statement was emitted
         self.written = set()     # (field, comp) of outputs with a value
+        self.temp_written = set()  # (temporary, comp) with a value
         self.lazy = sum(t.ncomp for t in self.ins) > LAZY_INPUTS
 
     def ref(self, e: Ref, env) -> str:
         t = e.tensor
         c = t.comp(e.resolve(env))
         if t in self.p.temps:
+            if (t, c) not in self.temp_written:
+                raise CodegenError(f"temporary {t.name}[{c}] is read before it is written")
             return f"t_{t.name}[{c}]"
         if t in self.fin:
             key = (self.fin[t], c)
@@ -163,38 +166,60 @@ class _Emitter:
             out.append(f"    const double {self.loaded[(f, c)]} = ld({f}, {c});")
         self.pending = []
 
+    def _emit(self, st, items, stmts, declared, order):
+        """The components ``items`` of statement ``st``, in order."""
+        t = st.lhs.tensor
+        rhs_f = factor_sums(st.rhs)
+        outer = None
+        for c, env in items:
+            if self.lazy and order:
+                if outer is not None and env[order[0]] != outer:
+                    # the next slice: nothing moves across this point
+                    stmts.append("    __builtin_amdgcn_sched_barrier(0);")
+                outer = env[order[0]]
+            rhs = self.expr(rhs_f, env)
+            if self.lazy:
+                self._flush_loads(stmts)
+            if t in self.p.temps:
+                self.temp_written.add((t, c))
+                stmts.append(f"    t_{t.name}[{c}] = {rhs};")
+            else:
+                f = self.fout[t]
+                var = f"o{f}_{c}"
+                decl = "" if (f, c) in declared else "double "
+                declared.add((f, c))
+                self.written.add((f, c))
+                stmts.append(f"    {decl}{var} = {rhs};")
+                stmts.append(f"    st({f}, {c}, {var});")
+
     def body(self) -> str:
         lines = []
         for t in self.p.temps:
             lines.append(f"    double t_{t.name}[{t.ncomp}];")
         stmts = []
         declared = set()
+        plans = []
         for st in self.p.statements:
-            stmts.append(f"    // {statement_text(st)}")
-            t = st.lhs.tensor
-            rhs_f = factor_sums(st.rhs)
-            order = index_order(st.lhs.free(), rhs_f)
+            order = index_order(st.lhs.free(), factor_sums(st.rhs))
+            if self.p.fused is not None:   # the fused index outermost
+                order = [self.p.fused] + [x for x in order if x is not self.p.fused]
             todo = sorted(st.assignments(), key=lambda ce: tuple(ce[1][x] for x in order))
-            outer = None
-            for c, env in todo:
-                if self.lazy and order:
-                    if outer is not None and env[order[0]] != outer:
-                        # the next slice: nothing moves across this point
-                        stmts.append("    __builtin_amdgcn_sched_barrier(0);")
-                    outer = env[order[0]]
-                rhs = self.expr(rhs_f, env)
-                if self.lazy:
-                    self._flush_loads(stmts)
-                if t in self.p.temps:
-                    stmts.append(f"    t_{t.name}[{c}] = {rhs};")
-                else:
-                    f = self.fout[t]
-                    var = f"o{f}_{c}"
-                    decl = "" if (f, c) in declared else "double "
-                    declared.add((f, c))
-                    self.written.add((f, c))
-                    stmts.append(f"    {decl}{var} = {rhs};")
-                    stmts.append(f"    st({f}, {c}, {var});")
+            plans.append((st, order, todo))
+        if self.p.fused is None:
+            for st, order, todo in plans:
+                stmts.append(f"    // {statement_text(st)}")
+                self._emit(st, todo, stmts, declared, order)
+        else:
+            x = self.p.fused
+            for st, _, _ in plans:
+                stmts.append(f"    // {statement_text(st)}")
+            stmts.append(f"    // slice by slice in {x}")
+            for v in range(x.dim):
+                if v:
+                    stmts.append("    __builtin_amdgcn_sched_barrier(0);")
+                for st, order, todo in plans:
+                    self._emit(st, [ce for ce in todo if ce[1][x] == v], stmts, declared,
+                               order[1:])
         if self.lazy:
             return "\n".join(lines + stmts)
         loads = [f"    const double {v} = ld({f}, {c});"

@@ -81,10 +81,17 @@ def programs():
                .let(A4[i, j, k, l], Sum(m, B[i, m] * E[m, j, k, l])))
     out.append(Program("contract2", "A_ijkl = C_j^n B_i^m E_mnkl (Sec. 5.1, eq:Contract2)")
                .let(A4[i, j, k, l], Sum(m, Sum(n_, C[j, n_] * B[i, m] * E[m, n_, k, l]))))
+    # the triple contraction one index at a time, slice by slice in l: for each
+    # l, T_ino = B_i^m E_mnol, then M_ijo = C_j^n T_ino, then A_ijkl = D_k^o M_ijo;
+    # each stage uses up the previous one's values as it forms its own
+    T3 = Tensor("T", (3, 3, 3, 3))
+    M3 = Tensor("M", (3, 3, 3, 3))
     out.append(Program("contract3", "A_ijkl = D_k^o C_j^n B_i^m E_mnol (Sec. 5.1, "
                                     "eq:Contract3)")
-               .let(A4[i, j, k, l],
-                    Sum(m, Sum(n_, Sum(o_, Dm[k, o_] * C[j, n_] * B[i, m] * E[m, n_, o_, l])))))
+               .temp(T3, M3).fuse(l).input_order(Dm, C, B, E)
+               .let(T3[i, n_, o_, l], Sum(m, B[i, m] * E[m, n_, o_, l]))
+               .let(M3[i, j, o_, l], Sum(n_, C[j, n_] * T3[i, n_, o_, l]))
+               .let(A4[i, j, k, l], Sum(o_, Dm[k, o_] * M3[i, j, o_, l])))
 
     # the examples of Sec. 4 (dimension-4 indices a, b, c; fixed and offset indices)
     A = Tensor("A", (4, 4))

@@ -1412,278 +1412,463 @@ struct Gen_contract3 {
   static constexpr int NIN = 108, NOUT = 81;
   template <class L, class S>
   __device__ static inline void stream(L&& ld, S&& st) {
-    // A(i,j,k,l) = Sum(m, Sum(n, Sum(o, (((D(k,o) * C(j,n)) * B(i,m)) * E(m,n,o,l)))))
+    double t_T[81];
+    double t_M[81];
+    // T(i,n,o,l) = Sum(m, (B(i,m) * E(m,n,o,l)))
+    // M(i,j,o,l) = Sum(n, (C(j,n) * T(i,n,o,l)))
+    // A(i,j,k,l) = Sum(o, (D(k,o) * M(i,j,o,l)))
+    // slice by slice in l
     const double x2_0 = ld(2, 0);
-    const double x1_0 = ld(1, 0);
-    const double x0_0 = ld(0, 0);
     const double x3_0 = ld(3, 0);
-    const double x0_1 = ld(0, 1);
-    const double x3_3 = ld(3, 3);
-    const double x0_2 = ld(0, 2);
-    const double x3_6 = ld(3, 6);
-    const double x1_1 = ld(1, 1);
-    const double x3_9 = ld(3, 9);
-    const double x3_12 = ld(3, 12);
-    const double x3_15 = ld(3, 15);
-    const double x1_2 = ld(1, 2);
-    const double x3_18 = ld(3, 18);
-    const double x3_21 = ld(3, 21);
-    const double x3_24 = ld(3, 24);
     const double x2_1 = ld(2, 1);
     const double x3_27 = ld(3, 27);
-    const double x3_30 = ld(3, 30);
-    const double x3_33 = ld(3, 33);
-    const double x3_36 = ld(3, 36);
-    const double x3_39 = ld(3, 39);
-    const double x3_42 = ld(3, 42);
-    const double x3_45 = ld(3, 45);
-    const double x3_48 = ld(3, 48);
-    const double x3_51 = ld(3, 51);
     const double x2_2 = ld(2, 2);
     const double x3_54 = ld(3, 54);
-    const double x3_57 = ld(3, 57);
-    const double x3_60 = ld(3, 60);
-    const double x3_63 = ld(3, 63);
-    const double x3_66 = ld(3, 66);
-    const double x3_69 = ld(3, 69);
-    const double x3_72 = ld(3, 72);
-    const double x3_75 = ld(3, 75);
-    const double x3_78 = ld(3, 78);
-    double o0_0 = ((x2_0 * ((x1_0 * ((x0_0 * x3_0) + (x0_1 * x3_3) + (x0_2 * x3_6))) + (x1_1 * ((x0_0 * x3_9) + (x0_1 * x3_12) + (x0_2 * x3_15))) + (x1_2 * ((x0_0 * x3_18) + (x0_1 * x3_21) + (x0_2 * x3_24))))) + (x2_1 * ((x1_0 * ((x0_0 * x3_27) + (x0_1 * x3_30) + (x0_2 * x3_33))) + (x1_1 * ((x0_0 * x3_36) + (x0_1 * x3_39) + (x0_2 * x3_42))) + (x1_2 * ((x0_0 * x3_45) + (x0_1 * x3_48) + (x0_2 * x3_51))))) + (x2_2 * ((x1_0 * ((x0_0 * x3_54) + (x0_1 * x3_57) + (x0_2 * x3_60))) + (x1_1 * ((x0_0 * x3_63) + (x0_1 * x3_66) + (x0_2 * x3_69))) + (x1_2 * ((x0_0 * x3_72) + (x0_1 * x3_75) + (x0_2 * x3_78))))));
-    st(0, 0, o0_0);
+    t_T[0] = ((x2_0 * x3_0) + (x2_1 * x3_27) + (x2_2 * x3_54));
     const double x2_3 = ld(2, 3);
     const double x2_4 = ld(2, 4);
     const double x2_5 = ld(2, 5);
-    double o0_27 = ((x2_3 * ((x1_0 * ((x0_0 * x3_0) + (x0_1 * x3_3) + (x0_2 * x3_6))) + (x1_1 * ((x0_0 * x3_9) + (x0_1 * x3_12) + (x0_2 * x3_15))) + (x1_2 * ((x0_0 * x3_18) + (x0_1 * x3_21) + (x0_2 * x3_24))))) + (x2_4 * ((x1_0 * ((x0_0 * x3_27) + (x0_1 * x3_30) + (x0_2 * x3_33))) + (x1_1 * ((x0_0 * x3_36) + (x0_1 * x3_39) + (x0_2 * x3_42))) + (x1_2 * ((x0_0 * x3_45) + (x0_1 * x3_48) + (x0_2 * x3_51))))) + (x2_5 * ((x1_0 * ((x0_0 * x3_54) + (x0_1 * x3_57) + (x0_2 * x3_60))) + (x1_1 * ((x0_0 * x3_63) + (x0_1 * x3_66) + (x0_2 * x3_69))) + (x1_2 * ((x0_0 * x3_72) + (x0_1 * x3_75) + (x0_2 * x3_78))))));
-    st(0, 27, o0_27);
+    t_T[27] = ((x2_3 * x3_0) + (x2_4 * x3_27) + (x2_5 * x3_54));
     const double x2_6 = ld(2, 6);
     const double x2_7 = ld(2, 7);
     const double x2_8 = ld(2, 8);
-    double o0_54 = ((x2_6 * ((x1_0 * ((x0_0 * x3_0) + (x0_1 * x3_3) + (x0_2 * x3_6))) + (x1_1 * ((x0_0 * x3_9) + (x0_1 * x3_12) + (x0_2 * x3_15))) + (x1_2 * ((x0_0 * x3_18) + (x0_1 * x3_21) + (x0_2 * x3_24))))) + (x2_7 * ((x1_0 * ((x0_0 * x3_27) + (x0_1 * x3_30) + (x0_2 * x3_33))) + (x1_1 * ((x0_0 * x3_36) + (x0_1 * x3_39) + (x0_2 * x3_42))) + (x1_2 * ((x0_0 * x3_45) + (x0_1 * x3_48) + (x0_2 * x3_51))))) + (x2_8 * ((x1_0 * ((x0_0 * x3_54) + (x0_1 * x3_57) + (x0_2 * x3_60))) + (x1_1 * ((x0_0 * x3_63) + (x0_1 * x3_66) + (x0_2 * x3_69))) + (x1_2 * ((x0_0 * x3_72) + (x0_1 * x3_75) + (x0_2 * x3_78))))));
-    st(0, 54, o0_54);
+    t_T[54] = ((x2_6 * x3_0) + (x2_7 * x3_27) + (x2_8 * x3_54));
+    const double x3_3 = ld(3, 3);
+    const double x3_30 = ld(3, 30);
+    const double x3_57 = ld(3, 57);
+    t_T[3] = ((x2_0 * x3_3) + (x2_1 * x3_30) + (x2_2 * x3_57));
+    t_T[30] = ((x2_3 * x3_3) + (x2_4 * x3_30) + (x2_5 * x3_57));
+    t_T[57] = ((x2_6 * x3_3) + (x2_7 * x3_30) + (x2_8 * x3_57));
+    const double x3_6 = ld(3, 6);
+    const double x3_33 = ld(3, 33);
+    const double x3_60 = ld(3, 60);
+    t_T[6] = ((x2_0 * x3_6) + (x2_1 * x3_33) + (x2_2 * x3_60));
+    t_T[33] = ((x2_3 * x3_6) + (x2_4 * x3_33) + (x2_5 * x3_60));
+    t_T[60] = ((x2_6 * x3_6) + (x2_7 * x3_33) + (x2_8 * x3_60));
+    __builtin_amdgcn_sched_barrier(0);
+    const double x3_9 = ld(3, 9);
+    const double x3_36 = ld(3, 36);
+    const double x3_63 = ld(3, 63);
+    t_T[9] = ((x2_0 * x3_9) + (x2_1 * x3_36) + (x2_2 * x3_63));
+    t_T[36] = ((x2_3 * x3_9) + (x2_4 * x3_36) + (x2_5 * x3_63));
+    t_T[63] = ((x2_6 * x3_9) + (x2_7 * x3_36) + (x2_8 * x3_63));
+    const double x3_12 = ld(3, 12);
+    const double x3_39 = ld(3, 39);
+    const double x3_66 = ld(3, 66);
+    t_T[12] = ((x2_0 * x3_12) + (x2_1 * x3_39) + (x2_2 * x3_66));
+    t_T[39] = ((x2_3 * x3_12) + (x2_4 * x3_39) + (x2_5 * x3_66));
+    t_T[66] = ((x2_6 * x3_12) + (x2_7 * x3_39) + (x2_8 * x3_66));
+    const double x3_15 = ld(3, 15);
+    const double x3_42 = ld(3, 42);
+    const double x3_69 = ld(3, 69);
+    t_T[15] = ((x2_0 * x3_15) + (x2_1 * x3_42) + (x2_2 * x3_69));
+    t_T[42] = ((x2_3 * x3_15) + (x2_4 * x3_42) + (x2_5 * x3_69));
+    t_T[69] = ((x2_6 * x3_15) + (x2_7 * x3_42) + (x2_8 * x3_69));
+    __builtin_amdgcn_sched_barrier(0);
+    const double x3_18 = ld(3, 18);
+    const double x3_45 = ld(3, 45);
+    const double x3_72 = ld(3, 72);
+    t_T[18] = ((x2_0 * x3_18) + (x2_1 * x3_45) + (x2_2 * x3_72));
+    t_T[45] = ((x2_3 * x3_18) + (x2_4 * x3_45) + (x2_5 * x3_72));
+    t_T[72] = ((x2_6 * x3_18) + (x2_7 * x3_45) + (x2_8 * x3_72));
+    const double x3_21 = ld(3, 21);
+    const double x3_48 = ld(3, 48);
+    const double x3_75 = ld(3, 75);
+    t_T[21] = ((x2_0 * x3_21) + (x2_1 * x3_48) + (x2_2 * x3_75));
+    t_T[48] = ((x2_3 * x3_21) + (x2_4 * x3_48) + (x2_5 * x3_75));
+    t_T[75] = ((x2_6 * x3_21) + (x2_7 * x3_48) + (x2_8 * x3_75));
+    const double x3_24 = ld(3, 24);
+    const double x3_51 = ld(3, 51);
+    const double x3_78 = ld(3, 78);
+    t_T[24] = ((x2_0 * x3_24) + (x2_1 * x3_51) + (x2_2 * x3_78));
+    t_T[51] = ((x2_3 * x3_24) + (x2_4 * x3_51) + (x2_5 * x3_78));
+    t_T[78] = ((x2_6 * x3_24) + (x2_7 * x3_51) + (x2_8 * x3_78));
+    const double x1_0 = ld(1, 0);
+    const double x1_1 = ld(1, 1);
+    const double x1_2 = ld(1, 2);
+    t_M[0] = ((x1_0 * t_T[0]) + (x1_1 * t_T[9]) + (x1_2 * t_T[18]));
     const double x1_3 = ld(1, 3);
     const double x1_4 = ld(1, 4);
     const double x1_5 = ld(1, 5);
-    double o0_9 = ((x2_0 * ((x1_3 * ((x0_0 * x3_0) + (x0_1 * x3_3) + (x0_2 * x3_6))) + (x1_4 * ((x0_0 * x3_9) + (x0_1 * x3_12) + (x0_2 * x3_15))) + (x1_5 * ((x0_0 * x3_18) + (x0_1 * x3_21) + (x0_2 * x3_24))))) + (x2_1 * ((x1_3 * ((x0_0 * x3_27) + (x0_1 * x3_30) + (x0_2 * x3_33))) + (x1_4 * ((x0_0 * x3_36) + (x0_1 * x3_39) + (x0_2 * x3_42))) + (x1_5 * ((x0_0 * x3_45) + (x0_1 * x3_48) + (x0_2 * x3_51))))) + (x2_2 * ((x1_3 * ((x0_0 * x3_54) + (x0_1 * x3_57) + (x0_2 * x3_60))) + (x1_4 * ((x0_0 * x3_63) + (x0_1 * x3_66) + (x0_2 * x3_69))) + (x1_5 * ((x0_0 * x3_72) + (x0_1 * x3_75) + (x0_2 * x3_78))))));
-    st(0, 9, o0_9);
-    double o0_36 = ((x2_3 * ((x1_3 * ((x0_0 * x3_0) + (x0_1 * x3_3) + (x0_2 * x3_6))) + (x1_4 * ((x0_0 * x3_9) + (x0_1 * x3_12) + (x0_2 * x3_15))) + (x1_5 * ((x0_0 * x3_18) + (x0_1 * x3_21) + (x0_2 * x3_24))))) + (x2_4 * ((x1_3 * ((x0_0 * x3_27) + (x0_1 * x3_30) + (x0_2 * x3_33))) + (x1_4 * ((x0_0 * x3_36) + (x0_1 * x3_39) + (x0_2 * x3_42))) + (x1_5 * ((x0_0 * x3_45) + (x0_1 * x3_48) + (x0_2 * x3_51))))) + (x2_5 * ((x1_3 * ((x0_0 * x3_54) + (x0_1 * x3_57) + (x0_2 * x3_60))) + (x1_4 * ((x0_0 * x3_63) + (x0_1 * x3_66) + (x0_2 * x3_69))) + (x1_5 * ((x0_0 * x3_72) + (x0_1 * x3_75) + (x0_2 * x3_78))))));
-    st(0, 36, o0_36);
-    double o0_63 = ((x2_6 * ((x1_3 * ((x0_0 * x3_0) + (x0_1 * x3_3) + (x0_2 * x3_6))) + (x1_4 * ((x0_0 * x3_9) + (x0_1 * x3_12) + (x0_2 * x3_15))) + (x1_5 * ((x0_0 * x3_18) + (x0_1 * x3_21) + (x0_2 * x3_24))))) + (x2_7 * ((x1_3 * ((x0_0 * x3_27) + (x0_1 * x3_30) + (x0_2 * x3_33))) + (x1_4 * ((x0_0 * x3_36) + (x0_1 * x3_39) + (x0_2 * x3_42))) + (x1_5 * ((x0_0 * x3_45) + (x0_1 * x3_48) + (x0_2 * x3_51))))) + (x2_8 * ((x1_3 * ((x0_0 * x3_54) + (x0_1 * x3_57) + (x0_2 * x3_60))) + (x1_4 * ((x0_0 * x3_63) + (x0_1 * x3_66) + (x0_2 * x3_69))) + (x1_5 * ((x0_0 * x3_72) + (x0_1 * x3_75) + (x0_2 * x3_78))))));
-    st(0, 63, o0_63);
+    t_M[9] = ((x1_3 * t_T[0]) + (x1_4 * t_T[9]) + (x1_5 * t_T[18]));
     const double x1_6 = ld(1, 6);
     const double x1_7 = ld(1, 7);
     const double x1_8 = ld(1, 8);
-    double o0_18 = ((x2_0 * ((x1_6 * ((x0_0 * x3_0) + (x0_1 * x3_3) + (x0_2 * x3_6))) + (x1_7 * ((x0_0 * x3_9) + (x0_1 * x3_12) + (x0_2 * x3_15))) + (x1_8 * ((x0_0 * x3_18) + (x0_1 * x3_21) + (x0_2 * x3_24))))) + (x2_1 * ((x1_6 * ((x0_0 * x3_27) + (x0_1 * x3_30) + (x0_2 * x3_33))) + (x1_7 * ((x0_0 * x3_36) + (x0_1 * x3_39) + (x0_2 * x3_42))) + (x1_8 * ((x0_0 * x3_45) + (x0_1 * x3_48) + (x0_2 * x3_51))))) + (x2_2 * ((x1_6 * ((x0_0 * x3_54) + (x0_1 * x3_57) + (x0_2 * x3_60))) + (x1_7 * ((x0_0 * x3_63) + (x0_1 * x3_66) + (x0_2 * x3_69))) + (x1_8 * ((x0_0 * x3_72) + (x0_1 * x3_75) + (x0_2 * x3_78))))));
-    st(0, 18, o0_18);
-    double o0_45 = ((x2_3 * ((x1_6 * ((x0_0 * x3_0) + (x0_1 * x3_3) + (x0_2 * x3_6))) + (x1_7 * ((x0_0 * x3_9) + (x0_1 * x3_12) + (x0_2 * x3_15))) + (x1_8 * ((x0_0 * x3_18) + (x0_1 * x3_21) + (x0_2 * x3_24))))) + (x2_4 * ((x1_6 * ((x0_0 * x3_27) + (x0_1 * x3_30) + (x0_2 * x3_33))) + (x1_7 * ((x0_0 * x3_36) + (x0_1 * x3_39) + (x0_2 * x3_42))) + (x1_8 * ((x0_0 * x3_45) + (x0_1 * x3_48) + (x0_2 * x3_51))))) + (x2_5 * ((x1_6 * ((x0_0 * x3_54) + (x0_1 * x3_57) + (x0_2 * x3_60))) + (x1_7 * ((x0_0 * x3_63) + (x0_1 * x3_66) + (x0_2 * x3_69))) + (x1_8 * ((x0_0 * x3_72) + (x0_1 * x3_75) + (x0_2 * x3_78))))));
-    st(0, 45, o0_45);
-    double o0_72 = ((x2_6 * ((x1_6 * ((x0_0 * x3_0) + (x0_1 * x3_3) + (x0_2 * x3_6))) + (x1_7 * ((x0_0 * x3_9) + (x0_1 * x3_12) + (x0_2 * x3_15))) + (x1_8 * ((x0_0 * x3_18) + (x0_1 * x3_21) + (x0_2 * x3_24))))) + (x2_7 * ((x1_6 * ((x0_0 * x3_27) + (x0_1 * x3_30) + (x0_2 * x3_33))) + (x1_7 * ((x0_0 * x3_36) + (x0_1 * x3_39) + (x0_2 * x3_42))) + (x1_8 * ((x0_0 * x3_45) + (x0_1 * x3_48) + (x0_2 * x3_51))))) + (x2_8 * ((x1_6 * ((x0_0 * x3_54) + (x0_1 * x3_57) + (x0_2 * x3_60))) + (x1_7 * ((x0_0 * x3_63) + (x0_1 * x3_66) + (x0_2 * x3_69))) + (x1_8 * ((x0_0 * x3_72) + (x0_1 * x3_75) + (x0_2 * x3_78))))));
-    st(0, 72, o0_72);
+    t_M[18] = ((x1_6 * t_T[0]) + (x1_7 * t_T[9]) + (x1_8 * t_T[18]));
+    t_M[3] = ((x1_0 * t_T[3]) + (x1_1 * t_T[12]) + (x1_2 * t_T[21]));
+    t_M[12] = ((x1_3 * t_T[3]) + (x1_4 * t_T[12]) + (x1_5 * t_T[21]));
+    t_M[21] = ((x1_6 * t_T[3]) + (x1_7 * t_T[12]) + (x1_8 * t_T[21]));
+    t_M[6] = ((x1_0 * t_T[6]) + (x1_1 * t_T[15]) + (x1_2 * t_T[24]));
+    t_M[15] = ((x1_3 * t_T[6]) + (x1_4 * t_T[15]) + (x1_5 * t_T[24]));
+    t_M[24] = ((x1_6 * t_T[6]) + (x1_7 * t_T[15]) + (x1_8 * t_T[24]));
+    __builtin_amdgcn_sched_barrier(0);
+    t_M[27] = ((x1_0 * t_T[27]) + (x1_1 * t_T[36]) + (x1_2 * t_T[45]));
+    t_M[36] = ((x1_3 * t_T[27]) + (x1_4 * t_T[36]) + (x1_5 * t_T[45]));
+    t_M[45] = ((x1_6 * t_T[27]) + (x1_7 * t_T[36]) + (x1_8 * t_T[45]));
+    t_M[30] = ((x1_0 * t_T[30]) + (x1_1 * t_T[39]) + (x1_2 * t_T[48]));
+    t_M[39] = ((x1_3 * t_T[30]) + (x1_4 * t_T[39]) + (x1_5 * t_T[48]));
+    t_M[48] = ((x1_6 * t_T[30]) + (x1_7 * t_T[39]) + (x1_8 * t_T[48]));
+    t_M[33] = ((x1_0 * t_T[33]) + (x1_1 * t_T[42]) + (x1_2 * t_T[51]));
+    t_M[42] = ((x1_3 * t_T[33]) + (x1_4 * t_T[42]) + (x1_5 * t_T[51]));
+    t_M[51] = ((x1_6 * t_T[33]) + (x1_7 * t_T[42]) + (x1_8 * t_T[51]));
+    __builtin_amdgcn_sched_barrier(0);
+    t_M[54] = ((x1_0 * t_T[54]) + (x1_1 * t_T[63]) + (x1_2 * t_T[72]));
+    t_M[63] = ((x1_3 * t_T[54]) + (x1_4 * t_T[63]) + (x1_5 * t_T[72]));
+    t_M[72] = ((x1_6 * t_T[54]) + (x1_7 * t_T[63]) + (x1_8 * t_T[72]));
+    t_M[57] = ((x1_0 * t_T[57]) + (x1_1 * t_T[66]) + (x1_2 * t_T[75]));
+    t_M[66] = ((x1_3 * t_T[57]) + (x1_4 * t_T[66]) + (x1_5 * t_T[75]));
+    t_M[75] = ((x1_6 * t_T[57]) + (x1_7 * t_T[66]) + (x1_8 * t_T[75]));
+    t_M[60] = ((x1_0 * t_T[60]) + (x1_1 * t_T[69]) + (x1_2 * t_T[78]));
+    t_M[69] = ((x1_3 * t_T[60]) + (x1_4 * t_T[69]) + (x1_5 * t_T[78]));
+    t_M[78] = ((x1_6 * t_T[60]) + (x1_7 * t_T[69]) + (x1_8 * t_T[78]));
+    const double x0_0 = ld(0, 0);
+    const double x0_1 = ld(0, 1);
+    const double x0_2 = ld(0, 2);
+    double o0_0 = ((x0_0 * t_M[0]) + (x0_1 * t_M[3]) + (x0_2 * t_M[6]));
+    st(0, 0, o0_0);
     const double x0_3 = ld(0, 3);
     const double x0_4 = ld(0, 4);
     const double x0_5 = ld(0, 5);
-    double o0_3 = ((x2_0 * ((x1_0 * ((x0_3 * x3_0) + (x0_4 * x3_3) + (x0_5 * x3_6))) + (x1_1 * ((x0_3 * x3_9) + (x0_4 * x3_12) + (x0_5 * x3_15))) + (x1_2 * ((x0_3 * x3_18) + (x0_4 * x3_21) + (x0_5 * x3_24))))) + (x2_1 * ((x1_0 * ((x0_3 * x3_27) + (x0_4 * x3_30) + (x0_5 * x3_33))) + (x1_1 * ((x0_3 * x3_36) + (x0_4 * x3_39) + (x0_5 * x3_42))) + (x1_2 * ((x0_3 * x3_45) + (x0_4 * x3_48) + (x0_5 * x3_51))))) + (x2_2 * ((x1_0 * ((x0_3 * x3_54) + (x0_4 * x3_57) + (x0_5 * x3_60))) + (x1_1 * ((x0_3 * x3_63) + (x0_4 * x3_66) + (x0_5 * x3_69))) + (x1_2 * ((x0_3 * x3_72) + (x0_4 * x3_75) + (x0_5 * x3_78))))));
+    double o0_3 = ((x0_3 * t_M[0]) + (x0_4 * t_M[3]) + (x0_5 * t_M[6]));
     st(0, 3, o0_3);
-    double o0_30 = ((x2_3 * ((x1_0 * ((x0_3 * x3_0) + (x0_4 * x3_3) + (x0_5 * x3_6))) + (x1_1 * ((x0_3 * x3_9) + (x0_4 * x3_12) + (x0_5 * x3_15))) + (x1_2 * ((x0_3 * x3_18) + (x0_4 * x3_21) + (x0_5 * x3_24))))) + (x2_4 * ((x1_0 * ((x0_3 * x3_27) + (x0_4 * x3_30) + (x0_5 * x3_33))) + (x1_1 * ((x0_3 * x3_36) + (x0_4 * x3_39) + (x0_5 * x3_42))) + (x1_2 * ((x0_3 * x3_45) + (x0_4 * x3_48) + (x0_5 * x3_51))))) + (x2_5 * ((x1_0 * ((x0_3 * x3_54) + (x0_4 * x3_57) + (x0_5 * x3_60))) + (x1_1 * ((x0_3 * x3_63) + (x0_4 * x3_66) + (x0_5 * x3_69))) + (x1_2 * ((x0_3 * x3_72) + (x0_4 * x3_75) + (x0_5 * x3_78))))));
-    st(0, 30, o0_30);
-    double o0_57 = ((x2_6 * ((x1_0 * ((x0_3 * x3_0) + (x0_4 * x3_3) + (x0_5 * x3_6))) + (x1_1 * ((x0_3 * x3_9) + (x0_4 * x3_12) + (x0_5 * x3_15))) + (x1_2 * ((x0_3 * x3_18) + (x0_4 * x3_21) + (x0_5 * x3_24))))) + (x2_7 * ((x1_0 * ((x0_3 * x3_27) + (x0_4 * x3_30) + (x0_5 * x3_33))) + (x1_1 * ((x0_3 * x3_36) + (x0_4 * x3_39) + (x0_5 * x3_42))) + (x1_2 * ((x0_3 * x3_45) + (x0_4 * x3_48) + (x0_5 * x3_51))))) + (x2_8 * ((x1_0 * ((x0_3 * x3_54) + (x0_4 * x3_57) + (x0_5 * x3_60))) + (x1_1 * ((x0_3 * x3_63) + (x0_4 * x3_66) + (x0_5 * x3_69))) + (x1_2 * ((x0_3 * x3_72) + (x0_4 * x3_75) + (x0_5 * x3_78))))));
-    st(0, 57, o0_57);
-    double o0_12 = ((x2_0 * ((x1_3 * ((x0_3 * x3_0) + (x0_4 * x3_3) + (x0_5 * x3_6))) + (x1_4 * ((x0_3 * x3_9) + (x0_4 * x3_12) + (x0_5 * x3_15))) + (x1_5 * ((x0_3 * x3_18) + (x0_4 * x3_21) + (x0_5 * x3_24))))) + (x2_1 * ((x1_3 * ((x0_3 * x3_27) + (x0_4 * x3_30) + (x0_5 * x3_33))) + (x1_4 * ((x0_3 * x3_36) + (x0_4 * x3_39) + (x0_5 * x3_42))) + (x1_5 * ((x0_3 * x3_45) + (x0_4 * x3_48) + (x0_5 * x3_51))))) + (x2_2 * ((x1_3 * ((x0_3 * x3_54) + (x0_4 * x3_57) + (x0_5 * x3_60))) + (x1_4 * ((x0_3 * x3_63) + (x0_4 * x3_66) + (x0_5 * x3_69))) + (x1_5 * ((x0_3 * x3_72) + (x0_4 * x3_75) + (x0_5 * x3_78))))));
-    st(0, 12, o0_12);
-    double o0_39 = ((x2_3 * ((x1_3 * ((x0_3 * x3_0) + (x0_4 * x3_3) + (x0_5 * x3_6))) + (x1_4 * ((x0_3 * x3_9) + (x0_4 * x3_12) + (x0_5 * x3_15))) + (x1_5 * ((x0_3 * x3_18) + (x0_4 * x3_21) + (x0_5 * x3_24))))) + (x2_4 * ((x1_3 * ((x0_3 * x3_27) + (x0_4 * x3_30) + (x0_5 * x3_33))) + (x1_4 * ((x0_3 * x3_36) + (x0_4 * x3_39) + (x0_5 * x3_42))) + (x1_5 * ((x0_3 * x3_45) + (x0_4 * x3_48) + (x0_5 * x3_51))))) + (x2_5 * ((x1_3 * ((x0_3 * x3_54) + (x0_4 * x3_57) + (x0_5 * x3_60))) + (x1_4 * ((x0_3 * x3_63) + (x0_4 * x3_66) + (x0_5 * x3_69))) + (x1_5 * ((x0_3 * x3_72) + (x0_4 * x3_75) + (x0_5 * x3_78))))));
-    st(0, 39, o0_39);
-    double o0_66 = ((x2_6 * ((x1_3 * ((x0_3 * x3_0) + (x0_4 * x3_3) + (x0_5 * x3_6))) + (x1_4 * ((x0_3 * x3_9) + (x0_4 * x3_12) + (x0_5 * x3_15))) + (x1_5 * ((x0_3 * x3_18) + (x0_4 * x3_21) + (x0_5 * x3_24))))) + (x2_7 * ((x1_3 * ((x0_3 * x3_27) + (x0_4 * x3_30) + (x0_5 * x3_33))) + (x1_4 * ((x0_3 * x3_36) + (x0_4 * x3_39) + (x0_5 * x3_42))) + (x1_5 * ((x0_3 * x3_45) + (x0_4 * x3_48) + (x0_5 * x3_51))))) + (x2_8 * ((x1_3 * ((x0_3 * x3_54) + (x0_4 * x3_57) + (x0_5 * x3_60))) + (x1_4 * ((x0_3 * x3_63) + (x0_4 * x3_66) + (x0_5 * x3_69))) + (x1_5 * ((x0_3 * x3_72) + (x0_4 * x3_75) + (x0_5 * x3_78))))));
-    st(0, 66, o0_66);
-    double o0_21 = ((x2_0 * ((x1_6 * ((x0_3 * x3_0) + (x0_4 * x3_3) + (x0_5 * x3_6))) + (x1_7 * ((x0_3 * x3_9) + (x0_4 * x3_12) + (x0_5 * x3_15))) + (x1_8 * ((x0_3 * x3_18) + (x0_4 * x3_21) + (x0_5 * x3_24))))) + (x2_1 * ((x1_6 * ((x0_3 * x3_27) + (x0_4 * x3_30) + (x0_5 * x3_33))) + (x1_7 * ((x0_3 * x3_36) + (x0_4 * x3_39) + (x0_5 * x3_42))) + (x1_8 * ((x0_3 * x3_45) + (x0_4 * x3_48) + (x0_5 * x3_51))))) + (x2_2 * ((x1_6 * ((x0_3 * x3_54) + (x0_4 * x3_57) + (x0_5 * x3_60))) + (x1_7 * ((x0_3 * x3_63) + (x0_4 * x3_66) + (x0_5 * x3_69))) + (x1_8 * ((x0_3 * x3_72) + (x0_4 * x3_75) + (x0_5 * x3_78))))));
-    st(0, 21, o0_21);
-    double o0_48 = ((x2_3 * ((x1_6 * ((x0_3 * x3_0) + (x0_4 * x3_3) + (x0_5 * x3_6))) + (x1_7 * ((x0_3 * x3_9) + (x0_4 * x3_12) + (x0_5 * x3_15))) + (x1_8 * ((x0_3 * x3_18) + (x0_4 * x3_21) + (x0_5 * x3_24))))) + (x2_4 * ((x1_6 * ((x0_3 * x3_27) + (x0_4 * x3_30) + (x0_5 * x3_33))) + (x1_7 * ((x0_3 * x3_36) + (x0_4 * x3_39) + (x0_5 * x3_42))) + (x1_8 * ((x0_3 * x3_45) + (x0_4 * x3_48) + (x0_5 * x3_51))))) + (x2_5 * ((x1_6 * ((x0_3 * x3_54) + (x0_4 * x3_57) + (x0_5 * x3_60))) + (x1_7 * ((x0_3 * x3_63) + (x0_4 * x3_66) + (x0_5 * x3_69))) + (x1_8 * ((x0_3 * x3_72) + (x0_4 * x3_75) + (x0_5 * x3_78))))));
-    st(0, 48, o0_48);
-    double o0_75 = ((x2_6 * ((x1_6 * ((x0_3 * x3_0) + (x0_4 * x3_3) + (x0_5 * x3_6))) + (x1_7 * ((x0_3 * x3_9) + (x0_4 * x3_12) + (x0_5 * x3_15))) + (x1_8 * ((x0_3 * x3_18) + (x0_4 * x3_21) + (x0_5 * x3_24))))) + (x2_7 * ((x1_6 * ((x0_3 * x3_27) + (x0_4 * x3_30) + (x0_5 * x3_33))) + (x1_7 * ((x0_3 * x3_36) + (x0_4 * x3_39) + (x0_5 * x3_42))) + (x1_8 * ((x0_3 * x3_45) + (x0_4 * x3_48) + (x0_5 * x3_51))))) + (x2_8 * ((x1_6 * ((x0_3 * x3_54) + (x0_4 * x3_57) + (x0_5 * x3_60))) + (x1_7 * ((x0_3 * x3_63) + (x0_4 * x3_66) + (x0_5 * x3_69))) + (x1_8 * ((x0_3 * x3_72) + (x0_4 * x3_75) + (x0_5 * x3_78))))));
-    st(0, 75, o0_75);
     const double x0_6 = ld(0, 6);
     const double x0_7 = ld(0, 7);
     const double x0_8 = ld(0, 8);
-    double o0_6 = ((x2_0 * ((x1_0 * ((x0_6 * x3_0) + (x0_7 * x3_3) + (x0_8 * x3_6))) + (x1_1 * ((x0_6 * x3_9) + (x0_7 * x3_12) + (x0_8 * x3_15))) + (x1_2 * ((x0_6 * x3_18) + (x0_7 * x3_21) + (x0_8 * x3_24))))) + (x2_1 * ((x1_0 * ((x0_6 * x3_27) + (x0_7 * x3_30) + (x0_8 * x3_33))) + (x1_1 * ((x0_6 * x3_36) + (x0_7 * x3_39) + (x0_8 * x3_42))) + (x1_2 * ((x0_6 * x3_45) + (x0_7 * x3_48) + (x0_8 * x3_51))))) + (x2_2 * ((x1_0 * ((x0_6 * x3_54) + (x0_7 * x3_57) + (x0_8 * x3_60))) + (x1_1 * ((x0_6 * x3_63) + (x0_7 * x3_66) + (x0_8 * x3_69))) + (x1_2 * ((x0_6 * x3_72) + (x0_7 * x3_75) + (x0_8 * x3_78))))));
+    double o0_6 = ((x0_6 * t_M[0]) + (x0_7 * t_M[3]) + (x0_8 * t_M[6]));
     st(0, 6, o0_6);
-    double o0_33 = ((x2_3 * ((x1_0 * ((x0_6 * x3_0) + (x0_7 * x3_3) + (x0_8 * x3_6))) + (x1_1 * ((x0_6 * x3_9) + (x0_7 * x3_12) + (x0_8 * x3_15))) + (x1_2 * ((x0_6 * x3_18) + (x0_7 * x3_21) + (x0_8 * x3_24))))) + (x2_4 * ((x1_0 * ((x0_6 * x3_27) + (x0_7 * x3_30) + (x0_8 * x3_33))) + (x1_1 * ((x0_6 * x3_36) + (x0_7 * x3_39) + (x0_8 * x3_42))) + (x1_2 * ((x0_6 * x3_45) + (x0_7 * x3_48) + (x0_8 * x3_51))))) + (x2_5 * ((x1_0 * ((x0_6 * x3_54) + (x0_7 * x3_57) + (x0_8 * x3_60))) + (x1_1 * ((x0_6 * x3_63) + (x0_7 * x3_66) + (x0_8 * x3_69))) + (x1_2 * ((x0_6 * x3_72) + (x0_7 * x3_75) + (x0_8 * x3_78))))));
-    st(0, 33, o0_33);
-    double o0_60 = ((x2_6 * ((x1_0 * ((x0_6 * x3_0) + (x0_7 * x3_3) + (x0_8 * x3_6))) + (x1_1 * ((x0_6 * x3_9) + (x0_7 * x3_12) + (x0_8 * x3_15))) + (x1_2 * ((x0_6 * x3_18) + (x0_7 * x3_21) + (x0_8 * x3_24))))) + (x2_7 * ((x1_0 * ((x0_6 * x3_27) + (x0_7 * x3_30) + (x0_8 * x3_33))) + (x1_1 * ((x0_6 * x3_36) + (x0_7 * x3_39) + (x0_8 * x3_42))) + (x1_2 * ((x0_6 * x3_45) + (x0_7 * x3_48) + (x0_8 * x3_51))))) + (x2_8 * ((x1_0 * ((x0_6 * x3_54) + (x0_7 * x3_57) + (x0_8 * x3_60))) + (x1_1 * ((x0_6 * x3_63) + (x0_7 * x3_66) + (x0_8 * x3_69))) + (x1_2 * ((x0_6 * x3_72) + (x0_7 * x3_75) + (x0_8 * x3_78))))));
-    st(0, 60, o0_60);
-    double o0_15 = ((x2_0 * ((x1_3 * ((x0_6 * x3_0) + (x0_7 * x3_3) + (x0_8 * x3_6))) + (x1_4 * ((x0_6 * x3_9) + (x0_7 * x3_12) + (x0_8 * x3_15))) + (x1_5 * ((x0_6 * x3_18) + (x0_7 * x3_21) + (x0_8 * x3_24))))) + (x2_1 * ((x1_3 * ((x0_6 * x3_27) + (x0_7 * x3_30) + (x0_8 * x3_33))) + (x1_4 * ((x0_6 * x3_36) + (x0_7 * x3_39) + (x0_8 * x3_42))) + (x1_5 * ((x0_6 * x3_45) + (x0_7 * x3_48) + (x0_8 * x3_51))))) + (x2_2 * ((x1_3 * ((x0_6 * x3_54) + (x0_7 * x3_57) + (x0_8 * x3_60))) + (x1_4 * ((x0_6 * x3_63) + (x0_7 * x3_66) + (x0_8 * x3_69))) + (x1_5 * ((x0_6 * x3_72) + (x0_7 * x3_75) + (x0_8 * x3_78))))));
+    double o0_9 = ((x0_0 * t_M[9]) + (x0_1 * t_M[12]) + (x0_2 * t_M[15]));
+    st(0, 9, o0_9);
+    double o0_12 = ((x0_3 * t_M[9]) + (x0_4 * t_M[12]) + (x0_5 * t_M[15]));
+    st(0, 12, o0_12);
+    double o0_15 = ((x0_6 * t_M[9]) + (x0_7 * t_M[12]) + (x0_8 * t_M[15]));
     st(0, 15, o0_15);
-    double o0_42 = ((x2_3 * ((x1_3 * ((x0_6 * x3_0) + (x0_7 * x3_3) + (x0_8 * x3_6))) + (x1_4 * ((x0_6 * x3_9) + (x0_7 * x3_12) + (x0_8 * x3_15))) + (x1_5 * ((x0_6 * x3_18) + (x0_7 * x3_21) + (x0_8 * x3_24))))) + (x2_4 * ((x1_3 * ((x0_6 * x3_27) + (x0_7 * x3_30) + (x0_8 * x3_33))) + (x1_4 * ((x0_6 * x3_36) + (x0_7 * x3_39) + (x0_8 * x3_42))) + (x1_5 * ((x0_6 * x3_45) + (x0_7 * x3_48) + (x0_8 * x3_51))))) + (x2_5 * ((x1_3 * ((x0_6 * x3_54) + (x0_7 * x3_57) + (x0_8 * x3_60))) + (x1_4 * ((x0_6 * x3_63) + (x0_7 * x3_66) + (x0_8 * x3_69))) + (x1_5 * ((x0_6 * x3_72) + (x0_7 * x3_75) + (x0_8 * x3_78))))));
-    st(0, 42, o0_42);
-    double o0_69 = ((x2_6 * ((x1_3 * ((x0_6 * x3_0) + (x0_7 * x3_3) + (x0_8 * x3_6))) + (x1_4 * ((x0_6 * x3_9) + (x0_7 * x3_12) + (x0_8 * x3_15))) + (x1_5 * ((x0_6 * x3_18) + (x0_7 * x3_21) + (x0_8 * x3_24))))) + (x2_7 * ((x1_3 * ((x0_6 * x3_27) + (x0_7 * x3_30) + (x0_8 * x3_33))) + (x1_4 * ((x0_6 * x3_36) + (x0_7 * x3_39) + (x0_8 * x3_42))) + (x1_5 * ((x0_6 * x3_45) + (x0_7 * x3_48) + (x0_8 * x3_51))))) + (x2_8 * ((x1_3 * ((x0_6 * x3_54) + (x0_7 * x3_57) + (x0_8 * x3_60))) + (x1_4 * ((x0_6 * x3_63) + (x0_7 * x3_66) + (x0_8 * x3_69))) + (x1_5 * ((x0_6 * x3_72) + (x0_7 * x3_75) + (x0_8 * x3_78))))));
-    st(0, 69, o0_69);
-    double o0_24 = ((x2_0 * ((x1_6 * ((x0_6 * x3_0) + (x0_7 * x3_3) + (x0_8 * x3_6))) + (x1_7 * ((x0_6 * x3_9) + (x0_7 * x3_12) + (x0_8 * x3_15))) + (x1_8 * ((x0_6 * x3_18) + (x0_7 * x3_21) + (x0_8 * x3_24))))) + (x2_1 * ((x1_6 * ((x0_6 * x3_27) + (x0_7 * x3_30) + (x0_8 * x3_33))) + (x1_7 * ((x0_6 * x3_36) + (x0_7 * x3_39) + (x0_8 * x3_42))) + (x1_8 * ((x0_6 * x3_45) + (x0_7 * x3_48) + (x0_8 * x3_51))))) + (x2_2 * ((x1_6 * ((x0_6 * x3_54) + (x0_7 * x3_57) + (x0_8 * x3_60))) + (x1_7 * ((x0_6 * x3_63) + (x0_7 * x3_66) + (x0_8 * x3_69))) + (x1_8 * ((x0_6 * x3_72) + (x0_7 * x3_75) + (x0_8 * x3_78))))));
+    double o0_18 = ((x0_0 * t_M[18]) + (x0_1 * t_M[21]) + (x0_2 * t_M[24]));
+    st(0, 18, o0_18);
+    double o0_21 = ((x0_3 * t_M[18]) + (x0_4 * t_M[21]) + (x0_5 * t_M[24]));
+    st(0, 21, o0_21);
+    double o0_24 = ((x0_6 * t_M[18]) + (x0_7 * t_M[21]) + (x0_8 * t_M[24]));
     st(0, 24, o0_24);
-    double o0_51 = ((x2_3 * ((x1_6 * ((x0_6 * x3_0) + (x0_7 * x3_3) + (x0_8 * x3_6))) + (x1_7 * ((x0_6 * x3_9) + (x0_7 * x3_12) + (x0_8 * x3_15))) + (x1_8 * ((x0_6 * x3_18) + (x0_7 * x3_21) + (x0_8 * x3_24))))) + (x2_4 * ((x1_6 * ((x0_6 * x3_27) + (x0_7 * x3_30) + (x0_8 * x3_33))) + (x1_7 * ((x0_6 * x3_36) + (x0_7 * x3_39) + (x0_8 * x3_42))) + (x1_8 * ((x0_6 * x3_45) + (x0_7 * x3_48) + (x0_8 * x3_51))))) + (x2_5 * ((x1_6 * ((x0_6 * x3_54) + (x0_7 * x3_57) + (x0_8 * x3_60))) + (x1_7 * ((x0_6 * x3_63) + (x0_7 * x3_66) + (x0_8 * x3_69))) + (x1_8 * ((x0_6 * x3_72) + (x0_7 * x3_75) + (x0_8 * x3_78))))));
+    __builtin_amdgcn_sched_barrier(0);
+    double o0_27 = ((x0_0 * t_M[27]) + (x0_1 * t_M[30]) + (x0_2 * t_M[33]));
+    st(0, 27, o0_27);
+    double o0_30 = ((x0_3 * t_M[27]) + (x0_4 * t_M[30]) + (x0_5 * t_M[33]));
+    st(0, 30, o0_30);
+    double o0_33 = ((x0_6 * t_M[27]) + (x0_7 * t_M[30]) + (x0_8 * t_M[33]));
+    st(0, 33, o0_33);
+    double o0_36 = ((x0_0 * t_M[36]) + (x0_1 * t_M[39]) + (x0_2 * t_M[42]));
+    st(0, 36, o0_36);
+    double o0_39 = ((x0_3 * t_M[36]) + (x0_4 * t_M[39]) + (x0_5 * t_M[42]));
+    st(0, 39, o0_39);
+    double o0_42 = ((x0_6 * t_M[36]) + (x0_7 * t_M[39]) + (x0_8 * t_M[42]));
+    st(0, 42, o0_42);
+    double o0_45 = ((x0_0 * t_M[45]) + (x0_1 * t_M[48]) + (x0_2 * t_M[51]));
+    st(0, 45, o0_45);
+    double o0_48 = ((x0_3 * t_M[45]) + (x0_4 * t_M[48]) + (x0_5 * t_M[51]));
+    st(0, 48, o0_48);
+    double o0_51 = ((x0_6 * t_M[45]) + (x0_7 * t_M[48]) + (x0_8 * t_M[51]));
     st(0, 51, o0_51);
-    double o0_78 = ((x2_6 * ((x1_6 * ((x0_6 * x3_0) + (x0_7 * x3_3) + (x0_8 * x3_6))) + (x1_7 * ((x0_6 * x3_9) + (x0_7 * x3_12) + (x0_8 * x3_15))) + (x1_8 * ((x0_6 * x3_18) + (x0_7 * x3_21) + (x0_8 * x3_24))))) + (x2_7 * ((x1_6 * ((x0_6 * x3_27) + (x0_7 * x3_30) + (x0_8 * x3_33))) + (x1_7 * ((x0_6 * x3_36) + (x0_7 * x3_39) + (x0_8 * x3_42))) + (x1_8 * ((x0_6 * x3_45) + (x0_7 * x3_48) + (x0_8 * x3_51))))) + (x2_8 * ((x1_6 * ((x0_6 * x3_54) + (x0_7 * x3_57) + (x0_8 * x3_60))) + (x1_7 * ((x0_6 * x3_63) + (x0_7 * x3_66) + (x0_8 * x3_69))) + (x1_8 * ((x0_6 * x3_72) + (x0_7 * x3_75) + (x0_8 * x3_78))))));
+    __builtin_amdgcn_sched_barrier(0);
+    double o0_54 = ((x0_0 * t_M[54]) + (x0_1 * t_M[57]) + (x0_2 * t_M[60]));
+    st(0, 54, o0_54);
+    double o0_57 = ((x0_3 * t_M[54]) + (x0_4 * t_M[57]) + (x0_5 * t_M[60]));
+    st(0, 57, o0_57);
+    double o0_60 = ((x0_6 * t_M[54]) + (x0_7 * t_M[57]) + (x0_8 * t_M[60]));
+    st(0, 60, o0_60);
+    double o0_63 = ((x0_0 * t_M[63]) + (x0_1 * t_M[66]) + (x0_2 * t_M[69]));
+    st(0, 63, o0_63);
+    double o0_66 = ((x0_3 * t_M[63]) + (x0_4 * t_M[66]) + (x0_5 * t_M[69]));
+    st(0, 66, o0_66);
+    double o0_69 = ((x0_6 * t_M[63]) + (x0_7 * t_M[66]) + (x0_8 * t_M[69]));
+    st(0, 69, o0_69);
+    double o0_72 = ((x0_0 * t_M[72]) + (x0_1 * t_M[75]) + (x0_2 * t_M[78]));
+    st(0, 72, o0_72);
+    double o0_75 = ((x0_3 * t_M[72]) + (x0_4 * t_M[75]) + (x0_5 * t_M[78]));
+    st(0, 75, o0_75);
+    double o0_78 = ((x0_6 * t_M[72]) + (x0_7 * t_M[75]) + (x0_8 * t_M[78]));
     st(0, 78, o0_78);
     __builtin_amdgcn_sched_barrier(0);
     const double x3_1 = ld(3, 1);
-    const double x3_4 = ld(3, 4);
-    const double x3_7 = ld(3, 7);
-    const double x3_10 = ld(3, 10);
-    const double x3_13 = ld(3, 13);
-    const double x3_16 = ld(3, 16);
-    const double x3_19 = ld(3, 19);
-    const double x3_22 = ld(3, 22);
-    const double x3_25 = ld(3, 25);
     const double x3_28 = ld(3, 28);
-    const double x3_31 = ld(3, 31);
-    const double x3_34 = ld(3, 34);
-    const double x3_37 = ld(3, 37);
-    const double x3_40 = ld(3, 40);
-    const double x3_43 = ld(3, 43);
-    const double x3_46 = ld(3, 46);
-    const double x3_49 = ld(3, 49);
-    const double x3_52 = ld(3, 52);
     const double x3_55 = ld(3, 55);
+    t_T[1] = ((x2_0 * x3_1) + (x2_1 * x3_28) + (x2_2 * x3_55));
+    t_T[28] = ((x2_3 * x3_1) + (x2_4 * x3_28) + (x2_5 * x3_55));
+    t_T[55] = ((x2_6 * x3_1) + (x2_7 * x3_28) + (x2_8 * x3_55));
+    const double x3_4 = ld(3, 4);
+    const double x3_31 = ld(3, 31);
     const double x3_58 = ld(3, 58);
+    t_T[4] = ((x2_0 * x3_4) + (x2_1 * x3_31) + (x2_2 * x3_58));
+    t_T[31] = ((x2_3 * x3_4) + (x2_4 * x3_31) + (x2_5 * x3_58));
+    t_T[58] = ((x2_6 * x3_4) + (x2_7 * x3_31) + (x2_8 * x3_58));
+    const double x3_7 = ld(3, 7);
+    const double x3_34 = ld(3, 34);
     const double x3_61 = ld(3, 61);
+    t_T[7] = ((x2_0 * x3_7) + (x2_1 * x3_34) + (x2_2 * x3_61));
+    t_T[34] = ((x2_3 * x3_7) + (x2_4 * x3_34) + (x2_5 * x3_61));
+    t_T[61] = ((x2_6 * x3_7) + (x2_7 * x3_34) + (x2_8 * x3_61));
+    __builtin_amdgcn_sched_barrier(0);
+    const double x3_10 = ld(3, 10);
+    const double x3_37 = ld(3, 37);
     const double x3_64 = ld(3, 64);
+    t_T[10] = ((x2_0 * x3_10) + (x2_1 * x3_37) + (x2_2 * x3_64));
+    t_T[37] = ((x2_3 * x3_10) + (x2_4 * x3_37) + (x2_5 * x3_64));
+    t_T[64] = ((x2_6 * x3_10) + (x2_7 * x3_37) + (x2_8 * x3_64));
+    const double x3_13 = ld(3, 13);
+    const double x3_40 = ld(3, 40);
     const double x3_67 = ld(3, 67);
+    t_T[13] = ((x2_0 * x3_13) + (x2_1 * x3_40) + (x2_2 * x3_67));
+    t_T[40] = ((x2_3 * x3_13) + (x2_4 * x3_40) + (x2_5 * x3_67));
+    t_T[67] = ((x2_6 * x3_13) + (x2_7 * x3_40) + (x2_8 * x3_67));
+    const double x3_16 = ld(3, 16);
+    const double x3_43 = ld(3, 43);
     const double x3_70 = ld(3, 70);
+    t_T[16] = ((x2_0 * x3_16) + (x2_1 * x3_43) + (x2_2 * x3_70));
+    t_T[43] = ((x2_3 * x3_16) + (x2_4 * x3_43) + (x2_5 * x3_70));
+    t_T[70] = ((x2_6 * x3_16) + (x2_7 * x3_43) + (x2_8 * x3_70));
+    __builtin_amdgcn_sched_barrier(0);
+    const double x3_19 = ld(3, 19);
+    const double x3_46 = ld(3, 46);
     const double x3_73 = ld(3, 73);
+    t_T[19] = ((x2_0 * x3_19) + (x2_1 * x3_46) + (x2_2 * x3_73));
+    t_T[46] = ((x2_3 * x3_19) + (x2_4 * x3_46) + (x2_5 * x3_73));
+    t_T[73] = ((x2_6 * x3_19) + (x2_7 * x3_46) + (x2_8 * x3_73));
+    const double x3_22 = ld(3, 22);
+    const double x3_49 = ld(3, 49);
     const double x3_76 = ld(3, 76);
+    t_T[22] = ((x2_0 * x3_22) + (x2_1 * x3_49) + (x2_2 * x3_76));
+    t_T[49] = ((x2_3 * x3_22) + (x2_4 * x3_49) + (x2_5 * x3_76));
+    t_T[76] = ((x2_6 * x3_22) + (x2_7 * x3_49) + (x2_8 * x3_76));
+    const double x3_25 = ld(3, 25);
+    const double x3_52 = ld(3, 52);
     const double x3_79 = ld(3, 79);
-    double o0_1 = ((x2_0 * ((x1_0 * ((x0_0 * x3_1) + (x0_1 * x3_4) + (x0_2 * x3_7))) + (x1_1 * ((x0_0 * x3_10) + (x0_1 * x3_13) + (x0_2 * x3_16))) + (x1_2 * ((x0_0 * x3_19) + (x0_1 * x3_22) + (x0_2 * x3_25))))) + (x2_1 * ((x1_0 * ((x0_0 * x3_28) + (x0_1 * x3_31) + (x0_2 * x3_34))) + (x1_1 * ((x0_0 * x3_37) + (x0_1 * x3_40) + (x0_2 * x3_43))) + (x1_2 * ((x0_0 * x3_46) + (x0_1 * x3_49) + (x0_2 * x3_52))))) + (x2_2 * ((x1_0 * ((x0_0 * x3_55) + (x0_1 * x3_58) + (x0_2 * x3_61))) + (x1_1 * ((x0_0 * x3_64) + (x0_1 * x3_67) + (x0_2 * x3_70))) + (x1_2 * ((x0_0 * x3_73) + (x0_1 * x3_76) + (x0_2 * x3_79))))));
+    t_T[25] = ((x2_0 * x3_25) + (x2_1 * x3_52) + (x2_2 * x3_79));
+    t_T[52] = ((x2_3 * x3_25) + (x2_4 * x3_52) + (x2_5 * x3_79));
+    t_T[79] = ((x2_6 * x3_25) + (x2_7 * x3_52) + (x2_8 * x3_79));
+    t_M[1] = ((x1_0 * t_T[1]) + (x1_1 * t_T[10]) + (x1_2 * t_T[19]));
+    t_M[10] = ((x1_3 * t_T[1]) + (x1_4 * t_T[10]) + (x1_5 * t_T[19]));
+    t_M[19] = ((x1_6 * t_T[1]) + (x1_7 * t_T[10]) + (x1_8 * t_T[19]));
+    t_M[4] = ((x1_0 * t_T[4]) + (x1_1 * t_T[13]) + (x1_2 * t_T[22]));
+    t_M[13] = ((x1_3 * t_T[4]) + (x1_4 * t_T[13]) + (x1_5 * t_T[22]));
+    t_M[22] = ((x1_6 * t_T[4]) + (x1_7 * t_T[13]) + (x1_8 * t_T[22]));
+    t_M[7] = ((x1_0 * t_T[7]) + (x1_1 * t_T[16]) + (x1_2 * t_T[25]));
+    t_M[16] = ((x1_3 * t_T[7]) + (x1_4 * t_T[16]) + (x1_5 * t_T[25]));
+    t_M[25] = ((x1_6 * t_T[7]) + (x1_7 * t_T[16]) + (x1_8 * t_T[25]));
+    __builtin_amdgcn_sched_barrier(0);
+    t_M[28] = ((x1_0 * t_T[28]) + (x1_1 * t_T[37]) + (x1_2 * t_T[46]));
+    t_M[37] = ((x1_3 * t_T[28]) + (x1_4 * t_T[37]) + (x1_5 * t_T[46]));
+    t_M[46] = ((x1_6 * t_T[28]) + (x1_7 * t_T[37]) + (x1_8 * t_T[46]));
+    t_M[31] = ((x1_0 * t_T[31]) + (x1_1 * t_T[40]) + (x1_2 * t_T[49]));
+    t_M[40] = ((x1_3 * t_T[31]) + (x1_4 * t_T[40]) + (x1_5 * t_T[49]));
+    t_M[49] = ((x1_6 * t_T[31]) + (x1_7 * t_T[40]) + (x1_8 * t_T[49]));
+    t_M[34] = ((x1_0 * t_T[34]) + (x1_1 * t_T[43]) + (x1_2 * t_T[52]));
+    t_M[43] = ((x1_3 * t_T[34]) + (x1_4 * t_T[43]) + (x1_5 * t_T[52]));
+    t_M[52] = ((x1_6 * t_T[34]) + (x1_7 * t_T[43]) + (x1_8 * t_T[52]));
+    __builtin_amdgcn_sched_barrier(0);
+    t_M[55] = ((x1_0 * t_T[55]) + (x1_1 * t_T[64]) + (x1_2 * t_T[73]));
+    t_M[64] = ((x1_3 * t_T[55]) + (x1_4 * t_T[64]) + (x1_5 * t_T[73]));
+    t_M[73] = ((x1_6 * t_T[55]) + (x1_7 * t_T[64]) + (x1_8 * t_T[73]));
+    t_M[58] = ((x1_0 * t_T[58]) + (x1_1 * t_T[67]) + (x1_2 * t_T[76]));
+    t_M[67] = ((x1_3 * t_T[58]) + (x1_4 * t_T[67]) + (x1_5 * t_T[76]));
+    t_M[76] = ((x1_6 * t_T[58]) + (x1_7 * t_T[67]) + (x1_8 * t_T[76]));
+    t_M[61] = ((x1_0 * t_T[61]) + (x1_1 * t_T[70]) + (x1_2 * t_T[79]));
+    t_M[70] = ((x1_3 * t_T[61]) + (x1_4 * t_T[70]) + (x1_5 * t_T[79]));
+    t_M[79] = ((x1_6 * t_T[61]) + (x1_7 * t_T[70]) + (x1_8 * t_T[79]));
+    double o0_1 = ((x0_0 * t_M[1]) + (x0_1 * t_M[4]) + (x0_2 * t_M[7]));
     st(0, 1, o0_1);
-    double o0_28 = ((x2_3 * ((x1_0 * ((x0_0 * x3_1) + (x0_1 * x3_4) + (x0_2 * x3_7))) + (x1_1 * ((x0_0 * x3_10) + (x0_1 * x3_13) + (x0_2 * x3_16))) + (x1_2 * ((x0_0 * x3_19) + (x0_1 * x3_22) + (x0_2 * x3_25))))) + (x2_4 * ((x1_0 * ((x0_0 * x3_28) + (x0_1 * x3_31) + (x0_2 * x3_34))) + (x1_1 * ((x0_0 * x3_37) + (x0_1 * x3_40) + (x0_2 * x3_43))) + (x1_2 * ((x0_0 * x3_46) + (x0_1 * x3_49) + (x0_2 * x3_52))))) + (x2_5 * ((x1_0 * ((x0_0 * x3_55) + (x0_1 * x3_58) + (x0_2 * x3_61))) + (x1_1 * ((x0_0 * x3_64) + (x0_1 * x3_67) + (x0_2 * x3_70))) + (x1_2 * ((x0_0 * x3_73) + (x0_1 * x3_76) + (x0_2 * x3_79))))));
-    st(0, 28, o0_28);
-    double o0_55 = ((x2_6 * ((x1_0 * ((x0_0 * x3_1) + (x0_1 * x3_4) + (x0_2 * x3_7))) + (x1_1 * ((x0_0 * x3_10) + (x0_1 * x3_13) + (x0_2 * x3_16))) + (x1_2 * ((x0_0 * x3_19) + (x0_1 * x3_22) + (x0_2 * x3_25))))) + (x2_7 * ((x1_0 * ((x0_0 * x3_28) + (x0_1 * x3_31) + (x0_2 * x3_34))) + (x1_1 * ((x0_0 * x3_37) + (x0_1 * x3_40) + (x0_2 * x3_43))) + (x1_2 * ((x0_0 * x3_46) + (x0_1 * x3_49) + (x0_2 * x3_52))))) + (x2_8 * ((x1_0 * ((x0_0 * x3_55) + (x0_1 * x3_58) + (x0_2 * x3_61))) + (x1_1 * ((x0_0 * x3_64) + (x0_1 * x3_67) + (x0_2 * x3_70))) + (x1_2 * ((x0_0 * x3_73) + (x0_1 * x3_76) + (x0_2 * x3_79))))));
-    st(0, 55, o0_55);
-    double o0_10 = ((x2_0 * ((x1_3 * ((x0_0 * x3_1) + (x0_1 * x3_4) + (x0_2 * x3_7))) + (x1_4 * ((x0_0 * x3_10) + (x0_1 * x3_13) + (x0_2 * x3_16))) + (x1_5 * ((x0_0 * x3_19) + (x0_1 * x3_22) + (x0_2 * x3_25))))) + (x2_1 * ((x1_3 * ((x0_0 * x3_28) + (x0_1 * x3_31) + (x0_2 * x3_34))) + (x1_4 * ((x0_0 * x3_37) + (x0_1 * x3_40) + (x0_2 * x3_43))) + (x1_5 * ((x0_0 * x3_46) + (x0_1 * x3_49) + (x0_2 * x3_52))))) + (x2_2 * ((x1_3 * ((x0_0 * x3_55) + (x0_1 * x3_58) + (x0_2 * x3_61))) + (x1_4 * ((x0_0 * x3_64) + (x0_1 * x3_67) + (x0_2 * x3_70))) + (x1_5 * ((x0_0 * x3_73) + (x0_1 * x3_76) + (x0_2 * x3_79))))));
-    st(0, 10, o0_10);
-    double o0_37 = ((x2_3 * ((x1_3 * ((x0_0 * x3_1) + (x0_1 * x3_4) + (x0_2 * x3_7))) + (x1_4 * ((x0_0 * x3_10) + (x0_1 * x3_13) + (x0_2 * x3_16))) + (x1_5 * ((x0_0 * x3_19) + (x0_1 * x3_22) + (x0_2 * x3_25))))) + (x2_4 * ((x1_3 * ((x0_0 * x3_28) + (x0_1 * x3_31) + (x0_2 * x3_34))) + (x1_4 * ((x0_0 * x3_37) + (x0_1 * x3_40) + (x0_2 * x3_43))) + (x1_5 * ((x0_0 * x3_46) + (x0_1 * x3_49) + (x0_2 * x3_52))))) + (x2_5 * ((x1_3 * ((x0_0 * x3_55) + (x0_1 * x3_58) + (x0_2 * x3_61))) + (x1_4 * ((x0_0 * x3_64) + (x0_1 * x3_67) + (x0_2 * x3_70))) + (x1_5 * ((x0_0 * x3_73) + (x0_1 * x3_76) + (x0_2 * x3_79))))));
-    st(0, 37, o0_37);
-    double o0_64 = ((x2_6 * ((x1_3 * ((x0_0 * x3_1) + (x0_1 * x3_4) + (x0_2 * x3_7))) + (x1_4 * ((x0_0 * x3_10) + (x0_1 * x3_13) + (x0_2 * x3_16))) + (x1_5 * ((x0_0 * x3_19) + (x0_1 * x3_22) + (x0_2 * x3_25))))) + (x2_7 * ((x1_3 * ((x0_0 * x3_28) + (x0_1 * x3_31) + (x0_2 * x3_34))) + (x1_4 * ((x0_0 * x3_37) + (x0_1 * x3_40) + (x0_2 * x3_43))) + (x1_5 * ((x0_0 * x3_46) + (x0_1 * x3_49) + (x0_2 * x3_52))))) + (x2_8 * ((x1_3 * ((x0_0 * x3_55) + (x0_1 * x3_58) + (x0_2 * x3_61))) + (x1_4 * ((x0_0 * x3_64) + (x0_1 * x3_67) + (x0_2 * x3_70))) + (x1_5 * ((x0_0 * x3_73) + (x0_1 * x3_76) + (x0_2 * x3_79))))));
-    st(0, 64, o0_64);
-    double o0_19 = ((x2_0 * ((x1_6 * ((x0_0 * x3_1) + (x0_1 * x3_4) + (x0_2 * x3_7))) + (x1_7 * ((x0_0 * x3_10) + (x0_1 * x3_13) + (x0_2 * x3_16))) + (x1_8 * ((x0_0 * x3_19) + (x0_1 * x3_22) + (x0_2 * x3_25))))) + (x2_1 * ((x1_6 * ((x0_0 * x3_28) + (x0_1 * x3_31) + (x0_2 * x3_34))) + (x1_7 * ((x0_0 * x3_37) + (x0_1 * x3_40) + (x0_2 * x3_43))) + (x1_8 * ((x0_0 * x3_46) + (x0_1 * x3_49) + (x0_2 * x3_52))))) + (x2_2 * ((x1_6 * ((x0_0 * x3_55) + (x0_1 * x3_58) + (x0_2 * x3_61))) + (x1_7 * ((x0_0 * x3_64) + (x0_1 * x3_67) + (x0_2 * x3_70))) + (x1_8 * ((x0_0 * x3_73) + (x0_1 * x3_76) + (x0_2 * x3_79))))));
-    st(0, 19, o0_19);
-    double o0_46 = ((x2_3 * ((x1_6 * ((x0_0 * x3_1) + (x0_1 * x3_4) + (x0_2 * x3_7))) + (x1_7 * ((x0_0 * x3_10) + (x0_1 * x3_13) + (x0_2 * x3_16))) + (x1_8 * ((x0_0 * x3_19) + (x0_1 * x3_22) + (x0_2 * x3_25))))) + (x2_4 * ((x1_6 * ((x0_0 * x3_28) + (x0_1 * x3_31) + (x0_2 * x3_34))) + (x1_7 * ((x0_0 * x3_37) + (x0_1 * x3_40) + (x0_2 * x3_43))) + (x1_8 * ((x0_0 * x3_46) + (x0_1 * x3_49) + (x0_2 * x3_52))))) + (x2_5 * ((x1_6 * ((x0_0 * x3_55) + (x0_1 * x3_58) + (x0_2 * x3_61))) + (x1_7 * ((x0_0 * x3_64) + (x0_1 * x3_67) + (x0_2 * x3_70))) + (x1_8 * ((x0_0 * x3_73) + (x0_1 * x3_76) + (x0_2 * x3_79))))));
-    st(0, 46, o0_46);
-    double o0_73 = ((x2_6 * ((x1_6 * ((x0_0 * x3_1) + (x0_1 * x3_4) + (x0_2 * x3_7))) + (x1_7 * ((x0_0 * x3_10) + (x0_1 * x3_13) + (x0_2 * x3_16))) + (x1_8 * ((x0_0 * x3_19) + (x0_1 * x3_22) + (x0_2 * x3_25))))) + (x2_7 * ((x1_6 * ((x0_0 * x3_28) + (x0_1 * x3_31) + (x0_2 * x3_34))) + (x1_7 * ((x0_0 * x3_37) + (x0_1 * x3_40) + (x0_2 * x3_43))) + (x1_8 * ((x0_0 * x3_46) + (x0_1 * x3_49) + (x0_2 * x3_52))))) + (x2_8 * ((x1_6 * ((x0_0 * x3_55) + (x0_1 * x3_58) + (x0_2 * x3_61))) + (x1_7 * ((x0_0 * x3_64) + (x0_1 * x3_67) + (x0_2 * x3_70))) + (x1_8 * ((x0_0 * x3_73) + (x0_1 * x3_76) + (x0_2 * x3_79))))));
-    st(0, 73, o0_73);
-    double o0_4 = ((x2_0 * ((x1_0 * ((x0_3 * x3_1) + (x0_4 * x3_4) + (x0_5 * x3_7))) + (x1_1 * ((x0_3 * x3_10) + (x0_4 * x3_13) + (x0_5 * x3_16))) + (x1_2 * ((x0_3 * x3_19) + (x0_4 * x3_22) + (x0_5 * x3_25))))) + (x2_1 * ((x1_0 * ((x0_3 * x3_28) + (x0_4 * x3_31) + (x0_5 * x3_34))) + (x1_1 * ((x0_3 * x3_37) + (x0_4 * x3_40) + (x0_5 * x3_43))) + (x1_2 * ((x0_3 * x3_46) + (x0_4 * x3_49) + (x0_5 * x3_52))))) + (x2_2 * ((x1_0 * ((x0_3 * x3_55) + (x0_4 * x3_58) + (x0_5 * x3_61))) + (x1_1 * ((x0_3 * x3_64) + (x0_4 * x3_67) + (x0_5 * x3_70))) + (x1_2 * ((x0_3 * x3_73) + (x0_4 * x3_76) + (x0_5 * x3_79))))));
+    double o0_4 = ((x0_3 * t_M[1]) + (x0_4 * t_M[4]) + (x0_5 * t_M[7]));
     st(0, 4, o0_4);
-    double o0_31 = ((x2_3 * ((x1_0 * ((x0_3 * x3_1) + (x0_4 * x3_4) + (x0_5 * x3_7))) + (x1_1 * ((x0_3 * x3_10) + (x0_4 * x3_13) + (x0_5 * x3_16))) + (x1_2 * ((x0_3 * x3_19) + (x0_4 * x3_22) + (x0_5 * x3_25))))) + (x2_4 * ((x1_0 * ((x0_3 * x3_28) + (x0_4 * x3_31) + (x0_5 * x3_34))) + (x1_1 * ((x0_3 * x3_37) + (x0_4 * x3_40) + (x0_5 * x3_43))) + (x1_2 * ((x0_3 * x3_46) + (x0_4 * x3_49) + (x0_5 * x3_52))))) + (x2_5 * ((x1_0 * ((x0_3 * x3_55) + (x0_4 * x3_58) + (x0_5 * x3_61))) + (x1_1 * ((x0_3 * x3_64) + (x0_4 * x3_67) + (x0_5 * x3_70))) + (x1_2 * ((x0_3 * x3_73) + (x0_4 * x3_76) + (x0_5 * x3_79))))));
-    st(0, 31, o0_31);
-    double o0_58 = ((x2_6 * ((x1_0 * ((x0_3 * x3_1) + (x0_4 * x3_4) + (x0_5 * x3_7))) + (x1_1 * ((x0_3 * x3_10) + (x0_4 * x3_13) + (x0_5 * x3_16))) + (x1_2 * ((x0_3 * x3_19) + (x0_4 * x3_22) + (x0_5 * x3_25))))) + (x2_7 * ((x1_0 * ((x0_3 * x3_28) + (x0_4 * x3_31) + (x0_5 * x3_34))) + (x1_1 * ((x0_3 * x3_37) + (x0_4 * x3_40) + (x0_5 * x3_43))) + (x1_2 * ((x0_3 * x3_46) + (x0_4 * x3_49) + (x0_5 * x3_52))))) + (x2_8 * ((x1_0 * ((x0_3 * x3_55) + (x0_4 * x3_58) + (x0_5 * x3_61))) + (x1_1 * ((x0_3 * x3_64) + (x0_4 * x3_67) + (x0_5 * x3_70))) + (x1_2 * ((x0_3 * x3_73) + (x0_4 * x3_76) + (x0_5 * x3_79))))));
-    st(0, 58, o0_58);
-    double o0_13 = ((x2_0 * ((x1_3 * ((x0_3 * x3_1) + (x0_4 * x3_4) + (x0_5 * x3_7))) + (x1_4 * ((x0_3 * x3_10) + (x0_4 * x3_13) + (x0_5 * x3_16))) + (x1_5 * ((x0_3 * x3_19) + (x0_4 * x3_22) + (x0_5 * x3_25))))) + (x2_1 * ((x1_3 * ((x0_3 * x3_28) + (x0_4 * x3_31) + (x0_5 * x3_34))) + (x1_4 * ((x0_3 * x3_37) + (x0_4 * x3_40) + (x0_5 * x3_43))) + (x1_5 * ((x0_3 * x3_46) + (x0_4 * x3_49) + (x0_5 * x3_52))))) + (x2_2 * ((x1_3 * ((x0_3 * x3_55) + (x0_4 * x3_58) + (x0_5 * x3_61))) + (x1_4 * ((x0_3 * x3_64) + (x0_4 * x3_67) + (x0_5 * x3_70))) + (x1_5 * ((x0_3 * x3_73) + (x0_4 * x3_76) + (x0_5 * x3_79))))));
-    st(0, 13, o0_13);
-    double o0_40 = ((x2_3 * ((x1_3 * ((x0_3 * x3_1) + (x0_4 * x3_4) + (x0_5 * x3_7))) + (x1_4 * ((x0_3 * x3_10) + (x0_4 * x3_13) + (x0_5 * x3_16))) + (x1_5 * ((x0_3 * x3_19) + (x0_4 * x3_22) + (x0_5 * x3_25))))) + (x2_4 * ((x1_3 * ((x0_3 * x3_28) + (x0_4 * x3_31) + (x0_5 * x3_34))) + (x1_4 * ((x0_3 * x3_37) + (x0_4 * x3_40) + (x0_5 * x3_43))) + (x1_5 * ((x0_3 * x3_46) + (x0_4 * x3_49) + (x0_5 * x3_52))))) + (x2_5 * ((x1_3 * ((x0_3 * x3_55) + (x0_4 * x3_58) + (x0_5 * x3_61))) + (x1_4 * ((x0_3 * x3_64) + (x0_4 * x3_67) + (x0_5 * x3_70))) + (x1_5 * ((x0_3 * x3_73) + (x0_4 * x3_76) + (x0_5 * x3_79))))));
-    st(0, 40, o0_40);
-    double o0_67 = ((x2_6 * ((x1_3 * ((x0_3 * x3_1) + (x0_4 * x3_4) + (x0_5 * x3_7))) + (x1_4 * ((x0_3 * x3_10) + (x0_4 * x3_13) + (x0_5 * x3_16))) + (x1_5 * ((x0_3 * x3_19) + (x0_4 * x3_22) + (x0_5 * x3_25))))) + (x2_7 * ((x1_3 * ((x0_3 * x3_28) + (x0_4 * x3_31) + (x0_5 * x3_34))) + (x1_4 * ((x0_3 * x3_37) + (x0_4 * x3_40) + (x0_5 * x3_43))) + (x1_5 * ((x0_3 * x3_46) + (x0_4 * x3_49) + (x0_5 * x3_52))))) + (x2_8 * ((x1_3 * ((x0_3 * x3_55) + (x0_4 * x3_58) + (x0_5 * x3_61))) + (x1_4 * ((x0_3 * x3_64) + (x0_4 * x3_67) + (x0_5 * x3_70))) + (x1_5 * ((x0_3 * x3_73) + (x0_4 * x3_76) + (x0_5 * x3_79))))));
-    st(0, 67, o0_67);
-    double o0_22 = ((x2_0 * ((x1_6 * ((x0_3 * x3_1) + (x0_4 * x3_4) + (x0_5 * x3_7))) + (x1_7 * ((x0_3 * x3_10) + (x0_4 * x3_13) + (x0_5 * x3_16))) + (x1_8 * ((x0_3 * x3_19) + (x0_4 * x3_22) + (x0_5 * x3_25))))) + (x2_1 * ((x1_6 * ((x0_3 * x3_28) + (x0_4 * x3_31) + (x0_5 * x3_34))) + (x1_7 * ((x0_3 * x3_37) + (x0_4 * x3_40) + (x0_5 * x3_43))) + (x1_8 * ((x0_3 * x3_46) + (x0_4 * x3_49) + (x0_5 * x3_52))))) + (x2_2 * ((x1_6 * ((x0_3 * x3_55) + (x0_4 * x3_58) + (x0_5 * x3_61))) + (x1_7 * ((x0_3 * x3_64) + (x0_4 * x3_67) + (x0_5 * x3_70))) + (x1_8 * ((x0_3 * x3_73) + (x0_4 * x3_76) + (x0_5 * x3_79))))));
-    st(0, 22, o0_22);
-    double o0_49 = ((x2_3 * ((x1_6 * ((x0_3 * x3_1) + (x0_4 * x3_4) + (x0_5 * x3_7))) + (x1_7 * ((x0_3 * x3_10) + (x0_4 * x3_13) + (x0_5 * x3_16))) + (x1_8 * ((x0_3 * x3_19) + (x0_4 * x3_22) + (x0_5 * x3_25))))) + (x2_4 * ((x1_6 * ((x0_3 * x3_28) + (x0_4 * x3_31) + (x0_5 * x3_34))) + (x1_7 * ((x0_3 * x3_37) + (x0_4 * x3_40) + (x0_5 * x3_43))) + (x1_8 * ((x0_3 * x3_46) + (x0_4 * x3_49) + (x0_5 * x3_52))))) + (x2_5 * ((x1_6 * ((x0_3 * x3_55) + (x0_4 * x3_58) + (x0_5 * x3_61))) + (x1_7 * ((x0_3 * x3_64) + (x0_4 * x3_67) + (x0_5 * x3_70))) + (x1_8 * ((x0_3 * x3_73) + (x0_4 * x3_76) + (x0_5 * x3_79))))));
-    st(0, 49, o0_49);
-    double o0_76 = ((x2_6 * ((x1_6 * ((x0_3 * x3_1) + (x0_4 * x3_4) + (x0_5 * x3_7))) + (x1_7 * ((x0_3 * x3_10) + (x0_4 * x3_13) + (x0_5 * x3_16))) + (x1_8 * ((x0_3 * x3_19) + (x0_4 * x3_22) + (x0_5 * x3_25))))) + (x2_7 * ((x1_6 * ((x0_3 * x3_28) + (x0_4 * x3_31) + (x0_5 * x3_34))) + (x1_7 * ((x0_3 * x3_37) + (x0_4 * x3_40) + (x0_5 * x3_43))) + (x1_8 * ((x0_3 * x3_46) + (x0_4 * x3_49) + (x0_5 * x3_52))))) + (x2_8 * ((x1_6 * ((x0_3 * x3_55) + (x0_4 * x3_58) + (x0_5 * x3_61))) + (x1_7 * ((x0_3 * x3_64) + (x0_4 * x3_67) + (x0_5 * x3_70))) + (x1_8 * ((x0_3 * x3_73) + (x0_4 * x3_76) + (x0_5 * x3_79))))));
-    st(0, 76, o0_76);
-    double o0_7 = ((x2_0 * ((x1_0 * ((x0_6 * x3_1) + (x0_7 * x3_4) + (x0_8 * x3_7))) + (x1_1 * ((x0_6 * x3_10) + (x0_7 * x3_13) + (x0_8 * x3_16))) + (x1_2 * ((x0_6 * x3_19) + (x0_7 * x3_22) + (x0_8 * x3_25))))) + (x2_1 * ((x1_0 * ((x0_6 * x3_28) + (x0_7 * x3_31) + (x0_8 * x3_34))) + (x1_1 * ((x0_6 * x3_37) + (x0_7 * x3_40) + (x0_8 * x3_43))) + (x1_2 * ((x0_6 * x3_46) + (x0_7 * x3_49) + (x0_8 * x3_52))))) + (x2_2 * ((x1_0 * ((x0_6 * x3_55) + (x0_7 * x3_58) + (x0_8 * x3_61))) + (x1_1 * ((x0_6 * x3_64) + (x0_7 * x3_67) + (x0_8 * x3_70))) + (x1_2 * ((x0_6 * x3_73) + (x0_7 * x3_76) + (x0_8 * x3_79))))));
+    double o0_7 = ((x0_6 * t_M[1]) + (x0_7 * t_M[4]) + (x0_8 * t_M[7]));
     st(0, 7, o0_7);
-    double o0_34 = ((x2_3 * ((x1_0 * ((x0_6 * x3_1) + (x0_7 * x3_4) + (x0_8 * x3_7))) + (x1_1 * ((x0_6 * x3_10) + (x0_7 * x3_13) + (x0_8 * x3_16))) + (x1_2 * ((x0_6 * x3_19) + (x0_7 * x3_22) + (x0_8 * x3_25))))) + (x2_4 * ((x1_0 * ((x0_6 * x3_28) + (x0_7 * x3_31) + (x0_8 * x3_34))) + (x1_1 * ((x0_6 * x3_37) + (x0_7 * x3_40) + (x0_8 * x3_43))) + (x1_2 * ((x0_6 * x3_46) + (x0_7 * x3_49) + (x0_8 * x3_52))))) + (x2_5 * ((x1_0 * ((x0_6 * x3_55) + (x0_7 * x3_58) + (x0_8 * x3_61))) + (x1_1 * ((x0_6 * x3_64) + (x0_7 * x3_67) + (x0_8 * x3_70))) + (x1_2 * ((x0_6 * x3_73) + (x0_7 * x3_76) + (x0_8 * x3_79))))));
-    st(0, 34, o0_34);
-    double o0_61 = ((x2_6 * ((x1_0 * ((x0_6 * x3_1) + (x0_7 * x3_4) + (x0_8 * x3_7))) + (x1_1 * ((x0_6 * x3_10) + (x0_7 * x3_13) + (x0_8 * x3_16))) + (x1_2 * ((x0_6 * x3_19) + (x0_7 * x3_22) + (x0_8 * x3_25))))) + (x2_7 * ((x1_0 * ((x0_6 * x3_28) + (x0_7 * x3_31) + (x0_8 * x3_34))) + (x1_1 * ((x0_6 * x3_37) + (x0_7 * x3_40) + (x0_8 * x3_43))) + (x1_2 * ((x0_6 * x3_46) + (x0_7 * x3_49) + (x0_8 * x3_52))))) + (x2_8 * ((x1_0 * ((x0_6 * x3_55) + (x0_7 * x3_58) + (x0_8 * x3_61))) + (x1_1 * ((x0_6 * x3_64) + (x0_7 * x3_67) + (x0_8 * x3_70))) + (x1_2 * ((x0_6 * x3_73) + (x0_7 * x3_76) + (x0_8 * x3_79))))));
-    st(0, 61, o0_61);
-    double o0_16 = ((x2_0 * ((x1_3 * ((x0_6 * x3_1) + (x0_7 * x3_4) + (x0_8 * x3_7))) + (x1_4 * ((x0_6 * x3_10) + (x0_7 * x3_13) + (x0_8 * x3_16))) + (x1_5 * ((x0_6 * x3_19) + (x0_7 * x3_22) + (x0_8 * x3_25))))) + (x2_1 * ((x1_3 * ((x0_6 * x3_28) + (x0_7 * x3_31) + (x0_8 * x3_34))) + (x1_4 * ((x0_6 * x3_37) + (x0_7 * x3_40) + (x0_8 * x3_43))) + (x1_5 * ((x0_6 * x3_46) + (x0_7 * x3_49) + (x0_8 * x3_52))))) + (x2_2 * ((x1_3 * ((x0_6 * x3_55) + (x0_7 * x3_58) + (x0_8 * x3_61))) + (x1_4 * ((x0_6 * x3_64) + (x0_7 * x3_67) + (x0_8 * x3_70))) + (x1_5 * ((x0_6 * x3_73) + (x0_7 * x3_76) + (x0_8 * x3_79))))));
+    double o0_10 = ((x0_0 * t_M[10]) + (x0_1 * t_M[13]) + (x0_2 * t_M[16]));
+    st(0, 10, o0_10);
+    double o0_13 = ((x0_3 * t_M[10]) + (x0_4 * t_M[13]) + (x0_5 * t_M[16]));
+    st(0, 13, o0_13);
+    double o0_16 = ((x0_6 * t_M[10]) + (x0_7 * t_M[13]) + (x0_8 * t_M[16]));
     st(0, 16, o0_16);
-    double o0_43 = ((x2_3 * ((x1_3 * ((x0_6 * x3_1) + (x0_7 * x3_4) + (x0_8 * x3_7))) + (x1_4 * ((x0_6 * x3_10) + (x0_7 * x3_13) + (x0_8 * x3_16))) + (x1_5 * ((x0_6 * x3_19) + (x0_7 * x3_22) + (x0_8 * x3_25))))) + (x2_4 * ((x1_3 * ((x0_6 * x3_28) + (x0_7 * x3_31) + (x0_8 * x3_34))) + (x1_4 * ((x0_6 * x3_37) + (x0_7 * x3_40) + (x0_8 * x3_43))) + (x1_5 * ((x0_6 * x3_46) + (x0_7 * x3_49) + (x0_8 * x3_52))))) + (x2_5 * ((x1_3 * ((x0_6 * x3_55) + (x0_7 * x3_58) + (x0_8 * x3_61))) + (x1_4 * ((x0_6 * x3_64) + (x0_7 * x3_67) + (x0_8 * x3_70))) + (x1_5 * ((x0_6 * x3_73) + (x0_7 * x3_76) + (x0_8 * x3_79))))));
-    st(0, 43, o0_43);
-    double o0_70 = ((x2_6 * ((x1_3 * ((x0_6 * x3_1) + (x0_7 * x3_4) + (x0_8 * x3_7))) + (x1_4 * ((x0_6 * x3_10) + (x0_7 * x3_13) + (x0_8 * x3_16))) + (x1_5 * ((x0_6 * x3_19) + (x0_7 * x3_22) + (x0_8 * x3_25))))) + (x2_7 * ((x1_3 * ((x0_6 * x3_28) + (x0_7 * x3_31) + (x0_8 * x3_34))) + (x1_4 * ((x0_6 * x3_37) + (x0_7 * x3_40) + (x0_8 * x3_43))) + (x1_5 * ((x0_6 * x3_46) + (x0_7 * x3_49) + (x0_8 * x3_52))))) + (x2_8 * ((x1_3 * ((x0_6 * x3_55) + (x0_7 * x3_58) + (x0_8 * x3_61))) + (x1_4 * ((x0_6 * x3_64) + (x0_7 * x3_67) + (x0_8 * x3_70))) + (x1_5 * ((x0_6 * x3_73) + (x0_7 * x3_76) + (x0_8 * x3_79))))));
-    st(0, 70, o0_70);
-    double o0_25 = ((x2_0 * ((x1_6 * ((x0_6 * x3_1) + (x0_7 * x3_4) + (x0_8 * x3_7))) + (x1_7 * ((x0_6 * x3_10) + (x0_7 * x3_13) + (x0_8 * x3_16))) + (x1_8 * ((x0_6 * x3_19) + (x0_7 * x3_22) + (x0_8 * x3_25))))) + (x2_1 * ((x1_6 * ((x0_6 * x3_28) + (x0_7 * x3_31) + (x0_8 * x3_34))) + (x1_7 * ((x0_6 * x3_37) + (x0_7 * x3_40) + (x0_8 * x3_43))) + (x1_8 * ((x0_6 * x3_46) + (x0_7 * x3_49) + (x0_8 * x3_52))))) + (x2_2 * ((x1_6 * ((x0_6 * x3_55) + (x0_7 * x3_58) + (x0_8 * x3_61))) + (x1_7 * ((x0_6 * x3_64) + (x0_7 * x3_67) + (x0_8 * x3_70))) + (x1_8 * ((x0_6 * x3_73) + (x0_7 * x3_76) + (x0_8 * x3_79))))));
+    double o0_19 = ((x0_0 * t_M[19]) + (x0_1 * t_M[22]) + (x0_2 * t_M[25]));
+    st(0, 19, o0_19);
+    double o0_22 = ((x0_3 * t_M[19]) + (x0_4 * t_M[22]) + (x0_5 * t_M[25]));
+    st(0, 22, o0_22);
+    double o0_25 = ((x0_6 * t_M[19]) + (x0_7 * t_M[22]) + (x0_8 * t_M[25]));
     st(0, 25, o0_25);
-    double o0_52 = ((x2_3 * ((x1_6 * ((x0_6 * x3_1) + (x0_7 * x3_4) + (x0_8 * x3_7))) + (x1_7 * ((x0_6 * x3_10) + (x0_7 * x3_13) + (x0_8 * x3_16))) + (x1_8 * ((x0_6 * x3_19) + (x0_7 * x3_22) + (x0_8 * x3_25))))) + (x2_4 * ((x1_6 * ((x0_6 * x3_28) + (x0_7 * x3_31) + (x0_8 * x3_34))) + (x1_7 * ((x0_6 * x3_37) + (x0_7 * x3_40) + (x0_8 * x3_43))) + (x1_8 * ((x0_6 * x3_46) + (x0_7 * x3_49) + (x0_8 * x3_52))))) + (x2_5 * ((x1_6 * ((x0_6 * x3_55) + (x0_7 * x3_58) + (x0_8 * x3_61))) + (x1_7 * ((x0_6 * x3_64) + (x0_7 * x3_67) + (x0_8 * x3_70))) + (x1_8 * ((x0_6 * x3_73) + (x0_7 * x3_76) + (x0_8 * x3_79))))));
+    __builtin_amdgcn_sched_barrier(0);
+    double o0_28 = ((x0_0 * t_M[28]) + (x0_1 * t_M[31]) + (x0_2 * t_M[34]));
+    st(0, 28, o0_28);
+    double o0_31 = ((x0_3 * t_M[28]) + (x0_4 * t_M[31]) + (x0_5 * t_M[34]));
+    st(0, 31, o0_31);
+    double o0_34 = ((x0_6 * t_M[28]) + (x0_7 * t_M[31]) + (x0_8 * t_M[34]));
+    st(0, 34, o0_34);
+    double o0_37 = ((x0_0 * t_M[37]) + (x0_1 * t_M[40]) + (x0_2 * t_M[43]));
+    st(0, 37, o0_37);
+    double o0_40 = ((x0_3 * t_M[37]) + (x0_4 * t_M[40]) + (x0_5 * t_M[43]));
+    st(0, 40, o0_40);
+    double o0_43 = ((x0_6 * t_M[37]) + (x0_7 * t_M[40]) + (x0_8 * t_M[43]));
+    st(0, 43, o0_43);
+    double o0_46 = ((x0_0 * t_M[46]) + (x0_1 * t_M[49]) + (x0_2 * t_M[52]));
+    st(0, 46, o0_46);
+    double o0_49 = ((x0_3 * t_M[46]) + (x0_4 * t_M[49]) + (x0_5 * t_M[52]));
+    st(0, 49, o0_49);
+    double o0_52 = ((x0_6 * t_M[46]) + (x0_7 * t_M[49]) + (x0_8 * t_M[52]));
     st(0, 52, o0_52);
-    double o0_79 = ((x2_6 * ((x1_6 * ((x0_6 * x3_1) + (x0_7 * x3_4) + (x0_8 * x3_7))) + (x1_7 * ((x0_6 * x3_10) + (x0_7 * x3_13) + (x0_8 * x3_16))) + (x1_8 * ((x0_6 * x3_19) + (x0_7 * x3_22) + (x0_8 * x3_25))))) + (x2_7 * ((x1_6 * ((x0_6 * x3_28) + (x0_7 * x3_31) + (x0_8 * x3_34))) + (x1_7 * ((x0_6 * x3_37) + (x0_7 * x3_40) + (x0_8 * x3_43))) + (x1_8 * ((x0_6 * x3_46) + (x0_7 * x3_49) + (x0_8 * x3_52))))) + (x2_8 * ((x1_6 * ((x0_6 * x3_55) + (x0_7 * x3_58) + (x0_8 * x3_61))) + (x1_7 * ((x0_6 * x3_64) + (x0_7 * x3_67) + (x0_8 * x3_70))) + (x1_8 * ((x0_6 * x3_73) + (x0_7 * x3_76) + (x0_8 * x3_79))))));
+    __builtin_amdgcn_sched_barrier(0);
+    double o0_55 = ((x0_0 * t_M[55]) + (x0_1 * t_M[58]) + (x0_2 * t_M[61]));
+    st(0, 55, o0_55);
+    double o0_58 = ((x0_3 * t_M[55]) + (x0_4 * t_M[58]) + (x0_5 * t_M[61]));
+    st(0, 58, o0_58);
+    double o0_61 = ((x0_6 * t_M[55]) + (x0_7 * t_M[58]) + (x0_8 * t_M[61]));
+    st(0, 61, o0_61);
+    double o0_64 = ((x0_0 * t_M[64]) + (x0_1 * t_M[67]) + (x0_2 * t_M[70]));
+    st(0, 64, o0_64);
+    double o0_67 = ((x0_3 * t_M[64]) + (x0_4 * t_M[67]) + (x0_5 * t_M[70]));
+    st(0, 67, o0_67);
+    double o0_70 = ((x0_6 * t_M[64]) + (x0_7 * t_M[67]) + (x0_8 * t_M[70]));
+    st(0, 70, o0_70);
+    double o0_73 = ((x0_0 * t_M[73]) + (x0_1 * t_M[76]) + (x0_2 * t_M[79]));
+    st(0, 73, o0_73);
+    double o0_76 = ((x0_3 * t_M[73]) + (x0_4 * t_M[76]) + (x0_5 * t_M[79]));
+    st(0, 76, o0_76);
+    double o0_79 = ((x0_6 * t_M[73]) + (x0_7 * t_M[76]) + (x0_8 * t_M[79]));
     st(0, 79, o0_79);
     __builtin_amdgcn_sched_barrier(0);
     const double x3_2 = ld(3, 2);
-    const double x3_5 = ld(3, 5);
-    const double x3_8 = ld(3, 8);
-    const double x3_11 = ld(3, 11);
-    const double x3_14 = ld(3, 14);
-    const double x3_17 = ld(3, 17);
-    const double x3_20 = ld(3, 20);
-    const double x3_23 = ld(3, 23);
-    const double x3_26 = ld(3, 26);
     const double x3_29 = ld(3, 29);
-    const double x3_32 = ld(3, 32);
-    const double x3_35 = ld(3, 35);
-    const double x3_38 = ld(3, 38);
-    const double x3_41 = ld(3, 41);
-    const double x3_44 = ld(3, 44);
-    const double x3_47 = ld(3, 47);
-    const double x3_50 = ld(3, 50);
-    const double x3_53 = ld(3, 53);
     const double x3_56 = ld(3, 56);
+    t_T[2] = ((x2_0 * x3_2) + (x2_1 * x3_29) + (x2_2 * x3_56));
+    t_T[29] = ((x2_3 * x3_2) + (x2_4 * x3_29) + (x2_5 * x3_56));
+    t_T[56] = ((x2_6 * x3_2) + (x2_7 * x3_29) + (x2_8 * x3_56));
+    const double x3_5 = ld(3, 5);
+    const double x3_32 = ld(3, 32);
     const double x3_59 = ld(3, 59);
+    t_T[5] = ((x2_0 * x3_5) + (x2_1 * x3_32) + (x2_2 * x3_59));
+    t_T[32] = ((x2_3 * x3_5) + (x2_4 * x3_32) + (x2_5 * x3_59));
+    t_T[59] = ((x2_6 * x3_5) + (x2_7 * x3_32) + (x2_8 * x3_59));
+    const double x3_8 = ld(3, 8);
+    const double x3_35 = ld(3, 35);
     const double x3_62 = ld(3, 62);
+    t_T[8] = ((x2_0 * x3_8) + (x2_1 * x3_35) + (x2_2 * x3_62));
+    t_T[35] = ((x2_3 * x3_8) + (x2_4 * x3_35) + (x2_5 * x3_62));
+    t_T[62] = ((x2_6 * x3_8) + (x2_7 * x3_35) + (x2_8 * x3_62));
+    __builtin_amdgcn_sched_barrier(0);
+    const double x3_11 = ld(3, 11);
+    const double x3_38 = ld(3, 38);
     const double x3_65 = ld(3, 65);
+    t_T[11] = ((x2_0 * x3_11) + (x2_1 * x3_38) + (x2_2 * x3_65));
+    t_T[38] = ((x2_3 * x3_11) + (x2_4 * x3_38) + (x2_5 * x3_65));
+    t_T[65] = ((x2_6 * x3_11) + (x2_7 * x3_38) + (x2_8 * x3_65));
+    const double x3_14 = ld(3, 14);
+    const double x3_41 = ld(3, 41);
     const double x3_68 = ld(3, 68);
+    t_T[14] = ((x2_0 * x3_14) + (x2_1 * x3_41) + (x2_2 * x3_68));
+    t_T[41] = ((x2_3 * x3_14) + (x2_4 * x3_41) + (x2_5 * x3_68));
+    t_T[68] = ((x2_6 * x3_14) + (x2_7 * x3_41) + (x2_8 * x3_68));
+    const double x3_17 = ld(3, 17);
+    const double x3_44 = ld(3, 44);
     const double x3_71 = ld(3, 71);
+    t_T[17] = ((x2_0 * x3_17) + (x2_1 * x3_44) + (x2_2 * x3_71));
+    t_T[44] = ((x2_3 * x3_17) + (x2_4 * x3_44) + (x2_5 * x3_71));
+    t_T[71] = ((x2_6 * x3_17) + (x2_7 * x3_44) + (x2_8 * x3_71));
+    __builtin_amdgcn_sched_barrier(0);
+    const double x3_20 = ld(3, 20);
+    const double x3_47 = ld(3, 47);
     const double x3_74 = ld(3, 74);
+    t_T[20] = ((x2_0 * x3_20) + (x2_1 * x3_47) + (x2_2 * x3_74));
+    t_T[47] = ((x2_3 * x3_20) + (x2_4 * x3_47) + (x2_5 * x3_74));
+    t_T[74] = ((x2_6 * x3_20) + (x2_7 * x3_47) + (x2_8 * x3_74));
+    const double x3_23 = ld(3, 23);
+    const double x3_50 = ld(3, 50);
     const double x3_77 = ld(3, 77);
+    t_T[23] = ((x2_0 * x3_23) + (x2_1 * x3_50) + (x2_2 * x3_77));
+    t_T[50] = ((x2_3 * x3_23) + (x2_4 * x3_50) + (x2_5 * x3_77));
+    t_T[77] = ((x2_6 * x3_23) + (x2_7 * x3_50) + (x2_8 * x3_77));
+    const double x3_26 = ld(3, 26);
+    const double x3_53 = ld(3, 53);
     const double x3_80 = ld(3, 80);
-    double o0_2 = ((x2_0 * ((x1_0 * ((x0_0 * x3_2) + (x0_1 * x3_5) + (x0_2 * x3_8))) + (x1_1 * ((x0_0 * x3_11) + (x0_1 * x3_14) + (x0_2 * x3_17))) + (x1_2 * ((x0_0 * x3_20) + (x0_1 * x3_23) + (x0_2 * x3_26))))) + (x2_1 * ((x1_0 * ((x0_0 * x3_29) + (x0_1 * x3_32) + (x0_2 * x3_35))) + (x1_1 * ((x0_0 * x3_38) + (x0_1 * x3_41) + (x0_2 * x3_44))) + (x1_2 * ((x0_0 * x3_47) + (x0_1 * x3_50) + (x0_2 * x3_53))))) + (x2_2 * ((x1_0 * ((x0_0 * x3_56) + (x0_1 * x3_59) + (x0_2 * x3_62))) + (x1_1 * ((x0_0 * x3_65) + (x0_1 * x3_68) + (x0_2 * x3_71))) + (x1_2 * ((x0_0 * x3_74) + (x0_1 * x3_77) + (x0_2 * x3_80))))));
+    t_T[26] = ((x2_0 * x3_26) + (x2_1 * x3_53) + (x2_2 * x3_80));
+    t_T[53] = ((x2_3 * x3_26) + (x2_4 * x3_53) + (x2_5 * x3_80));
+    t_T[80] = ((x2_6 * x3_26) + (x2_7 * x3_53) + (x2_8 * x3_80));
+    t_M[2] = ((x1_0 * t_T[2]) + (x1_1 * t_T[11]) + (x1_2 * t_T[20]));
+    t_M[11] = ((x1_3 * t_T[2]) + (x1_4 * t_T[11]) + (x1_5 * t_T[20]));
+    t_M[20] = ((x1_6 * t_T[2]) + (x1_7 * t_T[11]) + (x1_8 * t_T[20]));
+    t_M[5] = ((x1_0 * t_T[5]) + (x1_1 * t_T[14]) + (x1_2 * t_T[23]));
+    t_M[14] = ((x1_3 * t_T[5]) + (x1_4 * t_T[14]) + (x1_5 * t_T[23]));
+    t_M[23] = ((x1_6 * t_T[5]) + (x1_7 * t_T[14]) + (x1_8 * t_T[23]));
+    t_M[8] = ((x1_0 * t_T[8]) + (x1_1 * t_T[17]) + (x1_2 * t_T[26]));
+    t_M[17] = ((x1_3 * t_T[8]) + (x1_4 * t_T[17]) + (x1_5 * t_T[26]));
+    t_M[26] = ((x1_6 * t_T[8]) + (x1_7 * t_T[17]) + (x1_8 * t_T[26]));
+    __builtin_amdgcn_sched_barrier(0);
+    t_M[29] = ((x1_0 * t_T[29]) + (x1_1 * t_T[38]) + (x1_2 * t_T[47]));
+    t_M[38] = ((x1_3 * t_T[29]) + (x1_4 * t_T[38]) + (x1_5 * t_T[47]));
+    t_M[47] = ((x1_6 * t_T[29]) + (x1_7 * t_T[38]) + (x1_8 * t_T[47]));
+    t_M[32] = ((x1_0 * t_T[32]) + (x1_1 * t_T[41]) + (x1_2 * t_T[50]));
+    t_M[41] = ((x1_3 * t_T[32]) + (x1_4 * t_T[41]) + (x1_5 * t_T[50]));
+    t_M[50] = ((x1_6 * t_T[32]) + (x1_7 * t_T[41]) + (x1_8 * t_T[50]));
+    t_M[35] = ((x1_0 * t_T[35]) + (x1_1 * t_T[44]) + (x1_2 * t_T[53]));
+    t_M[44] = ((x1_3 * t_T[35]) + (x1_4 * t_T[44]) + (x1_5 * t_T[53]));
+    t_M[53] = ((x1_6 * t_T[35]) + (x1_7 * t_T[44]) + (x1_8 * t_T[53]));
+    __builtin_amdgcn_sched_barrier(0);
+    t_M[56] = ((x1_0 * t_T[56]) + (x1_1 * t_T[65]) + (x1_2 * t_T[74]));
+    t_M[65] = ((x1_3 * t_T[56]) + (x1_4 * t_T[65]) + (x1_5 * t_T[74]));
+    t_M[74] = ((x1_6 * t_T[56]) + (x1_7 * t_T[65]) + (x1_8 * t_T[74]));
+    t_M[59] = ((x1_0 * t_T[59]) + (x1_1 * t_T[68]) + (x1_2 * t_T[77]));
+    t_M[68] = ((x1_3 * t_T[59]) + (x1_4 * t_T[68]) + (x1_5 * t_T[77]));
+    t_M[77] = ((x1_6 * t_T[59]) + (x1_7 * t_T[68]) + (x1_8 * t_T[77]));
+    t_M[62] = ((x1_0 * t_T[62]) + (x1_1 * t_T[71]) + (x1_2 * t_T[80]));
+    t_M[71] = ((x1_3 * t_T[62]) + (x1_4 * t_T[71]) + (x1_5 * t_T[80]));
+    t_M[80] = ((x1_6 * t_T[62]) + (x1_7 * t_T[71]) + (x1_8 * t_T[80]));
+    double o0_2 = ((x0_0 * t_M[2]) + (x0_1 * t_M[5]) + (x0_2 * t_M[8]));
     st(0, 2, o0_2);
-    double o0_29 = ((x2_3 * ((x1_0 * ((x0_0 * x3_2) + (x0_1 * x3_5) + (x0_2 * x3_8))) + (x1_1 * ((x0_0 * x3_11) + (x0_1 * x3_14) + (x0_2 * x3_17))) + (x1_2 * ((x0_0 * x3_20) + (x0_1 * x3_23) + (x0_2 * x3_26))))) + (x2_4 * ((x1_0 * ((x0_0 * x3_29) + (x0_1 * x3_32) + (x0_2 * x3_35))) + (x1_1 * ((x0_0 * x3_38) + (x0_1 * x3_41) + (x0_2 * x3_44))) + (x1_2 * ((x0_0 * x3_47) + (x0_1 * x3_50) + (x0_2 * x3_53))))) + (x2_5 * ((x1_0 * ((x0_0 * x3_56) + (x0_1 * x3_59) + (x0_2 * x3_62))) + (x1_1 * ((x0_0 * x3_65) + (x0_1 * x3_68) + (x0_2 * x3_71))) + (x1_2 * ((x0_0 * x3_74) + (x0_1 * x3_77) + (x0_2 * x3_80))))));
-    st(0, 29, o0_29);
-    double o0_56 = ((x2_6 * ((x1_0 * ((x0_0 * x3_2) + (x0_1 * x3_5) + (x0_2 * x3_8))) + (x1_1 * ((x0_0 * x3_11) + (x0_1 * x3_14) + (x0_2 * x3_17))) + (x1_2 * ((x0_0 * x3_20) + (x0_1 * x3_23) + (x0_2 * x3_26))))) + (x2_7 * ((x1_0 * ((x0_0 * x3_29) + (x0_1 * x3_32) + (x0_2 * x3_35))) + (x1_1 * ((x0_0 * x3_38) + (x0_1 * x3_41) + (x0_2 * x3_44))) + (x1_2 * ((x0_0 * x3_47) + (x0_1 * x3_50) + (x0_2 * x3_53))))) + (x2_8 * ((x1_0 * ((x0_0 * x3_56) + (x0_1 * x3_59) + (x0_2 * x3_62))) + (x1_1 * ((x0_0 * x3_65) + (x0_1 * x3_68) + (x0_2 * x3_71))) + (x1_2 * ((x0_0 * x3_74) + (x0_1 * x3_77) + (x0_2 * x3_80))))));
-    st(0, 56, o0_56);
-    double o0_11 = ((x2_0 * ((x1_3 * ((x0_0 * x3_2) + (x0_1 * x3_5) + (x0_2 * x3_8))) + (x1_4 * ((x0_0 * x3_11) + (x0_1 * x3_14) + (x0_2 * x3_17))) + (x1_5 * ((x0_0 * x3_20) + (x0_1 * x3_23) + (x0_2 * x3_26))))) + (x2_1 * ((x1_3 * ((x0_0 * x3_29) + (x0_1 * x3_32) + (x0_2 * x3_35))) + (x1_4 * ((x0_0 * x3_38) + (x0_1 * x3_41) + (x0_2 * x3_44))) + (x1_5 * ((x0_0 * x3_47) + (x0_1 * x3_50) + (x0_2 * x3_53))))) + (x2_2 * ((x1_3 * ((x0_0 * x3_56) + (x0_1 * x3_59) + (x0_2 * x3_62))) + (x1_4 * ((x0_0 * x3_65) + (x0_1 * x3_68) + (x0_2 * x3_71))) + (x1_5 * ((x0_0 * x3_74) + (x0_1 * x3_77) + (x0_2 * x3_80))))));
-    st(0, 11, o0_11);
-    double o0_38 = ((x2_3 * ((x1_3 * ((x0_0 * x3_2) + (x0_1 * x3_5) + (x0_2 * x3_8))) + (x1_4 * ((x0_0 * x3_11) + (x0_1 * x3_14) + (x0_2 * x3_17))) + (x1_5 * ((x0_0 * x3_20) + (x0_1 * x3_23) + (x0_2 * x3_26))))) + (x2_4 * ((x1_3 * ((x0_0 * x3_29) + (x0_1 * x3_32) + (x0_2 * x3_35))) + (x1_4 * ((x0_0 * x3_38) + (x0_1 * x3_41) + (x0_2 * x3_44))) + (x1_5 * ((x0_0 * x3_47) + (x0_1 * x3_50) + (x0_2 * x3_53))))) + (x2_5 * ((x1_3 * ((x0_0 * x3_56) + (x0_1 * x3_59) + (x0_2 * x3_62))) + (x1_4 * ((x0_0 * x3_65) + (x0_1 * x3_68) + (x0_2 * x3_71))) + (x1_5 * ((x0_0 * x3_74) + (x0_1 * x3_77) + (x0_2 * x3_80))))));
-    st(0, 38, o0_38);
-    double o0_65 = ((x2_6 * ((x1_3 * ((x0_0 * x3_2) + (x0_1 * x3_5) + (x0_2 * x3_8))) + (x1_4 * ((x0_0 * x3_11) + (x0_1 * x3_14) + (x0_2 * x3_17))) + (x1_5 * ((x0_0 * x3_20) + (x0_1 * x3_23) + (x0_2 * x3_26))))) + (x2_7 * ((x1_3 * ((x0_0 * x3_29) + (x0_1 * x3_32) + (x0_2 * x3_35))) + (x1_4 * ((x0_0 * x3_38) + (x0_1 * x3_41) + (x0_2 * x3_44))) + (x1_5 * ((x0_0 * x3_47) + (x0_1 * x3_50) + (x0_2 * x3_53))))) + (x2_8 * ((x1_3 * ((x0_0 * x3_56) + (x0_1 * x3_59) + (x0_2 * x3_62))) + (x1_4 * ((x0_0 * x3_65) + (x0_1 * x3_68) + (x0_2 * x3_71))) + (x1_5 * ((x0_0 * x3_74) + (x0_1 * x3_77) + (x0_2 * x3_80))))));
-    st(0, 65, o0_65);
-    double o0_20 = ((x2_0 * ((x1_6 * ((x0_0 * x3_2) + (x0_1 * x3_5) + (x0_2 * x3_8))) + (x1_7 * ((x0_0 * x3_11) + (x0_1 * x3_14) + (x0_2 * x3_17))) + (x1_8 * ((x0_0 * x3_20) + (x0_1 * x3_23) + (x0_2 * x3_26))))) + (x2_1 * ((x1_6 * ((x0_0 * x3_29) + (x0_1 * x3_32) + (x0_2 * x3_35))) + (x1_7 * ((x0_0 * x3_38) + (x0_1 * x3_41) + (x0_2 * x3_44))) + (x1_8 * ((x0_0 * x3_47) + (x0_1 * x3_50) + (x0_2 * x3_53))))) + (x2_2 * ((x1_6 * ((x0_0 * x3_56) + (x0_1 * x3_59) + (x0_2 * x3_62))) + (x1_7 * ((x0_0 * x3_65) + (x0_1 * x3_68) + (x0_2 * x3_71))) + (x1_8 * ((x0_0 * x3_74) + (x0_1 * x3_77) + (x0_2 * x3_80))))));
-    st(0, 20, o0_20);
-    double o0_47 = ((x2_3 * ((x1_6 * ((x0_0 * x3_2) + (x0_1 * x3_5) + (x0_2 * x3_8))) + (x1_7 * ((x0_0 * x3_11) + (x0_1 * x3_14) + (x0_2 * x3_17))) + (x1_8 * ((x0_0 * x3_20) + (x0_1 * x3_23) + (x0_2 * x3_26))))) + (x2_4 * ((x1_6 * ((x0_0 * x3_29) + (x0_1 * x3_32) + (x0_2 * x3_35))) + (x1_7 * ((x0_0 * x3_38) + (x0_1 * x3_41) + (x0_2 * x3_44))) + (x1_8 * ((x0_0 * x3_47) + (x0_1 * x3_50) + (x0_2 * x3_53))))) + (x2_5 * ((x1_6 * ((x0_0 * x3_56) + (x0_1 * x3_59) + (x0_2 * x3_62))) + (x1_7 * ((x0_0 * x3_65) + (x0_1 * x3_68) + (x0_2 * x3_71))) + (x1_8 * ((x0_0 * x3_74) + (x0_1 * x3_77) + (x0_2 * x3_80))))));
-    st(0, 47, o0_47);
-    double o0_74 = ((x2_6 * ((x1_6 * ((x0_0 * x3_2) + (x0_1 * x3_5) + (x0_2 * x3_8))) + (x1_7 * ((x0_0 * x3_11) + (x0_1 * x3_14) + (x0_2 * x3_17))) + (x1_8 * ((x0_0 * x3_20) + (x0_1 * x3_23) + (x0_2 * x3_26))))) + (x2_7 * ((x1_6 * ((x0_0 * x3_29) + (x0_1 * x3_32) + (x0_2 * x3_35))) + (x1_7 * ((x0_0 * x3_38) + (x0_1 * x3_41) + (x0_2 * x3_44))) + (x1_8 * ((x0_0 * x3_47) + (x0_1 * x3_50) + (x0_2 * x3_53))))) + (x2_8 * ((x1_6 * ((x0_0 * x3_56) + (x0_1 * x3_59) + (x0_2 * x3_62))) + (x1_7 * ((x0_0 * x3_65) + (x0_1 * x3_68) + (x0_2 * x3_71))) + (x1_8 * ((x0_0 * x3_74) + (x0_1 * x3_77) + (x0_2 * x3_80))))));
-    st(0, 74, o0_74);
-    double o0_5 = ((x2_0 * ((x1_0 * ((x0_3 * x3_2) + (x0_4 * x3_5) + (x0_5 * x3_8))) + (x1_1 * ((x0_3 * x3_11) + (x0_4 * x3_14) + (x0_5 * x3_17))) + (x1_2 * ((x0_3 * x3_20) + (x0_4 * x3_23) + (x0_5 * x3_26))))) + (x2_1 * ((x1_0 * ((x0_3 * x3_29) + (x0_4 * x3_32) + (x0_5 * x3_35))) + (x1_1 * ((x0_3 * x3_38) + (x0_4 * x3_41) + (x0_5 * x3_44))) + (x1_2 * ((x0_3 * x3_47) + (x0_4 * x3_50) + (x0_5 * x3_53))))) + (x2_2 * ((x1_0 * ((x0_3 * x3_56) + (x0_4 * x3_59) + (x0_5 * x3_62))) + (x1_1 * ((x0_3 * x3_65) + (x0_4 * x3_68) + (x0_5 * x3_71))) + (x1_2 * ((x0_3 * x3_74) + (x0_4 * x3_77) + (x0_5 * x3_80))))));
+    double o0_5 = ((x0_3 * t_M[2]) + (x0_4 * t_M[5]) + (x0_5 * t_M[8]));
     st(0, 5, o0_5);
-    double o0_32 = ((x2_3 * ((x1_0 * ((x0_3 * x3_2) + (x0_4 * x3_5) + (x0_5 * x3_8))) + (x1_1 * ((x0_3 * x3_11) + (x0_4 * x3_14) + (x0_5 * x3_17))) + (x1_2 * ((x0_3 * x3_20) + (x0_4 * x3_23) + (x0_5 * x3_26))))) + (x2_4 * ((x1_0 * ((x0_3 * x3_29) + (x0_4 * x3_32) + (x0_5 * x3_35))) + (x1_1 * ((x0_3 * x3_38) + (x0_4 * x3_41) + (x0_5 * x3_44))) + (x1_2 * ((x0_3 * x3_47) + (x0_4 * x3_50) + (x0_5 * x3_53))))) + (x2_5 * ((x1_0 * ((x0_3 * x3_56) + (x0_4 * x3_59) + (x0_5 * x3_62))) + (x1_1 * ((x0_3 * x3_65) + (x0_4 * x3_68) + (x0_5 * x3_71))) + (x1_2 * ((x0_3 * x3_74) + (x0_4 * x3_77) + (x0_5 * x3_80))))));
-    st(0, 32, o0_32);
-    double o0_59 = ((x2_6 * ((x1_0 * ((x0_3 * x3_2) + (x0_4 * x3_5) + (x0_5 * x3_8))) + (x1_1 * ((x0_3 * x3_11) + (x0_4 * x3_14) + (x0_5 * x3_17))) + (x1_2 * ((x0_3 * x3_20) + (x0_4 * x3_23) + (x0_5 * x3_26))))) + (x2_7 * ((x1_0 * ((x0_3 * x3_29) + (x0_4 * x3_32) + (x0_5 * x3_35))) + (x1_1 * ((x0_3 * x3_38) + (x0_4 * x3_41) + (x0_5 * x3_44))) + (x1_2 * ((x0_3 * x3_47) + (x0_4 * x3_50) + (x0_5 * x3_53))))) + (x2_8 * ((x1_0 * ((x0_3 * x3_56) + (x0_4 * x3_59) + (x0_5 * x3_62))) + (x1_1 * ((x0_3 * x3_65) + (x0_4 * x3_68) + (x0_5 * x3_71))) + (x1_2 * ((x0_3 * x3_74) + (x0_4 * x3_77) + (x0_5 * x3_80))))));
-    st(0, 59, o0_59);
-    double o0_14 = ((x2_0 * ((x1_3 * ((x0_3 * x3_2) + (x0_4 * x3_5) + (x0_5 * x3_8))) + (x1_4 * ((x0_3 * x3_11) + (x0_4 * x3_14) + (x0_5 * x3_17))) + (x1_5 * ((x0_3 * x3_20) + (x0_4 * x3_23) + (x0_5 * x3_26))))) + (x2_1 * ((x1_3 * ((x0_3 * x3_29) + (x0_4 * x3_32) + (x0_5 * x3_35))) + (x1_4 * ((x0_3 * x3_38) + (x0_4 * x3_41) + (x0_5 * x3_44))) + (x1_5 * ((x0_3 * x3_47) + (x0_4 * x3_50) + (x0_5 * x3_53))))) + (x2_2 * ((x1_3 * ((x0_3 * x3_56) + (x0_4 * x3_59) + (x0_5 * x3_62))) + (x1_4 * ((x0_3 * x3_65) + (x0_4 * x3_68) + (x0_5 * x3_71))) + (x1_5 * ((x0_3 * x3_74) + (x0_4 * x3_77) + (x0_5 * x3_80))))));
-    st(0, 14, o0_14);
-    double o0_41 = ((x2_3 * ((x1_3 * ((x0_3 * x3_2) + (x0_4 * x3_5) + (x0_5 * x3_8))) + (x1_4 * ((x0_3 * x3_11) + (x0_4 * x3_14) + (x0_5 * x3_17))) + (x1_5 * ((x0_3 * x3_20) + (x0_4 * x3_23) + (x0_5 * x3_26))))) + (x2_4 * ((x1_3 * ((x0_3 * x3_29) + (x0_4 * x3_32) + (x0_5 * x3_35))) + (x1_4 * ((x0_3 * x3_38) + (x0_4 * x3_41) + (x0_5 * x3_44))) + (x1_5 * ((x0_3 * x3_47) + (x0_4 * x3_50) + (x0_5 * x3_53))))) + (x2_5 * ((x1_3 * ((x0_3 * x3_56) + (x0_4 * x3_59) + (x0_5 * x3_62))) + (x1_4 * ((x0_3 * x3_65) + (x0_4 * x3_68) + (x0_5 * x3_71))) + (x1_5 * ((x0_3 * x3_74) + (x0_4 * x3_77) + (x0_5 * x3_80))))));
-    st(0, 41, o0_41);
-    double o0_68 = ((x2_6 * ((x1_3 * ((x0_3 * x3_2) + (x0_4 * x3_5) + (x0_5 * x3_8))) + (x1_4 * ((x0_3 * x3_11) + (x0_4 * x3_14) + (x0_5 * x3_17))) + (x1_5 * ((x0_3 * x3_20) + (x0_4 * x3_23) + (x0_5 * x3_26))))) + (x2_7 * ((x1_3 * ((x0_3 * x3_29) + (x0_4 * x3_32) + (x0_5 * x3_35))) + (x1_4 * ((x0_3 * x3_38) + (x0_4 * x3_41) + (x0_5 * x3_44))) + (x1_5 * ((x0_3 * x3_47) + (x0_4 * x3_50) + (x0_5 * x3_53))))) + (x2_8 * ((x1_3 * ((x0_3 * x3_56) + (x0_4 * x3_59) + (x0_5 * x3_62))) + (x1_4 * ((x0_3 * x3_65) + (x0_4 * x3_68) + (x0_5 * x3_71))) + (x1_5 * ((x0_3 * x3_74) + (x0_4 * x3_77) + (x0_5 * x3_80))))));
-    st(0, 68, o0_68);
-    double o0_23 = ((x2_0 * ((x1_6 * ((x0_3 * x3_2) + (x0_4 * x3_5) + (x0_5 * x3_8))) + (x1_7 * ((x0_3 * x3_11) + (x0_4 * x3_14) + (x0_5 * x3_17))) + (x1_8 * ((x0_3 * x3_20) + (x0_4 * x3_23) + (x0_5 * x3_26))))) + (x2_1 * ((x1_6 * ((x0_3 * x3_29) + (x0_4 * x3_32) + (x0_5 * x3_35))) + (x1_7 * ((x0_3 * x3_38) + (x0_4 * x3_41) + (x0_5 * x3_44))) + (x1_8 * ((x0_3 * x3_47) + (x0_4 * x3_50) + (x0_5 * x3_53))))) + (x2_2 * ((x1_6 * ((x0_3 * x3_56) + (x0_4 * x3_59) + (x0_5 * x3_62))) + (x1_7 * ((x0_3 * x3_65) + (x0_4 * x3_68) + (x0_5 * x3_71))) + (x1_8 * ((x0_3 * x3_74) + (x0_4 * x3_77) + (x0_5 * x3_80))))));
-    st(0, 23, o0_23);
-    double o0_50 = ((x2_3 * ((x1_6 * ((x0_3 * x3_2) + (x0_4 * x3_5) + (x0_5 * x3_8))) + (x1_7 * ((x0_3 * x3_11) + (x0_4 * x3_14) + (x0_5 * x3_17))) + (x1_8 * ((x0_3 * x3_20) + (x0_4 * x3_23) + (x0_5 * x3_26))))) + (x2_4 * ((x1_6 * ((x0_3 * x3_29) + (x0_4 * x3_32) + (x0_5 * x3_35))) + (x1_7 * ((x0_3 * x3_38) + (x0_4 * x3_41) + (x0_5 * x3_44))) + (x1_8 * ((x0_3 * x3_47) + (x0_4 * x3_50) + (x0_5 * x3_53))))) + (x2_5 * ((x1_6 * ((x0_3 * x3_56) + (x0_4 * x3_59) + (x0_5 * x3_62))) + (x1_7 * ((x0_3 * x3_65) + (x0_4 * x3_68) + (x0_5 * x3_71))) + (x1_8 * ((x0_3 * x3_74) + (x0_4 * x3_77) + (x0_5 * x3_80))))));
-    st(0, 50, o0_50);
-    double o0_77 = ((x2_6 * ((x1_6 * ((x0_3 * x3_2) + (x0_4 * x3_5) + (x0_5 * x3_8))) + (x1_7 * ((x0_3 * x3_11) + (x0_4 * x3_14) + (x0_5 * x3_17))) + (x1_8 * ((x0_3 * x3_20) + (x0_4 * x3_23) + (x0_5 * x3_26))))) + (x2_7 * ((x1_6 * ((x0_3 * x3_29) + (x0_4 * x3_32) + (x0_5 * x3_35))) + (x1_7 * ((x0_3 * x3_38) + (x0_4 * x3_41) + (x0_5 * x3_44))) + (x1_8 * ((x0_3 * x3_47) + (x0_4 * x3_50) + (x0_5 * x3_53))))) + (x2_8 * ((x1_6 * ((x0_3 * x3_56) + (x0_4 * x3_59) + (x0_5 * x3_62))) + (x1_7 * ((x0_3 * x3_65) + (x0_4 * x3_68) + (x0_5 * x3_71))) + (x1_8 * ((x0_3 * x3_74) + (x0_4 * x3_77) + (x0_5 * x3_80))))));
-    st(0, 77, o0_77);
-    double o0_8 = ((x2_0 * ((x1_0 * ((x0_6 * x3_2) + (x0_7 * x3_5) + (x0_8 * x3_8))) + (x1_1 * ((x0_6 * x3_11) + (x0_7 * x3_14) + (x0_8 * x3_17))) + (x1_2 * ((x0_6 * x3_20) + (x0_7 * x3_23) + (x0_8 * x3_26))))) + (x2_1 * ((x1_0 * ((x0_6 * x3_29) + (x0_7 * x3_32) + (x0_8 * x3_35))) + (x1_1 * ((x0_6 * x3_38) + (x0_7 * x3_41) + (x0_8 * x3_44))) + (x1_2 * ((x0_6 * x3_47) + (x0_7 * x3_50) + (x0_8 * x3_53))))) + (x2_2 * ((x1_0 * ((x0_6 * x3_56) + (x0_7 * x3_59) + (x0_8 * x3_62))) + (x1_1 * ((x0_6 * x3_65) + (x0_7 * x3_68) + (x0_8 * x3_71))) + (x1_2 * ((x0_6 * x3_74) + (x0_7 * x3_77) + (x0_8 * x3_80))))));
+    double o0_8 = ((x0_6 * t_M[2]) + (x0_7 * t_M[5]) + (x0_8 * t_M[8]));
     st(0, 8, o0_8);
-    double o0_35 = ((x2_3 * ((x1_0 * ((x0_6 * x3_2) + (x0_7 * x3_5) + (x0_8 * x3_8))) + (x1_1 * ((x0_6 * x3_11) + (x0_7 * x3_14) + (x0_8 * x3_17))) + (x1_2 * ((x0_6 * x3_20) + (x0_7 * x3_23) + (x0_8 * x3_26))))) + (x2_4 * ((x1_0 * ((x0_6 * x3_29) + (x0_7 * x3_32) + (x0_8 * x3_35))) + (x1_1 * ((x0_6 * x3_38) + (x0_7 * x3_41) + (x0_8 * x3_44))) + (x1_2 * ((x0_6 * x3_47) + (x0_7 * x3_50) + (x0_8 * x3_53))))) + (x2_5 * ((x1_0 * ((x0_6 * x3_56) + (x0_7 * x3_59) + (x0_8 * x3_62))) + (x1_1 * ((x0_6 * x3_65) + (x0_7 * x3_68) + (x0_8 * x3_71))) + (x1_2 * ((x0_6 * x3_74) + (x0_7 * x3_77) + (x0_8 * x3_80))))));
-    st(0, 35, o0_35);
-    double o0_62 = ((x2_6 * ((x1_0 * ((x0_6 * x3_2) + (x0_7 * x3_5) + (x0_8 * x3_8))) + (x1_1 * ((x0_6 * x3_11) + (x0_7 * x3_14) + (x0_8 * x3_17))) + (x1_2 * ((x0_6 * x3_20) + (x0_7 * x3_23) + (x0_8 * x3_26))))) + (x2_7 * ((x1_0 * ((x0_6 * x3_29) + (x0_7 * x3_32) + (x0_8 * x3_35))) + (x1_1 * ((x0_6 * x3_38) + (x0_7 * x3_41) + (x0_8 * x3_44))) + (x1_2 * ((x0_6 * x3_47) + (x0_7 * x3_50) + (x0_8 * x3_53))))) + (x2_8 * ((x1_0 * ((x0_6 * x3_56) + (x0_7 * x3_59) + (x0_8 * x3_62))) + (x1_1 * ((x0_6 * x3_65) + (x0_7 * x3_68) + (x0_8 * x3_71))) + (x1_2 * ((x0_6 * x3_74) + (x0_7 * x3_77) + (x0_8 * x3_80))))));
-    st(0, 62, o0_62);
-    double o0_17 = ((x2_0 * ((x1_3 * ((x0_6 * x3_2) + (x0_7 * x3_5) + (x0_8 * x3_8))) + (x1_4 * ((x0_6 * x3_11) + (x0_7 * x3_14) + (x0_8 * x3_17))) + (x1_5 * ((x0_6 * x3_20) + (x0_7 * x3_23) + (x0_8 * x3_26))))) + (x2_1 * ((x1_3 * ((x0_6 * x3_29) + (x0_7 * x3_32) + (x0_8 * x3_35))) + (x1_4 * ((x0_6 * x3_38) + (x0_7 * x3_41) + (x0_8 * x3_44))) + (x1_5 * ((x0_6 * x3_47) + (x0_7 * x3_50) + (x0_8 * x3_53))))) + (x2_2 * ((x1_3 * ((x0_6 * x3_56) + (x0_7 * x3_59) + (x0_8 * x3_62))) + (x1_4 * ((x0_6 * x3_65) + (x0_7 * x3_68) + (x0_8 * x3_71))) + (x1_5 * ((x0_6 * x3_74) + (x0_7 * x3_77) + (x0_8 * x3_80))))));
+    double o0_11 = ((x0_0 * t_M[11]) + (x0_1 * t_M[14]) + (x0_2 * t_M[17]));
+    st(0, 11, o0_11);
+    double o0_14 = ((x0_3 * t_M[11]) + (x0_4 * t_M[14]) + (x0_5 * t_M[17]));
+    st(0, 14, o0_14);
+    double o0_17 = ((x0_6 * t_M[11]) + (x0_7 * t_M[14]) + (x0_8 * t_M[17]));
     st(0, 17, o0_17);
-    double o0_44 = ((x2_3 * ((x1_3 * ((x0_6 * x3_2) + (x0_7 * x3_5) + (x0_8 * x3_8))) + (x1_4 * ((x0_6 * x3_11) + (x0_7 * x3_14) + (x0_8 * x3_17))) + (x1_5 * ((x0_6 * x3_20) + (x0_7 * x3_23) + (x0_8 * x3_26))))) + (x2_4 * ((x1_3 * ((x0_6 * x3_29) + (x0_7 * x3_32) + (x0_8 * x3_35))) + (x1_4 * ((x0_6 * x3_38) + (x0_7 * x3_41) + (x0_8 * x3_44))) + (x1_5 * ((x0_6 * x3_47) + (x0_7 * x3_50) + (x0_8 * x3_53))))) + (x2_5 * ((x1_3 * ((x0_6 * x3_56) + (x0_7 * x3_59) + (x0_8 * x3_62))) + (x1_4 * ((x0_6 * x3_65) + (x0_7 * x3_68) + (x0_8 * x3_71))) + (x1_5 * ((x0_6 * x3_74) + (x0_7 * x3_77) + (x0_8 * x3_80))))));
-    st(0, 44, o0_44);
-    double o0_71 = ((x2_6 * ((x1_3 * ((x0_6 * x3_2) + (x0_7 * x3_5) + (x0_8 * x3_8))) + (x1_4 * ((x0_6 * x3_11) + (x0_7 * x3_14) + (x0_8 * x3_17))) + (x1_5 * ((x0_6 * x3_20) + (x0_7 * x3_23) + (x0_8 * x3_26))))) + (x2_7 * ((x1_3 * ((x0_6 * x3_29) + (x0_7 * x3_32) + (x0_8 * x3_35))) + (x1_4 * ((x0_6 * x3_38) + (x0_7 * x3_41) + (x0_8 * x3_44))) + (x1_5 * ((x0_6 * x3_47) + (x0_7 * x3_50) + (x0_8 * x3_53))))) + (x2_8 * ((x1_3 * ((x0_6 * x3_56) + (x0_7 * x3_59) + (x0_8 * x3_62))) + (x1_4 * ((x0_6 * x3_65) + (x0_7 * x3_68) + (x0_8 * x3_71))) + (x1_5 * ((x0_6 * x3_74) + (x0_7 * x3_77) + (x0_8 * x3_80))))));
-    st(0, 71, o0_71);
-    double o0_26 = ((x2_0 * ((x1_6 * ((x0_6 * x3_2) + (x0_7 * x3_5) + (x0_8 * x3_8))) + (x1_7 * ((x0_6 * x3_11) + (x0_7 * x3_14) + (x0_8 * x3_17))) + (x1_8 * ((x0_6 * x3_20) + (x0_7 * x3_23) + (x0_8 * x3_26))))) + (x2_1 * ((x1_6 * ((x0_6 * x3_29) + (x0_7 * x3_32) + (x0_8 * x3_35))) + (x1_7 * ((x0_6 * x3_38) + (x0_7 * x3_41) + (x0_8 * x3_44))) + (x1_8 * ((x0_6 * x3_47) + (x0_7 * x3_50) + (x0_8 * x3_53))))) + (x2_2 * ((x1_6 * ((x0_6 * x3_56) + (x0_7 * x3_59) + (x0_8 * x3_62))) + (x1_7 * ((x0_6 * x3_65) + (x0_7 * x3_68) + (x0_8 * x3_71))) + (x1_8 * ((x0_6 * x3_74) + (x0_7 * x3_77) + (x0_8 * x3_80))))));
+    double o0_20 = ((x0_0 * t_M[20]) + (x0_1 * t_M[23]) + (x0_2 * t_M[26]));
+    st(0, 20, o0_20);
+    double o0_23 = ((x0_3 * t_M[20]) + (x0_4 * t_M[23]) + (x0_5 * t_M[26]));
+    st(0, 23, o0_23);
+    double o0_26 = ((x0_6 * t_M[20]) + (x0_7 * t_M[23]) + (x0_8 * t_M[26]));
     st(0, 26, o0_26);
-    double o0_53 = ((x2_3 * ((x1_6 * ((x0_6 * x3_2) + (x0_7 * x3_5) + (x0_8 * x3_8))) + (x1_7 * ((x0_6 * x3_11) + (x0_7 * x3_14) + (x0_8 * x3_17))) + (x1_8 * ((x0_6 * x3_20) + (x0_7 * x3_23) + (x0_8 * x3_26))))) + (x2_4 * ((x1_6 * ((x0_6 * x3_29) + (x0_7 * x3_32) + (x0_8 * x3_35))) + (x1_7 * ((x0_6 * x3_38) + (x0_7 * x3_41) + (x0_8 * x3_44))) + (x1_8 * ((x0_6 * x3_47) + (x0_7 * x3_50) + (x0_8 * x3_53))))) + (x2_5 * ((x1_6 * ((x0_6 * x3_56) + (x0_7 * x3_59) + (x0_8 * x3_62))) + (x1_7 * ((x0_6 * x3_65) + (x0_7 * x3_68) + (x0_8 * x3_71))) + (x1_8 * ((x0_6 * x3_74) + (x0_7 * x3_77) + (x0_8 * x3_80))))));
+    __builtin_amdgcn_sched_barrier(0);
+    double o0_29 = ((x0_0 * t_M[29]) + (x0_1 * t_M[32]) + (x0_2 * t_M[35]));
+    st(0, 29, o0_29);
+    double o0_32 = ((x0_3 * t_M[29]) + (x0_4 * t_M[32]) + (x0_5 * t_M[35]));
+    st(0, 32, o0_32);
+    double o0_35 = ((x0_6 * t_M[29]) + (x0_7 * t_M[32]) + (x0_8 * t_M[35]));
+    st(0, 35, o0_35);
+    double o0_38 = ((x0_0 * t_M[38]) + (x0_1 * t_M[41]) + (x0_2 * t_M[44]));
+    st(0, 38, o0_38);
+    double o0_41 = ((x0_3 * t_M[38]) + (x0_4 * t_M[41]) + (x0_5 * t_M[44]));
+    st(0, 41, o0_41);
+    double o0_44 = ((x0_6 * t_M[38]) + (x0_7 * t_M[41]) + (x0_8 * t_M[44]));
+    st(0, 44, o0_44);
+    double o0_47 = ((x0_0 * t_M[47]) + (x0_1 * t_M[50]) + (x0_2 * t_M[53]));
+    st(0, 47, o0_47);
+    double o0_50 = ((x0_3 * t_M[47]) + (x0_4 * t_M[50]) + (x0_5 * t_M[53]));
+    st(0, 50, o0_50);
+    double o0_53 = ((x0_6 * t_M[47]) + (x0_7 * t_M[50]) + (x0_8 * t_M[53]));
     st(0, 53, o0_53);
-    double o0_80 = ((x2_6 * ((x1_6 * ((x0_6 * x3_2) + (x0_7 * x3_5) + (x0_8 * x3_8))) + (x1_7 * ((x0_6 * x3_11) + (x0_7 * x3_14) + (x0_8 * x3_17))) + (x1_8 * ((x0_6 * x3_20) + (x0_7 * x3_23) + (x0_8 * x3_26))))) + (x2_7 * ((x1_6 * ((x0_6 * x3_29) + (x0_7 * x3_32) + (x0_8 * x3_35))) + (x1_7 * ((x0_6 * x3_38) + (x0_7 * x3_41) + (x0_8 * x3_44))) + (x1_8 * ((x0_6 * x3_47) + (x0_7 * x3_50) + (x0_8 * x3_53))))) + (x2_8 * ((x1_6 * ((x0_6 * x3_56) + (x0_7 * x3_59) + (x0_8 * x3_62))) + (x1_7 * ((x0_6 * x3_65) + (x0_7 * x3_68) + (x0_8 * x3_71))) + (x1_8 * ((x0_6 * x3_74) + (x0_7 * x3_77) + (x0_8 * x3_80))))));
+    __builtin_amdgcn_sched_barrier(0);
+    double o0_56 = ((x0_0 * t_M[56]) + (x0_1 * t_M[59]) + (x0_2 * t_M[62]));
+    st(0, 56, o0_56);
+    double o0_59 = ((x0_3 * t_M[56]) + (x0_4 * t_M[59]) + (x0_5 * t_M[62]));
+    st(0, 59, o0_59);
+    double o0_62 = ((x0_6 * t_M[56]) + (x0_7 * t_M[59]) + (x0_8 * t_M[62]));
+    st(0, 62, o0_62);
+    double o0_65 = ((x0_0 * t_M[65]) + (x0_1 * t_M[68]) + (x0_2 * t_M[71]));
+    st(0, 65, o0_65);
+    double o0_68 = ((x0_3 * t_M[65]) + (x0_4 * t_M[68]) + (x0_5 * t_M[71]));
+    st(0, 68, o0_68);
+    double o0_71 = ((x0_6 * t_M[65]) + (x0_7 * t_M[68]) + (x0_8 * t_M[71]));
+    st(0, 71, o0_71);
+    double o0_74 = ((x0_0 * t_M[74]) + (x0_1 * t_M[77]) + (x0_2 * t_M[80]));
+    st(0, 74, o0_74);
+    double o0_77 = ((x0_3 * t_M[74]) + (x0_4 * t_M[77]) + (x0_5 * t_M[80]));
+    st(0, 77, o0_77);
+    double o0_80 = ((x0_6 * t_M[74]) + (x0_7 * t_M[77]) + (x0_8 * t_M[80]));
     st(0, 80, o0_80);
   }
 };

@@ -221,3 +221,60 @@ def _collect(e, out):
         _collect(e.b, out)
     elif isinstance(e, (Neg, SumExpr)):
         _collect(e.a if isinstance(e, Neg) else e.body, out)
+
+
+def _run_statements(prog, vals):
+    """Plain evaluation of a program's statements in order (temporaries and
+    outputs as arrays), for checking a staged program against one expression."""
+    import numpy as np
+    out = dict(vals)
+    for st in prog.statements:
+        t = st.lhs.tensor
+        arr = out.setdefault(t.name, np.full(t.ncomp, np.nan))
+        for c, env in st.assignments():
+            arr[c] = _evaluate(st.rhs, env, out)
+    return out
+
+
+def test_staged_triple_contraction_equals_the_single_expression():
+    """The registry's triple contraction (three stages fused slice by slice in
+    l) computes D_k^o C_j^n B_i^m E_mnol, with the inputs in the written order."""
+    import numpy as np
+    prog = {p.name: p for p in registry.programs()}["contract3"]
+    assert [t.name for t in prog.inputs] == ["D", "C", "B", "E"]
+    assert prog.fused is not None and prog.fused.name == "l"
+    rng = np.random.default_rng(9)
+    vals = {t.name: rng.uniform(-1, 1, t.ncomp) for t in prog.inputs}
+    got = _run_statements(prog, vals)["A"]
+    B, C, D = (vals[x].reshape(3, 3) for x in "BCD")
+    E = vals["E"].reshape(3, 3, 3, 3)
+    ref = np.einsum("ko,jn,im,mnol->ijkl", D, C, B, E).reshape(81)
+    assert np.abs(got - ref).max() <= 1e-13
+    from paper_1804_10120_amd.codegen.emit import generate
+    generate([prog])     # emits without reading a temporary before it is written
+
+
+def test_fusion_rules():
+    """A fused program may read a temporary only at the slice being evaluated;
+    the fused index must be free on every left-hand side; input_order must name
+    exactly the inputs."""
+    from paper_1804_10120_amd.codegen.emit import generate
+    i, j, l = indices("i j l")
+    X = Tensor("X", (3, 3))
+    T = Tensor("T", (3, 3))
+    Y = Tensor("Y", (3, 3))
+    # Y(i,l) reads T(i, 2-l)... written here as T(l, i) with the fused index in
+    # the other slot: slice l = 0 reads T(0, i) = components written at slices
+    # 0, 1 and 2 of T(i, l)
+    bad = (Program("bad_slice", "").temp(T).fuse(l)
+           .let(T[i, l], 2.0 * X[i, l]).let(Y[i, l], T[l, i]))
+    with pytest.raises(CodegenError, match="read before it is written"):
+        generate([bad])
+    ok = (Program("ok_slice", "").temp(T).fuse(l)
+          .let(T[i, l], 2.0 * X[i, l]).let(Y[i, l], T[i, l] + X[i, l]))
+    generate([ok])
+    Z = Tensor("Z", (3,))
+    with pytest.raises(CodegenError, match="fused index"):
+        Program("no_l", "").fuse(l).let(Z[i], X[i, 0]).check()
+    with pytest.raises(CodegenError, match="input_order"):
+        _ = Program("order", "").input_order(T).let(Y[i, j], X[i, j]).inputs
