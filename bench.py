@@ -794,6 +794,11 @@ def main():
             tl_batch_run_noalloc(na_doms)
         _, (ms_na,) = time_calls([na], 20, 3,
                                  labels=label(4, "dtg_chain_batched", npts, "no allocation"))
+        # queued back to back: the host's argument checks overlap the previous call's kernels
+        ms_na_q = back_to_back([na], 20,
+                               labels=label(4, "dtg_chain_batched", npts, "no allocation queued"))
+        ms_direct_q = back_to_back([[plan.run_direct]], 20,
+                                   labels=label(4, "dtg_chain_batched", npts, "direct queued"))
         na_same = all(torch.equal(a["dtg"], b) for a, b in zip(na_doms, plan.outputs))
         plan.close()
         del na, na_doms
@@ -826,6 +831,8 @@ def main():
             "separate_launches_match_batched": same,
             "direct_launch_us": ms_direct * 1e3,
             "no_allocation_us": ms_na * 1e3,
+            "no_allocation_queued_us": ms_na_q * 1e3,
+            "direct_launch_queued_us": ms_direct_q * 1e3,
             "no_allocation_matches_plan": na_same,
             "ld_unpadded_us": ms_flat * 1e3,
             "ld_unpadded_GB_s": rate(BYTES["dtg_chain_batched"] * npts, ms_flat)}

@@ -68,24 +68,37 @@ static_assert(word_of(14) * 8 == offsetof(BatchDomain, n), "BatchDomain layout")
 static_assert(kDomWords <= 64, "one wave writes a descriptor");
 
 // Packed descriptors of up to kFillCap consecutive domains, passed by value as
-// a kernel argument (under 3 KB).
-constexpr int kFillCap = 22;
+// a kernel argument; with the kernel's three pointers it stays within 4 KB,
+// the kernel-argument size every HIP runtime accepts.
+constexpr int kFillCap = 31;
 struct FillChunk {
   int32_t d0, nd;                   // domains d0 .. d0 + nd - 1
   int64_t start[kFillCap + 1];      // their first tiles, then the tile after the last
   int64_t w[kFillCap][kSetWords];   // word k of domain i: see word_of(k)
 };
-static_assert(sizeof(FillChunk) <= 3072, "kernel argument too large");
+static_assert(sizeof(FillChunk) + 3 * sizeof(void*) <= 4096, "kernel argument too large");
 
 // Block 0 writes the chunk's descriptors (lane l of the first wave writes word
 // l of each, so a descriptor is one store) and tile starts; every lane of the
 // grid then writes the domain of one tile of the chunk: the last domain whose
 // first tile is not after it (domains without tiles are passed over because
-// the next one starts at the same tile).
+// the next one starts at the same tile).  The argument words a block uses are
+// first copied to LDS by all its lanes at once, so the argument (which the
+// runtime may keep in host memory) is read in one round trip rather than one
+// per dependent load.
 __global__ __launch_bounds__(256) void k_fill_tables(FillChunk c, BatchDomain* __restrict__ doms,
                                                      int64_t* __restrict__ start,
                                                      int32_t* __restrict__ tile_dom) {
+  __shared__ int64_t s_start[kFillCap + 1];
+  __shared__ int64_t s_w[kFillCap * kSetWords];
   const int l = threadIdx.x;
+  const int nd = c.nd;
+  if (l <= nd) s_start[l] = c.start[l];
+  if (blockIdx.x == 0) {
+    const int64_t* w = &c.w[0][0];
+    for (int q = l; q < nd * kSetWords; q += 256) s_w[q] = w[q];
+  }
+  __syncthreads();
   if (blockIdx.x == 0) {
     int k = -1;  // the packed word this lane writes, if any
 #pragma unroll
@@ -93,14 +106,14 @@ __global__ __launch_bounds__(256) void k_fill_tables(FillChunk c, BatchDomain* _
       if (word_of(q) == l) k = q;
     if (l < kDomWords) {
       int64_t* out = reinterpret_cast<int64_t*>(doms + c.d0);
-      for (int i = 0; i < c.nd; ++i) out[i * kDomWords + l] = k >= 0 ? c.w[i][k] : 0;
+      for (int i = 0; i < nd; ++i) out[i * kDomWords + l] = k >= 0 ? s_w[i * kSetWords + k] : 0;
     }
-    if (l <= c.nd) start[c.d0 + l] = c.start[l];
+    if (l <= nd) start[c.d0 + l] = s_start[l];
   }
-  const int64_t t = c.start[0] + static_cast<int64_t>(blockIdx.x) * 256 + l;
-  if (t < c.start[c.nd]) {
+  const int64_t t = s_start[0] + static_cast<int64_t>(blockIdx.x) * 256 + l;
+  if (t < s_start[nd]) {
     int32_t i = 0;
-    for (int j = 1; j < c.nd; ++j) i += c.start[j] <= t ? 1 : 0;
+    for (int j = 1; j < nd; ++j) i += s_start[j] <= t ? 1 : 0;
     tile_dom[t] = c.d0 + i;
   }
 }
