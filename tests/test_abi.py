@@ -45,6 +45,16 @@ def test_every_declared_symbol_is_exported(L):
     assert set(declared()) <= set(_abi.SIGNATURES)
 
 
+def test_binding_constants_match_the_header():
+    text = open(HEADER).read()
+    for name in ("TL_ABI_VERSION", "TL_NOALLOC_MAX_DOMAINS", "TL_NOALLOC_MAX_TILES",
+                 "TL_BW_READ_BLOCKS", "TL_TUNE_NT", "TL_TUNE_XCD", "TL_TUNE_PTR64"):
+        m = re.search(rf"#define {name} (\d+)", text)
+        assert m, name
+        py = _abi.ABI_VERSION if name == "TL_ABI_VERSION" else getattr(_abi, name)
+        assert int(m.group(1)) == py, name
+
+
 def test_version_and_strings(L):
     assert L.tl_abi_version() == _abi.ABI_VERSION
     for s, name in enumerate(["TL_OK", "TL_ERR_NULL", "TL_ERR_SIZE", "TL_ERR_ALIAS",
