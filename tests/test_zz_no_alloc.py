@@ -130,3 +130,40 @@ def test_noalloc_captured_in_a_graph():
             assert torch.equal(a, o["dtg"]), f"replay {rep}: subgrid {i} differs from the eager call"
     for f, o in zip(hosts, outs):
         assert_close(o["dtg"], oracle.dtg_chain(*[f[k] for k in KEYS]), what="graph replay")
+
+
+def test_noalloc_at_its_limits():
+    """The largest batches the fixed array holds: 1024 subgrids (34 table-writing
+    launches), and one subgrid of exactly 262144 tiles of 64 points (16.8 M
+    points, fields made on the device); each bitwise equal to a plan, the
+    oracle checked on every subgrid of the first and on sampled points of the
+    second."""
+    rng = np.random.default_rng(31)
+    sizes = [int(x) for x in rng.integers(0, 40, size=_abi.TL_NOALLOC_MAX_DOMAINS)]
+    hosts, devs = _domains(sizes, seed=26)
+    ref, got = _run_both(hosts, devs, None)
+    _check(hosts, ref, got, "1024 subgrids")
+    del hosts, devs, ref, got
+
+    tune = dict(block=64, ppt=1, nt=True)
+    n = 64 * _abi.TL_NOALLOC_MAX_TILES
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    d = {}
+    for k, c in (("g", 6), ("dg", 18), ("beta", 3), ("dbeta", 9), ("K", 6), ("alpha", 1)):
+        d[k] = torch.rand(c, n, dtype=torch.float64, device="cuda", generator=gen) - 0.5
+    d["g"][[0, 3, 5]] += 2.5      # diagonal entries: a well-conditioned, diagonally dominant g
+    d["alpha"] += 1.0
+    plan = BatchPlan([d], tune=tune)
+    plan.run_direct()
+    torch.cuda.synchronize()
+    ref = plan.outputs[0].clone()
+    plan.close()
+    out = dict(d, dtg=empty_field(6, n, device="cuda"))
+    tl_batch_run_noalloc([out], tune=tune)
+    torch.cuda.synchronize()
+    assert torch.equal(ref, out["dtg"]), "max-tiles batch differs from the plan"
+    idx = np.unique(np.concatenate([np.arange(64), n - 64 + np.arange(64),
+                                    np.random.default_rng(3).integers(0, n, 4096)]))
+    ti = torch.from_numpy(idx).cuda()
+    sub = [d[k][:, ti].cpu().numpy() for k in KEYS]
+    assert_close(out["dtg"][:, ti], oracle.dtg_chain(*sub), what="max-tiles batch vs oracle")
