@@ -159,8 +159,13 @@ int num_cus() {
 
 // Default launch shapes, measured on MI355X with the library's autotuner.
 // Every kernel streams, so one rule serves nearly all of them: non-temporal
-// loads and stores always; for large grids one point per lane in blocks of 256
-// with XCD-contiguous tiles; below 2^20 points (where the whole grid is in
+// loads and stores always; for large grids one point per lane in blocks of 256,
+// with XCD-contiguous tiles when every XCD's share of each component is 1 or
+// 2 MiB (2^20 or 2^21 points), in plain order otherwise (measured for every
+// step kernel at 1 to 8 Mi points: the XCD order is 6-33 % faster at those two
+// sizes, and at the other sizes tried, powers of two included, up to 16 %
+// slower for all but the kernels with the fewest streams); below 2^20
+// points (where the whole grid is in
 // flight at once and the XCD order buys nothing) two points per lane in
 // blocks of 512, except the fused forward, which keeps one point per lane in
 // blocks of 256 (62 registers against 166 at two points); below 2^16 points
@@ -180,7 +185,7 @@ tl::Resolved defaults(tl::KernelId k, int64_t n) {
   } else if (n >= (int64_t(1) << 20)) {
     r.block = 256;
     r.ppt = 1;
-    r.xcd = true;
+    r.xcd = n == (int64_t(1) << 20) || n == (int64_t(1) << 21);
   } else if (n < (int64_t(1) << 16)) {
     r.block = 64;
     r.ppt = 1;
