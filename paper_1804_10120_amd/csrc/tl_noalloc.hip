@@ -5,7 +5,7 @@
 // descriptors, the first tile of every domain, and the tile -> domain map.
 // Here they live in `scratch`, one file-scope array per device, and are
 // written by small kernels that receive the descriptors as kernel arguments
-// (so nothing is copied from host memory and nothing is allocated); the
+// (so the call makes no memory copy of its own and allocates nothing); the
 // batched kernel of the plans then reads them from there.
 #include <hip/hip_runtime.h>
 
