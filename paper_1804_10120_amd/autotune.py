@@ -50,7 +50,12 @@ def _arch():
 
 
 def cache_key(kernel, n):
-    return f"{kernel}|{_arch()}|log2n={int(math.log2(max(n, 1)))}"
+    """Size class of a tuning: the power of two below n, and whether n is a
+    power of two itself (the tile order that pays differs between 2^21
+    points and the sizes just above, measured)."""
+    n = max(int(n), 1)
+    pow2 = "|pow2" if n & (n - 1) == 0 else ""
+    return f"{kernel}|{_arch()}|log2n={n.bit_length() - 1}{pow2}"
 
 
 _loaded = {}     # cache path -> (modification time, contents): tune="auto" looks up per call
