@@ -1,6 +1,7 @@
 // Test driver for the C ABI without Python or torch: device buffers from
 // hipMalloc, the fused chain, its adjoint and both in one pass on a stream of
-// its own, an unfused step, and argument errors; every result is compared on
+// its own, an unfused step, batch plans, the batch without allocation, and
+// argument errors; every result is compared on
 // the host with the CPU oracle (liboracle.so), per component, relative to the
 // component's largest magnitude, against 1e-12.  Exit status 0 means every
 // check passed.  Test infrastructure: built by the package build next to the
@@ -202,6 +203,19 @@ int main() {
       expect(e <= 1e-12, "batch plan vs oracle");
       expect(untouched, "points outside every subgrid untouched");
       expect(tl_batch_plan_destroy(plan) == TL_OK, "tl_batch_plan_destroy");
+      // the same subgrids without allocating: bitwise the plan's result
+      Dev outn(6 * n);
+      outn.put(fill);
+      tl_domain ndoms[3];
+      for (int k = 0; k < 3; ++k) {
+        ndoms[k] = doms[k];
+        ndoms[k].dtg.ptr = outn.p + lo[k];
+      }
+      expect(tl_batch_run_noalloc(ndoms, 3, nullptr, s) == TL_OK, "tl_batch_run_noalloc");
+      expect(hipStreamSynchronize(s) == hipSuccess, "no-allocation sync");
+      expect(outn.get() == got, "no-allocation batch equals the plan bitwise");
+      expect(tl_batch_run_noalloc(ndoms, TL_NOALLOC_MAX_DOMAINS + 1, nullptr, s) == TL_ERR_SIZE,
+             "no-allocation batch refuses too many subgrids");
     }
     // two subgrids sharing an output element are refused
     tl_domain clash[2] = {doms[0], doms[0]};
